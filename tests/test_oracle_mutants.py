@@ -1,0 +1,64 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a private copy of ``oracle/oracle.c`` (a
+flipped comparison, a dropped condition, a wrong extremum), rebuilds that
+copy, and runs the oracle pin tests against it in a subprocess: they must
+fail.  CPU only; the real oracle is never modified.
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    # H: '>= i' is the definition; '>' undercounts
+    "hindex_strict": ("if (a[i - 1] >= i) h = (int32_t)i;",
+                      "if (a[i - 1] > i) h = (int32_t)i;"),
+    # H: sorting ascending instead of descending
+    "hindex_sort_order": ("return (x < y) - (x > y);",
+                          "return (x > y) - (x < y);"),
+    # rho(S,R) is a minimum over the other r-cliques of S
+    "rho_max": ("if (tau[ids->a[q * k + j]] < m) m",
+                "if (tau[ids->a[q * k + j]] > m) m"),
+    # peeling decrements only neighbours of strictly larger degree
+    "peel_ge": ("if (ds[Rp] > ds[R]) {", "if (ds[Rp] >= ds[R]) {"),
+    # peeling skips s-cliques that lost a processed r-clique
+    "peel_no_skip": ("if (skip) continue;", "if (0) continue;"),
+    # simple graph: no self-loops, no repeated pairs
+    "keep_loops": ("if (a == b) continue;", "if (0) continue;"),
+    "keep_repeats": (
+        "if (i == 0 || key[i] != key[i - 1]) key[ne++] = key[i];",
+        "key[ne++] = key[i];"),
+    # degree levels: one decrement per removed s-clique
+    "levels_double_count": ("if (gone_before || counted_by_other) continue;",
+                            "if (gone_before) continue;"),
+    # s-clique extension vertices must be pairwise adjacent
+    "ext_not_clique": (
+        "for (int j = 0; j < depth && ok; j++) ok = adjacent(c->g, c->ext[j], x);",
+        ";"),
+}
+
+PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py"]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    before, after = MUTANTS[name]
+    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    assert src.count(before) == 1, "mutation site moved"
+    work = tmp_path / "repo"
+    for d in ("oracle", "synth", "tests"):
+        shutil.copytree(os.path.join(ROOT, d), work / d,
+                        ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    (work / "oracle" / "oracle.c").write_text(src.replace(before, after))
+    env = dict(os.environ, PYTHONPATH=str(work))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p",
+                        "no:cacheprovider", *PIN_FILES], cwd=work, env=env,
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "failed" in r.stdout
