@@ -1,0 +1,253 @@
+/*
+ * nd.h -- C ABI of the MI355X (gfx950) nucleus-decomposition library.
+ *
+ * Computes the kappa_s index of every r-clique of a simple undirected graph
+ * by the iterated h-index method of Sariyuce, Seshadhri and Pinar, "Local
+ * Algorithms for Hierarchical Dense Subgraph Discovery" (PVLDB 12(1), 2019):
+ * tau_0 = d_s (the S-degree), tau_{t+1} = U tau_t, where the update operator U
+ * (Section 3, Defn. of U) sets, for every r-clique R,
+ *     rho(S,R) = min over the other r-cliques R' of S of tau(R')  (S contains R)
+ *     U tau(R) = H({rho(S,R)} over all S containing R),
+ * H being the h-index (Section 2.2).  The iteration stops at the first sweep
+ * that changes nothing; the result is then exactly kappa_s (Theorem 3 and
+ * Lemma 2).  Three instances are supported (Section 5):
+ *     ND_KCORE      (r,s) = (1,2)  core number of every vertex
+ *     ND_KTRUSS     (r,s) = (2,3)  truss number of every edge, counted in
+ *                                  triangles (Section 2.1; Cohen's k-truss
+ *                                  number is this value + 2)
+ *     ND_NUCLEUS34  (r,s) = (3,4)  kappa_4 of every triangle
+ * under synchronous (SND, Alg. 2) or asynchronous (AND, Alg. 3) updates.
+ *
+ * Output order.  r-cliques are numbered by the lexicographic order of their
+ * sorted vertex tuples: vertices by id; edges (u,v), u<v; triangles (u,v,w),
+ * u<v<w.  nd_rcliques() lists them.  An r-clique contained in no s-clique
+ * has kappa = 0.
+ *
+ * Conventions for every entry point.
+ *   - All calls return an nd_status; on failure nd_last_error() (per calling
+ *     thread) describes it.  No call throws across the ABI.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the device's null
+ *     stream).  Work is ordered on it.  Every call returns only after its
+ *     device work has finished, unless stated otherwise.
+ *   - `on_device` != 0 means a pointer argument is a device pointer on the
+ *     context's device; 0 means host memory.  Inputs are read during the call
+ *     only (the library keeps its own copies); outputs are caller-allocated.
+ *   - The library owns every array it derives (canonical CSR, r-clique lists,
+ *     incidence lists, tau buffers) and frees them in nd_graph_destroy().
+ *   - Device memory is charged to the context's budget; a call that would
+ *     exceed it fails with ND_ERR_OOM and leaves the graph unchanged.
+ *   - Sizes: vertex ids and r-clique ids are int32 (so n, |E| and the number
+ *     of triangles must be below 2^31); offsets and incidence counts are
+ *     int64.
+ *   - Objects are not thread-safe: calls on one nd_ctx (and its graphs) must
+ *     not overlap, except the nd_server_* calls, which are.
+ */
+#ifndef ND_H
+#define ND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ND_OK = 0,
+  ND_ERR_INVALID = 1,       /* bad argument or malformed graph */
+  ND_ERR_OOM = 2,           /* device-memory budget or device exhausted */
+  ND_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+  ND_ERR_UNSUPPORTED = 4,   /* kind/mode/option not available */
+  ND_ERR_NOT_CONVERGED = 5, /* max_iters reached; output is tau_t >= kappa */
+  ND_ERR_BUSY = 6,          /* server queue full */
+  ND_ERR_CANCELLED = 7,     /* served request cancelled or stopped early */
+  ND_ERR_TIMEOUT = 8        /* nd_server_wait timed out; request still live */
+} nd_status;
+
+typedef enum { ND_KCORE = 0, ND_KTRUSS = 1, ND_NUCLEUS34 = 2 } nd_kind;
+
+/* ND_SND: Jacobi-style sweeps, tau_{t+1} = U tau_t from a snapshot (Alg. 2);
+ *         every iterate is deterministic.
+ * ND_AND: Gauss-Seidel-style sweeps that read the latest values in place
+ *         (Alg. 3 without the notification lines); the converged result is
+ *         identical, intermediate iterates depend on scheduling. */
+typedef enum { ND_SND = 0, ND_AND = 1 } nd_mode;
+
+typedef struct nd_ctx nd_ctx;
+typedef struct nd_graph nd_graph;
+typedef struct nd_server nd_server;
+
+/* Per-sweep report handed to nd_opts.on_iter. */
+typedef struct {
+  int32_t iter;           /* sweep number t >= 1; tau_dev holds tau_t */
+  int64_t evaluated;      /* r-cliques whose h-index was computed */
+  int64_t changed;        /* r-cliques whose value changed in this sweep */
+  int64_t active_next;    /* r-cliques scheduled for the next sweep */
+  const int32_t *tau_dev; /* device pointer, valid only during the callback */
+  double ms;              /* device time of the sweep */
+} nd_iter_info;
+
+/* Return nonzero to stop the iteration after this sweep (the call then
+ * returns ND_ERR_NOT_CONVERGED unless the sweep changed nothing). */
+typedef int (*nd_iter_cb)(void *user, const nd_iter_info *info);
+
+typedef struct {
+  nd_mode mode;
+  int32_t max_iters;        /* sweep limit; < 0: run until a sweep changes
+                               nothing */
+  int32_t use_frontier;     /* 1: recompute only r-cliques notified by a
+                               changed neighbour (Section 4.3); results are
+                               identical */
+  double stop_active_ratio; /* > 0: stop once the fraction of r-cliques that
+                               changed in a sweep falls below this ratio
+                               (Section 5.1.4); result is then tau_t */
+  nd_iter_cb on_iter;       /* optional per-sweep callback (snapshots) */
+  void *user;
+} nd_opts;
+
+/* Defaults: ND_SND, max_iters -1, no frontier, exact, no callback. */
+void nd_opts_init(nd_opts *opts);
+
+typedef struct {
+  int32_t sweeps;      /* sweeps run, the last being the one that observed
+                          no change when converged */
+  int32_t converged;   /* 1 when the last sweep changed nothing */
+  int64_t n_rcliques;  /* |R| */
+  int64_t n_incidence; /* P = sum over R of d_s(R) */
+  int64_t updates;     /* h-index evaluations summed over sweeps */
+  double ms_prep;      /* device time of prepare work done by this call */
+  double ms_iterate;   /* device time of the sweeps */
+} nd_result;
+
+/* ------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the library may hold for this context (0 = no cap beyond the
+ * device).  On success *out owns the context. */
+nd_status nd_ctx_create(int device, size_t hbm_budget_bytes, nd_ctx **out);
+/* Destroy a context; its graphs and servers must be destroyed first. */
+void nd_ctx_destroy(nd_ctx *ctx);
+/* Device bytes currently held for graphs of this context (incl. cache). */
+size_t nd_ctx_bytes_in_use(const nd_ctx *ctx);
+
+/* --------------------------------------------------------------- graph */
+
+/* Graph from m raw undirected pairs (src[i], dst[i]) on vertices 0..n-1
+ * (Section 2: the graph is simple and undirected).  Self-loops are dropped
+ * and repeated pairs merged, on the device.  ND_ERR_INVALID if n < 0, m < 0
+ * or an endpoint is outside [0,n). */
+nd_status nd_graph_from_edges(nd_ctx *ctx, int32_t n, int64_t m,
+                              const int32_t *src, const int32_t *dst,
+                              int on_device, void *stream, nd_graph **out);
+
+/* Graph from a canonical CSR: row_off[n+1] (row_off[0] = 0, non-decreasing,
+ * row_off[n] = nnz) and col[nnz], each list strictly ascending, no self-loop,
+ * symmetric (v in N(u) iff u in N(v)).  Checked on the device;
+ * ND_ERR_INVALID if any condition fails. */
+nd_status nd_graph_from_csr(nd_ctx *ctx, int32_t n, int64_t nnz,
+                            const int64_t *row_off, const int32_t *col,
+                            int on_device, void *stream, nd_graph **out);
+
+void nd_graph_destroy(nd_graph *g);
+
+/* Vertex count and stored adjacency entries (2|E|) of the simple graph. */
+nd_status nd_graph_dims(const nd_graph *g, int32_t *n, int64_t *nnz);
+
+/* Copy out the canonical CSR: row_off[n+1], col[nnz]. */
+nd_status nd_graph_csr(nd_graph *g, int64_t *row_off, int32_t *col,
+                       int on_device, void *stream);
+
+/* Build the r-clique list, the s-clique incidence lists and d_s for `kind`
+ * (idempotent).  For each r-clique R the incidence list holds, for every
+ * s-clique S containing R, the ids of the C(s,r)-1 other r-cliques of S
+ * (Defn. of U, step 1); the paper finds these on the fly (Section 5), this
+ * library stores them once.  Called implicitly by nd_decompose. */
+nd_status nd_prepare(nd_graph *g, nd_kind kind, void *stream);
+
+/* Sizes for `kind` (prepares it if needed): |R|, P = sum_R d_s(R), and the
+ * device bytes the graph holds after preparing it. */
+nd_status nd_sizes(nd_graph *g, nd_kind kind, int64_t *n_rcliques,
+                   int64_t *n_incidence, size_t *dev_bytes);
+
+/* Copy out the r-clique list: verts[i*r + j] = j-th smallest vertex of
+ * r-clique i (r = 1, 2, 3 for the three kinds), lexicographic order. */
+nd_status nd_rcliques(nd_graph *g, nd_kind kind, int32_t *verts, int on_device,
+                      void *stream);
+
+/* Copy out the incidence lists: off[|R|+1] (in s-cliques, int64) and
+ * ids[k * P] with k = C(s,r)-1, the k ids of each s-clique consecutive.
+ * Within a list the s-cliques are ordered by their vertex outside R; the
+ * exact order is an implementation detail (compare as sets). */
+nd_status nd_incidence(nd_graph *g, nd_kind kind, int64_t *off, int32_t *ids,
+                       int on_device, void *stream);
+
+/* S-degrees d_s = tau_0 (Alg. 2, initialisation). */
+nd_status nd_sdegree(nd_graph *g, nd_kind kind, int32_t *ds, int on_device,
+                     void *stream);
+
+/* --------------------------------------------------------- decompose */
+
+/* Run SND or AND from tau_0 = d_s until a sweep changes nothing (or a stop
+ * condition in opts) and write kappa[|R|] (int32).  opts may be NULL
+ * (defaults).  res may be NULL.  On ND_ERR_NOT_CONVERGED kappa holds the
+ * last iterate, an upper bound on kappa_s (Theorem 1). */
+nd_status nd_decompose(nd_graph *g, nd_kind kind, const nd_opts *opts,
+                       int32_t *kappa, int on_device, void *stream,
+                       nd_result *res);
+
+/* Apply the update operator once: tau_out = U tau_in (Section 3, Defn. of U),
+ * for an arbitrary tau_in[|R|] with 0 <= tau_in <= d_s (values above d_s are
+ * rejected).  Both arrays device or both host per on_device. */
+nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
+                    int32_t *tau_out, int on_device, void *stream);
+
+/* Decompose `count` graphs together: their r-cliques form one combined work
+ * list swept by each launch; a graph stops being swept once one of its sweeps
+ * changes nothing.  kappas[i] receives graph i's result (device pointers if
+ * on_device), res[i] its statistics (res may be NULL).  Results equal those
+ * of nd_decompose on each graph alone. */
+nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
+                             nd_graph *const *graphs, nd_kind kind,
+                             const nd_opts *opts, int32_t *const *kappas,
+                             int on_device, void *stream, nd_result *res);
+
+/* ------------------------------------------------------------ serving */
+
+/* A server owns a worker thread and its own stream.  Requests are graphs
+ * submitted for decomposition; a request is admitted when a slot is free and
+ * its device memory fits the context budget; admitted requests are swept
+ * together (continuous batching), each retiring when it converges, which
+ * frees its slot and memory for waiting requests. */
+nd_status nd_server_create(nd_ctx *ctx, int32_t max_slots, int32_t max_queue,
+                           nd_server **out);
+
+/* Submit: the server takes ownership of g (destroyed when the request ends)
+ * and writes the result to host buffer kappa[|R|] (caller keeps it alive
+ * until nd_server_wait returns for this ticket).  ND_ERR_BUSY when
+ * max_queue requests are waiting. */
+nd_status nd_server_submit(nd_server *srv, nd_graph *g, nd_kind kind,
+                           const nd_opts *opts, int32_t *kappa,
+                           uint64_t *ticket);
+
+/* Wait up to timeout_us (< 0: forever) for a request; returns its final
+ * status (ND_ERR_TIMEOUT if still running).  res receives statistics and
+ * latency_ms (submission to completion) when non-NULL. */
+nd_status nd_server_wait(nd_server *srv, uint64_t ticket, int64_t timeout_us,
+                         nd_result *res, double *latency_ms);
+
+/* Cancel a waiting or running request; its wait returns ND_ERR_CANCELLED. */
+nd_status nd_server_cancel(nd_server *srv, uint64_t ticket);
+
+/* Stop the worker, cancel what is left, free everything. */
+void nd_server_destroy(nd_server *srv);
+
+/* --------------------------------------------------------------- errors */
+
+const char *nd_status_str(nd_status s);
+const char *nd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ND_H */

@@ -190,10 +190,27 @@ static void enum_rec(const og *g, int r, int32_t *tup, int depth,
   for (int64_t i = 0; i < nc; i++) {
     int32_t x = cand[i];
     tup[depth] = x;
-    /* candidates for the next position: later candidates adjacent to x */
+    /* candidates for the next position: later candidates adjacent to x,
+     * i.e. cand[i+1..nc) & N(x), ascending.  Scan the shorter list and
+     * binary-search the other. */
     int64_t nn = 0;
-    for (int64_t j = i + 1; j < nc; j++)
-      if (adjacent(g, x, cand[j])) next[nn++] = cand[j];
+    const int64_t xb = g->row_off[x], xe = g->row_off[x + 1];
+    if (xe - xb < nc - i - 1) {
+      for (int64_t p = xb; p < xe; p++) {
+        int32_t y = g->col[p];
+        if (y <= x) continue;
+        int64_t lo = i + 1, hi = nc;
+        while (lo < hi) {
+          int64_t mid = lo + (hi - lo) / 2;
+          if (cand[mid] < y) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo < nc && cand[lo] == y) next[nn++] = y;
+      }
+    } else {
+      for (int64_t j = i + 1; j < nc; j++)
+        if (adjacent(g, x, cand[j])) next[nn++] = cand[j];
+    }
     enum_rec(g, r, tup, depth + 1, next, nn, out);
   }
   free(next);
@@ -332,11 +349,18 @@ static int64_t scliques_of(scl_ctx *c, int64_t Rid) {
   c->R = g->rv[c->r] + Rid * c->r;
   c->count = 0;
   c->cn.len = 0;
-  int32_t v0 = c->R[0];
+  /* scan the (ascending) neighbour list of R's lowest-degree vertex */
+  int lo = 0;
+  for (int j = 1; j < c->r; j++)
+    if (g->row_off[c->R[j] + 1] - g->row_off[c->R[j]] <
+        g->row_off[c->R[lo] + 1] - g->row_off[c->R[lo]])
+      lo = j;
+  int32_t v0 = c->R[lo];
   for (int64_t p = g->row_off[v0]; p < g->row_off[v0 + 1]; p++) {
     int32_t x = g->col[p];
     int ok = 1;
-    for (int j = 1; j < c->r && ok; j++) ok = adjacent(g, c->R[j], x);
+    for (int j = 0; j < c->r && ok; j++)
+      if (j != lo) ok = adjacent(g, c->R[j], x);
     if (ok) il_push(&c->cn, x);
   }
   extend_s(c, 0, 0);

@@ -1,0 +1,615 @@
+// api.hip -- the C ABI declared in include/nd.h: contexts, the caching
+// allocator, graph construction and preparation, nd_update and the status
+// plumbing.  Decomposition drivers are in driver.hip, batching in batch.hip,
+// serving in server.hip.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "api_util.h"
+#include "internal.h"
+
+namespace nd {
+
+// ------------------------------------------------------------ errors
+
+static thread_local char g_last_error[512];
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+  va_end(ap);
+}
+
+// ------------------------------------------------------------ streams
+
+static thread_local hipStream_t g_stream = nullptr;
+
+hipStream_t current_stream() { return g_stream; }
+StreamScope::StreamScope(hipStream_t s) : prev(g_stream) { g_stream = s; }
+StreamScope::~StreamScope() { g_stream = prev; }
+
+// ---------------------------------------------------------- allocator
+
+Allocator::~Allocator() {
+  std::lock_guard<std::mutex> lk(mu_);
+  trim_locked();
+}
+
+void Allocator::trim_locked() {
+  for (auto &kv : cache_) {
+    (void)hipStreamSynchronize(kv.second.s);
+    (void)hipFree(kv.second.p);
+  }
+  cache_.clear();
+  cache_total_ = 0;
+}
+
+void Allocator::trim() {
+  std::lock_guard<std::mutex> lk(mu_);
+  trim_locked();
+}
+
+static size_t round_bytes(size_t b) {
+  const size_t q = 256;
+  b = b < q ? q : b;
+  return (b + q - 1) / q * q;
+}
+
+void *Allocator::alloc(size_t bytes) {
+  bytes = round_bytes(bytes);
+  const hipStream_t s = current_stream();
+  std::lock_guard<std::mutex> lk(mu_);
+  // Best fit among cached blocks no more than twice the request: same stream
+  // first, then any stream after synchronising it.
+  for (int pass = 0; pass < 2; pass++) {
+    auto it = cache_.lower_bound(bytes);
+    for (; it != cache_.end() && it->first <= 2 * bytes; ++it) {
+      if (pass == 0 && it->second.s != s) continue;
+      if (pass == 1 && it->second.s != s) {
+        ND_HIP(hipStreamSynchronize(it->second.s));
+      }
+      void *p = it->second.p;
+      const size_t sz = it->first;
+      cache_.erase(it);
+      cache_total_ -= sz;
+      live_[p] = sz;
+      live_total_ += sz;
+      return p;
+    }
+  }
+  if (budget_ && live_total_ + cache_total_ + bytes > budget_) trim_locked();
+  ND_REQUIRE(!budget_ || live_total_ + bytes <= budget_, ND_ERR_OOM,
+             "device-memory budget exceeded: %zu live + %zu requested > %zu",
+             live_total_, bytes, budget_);
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    trim_locked();
+    e = hipMalloc(&p, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    throw Err(ND_ERR_OOM);
+  }
+  live_[p] = bytes;
+  live_total_ += bytes;
+  return p;
+}
+
+void Allocator::release(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  const size_t sz = it->second;
+  live_.erase(it);
+  live_total_ -= sz;
+  cache_.emplace(sz, Cached{p, current_stream()});
+  cache_total_ += sz;
+}
+
+size_t Allocator::live_bytes() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  return live_total_;
+}
+
+size_t Allocator::cached_bytes() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  return cache_total_;
+}
+
+size_t KindState::bytes() const {
+  size_t b = 0;
+  if (own_off.p) b += own_off.bytes();
+  if (own_ids.p) b += own_ids.bytes();
+  if (ds.p) b += ds.bytes();
+  if (rverts.p) b += rverts.bytes();
+  if (bin_items.p) b += bin_items.bytes();
+  return b;
+}
+
+// ------------------------------------------------------- preparation
+
+namespace {
+
+__global__ void k_degree_bins(const int64_t *__restrict__ off, int64_t nr,
+                              int32_t *__restrict__ ds,
+                              uint8_t *__restrict__ bin,
+                              int32_t *__restrict__ maxd,
+                              int32_t *__restrict__ err) {
+  int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (R >= nr) return;
+  const int64_t d = off[R + 1] - off[R];
+  if (d > 0x7fffffff) {
+    atomicOr(err, 1);
+    return;
+  }
+  ds[R] = (int32_t)d;
+  atomicMax(maxd, (int32_t)d);
+  uint8_t b;
+  if (d == 0) b = kBinZero;
+  else if (d <= 4) b = kBinG1;
+  else if (d <= 16) b = kBinG4;
+  else if (d <= 64) b = kBinG16;
+  else if (d <= 256) b = kBinG64;
+  else if (d <= 2047) b = kBinWave;
+  else b = kBinBlock;
+  bin[R] = b;
+}
+
+__global__ void k_iota(int32_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+__global__ void k_tri_verts(const int32_t *__restrict__ ev,
+                            const int32_t *__restrict__ tri_e,
+                            const int32_t *__restrict__ tri_w, int64_t nt,
+                            int32_t *__restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int32_t e = tri_e[t];
+  out[3 * t] = ev[2 * (int64_t)e];
+  out[3 * t + 1] = ev[2 * (int64_t)e + 1];
+  out[3 * t + 2] = tri_w[t];
+}
+
+// Every listed id must name another r-clique: a cheap guard that turns a
+// builder fault into an error instead of an out-of-range gather.
+__global__ void k_check_incidence(const int64_t *__restrict__ off,
+                                  const int32_t *__restrict__ ids, int k,
+                                  int64_t nr, int32_t *__restrict__ err) {
+  int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (R >= nr) return;
+  const int64_t b = off[R] * k, e = off[R + 1] * k;
+  for (int64_t j = b; j < e; j++) {
+    const int32_t x = ids[j];
+    if (x < 0 || x >= nr || x == R) {
+      atomicOr(err, 1);
+      return;
+    }
+  }
+}
+
+__global__ void k_check_tau(const int32_t *__restrict__ tau,
+                            const int32_t *__restrict__ ds, int64_t n,
+                            int32_t *__restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (tau[i] < 0 || tau[i] > ds[i])) atomicOr(err, 1);
+}
+
+}  // namespace
+
+void build_schedule(nd_graph *g, KindState &ks, hipStream_t s) {
+  Allocator &al = g->ctx->alloc;
+  const int64_t nr = ks.nr;
+  ks.ds.reset(al, nr);
+  DArr<uint8_t> bin(al, nr);
+  DArr<int32_t> dev(al, 2);  // [max d_s, error flags]
+  fill_i32(dev.p, 0, 2, s);
+  if (nr > 0) {
+    k_degree_bins<<<grid_for(nr, 256), 256, 0, s>>>(ks.inc_off, nr, ks.ds.p,
+                                                     bin.p, dev.p, dev.p + 1);
+    ND_LAUNCHED();
+  }
+  int32_t h[2];
+  ND_HIP(hipMemcpyAsync(h, dev.p, sizeof h, hipMemcpyDeviceToHost, s));
+  ND_HIP(hipStreamSynchronize(s));
+  ND_REQUIRE(h[1] == 0, ND_ERR_INVALID, "an S-degree exceeds int32");
+  ks.max_ds = h[0];
+  ks.bin_items.reset(al, nr);
+  partition_by_bin(bin.p, nr, kNumBins, ks.bin_items.p, ks.bin_off, s, al);
+}
+
+static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
+  KindState &ks = g->ks[kind];
+  if (ks.ready) return;
+  hipEvent_t e0, e1;
+  ND_HIP(hipEventCreate(&e0));
+  ND_HIP(hipEventCreate(&e1));
+  ND_HIP(hipEventRecord(e0, s));
+  switch (kind) {
+    case ND_KCORE:
+      // (1,2): the s-cliques containing vertex u are its edges and the other
+      // r-clique of each is the neighbour, so the CSR is the incidence list.
+      ks.r = 1; ks.s = 2; ks.k = 1;
+      ks.nr = g->n;
+      ks.P = g->nnz;
+      ks.inc_off = g->row_off.p;
+      ks.inc_ids = g->col.p;
+      break;
+    case ND_KTRUSS:
+      ks.r = 2; ks.s = 3; ks.k = 2;
+      build_incidence_truss(g, ks, s);
+      break;
+    case ND_NUCLEUS34:
+      ks.r = 3; ks.s = 4; ks.k = 3;
+      build_incidence_n34(g, ks, s);
+      break;
+    default:
+      ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "unknown kind %d", (int)kind);
+  }
+  build_schedule(g, ks, s);
+  ND_REQUIRE((int64_t)ks.max_ds < ((int64_t)1 << 28), ND_ERR_UNSUPPORTED,
+             "an S-degree of %d exceeds the 2^28 supported per r-clique",
+             ks.max_ds);
+  {
+    DArr<int32_t> err(g->ctx->alloc, 1);
+    fill_i32(err.p, 0, 1, s);
+    if (ks.nr > 0) {
+      k_check_incidence<<<grid_for(ks.nr, 256), 256, 0, s>>>(
+          ks.inc_off, ks.inc_ids, ks.k, ks.nr, err.p);
+      ND_LAUNCHED();
+    }
+    int32_t h = 0;
+    ND_HIP(hipMemcpyAsync(&h, err.p, sizeof h, hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+    ND_REQUIRE(h == 0, ND_ERR_DEVICE,
+               "internal error: incidence list holds an invalid r-clique id");
+  }
+  ND_HIP(hipEventRecord(e1, s));
+  ND_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  ND_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ks.ms_prep = ms;
+  ks.ready = true;
+}
+
+void prepare(nd_graph *g, nd_kind kind, hipStream_t s) {
+  ND_REQUIRE(kind == ND_KCORE || kind == ND_KTRUSS || kind == ND_NUCLEUS34,
+             ND_ERR_UNSUPPORTED, "unknown kind %d", (int)kind);
+  prepare_kind(g, kind, s);
+}
+
+void check_tau_range(nd_graph *g, const KindState &ks, const int32_t *tau,
+                     hipStream_t s) {
+  DArr<int32_t> err(g->ctx->alloc, 1);
+  fill_i32(err.p, 0, 1, s);
+  if (ks.nr > 0) {
+    k_check_tau<<<grid_for(ks.nr, 256), 256, 0, s>>>(tau, ks.ds.p, ks.nr, err.p);
+    ND_LAUNCHED();
+  }
+  int32_t h = 0;
+  ND_HIP(hipMemcpyAsync(&h, err.p, sizeof h, hipMemcpyDeviceToHost, s));
+  ND_HIP(hipStreamSynchronize(s));
+  ND_REQUIRE(h == 0, ND_ERR_INVALID, "tau must satisfy 0 <= tau <= d_s");
+}
+
+}  // namespace nd
+
+size_t nd_graph::bytes() const {
+  size_t b = 0;
+  auto add = [&](size_t x, const void *p) { if (p) b += x; };
+  add(row_off.bytes(), row_off.p);
+  add(col.bytes(), col.p);
+  add(rowid.bytes(), rowid.p);
+  add(nlow.bytes(), nlow.p);
+  add(eoff.bytes(), eoff.p);
+  add(eid.bytes(), eid.p);
+  add(toff.bytes(), toff.p);
+  add(tri_w.bytes(), tri_w.p);
+  add(tri_e.bytes(), tri_e.p);
+  for (const auto &k : ks) b += k.bytes();
+  return b;
+}
+
+using namespace nd;
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+const char *nd_status_str(nd_status s) {
+  switch (s) {
+    case ND_OK: return "ok";
+    case ND_ERR_INVALID: return "invalid argument";
+    case ND_ERR_OOM: return "out of device memory";
+    case ND_ERR_DEVICE: return "device error";
+    case ND_ERR_UNSUPPORTED: return "unsupported";
+    case ND_ERR_NOT_CONVERGED: return "not converged";
+    case ND_ERR_BUSY: return "busy";
+    case ND_ERR_CANCELLED: return "cancelled";
+    case ND_ERR_TIMEOUT: return "timeout";
+  }
+  return "unknown status";
+}
+
+const char *nd_last_error(void) { return g_last_error; }
+
+void nd_opts_init(nd_opts *o) {
+  if (!o) return;
+  memset(o, 0, sizeof *o);
+  o->mode = ND_SND;
+  o->max_iters = -1;
+}
+
+nd_status nd_ctx_create(int device, size_t hbm_budget_bytes, nd_ctx **out) {
+  return guarded([&] {
+    ND_REQUIRE(out, ND_ERR_INVALID, "out is NULL");
+    int count = 0;
+    ND_HIP(hipGetDeviceCount(&count));
+    ND_REQUIRE(device >= 0 && device < count, ND_ERR_INVALID,
+               "device %d not present (%d devices)", device, count);
+    ND_HIP(hipSetDevice(device));
+    nd_ctx *c = new nd_ctx(device, hbm_budget_bytes);
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount,
+                              device) == hipSuccess && cu > 0)
+      c->num_cu = cu;
+    *out = c;
+  });
+}
+
+void nd_ctx_destroy(nd_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->release();
+}
+
+size_t nd_ctx_bytes_in_use(const nd_ctx *ctx) {
+  return ctx ? ctx->alloc.live_bytes() + ctx->alloc.cached_bytes() : 0;
+}
+
+nd_status nd_graph_from_edges(nd_ctx *ctx, int32_t n, int64_t m,
+                              const int32_t *src, const int32_t *dst,
+                              int on_device, void *stream, nd_graph **out) {
+  nd_graph *g = nullptr;
+  nd_status st = guarded([&] {
+    ND_REQUIRE(ctx && out, ND_ERR_INVALID, "ctx/out is NULL");
+    ND_REQUIRE(n >= 0 && m >= 0, ND_ERR_INVALID, "negative size");
+    ND_REQUIRE(m == 0 || (src && dst), ND_ERR_INVALID, "src/dst is NULL");
+    ND_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    g = new nd_graph();
+    g->ctx = ctx;
+    ctx->retain();
+    g->n = n;
+    DArr<int32_t> hs, hd;
+    const int32_t *ds = src, *dd = dst;
+    if (!on_device && m > 0) {
+      hs.reset(ctx->alloc, m);
+      hd.reset(ctx->alloc, m);
+      ND_HIP(hipMemcpyAsync(hs.p, src, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+      ND_HIP(hipMemcpyAsync(hd.p, dst, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+      ds = hs.p;
+      dd = hd.p;
+    }
+    build_from_edges(g, m, ds, dd, s);
+    ND_HIP(hipStreamSynchronize(s));
+    *out = g;
+  });
+  if (st != ND_OK && g) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    nd_graph_destroy(g);
+  }
+  return st;
+}
+
+nd_status nd_graph_from_csr(nd_ctx *ctx, int32_t n, int64_t nnz,
+                            const int64_t *row_off, const int32_t *col,
+                            int on_device, void *stream, nd_graph **out) {
+  nd_graph *g = nullptr;
+  nd_status st = guarded([&] {
+    ND_REQUIRE(ctx && out && row_off, ND_ERR_INVALID, "NULL argument");
+    ND_REQUIRE(n >= 0 && nnz >= 0, ND_ERR_INVALID, "negative size");
+    ND_REQUIRE(nnz == 0 || col, ND_ERR_INVALID, "col is NULL");
+    ND_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    g = new nd_graph();
+    g->ctx = ctx;
+    ctx->retain();
+    g->n = n;
+    g->nnz = nnz;
+    g->row_off.reset(ctx->alloc, (int64_t)n + 1);
+    g->col.reset(ctx->alloc, nnz);
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    ND_HIP(hipMemcpyAsync(g->row_off.p, row_off, sizeof(int64_t) * ((size_t)n + 1), kind, s));
+    if (nnz > 0)
+      ND_HIP(hipMemcpyAsync(g->col.p, col, sizeof(int32_t) * nnz, kind, s));
+    validate_csr(g, s);
+    ND_HIP(hipStreamSynchronize(s));
+    *out = g;
+  });
+  if (st != ND_OK && g) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    nd_graph_destroy(g);
+  }
+  return st;
+}
+
+void nd_graph_destroy(nd_graph *g) {
+  if (!g) return;
+  nd_ctx *ctx = g->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  {
+    StreamScope scope(nullptr);
+    delete g;
+  }
+  ctx->release();
+}
+
+nd_status nd_graph_dims(const nd_graph *g, int32_t *n, int64_t *nnz) {
+  return guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+  });
+}
+
+nd_status nd_graph_csr(nd_graph *g, int64_t *row_off, int32_t *col,
+                       int on_device, void *stream) {
+  return guarded([&] {
+    ND_REQUIRE(g && row_off && (col || g->nnz == 0), ND_ERR_INVALID,
+               "NULL argument");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    ND_HIP(hipMemcpyAsync(row_off, g->row_off.p, sizeof(int64_t) * ((size_t)g->n + 1), kind, s));
+    if (g->nnz > 0)
+      ND_HIP(hipMemcpyAsync(col, g->col.p, sizeof(int32_t) * g->nnz, kind, s));
+    ND_HIP(hipStreamSynchronize(s));
+  });
+}
+
+nd_status nd_prepare(nd_graph *g, nd_kind kind, void *stream) {
+  return guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    StreamScope scope((hipStream_t)stream);
+    prepare(g, kind, (hipStream_t)stream);
+  });
+}
+
+nd_status nd_sizes(nd_graph *g, nd_kind kind, int64_t *n_rcliques,
+                   int64_t *n_incidence, size_t *dev_bytes) {
+  return guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    StreamScope scope(nullptr);
+    prepare(g, kind, nullptr);
+    if (n_rcliques) *n_rcliques = g->ks[kind].nr;
+    if (n_incidence) *n_incidence = g->ks[kind].P;
+    if (dev_bytes) *dev_bytes = g->bytes();
+  });
+}
+
+nd_status nd_rcliques(nd_graph *g, nd_kind kind, int32_t *verts, int on_device,
+                      void *stream) {
+  return guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    prepare(g, kind, s);
+    const KindState &ks = g->ks[kind];
+    const int r = ks.r;
+    const int64_t cnt = ks.nr * r;
+    ND_REQUIRE(verts || cnt == 0, ND_ERR_INVALID, "verts is NULL");
+    if (cnt == 0) return;
+    DArr<int32_t> tmp(g->ctx->alloc, cnt);
+    const int32_t *src = tmp.p;
+    if (kind == ND_KCORE) {
+      k_iota<<<grid_for(cnt, 256), 256, 0, s>>>(tmp.p, cnt);
+      ND_LAUNCHED();
+    } else if (kind == ND_KTRUSS) {
+      src = ks.rverts.p;
+    } else {
+      k_tri_verts<<<grid_for(ks.nr, 256), 256, 0, s>>>(
+          g->ks[ND_KTRUSS].rverts.p, g->tri_e.p, g->tri_w.p, ks.nr, tmp.p);
+      ND_LAUNCHED();
+    }
+    ND_HIP(hipMemcpyAsync(verts, src, sizeof(int32_t) * cnt,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+  });
+}
+
+nd_status nd_incidence(nd_graph *g, nd_kind kind, int64_t *off, int32_t *ids,
+                       int on_device, void *stream) {
+  return guarded([&] {
+    ND_REQUIRE(g && off, ND_ERR_INVALID, "NULL argument");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    prepare(g, kind, s);
+    const KindState &ks = g->ks[kind];
+    const hipMemcpyKind mk = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    ND_HIP(hipMemcpyAsync(off, ks.inc_off, sizeof(int64_t) * (ks.nr + 1), mk, s));
+    const int64_t nid = ks.P * ks.k;
+    ND_REQUIRE(ids || nid == 0, ND_ERR_INVALID, "ids is NULL");
+    if (nid > 0) ND_HIP(hipMemcpyAsync(ids, ks.inc_ids, sizeof(int32_t) * nid, mk, s));
+    ND_HIP(hipStreamSynchronize(s));
+  });
+}
+
+nd_status nd_sdegree(nd_graph *g, nd_kind kind, int32_t *ds, int on_device,
+                     void *stream) {
+  return guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    prepare(g, kind, s);
+    const KindState &ks = g->ks[kind];
+    ND_REQUIRE(ds || ks.nr == 0, ND_ERR_INVALID, "ds is NULL");
+    if (ks.nr > 0)
+      ND_HIP(hipMemcpyAsync(ds, ks.ds.p, sizeof(int32_t) * ks.nr,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+  });
+}
+
+nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
+                    int32_t *tau_out, int on_device, void *stream) {
+  return guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    StreamScope scope(s);
+    prepare(g, kind, s);
+    const KindState &ks = g->ks[kind];
+    if (ks.nr == 0) return;
+    ND_REQUIRE(tau_in && tau_out, ND_ERR_INVALID, "tau is NULL");
+    Allocator &al = g->ctx->alloc;
+    DArr<int32_t> din, dout;
+    const int32_t *pin = tau_in;
+    int32_t *pout = tau_out;
+    if (!on_device) {
+      din.reset(al, ks.nr);
+      dout.reset(al, ks.nr);
+      ND_HIP(hipMemcpyAsync(din.p, tau_in, sizeof(int32_t) * ks.nr, hipMemcpyHostToDevice, s));
+      pin = din.p;
+      pout = dout.p;
+    }
+    check_tau_range(g, ks, pin, s);
+    DArr<SweepStats> st(al, 1);
+    ND_HIP(hipMemsetAsync(st.p, 0, sizeof(SweepStats), s));
+    SweepArgs a{};
+    a.inc_off = ks.inc_off;
+    a.inc_ids = ks.inc_ids;
+    a.ds = ks.ds.p;
+    a.tau_in = pin;
+    a.tau_out = pout;
+    a.stats = st.p;
+    a.prev = nullptr;
+    a.cap_by_tau = 0;
+    launch_sweep(ks, a, false, s);
+    if (!on_device)
+      ND_HIP(hipMemcpyAsync(tau_out, pout, sizeof(int32_t) * ks.nr, hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+  });
+}
+
+}  // extern "C"

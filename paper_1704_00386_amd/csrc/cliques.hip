@@ -1,0 +1,359 @@
+// cliques.hip -- s-clique incidence lists (Section 3, Defn. of U, step 1).
+//
+// The paper finds the s-cliques containing an r-clique on the fly in every
+// iteration (Section 5).  Here they are listed once, by intersecting sorted
+// adjacency lists on the device, so that every sweep is a pure streaming
+// gather:
+//   k-truss (2,3): for edge (u,v) and every w in N(u) & N(v), the ids of the
+//                  edges (u,w) and (v,w);
+//   (3,4):         first the triangles (u,v,w), u<v<w, numbered
+//                  lexicographically; then for triangle (u,v,w) and every x
+//                  in N(u) & N(v) & N(w), the ids of the triangles {u,v,x},
+//                  {u,w,x} and {v,w,x}.
+// Both use two passes (count, exclusive scan, fill) so that the lists are
+// written in place with no atomics; each list is in ascending order of its
+// extension vertex, so the output is deterministic.
+//
+// Work per item is proportional to the shortest adjacency list involved:
+// each element of it is binary-searched in the others.  Items are binned by
+// that length and each bin gets a subgroup of G lanes per item (G = 1, 4, 16,
+// 64) that strides over the short list; matches are ordered with a ballot.
+#include "internal.h"
+
+namespace nd {
+
+namespace {
+
+enum IsectMode : int {
+  kCountTruss = 0,  // per edge: |N(u) & N(v)|
+  kFillTruss,       // per edge: (eid(u,w), eid(v,w)) for each common w
+  kCountTri,        // per edge: #{w > v common}
+  kFillTri,         // per edge: tri_w / tri_e for each common w > v
+};
+
+struct EdgeIsectArgs {
+  const int32_t *items;  // edge ids of this bin
+  int64_t nitems;
+  const int32_t *ev;     // edge endpoints (u, v), u < v
+  const int64_t *row_off;
+  const int32_t *col;
+  const int32_t *eid;
+  int32_t *count;        // count modes: per edge
+  const int64_t *off;    // fill modes: per-edge output offset
+  int32_t *out_a;        // fill: pair ids (truss) or tri_w (triangles)
+  int32_t *out_b;        // fill: tri_e (triangles)
+};
+
+template <int G>
+__device__ __forceinline__ uint64_t subgroup_mask() {
+  if constexpr (G == 64) {
+    return ~0ull;
+  } else {
+    const int sub = lane_id() / G;
+    return (((uint64_t)1 << G) - 1) << (sub * G);
+  }
+}
+
+template <int G, int MODE>
+__global__ __launch_bounds__(256) void k_edge_isect(EdgeIsectArgs a) {
+  const int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int sl = lane_id() % G;
+  if (gsub >= a.nitems) return;  // uniform within the subgroup
+  const int32_t e = a.items[gsub];
+  const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
+  const int64_t bu = a.row_off[u], eu = a.row_off[u + 1];
+  const int64_t bv = a.row_off[v], ev = a.row_off[v + 1];
+  const bool short_is_u = (eu - bu) <= (ev - bv);
+  const int64_t sb = short_is_u ? bu : bv, se = short_is_u ? eu : ev;
+  const int64_t lb = short_is_u ? bv : bu, le = short_is_u ? ev : eu;
+  int64_t start = sb;
+  if (MODE == kCountTri || MODE == kFillTri)
+    start = lower_bound<int32_t>(a.col, sb, se, v + 1);  // only w > v
+  const uint64_t smask = subgroup_mask<G>();
+  int64_t written = 0;
+  const int64_t base = (MODE == kFillTruss || MODE == kFillTri) ? a.off[e] : 0;
+  for (int64_t j0 = start; j0 < se; j0 += G) {
+    const int64_t j = j0 + sl;
+    bool found = false;
+    int64_t q = 0;
+    int32_t w = 0;
+    if (j < se) {
+      w = a.col[j];
+      q = lower_bound<int32_t>(a.col, lb, le, w);
+      found = q < le && a.col[q] == w;
+    }
+    const uint64_t m = ballot(found) & smask;
+    if (MODE == kFillTruss && found) {
+      const int64_t k = base + written + lanes_below(m);
+      const int32_t id_short = a.eid[j], id_long = a.eid[q];
+      a.out_a[2 * k] = short_is_u ? id_short : id_long;      // eid(u, w)
+      a.out_a[2 * k + 1] = short_is_u ? id_long : id_short;  // eid(v, w)
+    }
+    if (MODE == kFillTri && found) {
+      const int64_t k = base + written + lanes_below(m);
+      a.out_a[k] = w;
+      a.out_b[k] = e;
+    }
+    written += __popcll(m);
+  }
+  if ((MODE == kCountTruss || MODE == kCountTri) && sl == 0)
+    a.count[e] = (int32_t)written;
+}
+
+// ------------------------------------------------------------- (3,4)
+
+struct TriIsectArgs {
+  const int32_t *items;  // triangle ids of this bin
+  int64_t nitems;
+  const int32_t *ev;
+  const int64_t *row_off;
+  const int32_t *col;
+  const int32_t *eid;
+  const int64_t *toff;   // ne+1
+  const int32_t *tri_w;
+  const int32_t *tri_e;
+  int32_t *count;        // count pass
+  const int64_t *off;    // fill pass
+  int32_t *out;          // fill pass: 3 ids per 4-clique
+};
+
+__device__ __forceinline__ bool in_list(const int32_t *__restrict__ col,
+                                        int64_t b, int64_t e, int32_t x) {
+  int64_t q = lower_bound<int32_t>(col, b, e, x);
+  return q < e && col[q] == x;
+}
+
+// Id of the triangle with vertices {a, b, c} (any order).
+__device__ __forceinline__ int32_t tri_id(const TriIsectArgs &t, int32_t a,
+                                          int32_t b, int32_t c) {
+  // sort three values
+  int32_t x = min(a, b), y = max(a, b);
+  int32_t z = max(y, c);
+  y = min(y, c);
+  int32_t w = min(x, y);
+  y = max(x, y);
+  x = w;
+  // edge (x, y)
+  const int64_t q = lower_bound<int32_t>(t.col, t.row_off[x], t.row_off[x + 1], y);
+  const int32_t e = t.eid[q];
+  return (int32_t)lower_bound<int32_t>(t.tri_w, t.toff[e], t.toff[e + 1], z);
+}
+
+template <int G, bool FILL>
+__global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
+  const int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int sl = lane_id() % G;
+  if (gsub >= a.nitems) return;
+  const int32_t t = a.items[gsub];
+  const int32_t e = a.tri_e[t];
+  const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
+  const int32_t w = a.tri_w[t];
+  int64_t b[3] = {a.row_off[u], a.row_off[v], a.row_off[w]};
+  int64_t en[3] = {a.row_off[u + 1], a.row_off[v + 1], a.row_off[w + 1]};
+  // iterate the shortest list, search the other two
+  int s = 0;
+  if (en[1] - b[1] < en[s] - b[s]) s = 1;
+  if (en[2] - b[2] < en[s] - b[s]) s = 2;
+  const int o1 = s == 0 ? 1 : 0, o2 = s == 2 ? 1 : 2;
+  const uint64_t smask = subgroup_mask<G>();
+  const int64_t base = FILL ? a.off[t] : 0;
+  int64_t written = 0;
+  for (int64_t j0 = b[s]; j0 < en[s]; j0 += G) {
+    const int64_t j = j0 + sl;
+    bool found = false;
+    int32_t x = 0;
+    if (j < en[s]) {
+      x = a.col[j];
+      found = in_list(a.col, b[o1], en[o1], x) && in_list(a.col, b[o2], en[o2], x);
+    }
+    const uint64_t m = ballot(found) & smask;
+    if (FILL && found) {
+      const int64_t k = base + written + lanes_below(m);
+      a.out[3 * k] = tri_id(a, u, v, x);
+      a.out[3 * k + 1] = tri_id(a, u, w, x);
+      a.out[3 * k + 2] = tri_id(a, v, w, x);
+    }
+    written += __popcll(m);
+  }
+  if (!FILL && sl == 0) a.count[t] = (int32_t)written;
+}
+
+// ------------------------------------------------------------- binning
+
+constexpr int kIsectBins = 4;  // G = 1, 4, 16, 64
+
+__device__ __forceinline__ uint8_t isect_bin(int64_t len) {
+  return len <= 4 ? 0 : len <= 16 ? 1 : len <= 128 ? 2 : 3;
+}
+
+__global__ void k_edge_bins(const int32_t *__restrict__ ev,
+                            const int64_t *__restrict__ row_off, int64_t ne,
+                            uint8_t *__restrict__ bin) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int32_t u = ev[2 * e], v = ev[2 * e + 1];
+  int64_t du = row_off[u + 1] - row_off[u], dv = row_off[v + 1] - row_off[v];
+  bin[e] = isect_bin(min(du, dv));
+}
+
+__global__ void k_tri_bins(const int32_t *__restrict__ ev,
+                           const int32_t *__restrict__ tri_e,
+                           const int32_t *__restrict__ tri_w,
+                           const int64_t *__restrict__ row_off, int64_t nt,
+                           uint8_t *__restrict__ bin) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  int32_t e = tri_e[t];
+  int32_t u = ev[2 * (int64_t)e], v = ev[2 * (int64_t)e + 1], w = tri_w[t];
+  int64_t d = min(row_off[u + 1] - row_off[u], row_off[v + 1] - row_off[v]);
+  d = min(d, row_off[w + 1] - row_off[w]);
+  bin[t] = isect_bin(d);
+}
+
+template <int MODE>
+void run_edge_isect(EdgeIsectArgs a, const int32_t *items,
+                    const int64_t *bin_off, hipStream_t s) {
+  for (int b = 0; b < kIsectBins; b++) {
+    a.items = items + bin_off[b];
+    a.nitems = bin_off[b + 1] - bin_off[b];
+    if (a.nitems == 0) continue;
+    switch (b) {
+      case 0: k_edge_isect<1, MODE><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
+      case 1: k_edge_isect<4, MODE><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
+      case 2: k_edge_isect<16, MODE><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
+      default: k_edge_isect<64, MODE><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+  }
+}
+
+template <bool FILL>
+void run_tri_isect(TriIsectArgs a, const int32_t *items, const int64_t *bin_off,
+                   hipStream_t s) {
+  for (int b = 0; b < kIsectBins; b++) {
+    a.items = items + bin_off[b];
+    a.nitems = bin_off[b + 1] - bin_off[b];
+    if (a.nitems == 0) continue;
+    switch (b) {
+      case 0: k_tri_isect<1, FILL><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
+      case 1: k_tri_isect<4, FILL><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
+      case 2: k_tri_isect<16, FILL><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
+      default: k_tri_isect<64, FILL><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+  }
+}
+
+// Edges grouped by intersection bin (host offsets in bin_off).
+void edge_schedule(nd_graph *g, DArr<int32_t> &items, int64_t *bin_off,
+                   hipStream_t s) {
+  Allocator &al = g->ctx->alloc;
+  const int64_t ne = g->ne;
+  DArr<uint8_t> bin(al, ne);
+  items.reset(al, ne);
+  if (ne > 0) {
+    k_edge_bins<<<grid_for(ne, 256), 256, 0, s>>>(g->ks[ND_KTRUSS].rverts.p,
+                                                   g->row_off.p, ne, bin.p);
+    ND_LAUNCHED();
+  }
+  partition_by_bin(bin.p, ne, kIsectBins, items.p, bin_off, s, al);
+}
+
+EdgeIsectArgs edge_args(nd_graph *g) {
+  EdgeIsectArgs a{};
+  a.ev = g->ks[ND_KTRUSS].rverts.p;
+  a.row_off = g->row_off.p;
+  a.col = g->col.p;
+  a.eid = g->eid.p;
+  return a;
+}
+
+}  // namespace
+
+void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
+  build_edges(g, s);
+  Allocator &al = g->ctx->alloc;
+  const int64_t ne = g->ne;
+  DArr<int32_t> items;
+  int64_t bin_off[kIsectBins + 1];
+  edge_schedule(g, items, bin_off, s);
+  DArr<int32_t> cnt(al, ne);
+  EdgeIsectArgs a = edge_args(g);
+  a.count = cnt.p;
+  run_edge_isect<kCountTruss>(a, items.p, bin_off, s);
+  ks.own_off.reset(al, ne + 1);
+  exclusive_scan_i32(cnt.p, ks.own_off.p, ne, s, al);
+  ks.P = read_i64(ks.own_off.p + ne, s);
+  ks.own_ids.reset(al, 2 * ks.P);
+  a.off = ks.own_off.p;
+  a.out_a = ks.own_ids.p;
+  run_edge_isect<kFillTruss>(a, items.p, bin_off, s);
+  ks.nr = ne;
+  ks.inc_off = ks.own_off.p;
+  ks.inc_ids = ks.own_ids.p;
+}
+
+void build_triangles(nd_graph *g, hipStream_t s) {
+  if (g->tris_ready) return;
+  build_edges(g, s);
+  Allocator &al = g->ctx->alloc;
+  const int64_t ne = g->ne;
+  DArr<int32_t> items;
+  int64_t bin_off[kIsectBins + 1];
+  edge_schedule(g, items, bin_off, s);
+  DArr<int32_t> cnt(al, ne);
+  EdgeIsectArgs a = edge_args(g);
+  a.count = cnt.p;
+  run_edge_isect<kCountTri>(a, items.p, bin_off, s);
+  g->toff.reset(al, ne + 1);
+  exclusive_scan_i32(cnt.p, g->toff.p, ne, s, al);
+  g->nt = read_i64(g->toff.p + ne, s);
+  ND_REQUIRE(g->nt < ((int64_t)1 << 31), ND_ERR_INVALID,
+             "%lld triangles: triangle ids must fit int32", (long long)g->nt);
+  g->tri_w.reset(al, g->nt);
+  g->tri_e.reset(al, g->nt);
+  a.off = g->toff.p;
+  a.out_a = g->tri_w.p;
+  a.out_b = g->tri_e.p;
+  run_edge_isect<kFillTri>(a, items.p, bin_off, s);
+  g->tris_ready = true;
+}
+
+void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
+  build_triangles(g, s);
+  Allocator &al = g->ctx->alloc;
+  const int64_t nt = g->nt;
+  DArr<uint8_t> bin(al, nt);
+  DArr<int32_t> items(al, nt);
+  if (nt > 0) {
+    k_tri_bins<<<grid_for(nt, 256), 256, 0, s>>>(g->ks[ND_KTRUSS].rverts.p,
+                                                  g->tri_e.p, g->tri_w.p,
+                                                  g->row_off.p, nt, bin.p);
+    ND_LAUNCHED();
+  }
+  int64_t bin_off[kIsectBins + 1];
+  partition_by_bin(bin.p, nt, kIsectBins, items.p, bin_off, s, al);
+  DArr<int32_t> cnt(al, nt);
+  TriIsectArgs a{};
+  a.ev = g->ks[ND_KTRUSS].rverts.p;
+  a.row_off = g->row_off.p;
+  a.col = g->col.p;
+  a.eid = g->eid.p;
+  a.toff = g->toff.p;
+  a.tri_w = g->tri_w.p;
+  a.tri_e = g->tri_e.p;
+  a.count = cnt.p;
+  run_tri_isect<false>(a, items.p, bin_off, s);
+  ks.own_off.reset(al, nt + 1);
+  exclusive_scan_i32(cnt.p, ks.own_off.p, nt, s, al);
+  ks.P = read_i64(ks.own_off.p + nt, s);
+  ks.own_ids.reset(al, 3 * ks.P);
+  a.off = ks.own_off.p;
+  a.out = ks.own_ids.p;
+  run_tri_isect<true>(a, items.p, bin_off, s);
+  ks.nr = nt;
+  ks.inc_off = ks.own_off.p;
+  ks.inc_ids = ks.own_ids.p;
+}
+
+}  // namespace nd

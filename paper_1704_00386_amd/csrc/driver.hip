@@ -1,0 +1,202 @@
+// driver.hip -- the iteration driver of Alg. 2 (SND) and Alg. 3 (AND): start
+// from tau_0 = d_s, sweep until a sweep changes nothing (the flag F of the
+// algorithms), optionally stop early, and hand out per-sweep reports.
+//
+// Host round trips are amortised: sweeps are enqueued in chunks and each
+// sweep kernel first reads the previous sweep's changed-counter and returns
+// at once when it is zero, so sweeps queued past convergence cost only their
+// launch.  For SND the two buffers then hold identical values, so the result
+// is the same whichever was written last.
+#include <string.h>
+
+#include <vector>
+
+#include "api_util.h"
+#include "internal.h"
+
+namespace nd {
+
+namespace {
+
+constexpr int kStatsRing = 1024;  // device counters kept per decomposition
+constexpr int kMaxChunk = 16;     // sweeps enqueued per host round trip
+
+__global__ void k_zero_stats(SweepStats *ring, int64_t first, int count) {
+  int i = threadIdx.x;
+  if (i < count) {
+    SweepStats &z = ring[(first + i) % kStatsRing];
+    z.changed = 0;
+    z.evaluated = 0;
+    z.active_next = 0;
+    z.pad = 0;
+  }
+}
+
+struct Timer {
+  hipEvent_t a, b;
+  Timer() {
+    ND_HIP(hipEventCreate(&a));
+    ND_HIP(hipEventCreate(&b));
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  void start(hipStream_t s) { ND_HIP(hipEventRecord(a, s)); }
+  void stop(hipStream_t s) { ND_HIP(hipEventRecord(b, s)); }
+  double ms() {
+    ND_HIP(hipEventSynchronize(b));
+    float m = 0;
+    ND_HIP(hipEventElapsedTime(&m, a, b));
+    return m;
+  }
+};
+
+}  // namespace
+
+nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
+                    int32_t *kappa, int on_device, hipStream_t s,
+                    nd_result *res) {
+  nd_opts opts;
+  nd_opts_init(&opts);
+  if (opts_in) opts = *opts_in;
+  ND_REQUIRE(opts.mode == ND_SND || opts.mode == ND_AND, ND_ERR_INVALID,
+             "unknown mode %d", (int)opts.mode);
+  ND_REQUIRE(opts.stop_active_ratio >= 0 && opts.stop_active_ratio <= 1,
+             ND_ERR_INVALID, "stop_active_ratio must be in [0,1]");
+  ND_REQUIRE(!opts.use_frontier, ND_ERR_UNSUPPORTED,
+             "frontier sweeps are not available in this build");
+  const bool was_ready = g->ks[kind].ready;
+  prepare(g, kind, s);
+  const KindState &ks = g->ks[kind];
+  const int64_t nr = ks.nr;
+  nd_result r{};
+  r.n_rcliques = nr;
+  r.n_incidence = ks.P;
+  r.ms_prep = was_ready ? 0.0 : ks.ms_prep;
+  ND_REQUIRE(kappa || nr == 0, ND_ERR_INVALID, "kappa is NULL");
+  if (nr == 0) {
+    r.converged = 1;
+    if (res) *res = r;
+    return ND_OK;
+  }
+  Allocator &al = g->ctx->alloc;
+  const bool and_mode = opts.mode == ND_AND;
+  DArr<int32_t> tau0(al, nr), tau1;
+  ND_HIP(hipMemcpyAsync(tau0.p, ks.ds.p, sizeof(int32_t) * nr,
+                        hipMemcpyDeviceToDevice, s));
+  if (!and_mode) {
+    tau1.reset(al, nr);
+    ND_HIP(hipMemcpyAsync(tau1.p, ks.ds.p, sizeof(int32_t) * nr,
+                          hipMemcpyDeviceToDevice, s));
+  }
+  int32_t *buf[2] = {tau0.p, and_mode ? tau0.p : tau1.p};
+  DArr<SweepStats> ring(al, kStatsRing);
+  if (!g->ctx->host_stats)
+    ND_HIP(hipHostMalloc(&g->ctx->host_stats, sizeof(SweepStats) * kStatsRing,
+                         hipHostMallocDefault));
+  SweepStats *hst = (SweepStats *)g->ctx->host_stats;
+
+  const bool step_by_step = opts.on_iter != nullptr || opts.stop_active_ratio > 0;
+  int chunk = step_by_step ? 1 : 2;
+  int64_t t = 0;  // sweeps enqueued
+  int64_t sweeps = 0;
+  bool converged = false, stop_ratio = false, stop_cb = false;
+  Timer total, one;
+  total.start(s);
+  // Lemma 2: the iteration is exact after at most (number of degree levels)
+  // <= |R| sweeps, so |R| + 1 sweeps always observe convergence; the cap only
+  // guards against a defect turning into an endless loop.
+  if (opts.max_iters < 0 || opts.max_iters > nr + 1)
+    opts.max_iters = (int32_t)std::min<int64_t>(nr + 1, 0x7fffffff);
+  while (true) {
+    if (t >= opts.max_iters) break;
+    int nb = chunk;
+    if (t + nb > opts.max_iters) nb = (int)(opts.max_iters - t);
+    k_zero_stats<<<1, kMaxChunk, 0, s>>>(ring.p, t, nb);
+    ND_LAUNCHED();
+    const int64_t t0 = t;
+    for (int i = 0; i < nb; i++, t++) {
+      SweepArgs a{};
+      a.inc_off = ks.inc_off;
+      a.inc_ids = ks.inc_ids;
+      a.ds = ks.ds.p;
+      a.tau_in = buf[t & 1];
+      a.tau_out = buf[(t + 1) & 1];
+      a.stats = ring.p + (t % kStatsRing);
+      a.prev = t > 0 ? ring.p + ((t - 1) % kStatsRing) : nullptr;
+      a.cap_by_tau = 1;
+      if (step_by_step) one.start(s);
+      launch_sweep(ks, a, and_mode, s);
+      if (step_by_step) one.stop(s);
+    }
+    // read back this chunk's counters (the ring may wrap once)
+    const int64_t f = t0 % kStatsRing;
+    const int64_t first_n = std::min<int64_t>(nb, kStatsRing - f);
+    ND_HIP(hipMemcpyAsync(hst + f, ring.p + f, sizeof(SweepStats) * first_n,
+                          hipMemcpyDeviceToHost, s));
+    if (first_n < nb)
+      ND_HIP(hipMemcpyAsync(hst, ring.p, sizeof(SweepStats) * (nb - first_n),
+                            hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+    bool done = false;
+    for (int64_t j = t0; j < t0 + nb && !done; j++) {
+      const SweepStats &st = hst[j % kStatsRing];
+      sweeps = j + 1;
+      const int64_t changed = (int64_t)st.changed;
+      if (opts.on_iter) {
+        nd_iter_info info{};
+        info.iter = (int32_t)(j + 1);
+        info.evaluated = nr;
+        info.changed = changed;
+        info.active_next = nr;
+        info.tau_dev = buf[(j + 1) & 1];
+        info.ms = one.ms();
+        if (opts.on_iter(opts.user, &info)) stop_cb = true;
+      }
+      if (changed == 0) {
+        converged = true;
+        done = true;
+      } else if (opts.stop_active_ratio > 0 &&
+                 (double)changed < opts.stop_active_ratio * (double)nr) {
+        stop_ratio = true;
+        done = true;
+      } else if (stop_cb) {
+        done = true;
+      }
+    }
+    if (done) break;
+    chunk = std::min(chunk * 2, step_by_step ? 1 : kMaxChunk);
+  }
+  total.stop(s);
+  r.ms_iterate = total.ms();
+  r.sweeps = (int32_t)sweeps;
+  r.converged = converged ? 1 : 0;
+  r.updates = nr * sweeps;
+  const int32_t *result = buf[sweeps & 1];
+  ND_HIP(hipMemcpyAsync(kappa, result, sizeof(int32_t) * nr,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        s));
+  ND_HIP(hipStreamSynchronize(s));
+  if (res) *res = r;
+  if (converged || stop_ratio) return ND_OK;
+  set_error("stopped after %lld sweeps without converging", (long long)sweeps);
+  return ND_ERR_NOT_CONVERGED;
+}
+
+}  // namespace nd
+
+using namespace nd;
+
+extern "C" nd_status nd_decompose(nd_graph *g, nd_kind kind,
+                                  const nd_opts *opts, int32_t *kappa,
+                                  int on_device, void *stream, nd_result *res) {
+  nd_status out = ND_OK;
+  nd_status st = guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    StreamScope scope((hipStream_t)stream);
+    out = decompose(g, kind, opts, kappa, on_device, (hipStream_t)stream, res);
+  });
+  return st != ND_OK ? st : out;
+}

@@ -1,0 +1,241 @@
+// internal.h -- library-internal types: context, caching allocator, graph
+// state and the host entry points of each kernel family.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace nd {
+
+// ------------------------------------------------------------ allocator
+
+// The stream that work issued by the current thread is ordered on.  Set at
+// every ABI entry (StreamScope); the allocator tags blocks with it.
+hipStream_t current_stream();
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s);
+  ~StreamScope();
+};
+
+// Device allocator with a byte budget and a cache of freed blocks, so that
+// repeated decompositions do not pay hipMalloc/hipFree (which synchronises the
+// device) on every call.  A freed block remembers the stream it was last used
+// on: the same stream may reuse it at once (stream order protects it), any
+// other stream only after synchronising that stream.  Thread-safe.
+class Allocator {
+ public:
+  Allocator(int device, size_t budget) : device_(device), budget_(budget) {}
+  ~Allocator();
+  void *alloc(size_t bytes);  // throws Err(ND_ERR_OOM)
+  void release(void *p);      // back to the cache, tagged current_stream()
+  void trim();                // return cached blocks to the device
+  size_t live_bytes() const;
+  size_t cached_bytes() const;
+  size_t budget() const { return budget_; }
+  int device() const { return device_; }
+
+ private:
+  struct Cached {
+    void *p;
+    hipStream_t s;
+  };
+  void trim_locked();
+  int device_;
+  size_t budget_;
+  mutable std::mutex mu_;
+  std::map<void *, size_t> live_;
+  std::multimap<size_t, Cached> cache_;
+  size_t live_total_ = 0, cache_total_ = 0;
+};
+
+// Owning device array of T.
+template <typename T>
+struct DArr {
+  T *p = nullptr;
+  int64_t n = 0;
+  Allocator *a = nullptr;
+  DArr() = default;
+  DArr(Allocator &al, int64_t count) { reset(al, count); }
+  DArr(const DArr &) = delete;
+  DArr &operator=(const DArr &) = delete;
+  DArr(DArr &&o) noexcept : p(o.p), n(o.n), a(o.a) { o.p = nullptr; o.n = 0; }
+  DArr &operator=(DArr &&o) noexcept {
+    if (this != &o) {
+      free();
+      p = o.p; n = o.n; a = o.a;
+      o.p = nullptr; o.n = 0;
+    }
+    return *this;
+  }
+  ~DArr() { free(); }
+  void reset(Allocator &al, int64_t count) {
+    free();
+    a = &al;
+    n = count;
+    p = (T *)al.alloc(sizeof(T) * (size_t)(count > 0 ? count : 1));
+  }
+  void free() {
+    if (p && a) a->release(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return sizeof(T) * (size_t)(n > 0 ? n : 1); }
+};
+
+// -------------------------------------------------------------- context
+
+}  // namespace nd
+
+// A context lives until nd_ctx_destroy has been called and every graph made
+// from it has been destroyed, whatever the order of those calls.
+struct nd_ctx {
+  int device = 0;
+  nd::Allocator alloc;
+  int num_cu = 256;
+  void *host_stats = nullptr;  // pinned read-back ring for sweep counters
+  std::atomic<int> refs{1};    // the owner's reference + one per graph
+  nd_ctx(int dev, size_t budget) : device(dev), alloc(dev, budget) {}
+  ~nd_ctx() {
+    if (host_stats) (void)hipHostFree(host_stats);
+  }
+  void retain() { refs.fetch_add(1); }
+  void release() {
+    if (refs.fetch_sub(1) == 1) delete this;
+  }
+};
+
+namespace nd {
+
+// ---------------------------------------------------------- sweep bins
+
+// r-cliques are swept in bins of similar S-degree; each bin has its own
+// lanes-per-r-clique mapping.  Bin boundaries (inclusive upper d_s bounds).
+enum SweepBin : int {
+  kBinZero = 0,   // d_s = 0: tau stays 0, never swept
+  kBinG1,         // d_s <= 4:     one lane per r-clique
+  kBinG4,         // d_s <= 16:    4 lanes
+  kBinG16,        // d_s <= 64:    16 lanes
+  kBinG64,        // d_s <= 256:   one wave, values in registers
+  kBinWave,       // d_s <= 2047:  one wave, LDS histogram
+  kBinBlock,      // larger:       one workgroup, LDS histogram
+  kNumBins
+};
+
+int bin_of_degree_host(int64_t d);
+
+// Per-kind state of a graph: r-cliques, incidence lists, sweep schedule.
+struct KindState {
+  bool ready = false;
+  int r = 0, s = 0, k = 0;  // k = C(s,r) - 1
+  int64_t nr = 0;           // |R|
+  int64_t P = 0;            // sum_R d_s(R)
+  // incidence: for R, s-cliques inc_off[R] .. inc_off[R+1], ids
+  // inc_ids[k*j .. k*j+k) for each of them.
+  const int64_t *inc_off = nullptr;
+  const int32_t *inc_ids = nullptr;
+  DArr<int64_t> own_off;
+  DArr<int32_t> own_ids;
+  DArr<int32_t> ds;          // d_s(R), int32
+  DArr<int32_t> rverts;      // r-clique vertex tuples (r >= 2)
+  DArr<int32_t> bin_items;   // R ids grouped by sweep bin (ascending in bin)
+  int64_t bin_off[kNumBins + 1] = {0};
+  int32_t max_ds = 0;
+  double ms_prep = 0;
+  size_t bytes() const;
+};
+
+}  // namespace nd
+
+struct nd_graph {
+  nd_ctx *ctx = nullptr;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  nd::DArr<int64_t> row_off;  // n+1
+  nd::DArr<int32_t> col;      // nnz, ascending per row
+  nd::DArr<int32_t> rowid;    // nnz: row of each entry
+  // edge numbering (r = 2): edges u<v lexicographic
+  bool edges_ready = false;
+  int64_t ne = 0;
+  nd::DArr<int32_t> nlow;     // n: neighbours below u
+  nd::DArr<int64_t> eoff;     // n+1: first edge id of u
+  nd::DArr<int32_t> eid;      // nnz: id of the edge of each entry
+  // triangle numbering (r = 3): triangles u<v<w lexicographic
+  bool tris_ready = false;
+  int64_t nt = 0;
+  nd::DArr<int64_t> toff;     // ne+1: first triangle id of edge (u,v)
+  nd::DArr<int32_t> tri_w;    // nt: third vertex w
+  nd::DArr<int32_t> tri_e;    // nt: edge id of (u,v)
+  nd::KindState ks[3];
+  double ms_build = 0;
+  size_t bytes() const;
+};
+
+namespace nd {
+
+// ------------------------------------------------------- primitives
+
+// out[i] = sum_{j<i} in[j] for i <= n (out has n+1 entries).
+void exclusive_scan_i32(const int32_t *in, int64_t *out, int64_t n,
+                        hipStream_t s, Allocator &al);
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n,
+                        hipStream_t s, Allocator &al);
+// Stable LSD radix sort of keys by bits [lo_bit, hi_bit); returns whichever
+// of keys/tmp holds the result.
+uint64_t *radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t n, int lo_bit,
+                         int hi_bit, hipStream_t s, Allocator &al);
+// items[] = 0..n-1 grouped by bin[i] (stable), offsets[b] = first index of
+// bin b (host, nbins+1 entries).  nbins <= 256.
+void partition_by_bin(const uint8_t *bin, int64_t n, int nbins, int32_t *items,
+                      int64_t *offsets, hipStream_t s, Allocator &al);
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+int64_t read_i64(const int64_t *dev, hipStream_t s);  // synchronous
+
+// ------------------------------------------------------------ graph prep
+
+// Canonical CSR from raw device pairs (validates ids; ND_ERR_INVALID).
+void build_from_edges(nd_graph *g, int64_t m, const int32_t *src,
+                      const int32_t *dst, hipStream_t s);
+// Check a device CSR already copied into g (ND_ERR_INVALID when malformed).
+void validate_csr(nd_graph *g, hipStream_t s);
+void build_rowid(nd_graph *g, hipStream_t s);
+void build_edges(nd_graph *g, hipStream_t s);
+void build_triangles(nd_graph *g, hipStream_t s);
+void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s);
+void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s);
+// d_s from offsets, bins and the bin schedule.
+void build_schedule(nd_graph *g, KindState &ks, hipStream_t s);
+
+// ---------------------------------------------------------------- sweeps
+
+struct SweepStats {
+  unsigned long long changed;
+  unsigned long long evaluated;
+  unsigned long long active_next;
+  unsigned long long pad;
+};
+
+struct SweepArgs {
+  const int64_t *inc_off;
+  const int32_t *inc_ids;
+  const int32_t *ds;
+  const int32_t *tau_in;   // SND: tau_t; AND: the in-place array
+  int32_t *tau_out;        // SND: tau_{t+1}; AND: same as tau_in
+  SweepStats *stats;       // this sweep's counters
+  const SweepStats *prev;  // previous sweep's counters (skip when converged)
+  int cap_by_tau;          // 1: clamp at tau_in(R) (iterates); 0: at d_s
+};
+
+// Launch one sweep over every bin of ks.  `and_mode` selects in-place reads.
+void launch_sweep(const KindState &ks, const SweepArgs &a, bool and_mode,
+                  hipStream_t s);
+
+}  // namespace nd

@@ -1,0 +1,276 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+Every comparison is bit-exact: canonical CSR, r-clique lists, S-degrees,
+incidence lists (as sets), one application of U on arbitrary inputs, every
+SND iterate, and the converged kappa of SND and AND.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import chung_lu, erdos_renyi, sbm
+
+pytestmark = pytest.mark.gpu
+
+KINDS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4)}
+
+
+@pytest.fixture(scope="module")
+def ctx(nd):
+    return nd.Context(0)
+
+
+def gpu_graph(nd, ctx, raw):
+    return nd.Graph.from_edges(ctx, raw.n, torch.from_numpy(raw.src),
+                               torch.from_numpy(raw.dst))
+
+
+def canon_incidence(off, ids):
+    """Per r-clique, the multiset of s-cliques (each a sorted id tuple), in a
+    canonical order: returns (R index per row, sorted rows)."""
+    off = np.asarray(off, np.int64)
+    ids = np.sort(np.asarray(ids), axis=1)
+    rid = np.repeat(np.arange(off.size - 1), np.diff(off))
+    keys = [ids[:, j] for j in range(ids.shape[1] - 1, -1, -1)] + [rid]
+    order = np.lexsort(keys)
+    return rid[order], ids[order]
+
+
+def oracle_incidence(og, r, s):
+    nr = og.num_rcliques(r)
+    rows, off = [], [0]
+    for R in range(nr):
+        m = og.members(r, s, R)
+        rows.append(m)
+        off.append(off[-1] + m.shape[0])
+    k = math.comb(s, r) - 1
+    ids = np.concatenate(rows) if rows else np.zeros((0, k), np.int32)
+    return np.array(off), ids.reshape(-1, k)
+
+
+SMALL = [
+    ("er2000", lambda: erdos_renyi(2000, 0.005, seed=1)),
+    ("cl4k", lambda: chung_lu(4096, 2.1, 16.0, seed=7)),
+    ("sbm40", lambda: sbm(n_comm=40, size_lo=10, size_hi=40, p_in=0.3,
+                          p_out=0.002, seed=9)),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_canonical_csr(nd, ctx, name, make):
+    raw = make()
+    # add loops and reversed repeats to exercise canonicalisation
+    src = np.concatenate([raw.src, raw.src[:50], np.arange(20, dtype=np.int32)])
+    dst = np.concatenate([raw.dst, raw.dst[:50], np.arange(20, dtype=np.int32)])
+    src[-70:-20], dst[-70:-20] = raw.dst[:50], raw.src[:50]
+    g = nd.Graph.from_edges(ctx, raw.n, torch.from_numpy(src),
+                            torch.from_numpy(dst))
+    og = oracle.Graph(raw.n, src, dst)
+    ro, col = g.csr()
+    oro, ocol = og.csr()
+    assert np.array_equal(ro.cpu().numpy(), oro)
+    assert np.array_equal(col.cpu().numpy(), ocol)
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_rcliques_sdeg_incidence(nd, ctx, name, make, kind):
+    raw = make()
+    r, s = KINDS[kind]
+    g = gpu_graph(nd, ctx, raw)
+    og = oracle.Graph.from_raw(raw)
+    rc = g.rcliques(kind).cpu().numpy()
+    assert np.array_equal(rc, og.rcliques(r))
+    ds = g.sdegree(kind).cpu().numpy()
+    assert np.array_equal(ds, og.sdeg(r, s))
+    off, ids = g.incidence(kind)
+    goff, gids = off.cpu().numpy(), ids.cpu().numpy()
+    assert np.array_equal(np.diff(goff), ds)
+    ooff, oids = oracle_incidence(og, r, s)
+    a = canon_incidence(goff, gids)
+    b = canon_incidence(ooff, oids)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_update_arbitrary_tau(nd, ctx, name, make, kind):
+    raw = make()
+    r, s = KINDS[kind]
+    g = gpu_graph(nd, ctx, raw)
+    og = oracle.Graph.from_raw(raw)
+    ds = og.sdeg(r, s)
+    rng = np.random.default_rng(17)
+    for trial in range(3):
+        tau = (rng.random(ds.size) * (ds + 1)).astype(np.int32)
+        tau = np.minimum(tau, ds)
+        got = g.update(kind, torch.from_numpy(tau)).cpu().numpy()
+        assert np.array_equal(got, og.update(r, s, tau)), trial
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_snd_every_iterate_and_kappa(nd, ctx, name, make, kind):
+    raw = make()
+    r, s = KINDS[kind]
+    g = gpu_graph(nd, ctx, raw)
+    og = oracle.Graph.from_raw(raw)
+    seq = og.snd(r, s)  # tau_0 .. tau_T, tau_T == tau_{T-1}
+    its = []
+    kappa, res = g.decompose(kind, "snd", keep_iterates=its)
+    kappa = kappa.cpu().numpy()
+    assert res["converged"] == 1
+    if og.num_rcliques(r) == 0:
+        assert res["sweeps"] == 0
+        return
+    assert res["sweeps"] == len(seq) - 1 == len(its)
+    for t, (changed, tau) in enumerate(its, start=1):
+        want = seq[t]
+        assert np.array_equal(tau.cpu().numpy(), want), f"iterate {t}"
+        assert changed == int((seq[t] != seq[t - 1]).sum())
+    assert np.array_equal(kappa, og.peel(r, s))
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_and_converges_to_kappa(nd, ctx, name, make, kind):
+    raw = make()
+    r, s = KINDS[kind]
+    g = gpu_graph(nd, ctx, raw)
+    og = oracle.Graph.from_raw(raw)
+    if og.num_rcliques(r) == 0:
+        pytest.skip("no r-cliques")
+    seq = og.snd(r, s)
+    kref = og.peel(r, s)
+    its = []
+    kappa, res = g.decompose(kind, "and", keep_iterates=its)
+    assert np.array_equal(kappa.cpu().numpy(), kref)
+    assert res["converged"] == 1
+    # never more sweeps than SND; every AND iterate between kappa and SND's
+    assert res["sweeps"] <= len(seq) - 1
+    for t, (_, tau) in enumerate(its, start=1):
+        a = tau.cpu().numpy()
+        assert (a >= kref).all() and (a <= seq[min(t, len(seq) - 1)]).all()
+
+
+def test_snd_deterministic_and_chunked(nd, ctx):
+    raw = chung_lu(8192, 2.1, 24.0, seed=23)
+    g = gpu_graph(nd, ctx, raw)
+    k1, r1 = g.decompose("truss", "snd")
+    k2, r2 = g.decompose("truss", "snd")
+    its = []
+    k3, r3 = g.decompose("truss", "snd", keep_iterates=its)
+    assert torch.equal(k1, k2) and torch.equal(k1, k3)
+    assert r1["sweeps"] == r2["sweeps"] == r3["sweeps"]
+    k4, _ = g.decompose("truss", "and")
+    assert torch.equal(k1, k4)
+
+
+def test_max_iters_returns_iterate(nd, ctx):
+    raw = chung_lu(4096, 2.1, 16.0, seed=7)
+    g = gpu_graph(nd, ctx, raw)
+    og = oracle.Graph.from_raw(raw)
+    seq = og.snd(2, 3)
+    assert len(seq) > 3
+    tau, res = g.decompose("truss", "snd", max_iters=2,
+                           allow_not_converged=True)
+    assert res["converged"] == 0 and res["sweeps"] == 2
+    assert np.array_equal(tau.cpu().numpy(), seq[2])
+    with pytest.raises(nd.NdError) as e:
+        g.decompose("truss", "snd", max_iters=2)
+    assert e.value.name == "not_converged"
+
+
+def test_stop_active_ratio(nd, ctx):
+    raw = chung_lu(4096, 2.1, 16.0, seed=7)
+    g = gpu_graph(nd, ctx, raw)
+    og = oracle.Graph.from_raw(raw)
+    seq = og.snd(2, 3)
+    nr = seq[0].size
+    ratio = 0.01
+    tau, res = g.decompose("truss", "snd", stop_active_ratio=ratio)
+    t = res["sweeps"]
+    changed = [(seq[i] != seq[i - 1]).sum() for i in range(1, len(seq))]
+    want_t = next(i + 1 for i, c in enumerate(changed) if c < ratio * nr)
+    assert t == want_t
+    assert np.array_equal(tau.cpu().numpy(), seq[t])
+
+
+# ----------------------------------------------------------- edge cases
+
+
+def edges_graph(nd, ctx, n, pairs):
+    src = np.array([a for a, b in pairs], np.int32)
+    dst = np.array([b for a, b in pairs], np.int32)
+    return (nd.Graph.from_edges(ctx, n, torch.from_numpy(src),
+                                torch.from_numpy(dst)),
+            oracle.Graph(n, src, dst))
+
+
+EDGE_CASES = {
+    "empty": (0, []),
+    "isolated": (7, []),
+    "single_edge": (2, [(0, 1)]),
+    "loops_only": (3, [(0, 0), (1, 1), (2, 2)]),
+    "k6": (6, [(a, b) for a in range(6) for b in range(a + 1, 6)]),
+    "k40": (40, [(a, b) for a in range(40) for b in range(a + 1, 40)]),
+    # hub of degree 20000 > 16384 bins: coarse-then-fine histogram path
+    "star20000": (20001, [(0, i) for i in range(1, 20001)]),
+    # K_{40,20000} plus a 60-clique joined to vertex 0, whose degree
+    # 20060 takes the coarse path with a large H
+    "bipartite_hub": (20100, [(a, 100 + b) for a in range(40) for b in range(20000)]
+                      + [(40 + a, 40 + b) for a in range(60) for b in range(a + 1, 60)]
+                      + [(0, 40 + a) for a in range(60)]),
+    # an edge in 3000 triangles, a triangle in 3000 4-cliques (workgroup bins)
+    "book3000": (3003, [(0, 1), (0, 2), (1, 2)] + [(x, 3 + i) for i in range(3000)
+                                                    for x in (0, 1, 2)]),
+}
+
+
+@pytest.mark.parametrize("case", list(EDGE_CASES))
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_edge_cases(nd, ctx, case, kind):
+    n, pairs = EDGE_CASES[case]
+    r, s = KINDS[kind]
+    g, og = edges_graph(nd, ctx, n, pairs)
+    nr = og.num_rcliques(r)
+    for mode in ("snd", "and"):
+        kappa, res = g.decompose(kind, mode)
+        assert res["converged"] == 1
+        assert np.array_equal(kappa.cpu().numpy(), og.peel(r, s)), mode
+    assert g.sizes(kind)[0] == nr
+    if nr:
+        ds = og.sdeg(r, s)
+        tau = np.minimum(np.arange(nr, dtype=np.int32) % 7, ds).astype(np.int32)
+        assert np.array_equal(g.update(kind, torch.from_numpy(tau)).cpu().numpy(),
+                              og.update(r, s, tau))
+
+
+def test_invalid_inputs(nd, ctx):
+    with pytest.raises(nd.NdError) as e:
+        nd.Graph.from_edges(ctx, 3, torch.tensor([0, 5]), torch.tensor([1, 2]))
+    assert e.value.name == "invalid"
+    ro = torch.tensor([0, 1, 3, 4], dtype=torch.int64)
+    col = torch.tensor([1, 0, 2, 1], dtype=torch.int32)
+    g = nd.Graph.from_csr(ctx, 3, ro, col)
+    assert g.dims() == (3, 4)
+    bad = {
+        "unsorted": ([0, 1, 3, 4], [1, 2, 0, 1]),
+        "asymmetric": ([0, 1, 2, 3], [1, 2, 1]),
+        "self_loop": ([0, 2, 3, 4], [0, 1, 0, 1]),
+        "out_of_range": ([0, 1, 3, 4], [1, 0, 7, 1]),
+        "bad_offsets": ([0, 3, 1, 4], [1, 0, 2, 1]),
+        "duplicate": ([0, 2, 4, 4], [1, 1, 0, 0]),
+    }
+    for name, (r, c) in bad.items():
+        with pytest.raises(nd.NdError) as e:
+            nd.Graph.from_csr(ctx, 3, torch.tensor(r, dtype=torch.int64),
+                              torch.tensor(c, dtype=torch.int32))
+        assert e.value.name == "invalid", name
+    g2 = nd.Graph.from_edges(ctx, 4, torch.tensor([0, 1]), torch.tensor([1, 2]))
+    with pytest.raises(nd.NdError):
+        g2.update("core", torch.tensor([5, 0, 0, 0]))  # above d_s
