@@ -114,9 +114,14 @@ typedef struct {
   int32_t converged;   /* 1 when the last sweep changed nothing */
   int64_t n_rcliques;  /* |R| */
   int64_t n_incidence; /* P = sum over R of d_s(R) */
-  int64_t updates;     /* h-index evaluations summed over sweeps */
+  int64_t updates;     /* h-index evaluations summed over sweeps (r-cliques
+                          with d_s = 0 are exact from the start and are not
+                          evaluated) */
   double ms_prep;      /* device time of prepare work done by this call */
   double ms_iterate;   /* device time of the sweeps */
+  int32_t max_sdegree; /* max over R of d_s(R) */
+  int32_t tau_bytes;   /* bytes per stored tau value (2 when every d_s fits
+                          in 15 bits, else 4) */
 } nd_result;
 
 /* ------------------------------------------------------------ context */

@@ -72,7 +72,8 @@ class nd_result(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("n_rcliques", ctypes.c_int64),
                 ("n_incidence", ctypes.c_int64), ("updates", ctypes.c_int64),
-                ("ms_prep", ctypes.c_double), ("ms_iterate", ctypes.c_double)]
+                ("ms_prep", ctypes.c_double), ("ms_iterate", ctypes.c_double),
+                ("max_sdegree", ctypes.c_int32), ("tau_bytes", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

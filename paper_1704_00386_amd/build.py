@@ -18,8 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libnd.so")
 
-SOURCES = ["api.hip", "prim.hip", "graph.hip", "cliques.hip", "sweep.hip",
-           "driver.hip", "batch.hip", "server.hip"]
+SOURCES = ["api.hip", "prim.hip", "graph.hip", "cliques.hip", "layout.hip",
+           "sweep.hip", "driver.hip", "batch.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

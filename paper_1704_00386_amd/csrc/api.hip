@@ -126,42 +126,17 @@ size_t Allocator::cached_bytes() const {
 
 size_t KindState::bytes() const {
   size_t b = 0;
-  if (own_off.p) b += own_off.bytes();
-  if (own_ids.p) b += own_ids.bytes();
+  if (perm.p) b += perm.bytes();
+  if (inv.p) b += inv.bytes();
   if (ds.p) b += ds.bytes();
-  if (rverts.p) b += rverts.bytes();
-  if (bin_items.p) b += bin_items.bytes();
+  if (inc_off.p) b += inc_off.bytes();
+  if (inc_ids.p) b += inc_ids.bytes();
   return b;
 }
 
 // ------------------------------------------------------- preparation
 
 namespace {
-
-__global__ void k_degree_bins(const int64_t *__restrict__ off, int64_t nr,
-                              int32_t *__restrict__ ds,
-                              uint8_t *__restrict__ bin,
-                              int32_t *__restrict__ maxd,
-                              int32_t *__restrict__ err) {
-  int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (R >= nr) return;
-  const int64_t d = off[R + 1] - off[R];
-  if (d > 0x7fffffff) {
-    atomicOr(err, 1);
-    return;
-  }
-  ds[R] = (int32_t)d;
-  atomicMax(maxd, (int32_t)d);
-  uint8_t b;
-  if (d == 0) b = kBinZero;
-  else if (d <= 4) b = kBinG1;
-  else if (d <= 16) b = kBinG4;
-  else if (d <= 64) b = kBinG16;
-  else if (d <= 256) b = kBinG64;
-  else if (d <= 2047) b = kBinWave;
-  else b = kBinBlock;
-  bin[R] = b;
-}
 
 __global__ void k_iota(int32_t *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,50 +157,31 @@ __global__ void k_tri_verts(const int32_t *__restrict__ ev,
 
 // Every listed id must name another r-clique: a cheap guard that turns a
 // builder fault into an error instead of an out-of-range gather.
-__global__ void k_check_incidence(const int64_t *__restrict__ off,
-                                  const int32_t *__restrict__ ids, int k,
-                                  int64_t nr, int32_t *__restrict__ err) {
-  int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (R >= nr) return;
-  const int64_t b = off[R] * k, e = off[R + 1] * k;
-  for (int64_t j = b; j < e; j++) {
+__global__ void k_check_incidence(const int32_t *__restrict__ ids,
+                                  int64_t nids, int64_t nr,
+                                  int32_t *__restrict__ err) {
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nids;
+       j += (int64_t)gridDim.x * blockDim.x) {
     const int32_t x = ids[j];
-    if (x < 0 || x >= nr || x == R) {
-      atomicOr(err, 1);
-      return;
-    }
+    bad |= x < 0 || x >= nr;
   }
+  if (ballot(bad) && lane_id() == 0) atomicOr(err, 1);
 }
 
+// tau given in r-clique-id order must satisfy 0 <= tau <= d_s.
 __global__ void k_check_tau(const int32_t *__restrict__ tau,
+                            const int32_t *__restrict__ perm,
                             const int32_t *__restrict__ ds, int64_t n,
                             int32_t *__restrict__ err) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && (tau[i] < 0 || tau[i] > ds[i])) atomicOr(err, 1);
+  if (i < n) {
+    const int32_t t = tau[perm[i]];
+    if (t < 0 || t > ds[i]) atomicOr(err, 1);
+  }
 }
 
 }  // namespace
-
-void build_schedule(nd_graph *g, KindState &ks, hipStream_t s) {
-  Allocator &al = g->ctx->alloc;
-  const int64_t nr = ks.nr;
-  ks.ds.reset(al, nr);
-  DArr<uint8_t> bin(al, nr);
-  DArr<int32_t> dev(al, 2);  // [max d_s, error flags]
-  fill_i32(dev.p, 0, 2, s);
-  if (nr > 0) {
-    k_degree_bins<<<grid_for(nr, 256), 256, 0, s>>>(ks.inc_off, nr, ks.ds.p,
-                                                     bin.p, dev.p, dev.p + 1);
-    ND_LAUNCHED();
-  }
-  int32_t h[2];
-  ND_HIP(hipMemcpyAsync(h, dev.p, sizeof h, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
-  ND_REQUIRE(h[1] == 0, ND_ERR_INVALID, "an S-degree exceeds int32");
-  ks.max_ds = h[0];
-  ks.bin_items.reset(al, nr);
-  partition_by_bin(bin.p, nr, kNumBins, ks.bin_items.p, ks.bin_off, s, al);
-}
 
 static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
   KindState &ks = g->ks[kind];
@@ -237,12 +193,9 @@ static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
   switch (kind) {
     case ND_KCORE:
       // (1,2): the s-cliques containing vertex u are its edges and the other
-      // r-clique of each is the neighbour, so the CSR is the incidence list.
+      // r-clique of each is the neighbour: the incidence is the CSR.
       ks.r = 1; ks.s = 2; ks.k = 1;
-      ks.nr = g->n;
-      ks.P = g->nnz;
-      ks.inc_off = g->row_off.p;
-      ks.inc_ids = g->col.p;
+      build_incidence_core(g, ks, s);
       break;
     case ND_KTRUSS:
       ks.r = 2; ks.s = 3; ks.k = 2;
@@ -255,16 +208,16 @@ static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
     default:
       ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "unknown kind %d", (int)kind);
   }
-  build_schedule(g, ks, s);
   ND_REQUIRE((int64_t)ks.max_ds < ((int64_t)1 << 28), ND_ERR_UNSUPPORTED,
              "an S-degree of %d exceeds the 2^28 supported per r-clique",
              ks.max_ds);
   {
     DArr<int32_t> err(g->ctx->alloc, 1);
     fill_i32(err.p, 0, 1, s);
-    if (ks.nr > 0) {
-      k_check_incidence<<<grid_for(ks.nr, 256), 256, 0, s>>>(
-          ks.inc_off, ks.inc_ids, ks.k, ks.nr, err.p);
+    const int64_t nids = ks.P * ks.k;
+    if (nids > 0) {
+      const unsigned grid = (unsigned)std::min<int64_t>(grid_for(nids, 256), 65536);
+      k_check_incidence<<<grid, 256, 0, s>>>(ks.inc_ids.p, nids, ks.nr, err.p);
       ND_LAUNCHED();
     }
     int32_t h = 0;
@@ -294,7 +247,8 @@ void check_tau_range(nd_graph *g, const KindState &ks, const int32_t *tau,
   DArr<int32_t> err(g->ctx->alloc, 1);
   fill_i32(err.p, 0, 1, s);
   if (ks.nr > 0) {
-    k_check_tau<<<grid_for(ks.nr, 256), 256, 0, s>>>(tau, ks.ds.p, ks.nr, err.p);
+    k_check_tau<<<grid_for(ks.nr, 256), 256, 0, s>>>(tau, ks.perm.p, ks.ds.p,
+                                                      ks.nr, err.p);
     ND_LAUNCHED();
   }
   int32_t h = 0;
@@ -314,6 +268,7 @@ size_t nd_graph::bytes() const {
   add(nlow.bytes(), nlow.p);
   add(eoff.bytes(), eoff.p);
   add(eid.bytes(), eid.p);
+  add(ev.bytes(), ev.p);
   add(toff.bytes(), toff.p);
   add(tri_w.bytes(), tri_w.p);
   add(tri_e.bytes(), tri_e.p);
@@ -524,10 +479,10 @@ nd_status nd_rcliques(nd_graph *g, nd_kind kind, int32_t *verts, int on_device,
       k_iota<<<grid_for(cnt, 256), 256, 0, s>>>(tmp.p, cnt);
       ND_LAUNCHED();
     } else if (kind == ND_KTRUSS) {
-      src = ks.rverts.p;
+      src = g->ev.p;
     } else {
       k_tri_verts<<<grid_for(ks.nr, 256), 256, 0, s>>>(
-          g->ks[ND_KTRUSS].rverts.p, g->tri_e.p, g->tri_w.p, ks.nr, tmp.p);
+          g->ev.p, g->tri_e.p, g->tri_w.p, ks.nr, tmp.p);
       ND_LAUNCHED();
     }
     ND_HIP(hipMemcpyAsync(verts, src, sizeof(int32_t) * cnt,
@@ -545,11 +500,24 @@ nd_status nd_incidence(nd_graph *g, nd_kind kind, int64_t *off, int32_t *ids,
     StreamScope scope(s);
     prepare(g, kind, s);
     const KindState &ks = g->ks[kind];
-    const hipMemcpyKind mk = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    ND_HIP(hipMemcpyAsync(off, ks.inc_off, sizeof(int64_t) * (ks.nr + 1), mk, s));
     const int64_t nid = ks.P * ks.k;
     ND_REQUIRE(ids || nid == 0, ND_ERR_INVALID, "ids is NULL");
-    if (nid > 0) ND_HIP(hipMemcpyAsync(ids, ks.inc_ids, sizeof(int32_t) * nid, mk, s));
+    Allocator &al = g->ctx->alloc;
+    DArr<int64_t> doff;
+    DArr<int32_t> dids;
+    int64_t *po = off;
+    int32_t *pi = ids;
+    if (!on_device) {
+      doff.reset(al, ks.nr + 1);
+      dids.reset(al, nid);
+      po = doff.p;
+      pi = dids.p;
+    }
+    incidence_original(g, ks, po, pi, s);
+    if (!on_device) {
+      ND_HIP(hipMemcpyAsync(off, po, sizeof(int64_t) * (ks.nr + 1), hipMemcpyDeviceToHost, s));
+      if (nid > 0) ND_HIP(hipMemcpyAsync(ids, pi, sizeof(int32_t) * nid, hipMemcpyDeviceToHost, s));
+    }
     ND_HIP(hipStreamSynchronize(s));
   });
 }
@@ -564,9 +532,16 @@ nd_status nd_sdegree(nd_graph *g, nd_kind kind, int32_t *ds, int on_device,
     prepare(g, kind, s);
     const KindState &ks = g->ks[kind];
     ND_REQUIRE(ds || ks.nr == 0, ND_ERR_INVALID, "ds is NULL");
-    if (ks.nr > 0)
-      ND_HIP(hipMemcpyAsync(ds, ks.ds.p, sizeof(int32_t) * ks.nr,
-                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (ks.nr == 0) return;
+    DArr<int32_t> tmp;
+    int32_t *out = ds;
+    if (!on_device) {
+      tmp.reset(g->ctx->alloc, ks.nr);
+      out = tmp.p;
+    }
+    sdegree_original(ks, out, s);
+    if (!on_device)
+      ND_HIP(hipMemcpyAsync(ds, out, sizeof(int32_t) * ks.nr, hipMemcpyDeviceToHost, s));
     ND_HIP(hipStreamSynchronize(s));
   });
 }
@@ -594,18 +569,21 @@ nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
       pout = dout.p;
     }
     check_tau_range(g, ks, pin, s);
+    const size_t tb = ks.tau16 ? 2 : 4;
+    DArr<uint8_t> ta(al, (int64_t)(tb * ks.nr)), tbuf(al, (int64_t)(tb * ks.nr));
+    to_internal(ks, pin, ta.p, ks.tau16, s);
     DArr<SweepStats> st(al, 1);
     ND_HIP(hipMemsetAsync(st.p, 0, sizeof(SweepStats), s));
     SweepArgs a{};
-    a.inc_off = ks.inc_off;
-    a.inc_ids = ks.inc_ids;
-    a.ds = ks.ds.p;
-    a.tau_in = pin;
-    a.tau_out = pout;
+    a.inc_off = ks.inc_off.p;
+    a.inc_ids = ks.inc_ids.p;
+    a.tau_in = ta.p;
+    a.tau_out = tbuf.p;
     a.stats = st.p;
     a.prev = nullptr;
     a.cap_by_tau = 0;
     launch_sweep(ks, a, false, s);
+    to_original(ks, tbuf.p, ks.tau16, pout, s);
     if (!on_device)
       ND_HIP(hipMemcpyAsync(tau_out, pout, sizeof(int32_t) * ks.nr, hipMemcpyDeviceToHost, s));
     ND_HIP(hipStreamSynchronize(s));

@@ -10,9 +10,12 @@
 //                  lexicographically; then for triangle (u,v,w) and every x
 //                  in N(u) & N(v) & N(w), the ids of the triangles {u,v,x},
 //                  {u,w,x} and {v,w,x}.
-// Both use two passes (count, exclusive scan, fill) so that the lists are
-// written in place with no atomics; each list is in ascending order of its
-// extension vertex, so the output is deterministic.
+// Both use two passes: count, then (once every S-degree is known and the
+// internal numbering is fixed, see build_layout) fill, which writes each list
+// straight into its place in the internal order, with internal ids, and no
+// atomics.  Each list is in ascending order of its extension vertex, so the
+// output is deterministic.  The k-core incidence is the CSR itself,
+// re-indexed the same way.
 //
 // Work per item is proportional to the shortest adjacency list involved:
 // each element of it is binary-searched in the others.  Items are binned by
@@ -39,7 +42,8 @@ struct EdgeIsectArgs {
   const int32_t *col;
   const int32_t *eid;
   int32_t *count;        // count modes: per edge
-  const int64_t *off;    // fill modes: per-edge output offset
+  const int64_t *off;    // fill modes: output offset (truss: internal order)
+  const int32_t *inv;    // truss fill: edge id -> internal id
   int32_t *out_a;        // fill: pair ids (truss) or tri_w (triangles)
   int32_t *out_b;        // fill: tri_e (triangles)
 };
@@ -71,7 +75,9 @@ __global__ __launch_bounds__(256) void k_edge_isect(EdgeIsectArgs a) {
     start = lower_bound<int32_t>(a.col, sb, se, v + 1);  // only w > v
   const uint64_t smask = subgroup_mask<G>();
   int64_t written = 0;
-  const int64_t base = (MODE == kFillTruss || MODE == kFillTri) ? a.off[e] : 0;
+  int64_t base = 0;
+  if (MODE == kFillTruss) base = a.off[a.inv[e]];
+  if (MODE == kFillTri) base = a.off[e];
   for (int64_t j0 = start; j0 < se; j0 += G) {
     const int64_t j = j0 + sl;
     bool found = false;
@@ -85,7 +91,7 @@ __global__ __launch_bounds__(256) void k_edge_isect(EdgeIsectArgs a) {
     const uint64_t m = ballot(found) & smask;
     if (MODE == kFillTruss && found) {
       const int64_t k = base + written + lanes_below(m);
-      const int32_t id_short = a.eid[j], id_long = a.eid[q];
+      const int32_t id_short = a.inv[a.eid[j]], id_long = a.inv[a.eid[q]];
       a.out_a[2 * k] = short_is_u ? id_short : id_long;      // eid(u, w)
       a.out_a[2 * k + 1] = short_is_u ? id_long : id_short;  // eid(v, w)
     }
@@ -113,7 +119,8 @@ struct TriIsectArgs {
   const int32_t *tri_w;
   const int32_t *tri_e;
   int32_t *count;        // count pass
-  const int64_t *off;    // fill pass
+  const int64_t *off;    // fill pass: output offset, internal order
+  const int32_t *inv;    // fill pass: triangle id -> internal id
   int32_t *out;          // fill pass: 3 ids per 4-clique
 };
 
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
   if (en[2] - b[2] < en[s] - b[s]) s = 2;
   const int o1 = s == 0 ? 1 : 0, o2 = s == 2 ? 1 : 2;
   const uint64_t smask = subgroup_mask<G>();
-  const int64_t base = FILL ? a.off[t] : 0;
+  const int64_t base = FILL ? a.off[a.inv[t]] : 0;
   int64_t written = 0;
   for (int64_t j0 = b[s]; j0 < en[s]; j0 += G) {
     const int64_t j = j0 + sl;
@@ -169,9 +176,9 @@ __global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
     const uint64_t m = ballot(found) & smask;
     if (FILL && found) {
       const int64_t k = base + written + lanes_below(m);
-      a.out[3 * k] = tri_id(a, u, v, x);
-      a.out[3 * k + 1] = tri_id(a, u, w, x);
-      a.out[3 * k + 2] = tri_id(a, v, w, x);
+      a.out[3 * k] = a.inv[tri_id(a, u, v, x)];
+      a.out[3 * k + 1] = a.inv[tri_id(a, u, w, x)];
+      a.out[3 * k + 2] = a.inv[tri_id(a, v, w, x)];
     }
     written += __popcll(m);
   }
@@ -252,7 +259,7 @@ void edge_schedule(nd_graph *g, DArr<int32_t> &items, int64_t *bin_off,
   DArr<uint8_t> bin(al, ne);
   items.reset(al, ne);
   if (ne > 0) {
-    k_edge_bins<<<grid_for(ne, 256), 256, 0, s>>>(g->ks[ND_KTRUSS].rverts.p,
+    k_edge_bins<<<grid_for(ne, 256), 256, 0, s>>>(g->ev.p,
                                                    g->row_off.p, ne, bin.p);
     ND_LAUNCHED();
   }
@@ -261,7 +268,7 @@ void edge_schedule(nd_graph *g, DArr<int32_t> &items, int64_t *bin_off,
 
 EdgeIsectArgs edge_args(nd_graph *g) {
   EdgeIsectArgs a{};
-  a.ev = g->ks[ND_KTRUSS].rverts.p;
+  a.ev = g->ev.p;
   a.row_off = g->row_off.p;
   a.col = g->col.p;
   a.eid = g->eid.p;
@@ -281,16 +288,14 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   EdgeIsectArgs a = edge_args(g);
   a.count = cnt.p;
   run_edge_isect<kCountTruss>(a, items.p, bin_off, s);
-  ks.own_off.reset(al, ne + 1);
-  exclusive_scan_i32(cnt.p, ks.own_off.p, ne, s, al);
-  ks.P = read_i64(ks.own_off.p + ne, s);
-  ks.own_ids.reset(al, 2 * ks.P);
-  a.off = ks.own_off.p;
-  a.out_a = ks.own_ids.p;
-  run_edge_isect<kFillTruss>(a, items.p, bin_off, s);
   ks.nr = ne;
-  ks.inc_off = ks.own_off.p;
-  ks.inc_ids = ks.own_ids.p;
+  build_layout(g, ks, cnt.p, s);
+  cnt.free();
+  ks.inc_ids.reset(al, 2 * ks.P);
+  a.off = ks.inc_off.p;
+  a.inv = ks.inv.p;
+  a.out_a = ks.inc_ids.p;
+  run_edge_isect<kFillTruss>(a, items.p, bin_off, s);
 }
 
 void build_triangles(nd_graph *g, hipStream_t s) {
@@ -326,16 +331,17 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   DArr<uint8_t> bin(al, nt);
   DArr<int32_t> items(al, nt);
   if (nt > 0) {
-    k_tri_bins<<<grid_for(nt, 256), 256, 0, s>>>(g->ks[ND_KTRUSS].rverts.p,
-                                                  g->tri_e.p, g->tri_w.p,
-                                                  g->row_off.p, nt, bin.p);
+    k_tri_bins<<<grid_for(nt, 256), 256, 0, s>>>(g->ev.p, g->tri_e.p,
+                                                  g->tri_w.p, g->row_off.p, nt,
+                                                  bin.p);
     ND_LAUNCHED();
   }
   int64_t bin_off[kIsectBins + 1];
   partition_by_bin(bin.p, nt, kIsectBins, items.p, bin_off, s, al);
+  bin.free();
   DArr<int32_t> cnt(al, nt);
   TriIsectArgs a{};
-  a.ev = g->ks[ND_KTRUSS].rverts.p;
+  a.ev = g->ev.p;
   a.row_off = g->row_off.p;
   a.col = g->col.p;
   a.eid = g->eid.p;
@@ -344,16 +350,70 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   a.tri_e = g->tri_e.p;
   a.count = cnt.p;
   run_tri_isect<false>(a, items.p, bin_off, s);
-  ks.own_off.reset(al, nt + 1);
-  exclusive_scan_i32(cnt.p, ks.own_off.p, nt, s, al);
-  ks.P = read_i64(ks.own_off.p + nt, s);
-  ks.own_ids.reset(al, 3 * ks.P);
-  a.off = ks.own_off.p;
-  a.out = ks.own_ids.p;
-  run_tri_isect<true>(a, items.p, bin_off, s);
   ks.nr = nt;
-  ks.inc_off = ks.own_off.p;
-  ks.inc_ids = ks.own_ids.p;
+  build_layout(g, ks, cnt.p, s);
+  cnt.free();
+  ks.inc_ids.reset(al, 3 * ks.P);
+  a.off = ks.inc_off.p;
+  a.inv = ks.inv.p;
+  a.out = ks.inc_ids.p;
+  run_tri_isect<true>(a, items.p, bin_off, s);
+}
+
+// ------------------------------------------------------------- (1,2)
+
+namespace {
+
+__global__ void k_degree(const int64_t *__restrict__ row_off, int32_t n,
+                         int32_t *__restrict__ deg) {
+  int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < n) deg[u] = (int32_t)(row_off[u + 1] - row_off[u]);
+}
+
+// The neighbour list of vertex perm[i], re-indexed, at inc_off[i].
+template <int G>
+__global__ __launch_bounds__(256) void k_csr_fill(
+    const int64_t *__restrict__ row_off, const int32_t *__restrict__ col,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
+    const int64_t *__restrict__ off, int64_t lo, int64_t hi,
+    int32_t *__restrict__ out) {
+  const int64_t i = lo + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int sl = lane_id() % G;
+  if (i >= hi) return;
+  const int32_t u = perm[i];
+  const int64_t b = row_off[u], d = row_off[u + 1] - b, o = off[i];
+  for (int64_t j = sl; j < d; j += G) out[o + j] = inv[col[b + j]];
+}
+
+}  // namespace
+
+void build_incidence_core(nd_graph *g, KindState &ks, hipStream_t s) {
+  Allocator &al = g->ctx->alloc;
+  const int32_t n = g->n;
+  DArr<int32_t> deg(al, n);
+  if (n > 0) {
+    k_degree<<<grid_for(n, 256), 256, 0, s>>>(g->row_off.p, n, deg.p);
+    ND_LAUNCHED();
+  }
+  ks.nr = n;
+  build_layout(g, ks, deg.p, s);
+  deg.free();
+  ks.inc_ids.reset(al, ks.P);
+  // high-degree vertices first in the internal order: a wave each; the rest
+  // four lanes each
+  const int64_t split = ks.bin_hi[kBinG64];
+  if (split > 0) {
+    k_csr_fill<64><<<grid_for(split * 64, 256), 256, 0, s>>>(
+        g->row_off.p, g->col.p, ks.perm.p, ks.inv.p, ks.inc_off.p, 0, split,
+        ks.inc_ids.p);
+    ND_LAUNCHED();
+  }
+  if (n > split) {
+    k_csr_fill<4><<<grid_for((n - split) * 4, 256), 256, 0, s>>>(
+        g->row_off.p, g->col.p, ks.perm.p, ks.inv.p, ks.inc_off.p, split, n,
+        ks.inc_ids.p);
+    ND_LAUNCHED();
+  }
 }
 
 }  // namespace nd

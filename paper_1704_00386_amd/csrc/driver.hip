@@ -74,6 +74,8 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   r.n_rcliques = nr;
   r.n_incidence = ks.P;
   r.ms_prep = was_ready ? 0.0 : ks.ms_prep;
+  r.max_sdegree = ks.max_ds;
+  r.tau_bytes = ks.tau16 ? 2 : 4;
   ND_REQUIRE(kappa || nr == 0, ND_ERR_INVALID, "kappa is NULL");
   if (nr == 0) {
     r.converged = 1;
@@ -82,21 +84,25 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   }
   Allocator &al = g->ctx->alloc;
   const bool and_mode = opts.mode == ND_AND;
-  DArr<int32_t> tau0(al, nr), tau1;
-  ND_HIP(hipMemcpyAsync(tau0.p, ks.ds.p, sizeof(int32_t) * nr,
-                        hipMemcpyDeviceToDevice, s));
+  // tau in the internal numbering, uint16 when it fits (ks.tau16)
+  const int64_t tbytes = (ks.tau16 ? 2 : 4) * nr;
+  DArr<uint8_t> tau0(al, tbytes), tau1;
+  init_tau(ks, tau0.p, s);
   if (!and_mode) {
-    tau1.reset(al, nr);
-    ND_HIP(hipMemcpyAsync(tau1.p, ks.ds.p, sizeof(int32_t) * nr,
-                          hipMemcpyDeviceToDevice, s));
+    tau1.reset(al, tbytes);
+    ND_HIP(hipMemcpyAsync(tau1.p, tau0.p, tbytes, hipMemcpyDeviceToDevice, s));
   }
-  int32_t *buf[2] = {tau0.p, and_mode ? tau0.p : tau1.p};
+  void *buf[2] = {tau0.p, and_mode ? tau0.p : tau1.p};
+  DArr<int32_t> snap;  // callback view, r-clique-id order, int32
+  if (opts.on_iter) snap.reset(al, nr);
   DArr<SweepStats> ring(al, kStatsRing);
   if (!g->ctx->host_stats)
     ND_HIP(hipHostMalloc(&g->ctx->host_stats, sizeof(SweepStats) * kStatsRing,
                          hipHostMallocDefault));
   SweepStats *hst = (SweepStats *)g->ctx->host_stats;
 
+  // r-cliques whose h-index a sweep computes (d_s = 0 ones stay 0)
+  const int64_t evaluated = ks.bin_lo[kBinZero];
   const bool step_by_step = opts.on_iter != nullptr || opts.stop_active_ratio > 0;
   int chunk = step_by_step ? 1 : 2;
   int64_t t = 0;  // sweeps enqueued
@@ -118,9 +124,8 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
     const int64_t t0 = t;
     for (int i = 0; i < nb; i++, t++) {
       SweepArgs a{};
-      a.inc_off = ks.inc_off;
-      a.inc_ids = ks.inc_ids;
-      a.ds = ks.ds.p;
+      a.inc_off = ks.inc_off.p;
+      a.inc_ids = ks.inc_ids.p;
       a.tau_in = buf[t & 1];
       a.tau_out = buf[(t + 1) & 1];
       a.stats = ring.p + (t % kStatsRing);
@@ -145,12 +150,14 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
       sweeps = j + 1;
       const int64_t changed = (int64_t)st.changed;
       if (opts.on_iter) {
+        to_original(ks, buf[(j + 1) & 1], ks.tau16, snap.p, s);
+        ND_HIP(hipStreamSynchronize(s));
         nd_iter_info info{};
         info.iter = (int32_t)(j + 1);
-        info.evaluated = nr;
+        info.evaluated = evaluated;
         info.changed = changed;
-        info.active_next = nr;
-        info.tau_dev = buf[(j + 1) & 1];
+        info.active_next = evaluated;
+        info.tau_dev = snap.p;
         info.ms = one.ms();
         if (opts.on_iter(opts.user, &info)) stop_cb = true;
       }
@@ -172,11 +179,17 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   r.ms_iterate = total.ms();
   r.sweeps = (int32_t)sweeps;
   r.converged = converged ? 1 : 0;
-  r.updates = nr * sweeps;
-  const int32_t *result = buf[sweeps & 1];
-  ND_HIP(hipMemcpyAsync(kappa, result, sizeof(int32_t) * nr,
-                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                        s));
+  r.updates = evaluated * sweeps;
+  const void *result = buf[sweeps & 1];
+  if (on_device) {
+    to_original(ks, result, ks.tau16, kappa, s);
+  } else {
+    DArr<int32_t> out(al, nr);
+    to_original(ks, result, ks.tau16, out.p, s);
+    ND_HIP(hipMemcpyAsync(kappa, out.p, sizeof(int32_t) * nr,
+                          hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+  }
   ND_HIP(hipStreamSynchronize(s));
   if (res) *res = r;
   if (converged || stop_ratio) return ND_OK;

@@ -250,13 +250,11 @@ void build_edges(nd_graph *g, hipStream_t s) {
   ND_REQUIRE(g->ne < ((int64_t)1 << 31), ND_ERR_INVALID,
              "%lld edges: edge ids must fit int32", (long long)g->ne);
   g->eid.reset(al, g->nnz);
-  // the edge list doubles as the k-truss r-clique table
-  KindState &ks = g->ks[ND_KTRUSS];
-  ks.rverts.reset(al, 2 * g->ne);
+  g->ev.reset(al, 2 * g->ne);  // also the k-truss r-clique table
   if (g->nnz > 0) {
     k_eid<<<grid_for(g->nnz, 256), 256, 0, s>>>(
         g->row_off.p, g->col.p, g->rowid.p, g->nlow.p, g->eoff.p, g->nnz,
-        g->eid.p, ks.rverts.p);
+        g->eid.p, g->ev.p);
     ND_LAUNCHED();
   }
   g->edges_ready = true;

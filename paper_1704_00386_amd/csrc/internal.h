@@ -116,38 +116,38 @@ namespace nd {
 
 // ---------------------------------------------------------- sweep bins
 
-// r-cliques are swept in bins of similar S-degree; each bin has its own
-// lanes-per-r-clique mapping.  Bin boundaries (inclusive upper d_s bounds).
+// r-cliques are numbered internally by descending S-degree (ties by id), so
+// every sweep bin is a contiguous range of internal ids, hot tau values (those
+// gathered most often: a tau value is read once per s-clique it shares) sit
+// together at the front, and zero-degree r-cliques (never swept) sit at the
+// end.  Bins in internal order, with their d_s ranges:
 enum SweepBin : int {
-  kBinZero = 0,   // d_s = 0: tau stays 0, never swept
-  kBinG1,         // d_s <= 4:     one lane per r-clique
-  kBinG4,         // d_s <= 16:    4 lanes
-  kBinG16,        // d_s <= 64:    16 lanes
-  kBinG64,        // d_s <= 256:   one wave, values in registers
-  kBinWave,       // d_s <= 2047:  one wave, LDS histogram
-  kBinBlock,      // larger:       one workgroup, LDS histogram
+  kBinBlock = 0,  // d_s >= 2048:  one workgroup per r-clique, LDS histogram
+  kBinWave,       // 257..2047:    one wave, 32 values per lane in registers
+  kBinG64,        // 65..256:      one wave, 4 values per lane
+  kBinG16,        // 17..64:       16 lanes
+  kBinG4,         // 5..16:        4 lanes
+  kBinG1,         // 1..4:         one lane
+  kBinZero,       // 0:            tau stays 0
   kNumBins
 };
 
-int bin_of_degree_host(int64_t d);
-
-// Per-kind state of a graph: r-cliques, incidence lists, sweep schedule.
+// Per-kind state of a graph: internal numbering, incidence lists, schedule.
 struct KindState {
   bool ready = false;
   int r = 0, s = 0, k = 0;  // k = C(s,r) - 1
   int64_t nr = 0;           // |R|
   int64_t P = 0;            // sum_R d_s(R)
-  // incidence: for R, s-cliques inc_off[R] .. inc_off[R+1], ids
-  // inc_ids[k*j .. k*j+k) for each of them.
-  const int64_t *inc_off = nullptr;
-  const int32_t *inc_ids = nullptr;
-  DArr<int64_t> own_off;
-  DArr<int32_t> own_ids;
-  DArr<int32_t> ds;          // d_s(R), int32
-  DArr<int32_t> rverts;      // r-clique vertex tuples (r >= 2)
-  DArr<int32_t> bin_items;   // R ids grouped by sweep bin (ascending in bin)
-  int64_t bin_off[kNumBins + 1] = {0};
+  DArr<int32_t> perm;       // internal id -> r-clique id
+  DArr<int32_t> inv;        // r-clique id -> internal id
+  DArr<int32_t> ds;         // d_s, internal order
+  // incidence, internal order and ids: r-clique i owns the s-cliques
+  // inc_off[i] .. inc_off[i+1]; s-clique j lists inc_ids[k*j .. k*j+k)
+  DArr<int64_t> inc_off;
+  DArr<int32_t> inc_ids;
+  int64_t bin_lo[kNumBins] = {0}, bin_hi[kNumBins] = {0};
   int32_t max_ds = 0;
+  bool tau16 = false;       // tau fits uint16 (max d_s < 32768)
   double ms_prep = 0;
   size_t bytes() const;
 };
@@ -164,6 +164,7 @@ struct nd_graph {
   // edge numbering (r = 2): edges u<v lexicographic
   bool edges_ready = false;
   int64_t ne = 0;
+  nd::DArr<int32_t> ev;       // 2*ne: endpoints (u, v) of each edge
   nd::DArr<int32_t> nlow;     // n: neighbours below u
   nd::DArr<int64_t> eoff;     // n+1: first edge id of u
   nd::DArr<int32_t> eid;      // nnz: id of the edge of each entry
@@ -209,10 +210,25 @@ void validate_csr(nd_graph *g, hipStream_t s);
 void build_rowid(nd_graph *g, hipStream_t s);
 void build_edges(nd_graph *g, hipStream_t s);
 void build_triangles(nd_graph *g, hipStream_t s);
+// Incidence lists in the internal numbering (each calls build_layout once
+// the S-degrees are counted, then writes the lists in place).
+void build_incidence_core(nd_graph *g, KindState &ks, hipStream_t s);
 void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s);
 void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s);
-// d_s from offsets, bins and the bin schedule.
-void build_schedule(nd_graph *g, KindState &ks, hipStream_t s);
+// From S-degrees in r-clique-id order: perm, inv, ds, inc_off, bins.
+void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
+                  hipStream_t s);
+// Re-index between internal and r-clique-id order.
+void to_internal(const KindState &ks, const int32_t *in, void *out, bool out16,
+                 hipStream_t s);
+void to_original(const KindState &ks, const void *in, bool in16, int32_t *out,
+                 hipStream_t s);
+// Incidence lists in r-clique-id order with r-clique ids (off[nr+1]).
+void incidence_original(nd_graph *g, const KindState &ks, int64_t *off,
+                        int32_t *ids, hipStream_t s);
+void sdegree_original(const KindState &ks, int32_t *ds, hipStream_t s);
+// tau_0 = d_s in the internal numbering and tau type.
+void init_tau(const KindState &ks, void *tau, hipStream_t s);
 
 // ---------------------------------------------------------------- sweeps
 
@@ -226,15 +242,15 @@ struct SweepStats {
 struct SweepArgs {
   const int64_t *inc_off;
   const int32_t *inc_ids;
-  const int32_t *ds;
-  const int32_t *tau_in;   // SND: tau_t; AND: the in-place array
-  int32_t *tau_out;        // SND: tau_{t+1}; AND: same as tau_in
+  const void *tau_in;      // SND: tau_t; AND: the in-place array
+  void *tau_out;           // SND: tau_{t+1}; AND: same as tau_in
   SweepStats *stats;       // this sweep's counters
   const SweepStats *prev;  // previous sweep's counters (skip when converged)
   int cap_by_tau;          // 1: clamp at tau_in(R) (iterates); 0: at d_s
 };
 
-// Launch one sweep over every bin of ks.  `and_mode` selects in-place reads.
+// Launch one sweep over every bin of ks (internal numbering, tau of
+// ks.tau16 ? uint16 : int32).  `and_mode` selects in-place reads.
 void launch_sweep(const KindState &ks, const SweepArgs &a, bool and_mode,
                   hipStream_t s);
 

@@ -190,14 +190,27 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_bin_keys(const uint8_t *__restrict__ bin, int64_t n,
-                           uint64_t *__restrict__ keys,
-                           unsigned long long *__restrict__ counts) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    keys[i] = ((uint64_t)bin[i] << 32) | (uint64_t)i;
-    atomicAdd(&counts[bin[i]], 1ull);
+// Keys bin<<32 | i, and the bin sizes: counted per block in LDS first, so
+// that the global counters see one atomic per (block, bin) rather than one
+// per item (a handful of bins would otherwise serialise every thread).
+__global__ __launch_bounds__(256) void k_bin_keys(
+    const uint8_t *__restrict__ bin, int64_t n, int nbins,
+    uint64_t *__restrict__ keys, unsigned long long *__restrict__ counts) {
+  __shared__ unsigned int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * 256 * 8;
+  for (int j = 0; j < 8; j++) {
+    const int64_t i = base + j * 256 + threadIdx.x;
+    if (i < n) {
+      const uint8_t b = bin[i];
+      keys[i] = ((uint64_t)b << 32) | (uint64_t)i;
+      atomicAdd(&h[b], 1u);
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < nbins && h[threadIdx.x])
+    atomicAdd(&counts[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
 __global__ void k_low32(const uint64_t *__restrict__ keys, int64_t n,
@@ -250,7 +263,8 @@ void partition_by_bin(const uint8_t *bin, int64_t n, int nbins, int32_t *items,
   DArr<uint64_t> keys(al, n), tmp(al, n);
   DArr<unsigned long long> counts(al, nbins);
   ND_HIP(hipMemsetAsync(counts.p, 0, sizeof(unsigned long long) * nbins, s));
-  k_bin_keys<<<grid_for(n, 256), 256, 0, s>>>(bin, n, keys.p, counts.p);
+  k_bin_keys<<<grid_for(n, 256 * 8), 256, 0, s>>>(bin, n, nbins, keys.p,
+                                                   counts.p);
   ND_LAUNCHED();
   uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, n, 32, 40, s, al);
   k_low32<<<grid_for(n, 256), 256, 0, s>>>(sorted, n, items);

@@ -5,8 +5,11 @@
 //   tau'(R)   = H({rho(S,R)} over the d_s(R) s-cliques S containing R)
 //   changed  += (tau'(R) != tau(R))                         (convergence flag)
 //
-// The incidence list of R is k*d_s(R) consecutive int32 ids, so the id stream
-// is read once, coalesced; the tau reads are the random part.
+// r-cliques are in the internal numbering (descending d_s), so each bin is a
+// contiguous id range and the incidence lists are read in one sequential,
+// coalesced stream; the tau reads are the random part.  tau is stored as
+// uint16 when every d_s fits (then every tau does: tau <= d_s), halving the
+// bytes of the gathered array.
 //
 // H is computed exactly with a cap c (Section 4.4 "can the current value be
 // preserved" check, made exact):
@@ -14,19 +17,18 @@
 //     H(K) <= |K| = d_s(R), so with c = d_s(R) the cap never changes H.
 //   * For the iterates of SND/AND, U tau(R) <= tau(R) (Theorem 1, and the same
 //     argument for in-place sweeps, whose inputs only decrease), so c = tau(R)
-//     is exact there too and keeps the work and histograms small.
+//     is exact there too and keeps the work small.
 //   * If #{rho >= c} >= c then H = c (the preserve check).  Otherwise H is
-//     the largest x < c with #{rho >= x} >= x.
+//     the largest x < c with #{rho >= x} >= x, found by binary search on x
+//     with counts reduced across the lanes that hold the rho values.
 //
 // Mappings by S-degree bin:
-//   d_s <= 256   G = 1/4/16/64 lanes per r-clique, M = 4 rho values per lane
-//                in registers; H by binary search on x with subgroup sums.
-//   d_s <= 2047  one wave per r-clique; LDS histogram of min(rho, c) with
-//                c+1 bins, then a wave-parallel suffix search.
-//   larger       one 256-thread workgroup per r-clique; LDS histogram of up
-//                to 16384 bins; when c is larger, values are binned coarsely
-//                first and the one coarse bin holding H is refined with a
-//                second gather.
+//   d_s <= 256     G = 1/4/16/64 lanes per r-clique, 4 rho values per lane
+//   257..2047      one wave per r-clique, 32 rho values per lane
+//   >= 2048        one 256-thread workgroup per r-clique; LDS histogram of
+//                  min(rho, c) in up to 16384 bins; for larger c the values
+//                  are binned coarsely and the coarse bin holding H is refined
+//                  with a second gather.
 // SND reads tau_t and writes tau_{t+1} (double buffer, race free, so every
 // iterate is deterministic).  AND reads and writes one array in place; its
 // neighbour reads bypass the per-CU cache so that they see other workgroups'
@@ -35,46 +37,45 @@
 
 namespace nd {
 
-int bin_of_degree_host(int64_t d) {
-  if (d == 0) return kBinZero;
-  if (d <= 4) return kBinG1;
-  if (d <= 16) return kBinG4;
-  if (d <= 64) return kBinG16;
-  if (d <= 256) return kBinG64;
-  if (d <= 2047) return kBinWave;
-  return kBinBlock;
-}
-
 namespace {
 
-constexpr int kWaveHistBins = 2048;     // c + 1 <= 2048 in the wave bin
 constexpr int kBlockThreads = 256;
-constexpr int kBlockHistBins = 16384;   // 64 KiB of LDS
+constexpr int kBlockHistBins = 16384;  // 64 KiB of LDS
 
-template <bool AND>
-__device__ __forceinline__ int32_t load_tau(const int32_t *p) {
+template <typename T, bool AND>
+__device__ __forceinline__ int32_t load_tau(const T *p) {
   if constexpr (AND) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (int32_t)__hip_atomic_load(p, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
   } else {
-    return *p;
+    return (int32_t)*p;
+  }
+}
+
+template <typename T, bool AND>
+__device__ __forceinline__ void store_tau(T *p, int32_t h, bool changed) {
+  if constexpr (AND) {
+    if (changed)
+      __hip_atomic_store(p, (T)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = (T)h;
   }
 }
 
 // rho for the s-clique j of the incidence list (k = K ids per s-clique).
-template <int K, bool AND>
+template <int K, typename T, bool AND>
 __device__ __forceinline__ int32_t gather_rho(const int32_t *__restrict__ ids,
-                                              int64_t j,
-                                              const int32_t *tau) {
+                                              int64_t j, const T *tau) {
   if constexpr (K == 1) {
-    return load_tau<AND>(tau + ids[j]);
+    return load_tau<T, AND>(tau + ids[j]);
   } else if constexpr (K == 2) {
     const int2 p = *reinterpret_cast<const int2 *>(ids + 2 * j);
-    return min(load_tau<AND>(tau + p.x), load_tau<AND>(tau + p.y));
+    return min(load_tau<T, AND>(tau + p.x), load_tau<T, AND>(tau + p.y));
   } else {
     const int32_t *q = ids + 3 * j;
     const int32_t x = q[0], y = q[1], z = q[2];
-    return min(min(load_tau<AND>(tau + x), load_tau<AND>(tau + y)),
-               load_tau<AND>(tau + z));
+    return min(min(load_tau<T, AND>(tau + x), load_tau<T, AND>(tau + y)),
+               load_tau<T, AND>(tau + z));
   }
 }
 
@@ -94,68 +95,63 @@ __device__ __forceinline__ void count_changed(SweepStats *st, bool changed) {
   if (lane_id() == 0 && m) atomicAdd(&st->changed, (unsigned long long)__popcll(m));
 }
 
-template <bool AND>
-__device__ __forceinline__ void store_tau(int32_t *p, int32_t h, bool changed) {
-  if constexpr (AND) {
-    if (changed) __hip_atomic_store(p, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    *p = h;
+// Largest x in [0, c-1] with #{rho >= x} >= x, given that x = 0 satisfies it;
+// G lanes of a subgroup each hold M values (absent values are -1).
+template <int G, int M>
+__device__ __forceinline__ int32_t hindex_search(const int32_t (&rho)[M],
+                                                 int32_t c) {
+  int32_t lo = 0, hi = c - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    int cm = 0;
+#pragma unroll
+    for (int m = 0; m < M; m++) cm += rho[m] >= mid;
+    cm = subgroup_sum<G>(cm);
+    if (cm >= mid)
+      lo = mid;
+    else
+      hi = mid - 1;
   }
+  return lo;
 }
 
-// ------------------------------------------------- registers, G lanes per R
+// ------------------------------------------- registers, G lanes per R
 
-template <int K, int G, int M, bool AND>
-__global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a,
-                                                    const int32_t *__restrict__ items,
-                                                    int64_t nitems) {
+template <int K, int G, int M, typename T, bool AND>
+__global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
+                                                    int64_t hi) {
   if (converged_before(a.prev)) return;
-  const int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const T *tau_in = (const T *)a.tau_in;
+  T *tau_out = (T *)a.tau_out;
+  const int64_t R = lo + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sl = lane_id() % G;
-  const bool active = gsub < nitems;
-  int32_t R = 0, told = 0, c = 0;
+  const bool active = R < hi;
+  int32_t told = 0, c = 0;
   int64_t b = 0, d = 0;
   if (active) {
-    R = items[gsub];
     b = a.inc_off[R];
     d = a.inc_off[R + 1] - b;
-    told = a.tau_in[R];
+    told = (int32_t)tau_in[R];
     c = a.cap_by_tau ? told : (int32_t)d;
   }
   int32_t rho[M];
 #pragma unroll
   for (int m = 0; m < M; m++) {
     const int64_t j = sl + (int64_t)m * G;
-    rho[m] = (j < d) ? gather_rho<K, AND>(a.inc_ids, b + j, a.tau_in) : -1;
+    rho[m] = (j < d) ? gather_rho<K, T, AND>(a.inc_ids, b + j, tau_in) : -1;
   }
   int cnt = 0;
 #pragma unroll
   for (int m = 0; m < M; m++) cnt += rho[m] >= c;
   cnt = subgroup_sum<G>(cnt);
-  int32_t h = c;
-  if (cnt < c) {
-    // largest x in [0, c-1] with #{rho >= x} >= x (true at x = 0)
-    int32_t lo = 0, hi = c - 1;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi + 1) >> 1;
-      int cm = 0;
-#pragma unroll
-      for (int m = 0; m < M; m++) cm += rho[m] >= mid;
-      cm = subgroup_sum<G>(cm);
-      if (cm >= mid)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    h = lo;
-  }
+  const int32_t h = cnt >= c ? c : hindex_search<G, M>(rho, c);
   const bool lead = active && sl == 0;
   const bool changed = lead && h != told;
-  if (lead) store_tau<AND>(a.tau_out + R, h, changed);
+  if (lead) store_tau<T, AND>(tau_out + R, h, changed);
   count_changed(a.stats, changed);
 }
 
-// ------------------------------------------------------ histogram search
+// ------------------------------------------- workgroup per R (LDS)
 
 // Bins hist[0..nb) count values, bin i standing for the value x0 + i*scale.
 // Returns the largest i with base + sum_{i' >= i} hist[i'] >= x0 + i*scale,
@@ -173,8 +169,7 @@ __device__ int suffix_search(const int32_t *hist, int nb, int64_t base,
   part[t] = mine;
   if (t == 0) best_s = -1;
   __syncthreads();
-  // sum of the chunks above mine (NT <= 256: a plain loop over LDS)
-  int64_t above = base;
+  int64_t above = base;  // the chunks above mine
   for (int q = t + 1; q < NT; q++) above += part[q];
   int found = -1;
   int64_t run = above;
@@ -192,39 +187,6 @@ __device__ int suffix_search(const int32_t *hist, int nb, int64_t base,
   return r;
 }
 
-// ------------------------------------------------- one wave per R (LDS)
-
-template <int K, bool AND>
-__global__ __launch_bounds__(kWave) void k_sweep_wave(SweepArgs a,
-                                                      const int32_t *__restrict__ items,
-                                                      int64_t nitems) {
-  __shared__ int32_t hist[kWaveHistBins];
-  if (converged_before(a.prev)) return;
-  const int lane = threadIdx.x;
-  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int32_t R = items[it];
-    const int64_t b = a.inc_off[R];
-    const int64_t d = a.inc_off[R + 1] - b;
-    const int32_t told = a.tau_in[R];
-    const int32_t c = a.cap_by_tau ? told : (int32_t)d;  // c <= d < 2048
-    for (int x = lane; x <= c; x += kWave) hist[x] = 0;
-    __syncthreads();
-    for (int64_t j = lane; j < d; j += kWave) {
-      const int32_t rho = gather_rho<K, AND>(a.inc_ids, b + j, a.tau_in);
-      atomicAdd(&hist[min(rho, c)], 1);
-    }
-    __syncthreads();
-    int32_t h = c;
-    if (hist[c] < c) h = suffix_search<kWave>(hist, c + 1, 0, 0, 1);
-    const bool changed = lane == 0 && h != told;
-    if (lane == 0) store_tau<AND>(a.tau_out + R, h, changed);
-    count_changed(a.stats, changed);
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------- one workgroup per R (LDS)
-
 __device__ __forceinline__ int64_t block_sum(int64_t x) {
   __shared__ int64_t ws[kBlockThreads / kWave];
 #pragma unroll
@@ -238,18 +200,19 @@ __device__ __forceinline__ int64_t block_sum(int64_t x) {
   return s;
 }
 
-template <int K, bool AND>
+template <int K, typename T, bool AND>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
-                                                               const int32_t *__restrict__ items,
-                                                               int64_t nitems) {
+                                                               int64_t lo,
+                                                               int64_t hi) {
   __shared__ int32_t hist[kBlockHistBins];
   if (converged_before(a.prev)) return;
+  const T *tau_in = (const T *)a.tau_in;
+  T *tau_out = (T *)a.tau_out;
   const int t = threadIdx.x;
-  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int32_t R = items[it];
+  for (int64_t R = lo + blockIdx.x; R < hi; R += gridDim.x) {
     const int64_t b = a.inc_off[R];
     const int64_t d = a.inc_off[R + 1] - b;
-    const int32_t told = a.tau_in[R];
+    const int32_t told = (int32_t)tau_in[R];
     const int32_t c = a.cap_by_tau ? told : (int32_t)d;
     // bin width: 1 when c+1 bins fit, else coarse
     const int64_t w = ((int64_t)c + kBlockHistBins) / kBlockHistBins;
@@ -258,7 +221,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
     __syncthreads();
     int64_t ge = 0;
     for (int64_t j = t; j < d; j += kBlockThreads) {
-      const int32_t rho = gather_rho<K, AND>(a.inc_ids, b + j, a.tau_in);
+      const int32_t rho = gather_rho<K, T, AND>(a.inc_ids, b + j, tau_in);
       ge += rho >= c;
       atomicAdd(&hist[min(rho, c) / w], 1);
     }
@@ -278,7 +241,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
         __syncthreads();
         int64_t above = 0;
         for (int64_t j = t; j < d; j += kBlockThreads) {
-          const int32_t rho = min(gather_rho<K, AND>(a.inc_ids, b + j, a.tau_in), c);
+          const int32_t rho =
+              min(gather_rho<K, T, AND>(a.inc_ids, b + j, tau_in), c);
           if (rho >= x1)
             above++;
           else if (rho >= x0)
@@ -290,50 +254,69 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
       }
     }
     const bool changed = t == 0 && h != told;
-    if (t == 0) store_tau<AND>(a.tau_out + R, h, changed);
+    if (t == 0) store_tau<T, AND>(tau_out + R, h, changed);
     count_changed(a.stats, changed);
     __syncthreads();
   }
 }
 
-__global__ void k_zero_items(int32_t *__restrict__ tau,
-                             const int32_t *__restrict__ items, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) tau[items[i]] = 0;
+template <typename T>
+__global__ void k_zero_range(T *__restrict__ tau, int64_t lo, int64_t hi) {
+  const int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < hi) tau[i] = 0;
 }
 
-unsigned capped_grid(int64_t items, unsigned cap) {
-  return (unsigned)(items < (int64_t)cap ? (items < 1 ? 1 : items) : cap);
-}
-
-template <int K, bool AND>
+template <int K, typename T, bool AND>
 void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
-  for (int bin = kBinG1; bin < kNumBins; bin++) {
-    const int64_t n = ks.bin_off[bin + 1] - ks.bin_off[bin];
+  for (int bin = kBinBlock; bin < kBinZero; bin++) {
+    const int64_t lo = ks.bin_lo[bin], hi = ks.bin_hi[bin], n = hi - lo;
     if (n == 0) continue;
-    const int32_t *items = ks.bin_items.p + ks.bin_off[bin];
     switch (bin) {
       case kBinG1:
-        k_sweep_regs<K, 1, 4, AND><<<grid_for(n, 256), 256, 0, s>>>(a, items, n);
+        k_sweep_regs<K, 1, 4, T, AND><<<grid_for(n, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG4:
-        k_sweep_regs<K, 4, 4, AND><<<grid_for(n * 4, 256), 256, 0, s>>>(a, items, n);
+        k_sweep_regs<K, 4, 4, T, AND><<<grid_for(n * 4, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG16:
-        k_sweep_regs<K, 16, 4, AND><<<grid_for(n * 16, 256), 256, 0, s>>>(a, items, n);
+        k_sweep_regs<K, 16, 4, T, AND><<<grid_for(n * 16, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG64:
-        k_sweep_regs<K, 64, 4, AND><<<grid_for(n * 64, 256), 256, 0, s>>>(a, items, n);
+        k_sweep_regs<K, 64, 4, T, AND><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinWave:
-        k_sweep_wave<K, AND><<<capped_grid(n, 1u << 20), kWave, 0, s>>>(a, items, n);
+        k_sweep_regs<K, 64, 32, T, AND><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
         break;
-      default:
-        k_sweep_block<K, AND><<<capped_grid(n, 1u << 16), kBlockThreads, 0, s>>>(
-            a, items, n);
+      default: {
+        const unsigned grid = (unsigned)(n < 65536 ? n : 65536);
+        k_sweep_block<K, T, AND><<<grid, kBlockThreads, 0, s>>>(a, lo, hi);
         break;
+      }
     }
     ND_LAUNCHED();
+  }
+}
+
+template <typename T>
+void launch_typed(const KindState &ks, const SweepArgs &a, bool and_mode,
+                  hipStream_t s) {
+  if (!a.cap_by_tau) {
+    // plain U on an arbitrary tau: r-cliques in no s-clique get H({}) = 0
+    const int64_t lo = ks.bin_lo[kBinZero], hi = ks.bin_hi[kBinZero];
+    if (hi > lo) {
+      k_zero_range<T><<<grid_for(hi - lo, 256), 256, 0, s>>>((T *)a.tau_out, lo, hi);
+      ND_LAUNCHED();
+    }
+  }
+  switch (ks.k * 2 + (and_mode ? 1 : 0)) {
+    case 2: launch_bins<1, T, false>(ks, a, s); break;
+    case 3: launch_bins<1, T, true>(ks, a, s); break;
+    case 4: launch_bins<2, T, false>(ks, a, s); break;
+    case 5: launch_bins<2, T, true>(ks, a, s); break;
+    case 6: launch_bins<3, T, false>(ks, a, s); break;
+    case 7: launch_bins<3, T, true>(ks, a, s); break;
+    default:
+      ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "no sweep kernel for k=%d", ks.k);
   }
 }
 
@@ -341,24 +324,10 @@ void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
 
 void launch_sweep(const KindState &ks, const SweepArgs &a, bool and_mode,
                   hipStream_t s) {
-  if (!a.cap_by_tau) {
-    // plain U on an arbitrary tau: r-cliques in no s-clique get H({}) = 0
-    const int64_t n0 = ks.bin_off[kBinZero + 1] - ks.bin_off[kBinZero];
-    if (n0 > 0) {
-      k_zero_items<<<grid_for(n0, 256), 256, 0, s>>>(a.tau_out, ks.bin_items.p, n0);
-      ND_LAUNCHED();
-    }
-  }
-  switch (ks.k * 2 + (and_mode ? 1 : 0)) {
-    case 2: launch_bins<1, false>(ks, a, s); break;
-    case 3: launch_bins<1, true>(ks, a, s); break;
-    case 4: launch_bins<2, false>(ks, a, s); break;
-    case 5: launch_bins<2, true>(ks, a, s); break;
-    case 6: launch_bins<3, false>(ks, a, s); break;
-    case 7: launch_bins<3, true>(ks, a, s); break;
-    default:
-      ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "no sweep kernel for k=%d", ks.k);
-  }
+  if (ks.tau16)
+    launch_typed<uint16_t>(ks, a, and_mode, s);
+  else
+    launch_typed<int32_t>(ks, a, and_mode, s);
 }
 
 }  // namespace nd
