@@ -357,9 +357,11 @@ def batch_decompose(ctx: Context, graphs: Sequence[Graph], kind: str,
 
 
 class Server:
-    """Continuous-batching request loop (nd_server)."""
+    """Continuous-batching request loop (nd_server).  Submitted graphs are
+    owned by the server; results land in pinned host tensors."""
 
-    def __init__(self, ctx: Context, max_slots: int = 64, max_queue: int = 1 << 16):
+    def __init__(self, ctx: Context, max_slots: int = 64,
+                 max_queue: int = 1 << 16):
         h = _P()
         _check(_lib.nd_server_create(ctx._h, int(max_slots), int(max_queue),
                                      ctypes.byref(h)), "nd_server_create")
@@ -367,19 +369,22 @@ class Server:
         self.ctx = ctx
         self._bufs = {}
 
-    def submit(self, graph: Graph, kind: str, mode: str = "snd") -> int:
-        o, keep = _make_opts(mode)
+    def submit(self, graph: Graph, kind: str, mode: str = "snd",
+               max_iters: int = -1) -> int:
+        o, keep = _make_opts(mode, max_iters)
         n_r = _server_rcount(graph, kind)
-        buf = torch.empty(max(n_r, 1), dtype=torch.int32).pin_memory()
+        buf = torch.empty(max(n_r, 1), dtype=torch.int32, pin_memory=True)
         t = ctypes.c_uint64()
         _check(_lib.nd_server_submit(self._h, graph._h, KIND[kind],
                                      ctypes.byref(o), _P(buf.data_ptr()),
                                      ctypes.byref(t)), "nd_server_submit")
         graph.detach()
-        self._bufs[int(t.value)] = (buf[:n_r], keep)
+        self._bufs[int(t.value)] = buf[:n_r]
         return int(t.value)
 
     def wait(self, ticket: int, timeout_us: int = -1):
+        """(kappa, result dict, latency ms), or None on timeout.  Raises
+        NdError for a failed or cancelled request."""
         res = nd_result()
         lat = ctypes.c_double()
         st = _lib.nd_server_wait(self._h, ctypes.c_uint64(ticket),
@@ -387,7 +392,7 @@ class Server:
                                  ctypes.byref(lat))
         if st == 8:
             return None
-        buf, _ = self._bufs.pop(ticket)
+        buf = self._bufs.pop(ticket, None)
         _check(st, "nd_server_wait")
         return buf, res.as_dict(), float(lat.value)
 

@@ -41,11 +41,25 @@ Allocator::~Allocator() {
 
 void Allocator::trim_locked() {
   for (auto &kv : cache_) {
-    (void)hipStreamSynchronize(kv.second.s);
-    (void)hipFree(kv.second.p);
+    try {
+      if (!kv.second.idle) (void)hipStreamSynchronize(kv.second.s);
+      (void)hipFree(kv.second.p);
+    } catch (...) {
+      // runtime already torn down (process exit): leave the block
+    }
   }
   cache_.clear();
   cache_total_ = 0;
+}
+
+void Allocator::forget_stream(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(mu_);
+  (void)hipStreamSynchronize(s);
+  for (auto &kv : cache_)
+    if (kv.second.s == s) {
+      kv.second.idle = true;
+      kv.second.s = nullptr;
+    }
 }
 
 void Allocator::trim() {
@@ -68,8 +82,9 @@ void *Allocator::alloc(size_t bytes) {
   for (int pass = 0; pass < 2; pass++) {
     auto it = cache_.lower_bound(bytes);
     for (; it != cache_.end() && it->first <= 2 * bytes; ++it) {
-      if (pass == 0 && it->second.s != s) continue;
-      if (pass == 1 && it->second.s != s) {
+      const bool free_now = it->second.idle || it->second.s == s;
+      if (pass == 0 && !free_now) continue;
+      if (pass == 1 && !free_now) {
         ND_HIP(hipStreamSynchronize(it->second.s));
       }
       void *p = it->second.p;
@@ -110,7 +125,7 @@ void Allocator::release(void *p) {
   const size_t sz = it->second;
   live_.erase(it);
   live_total_ -= sz;
-  cache_.emplace(sz, Cached{p, current_stream()});
+  cache_.emplace(sz, Cached{p, current_stream(), false});
   cache_total_ += sz;
 }
 

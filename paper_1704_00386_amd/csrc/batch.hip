@@ -1,7 +1,616 @@
-// batch.hip -- several graphs swept together (placeholder until the batched
-// driver lands).
+// batch.hip -- many graphs swept together.
+//
+// Every graph of a batch keeps its own internal numbering, incidence lists,
+// tau buffers and per-sweep counters.  Their r-cliques are cut into tiles
+// (graph, bin, id range) that form one combined work list; one epoch is one
+// sweep of every graph still running, done by a persistent kernel whose
+// workgroups pull tiles from an atomic counter until the list is exhausted
+// (heaviest tiles first, so the tail of an epoch is short).  A graph whose
+// previous sweep changed nothing is skipped tile by tile and dropped from the
+// table at the next poll; graphs may join at any epoch (the server uses
+// this), each counting its own sweeps from the epoch it joined.  All launch
+// arguments are fixed device pointers and grid sizes -- the epoch number and
+// table sizes live in device memory -- so a chunk of epochs is captured once
+// in a HIP graph and replayed until the table outgrows its buffers.
+//
+// Tile and grid sizes come from a small autotuner: the first batch of a given
+// shape times one sweep under each candidate on scratch state, keeps the
+// fastest, and caches it by (kind, mode, tau width, work bucket).
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <tuple>
+#include <vector>
+
 #include "api_util.h"
-#include "internal.h"
+#include "batch.h"
+#include "sweep_dev.h"
+
+namespace nd {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kHubGrid = 256;
+constexpr int kBeginGrid = 64;
+
+// R's one 256-thread block pass covers, per bin type.
+__host__ __device__ constexpr int rclq_per_pass(int type) {
+  return type == kBinG1 ? 256 : type == kBinG4 ? 64 : type == kBinG16 ? 16 : 4;
+}
+
+__device__ __forceinline__ bool graph_live(const BGraph &G, int64_t e,
+                                           int64_t *local) {
+  *local = e - G.t0;
+  if (*local < 0 || *local >= G.max_local) return false;
+  return *local == 0 || G.ring[(*local - 1) % kBatchRing].changed != 0;
+}
+
+template <int K, typename T, bool AND>
+__global__ __launch_bounds__(256) void k_batch_sweep(
+    const BGraph *__restrict__ gs, const BTile *__restrict__ tiles,
+    BState *__restrict__ st) {
+  __shared__ int s_tile;
+  const int64_t e = st->epoch;
+  const int ntiles = st->ntiles;
+  unsigned int *counter = &st->counters[e % kCounterRing];
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int ti = s_tile;
+    __syncthreads();
+    if (ti >= ntiles) break;
+    const BTile tile = tiles[ti];
+    const BGraph &G = gs[tile.g];
+    int64_t local;
+    if (!graph_live(G, e, &local)) continue;
+    const T *in = (const T *)G.tau[local & 1];
+    T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
+    SweepStats *sst = &G.ring[local % kBatchRing];
+    const int per = rclq_per_pass(tile.type);
+    for (int64_t base = tile.lo; base < tile.hi; base += per) {
+      bool ch = false;
+      switch (tile.type) {
+        case kBinG1: {
+          const int64_t R = base + threadIdx.x;
+          ch = update_regs<K, 1, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                            R < tile.hi);
+          break;
+        }
+        case kBinG4: {
+          const int64_t R = base + threadIdx.x / 4;
+          ch = update_regs<K, 4, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                            R < tile.hi);
+          break;
+        }
+        case kBinG16: {
+          const int64_t R = base + threadIdx.x / 16;
+          ch = update_regs<K, 16, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
+                                             R, R < tile.hi);
+          break;
+        }
+        case kBinG64: {
+          const int64_t R = base + threadIdx.x / 64;
+          ch = update_regs<K, 64, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
+                                             R, R < tile.hi);
+          break;
+        }
+        default: {  // kBinWave
+          const int64_t R = base + threadIdx.x / 64;
+          ch = update_regs<K, 64, 32, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
+                                              R, R < tile.hi);
+          break;
+        }
+      }
+      count_changed(sst, ch);
+    }
+  }
+}
+
+// r-cliques with d_s >= 2048: one workgroup each, grid-stride over the list.
+template <int K, typename T, bool AND>
+__global__ __launch_bounds__(kBlockThreads) void k_batch_hubs(
+    const BGraph *__restrict__ gs, const BHub *__restrict__ hubs,
+    const BState *__restrict__ st) {
+  __shared__ int32_t hist[kBlockHistBins];
+  const int64_t e = st->epoch;
+  const int nhubs = st->nhubs;
+  for (int i = blockIdx.x; i < nhubs; i += gridDim.x) {
+    const BHub hb = hubs[i];
+    const BGraph &G = gs[hb.g];
+    int64_t local;
+    if (!graph_live(G, e, &local)) continue;
+    const T *in = (const T *)G.tau[local & 1];
+    T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
+    const bool ch = update_block<K, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
+                                            hb.R, hist);
+    count_changed(&G.ring[local % kBatchRing], ch);
+  }
+}
+
+// Before an epoch: clear its tile counter and each live graph's counters.
+__global__ void k_epoch_begin(const BGraph *__restrict__ gs,
+                              BState *__restrict__ st) {
+  const int64_t e = st->epoch;
+  const int ng = st->ng;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) st->counters[e % kCounterRing] = 0;
+  for (int i = i0; i < ng; i += gridDim.x * blockDim.x) {
+    const int64_t local = e - gs[i].t0;
+    if (local >= 0 && local < gs[i].max_local) {
+      SweepStats &z = gs[i].ring[local % kBatchRing];
+      z.changed = 0;
+      z.evaluated = 0;
+      z.active_next = 0;
+      z.pad = 0;
+    }
+  }
+}
+
+__global__ void k_epoch_end(BState *__restrict__ st) { st->epoch += 1; }
+
+// Changed-counters of the last `n` epochs (ending before `e_end`), one row
+// of kPollMax per graph; ~0 marks a sweep the graph did not run.
+__global__ void k_collect(const BGraph *__restrict__ gs, int ng, int64_t e_end,
+                          int n, unsigned long long *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  for (int q = 0; q < n; q++) {
+    const int64_t local = e_end - n + q - gs[i].t0;
+    unsigned long long v = ~0ull;
+    if (local >= 0 && local < gs[i].max_local)
+      v = gs[i].ring[local % kBatchRing].changed;
+    out[(int64_t)i * kPollMax + q] = v;
+  }
+}
+
+struct TuneKey {
+  int kind, mode, t16, bucket;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(kind, mode, t16, bucket) <
+           std::tie(o.kind, o.mode, o.t16, o.bucket);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, BatchConfig> g_tune_cache;
+
+int work_bucket(int64_t P) {
+  int b = 0;
+  while (P > 1) {
+    P >>= 1;
+    b++;
+  }
+  return b;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ Batch
+
+Batch::Batch(nd_ctx *ctx, nd_kind kind, nd_mode mode, bool tau16,
+             hipStream_t caller)
+    : ctx_(ctx), kind_(kind), mode_(mode), tau16_(tau16) {
+  cfg_ = default_config(ctx);
+  if (const char *v = getenv("ND_BATCH_NO_GRAPH")) use_graph = v[0] != '1';
+  ND_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+  hipEvent_t ev;
+  ND_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  ND_HIP(hipEventRecord(ev, caller));
+  ND_HIP(hipStreamWaitEvent(s_, ev, 0));
+  (void)hipEventDestroy(ev);
+  StreamScope scope(s_);
+  state_.reset(ctx->alloc, 1);
+  BState z{};
+  ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
+  ND_HIP(hipStreamSynchronize(s_));
+}
+
+Batch::~Batch() {
+  (void)hipStreamSynchronize(s_);
+  drop_graph();
+  {
+    StreamScope scope(s_);
+    members_.clear();
+    gs_.free();
+    tiles_.free();
+    hubs_.free();
+    state_.free();
+    poll_buf_.free();
+  }
+  ctx_->alloc.forget_stream(s_);
+  (void)hipStreamDestroy(s_);
+}
+
+void Batch::drop_graph() {
+  if (graph_exec_) {
+    (void)hipGraphExecDestroy(graph_exec_);
+    graph_exec_ = nullptr;
+  }
+}
+
+BatchConfig Batch::default_config(nd_ctx *ctx) {
+  BatchConfig c;
+  c.grid = ctx->num_cu * 8;
+  c.tile_passes = 1;
+  return c;
+}
+
+Member *Batch::add(nd_graph *g, int32_t max_iters, void *user) {
+  StreamScope scope(s_);
+  KindState &ks = g->ks[kind_];
+  ND_REQUIRE(ks.ready, ND_ERR_INVALID, "graph not prepared for the batch");
+  ND_REQUIRE(ks.tau16 || !tau16_, ND_ERR_INVALID,
+             "a 16-bit batch cannot hold a graph needing 32-bit tau");
+  auto m = std::make_unique<Member>();
+  m->g = g;
+  m->user = user;
+  m->t0 = epoch_;
+  const int64_t cap = ks.nr + 1;  // Lemma 2: enough to observe convergence
+  m->max_local = (max_iters < 0 || max_iters > cap) ? cap : max_iters;
+  const int64_t tb = (tau16_ ? 2 : 4) * std::max<int64_t>(ks.nr, 1);
+  m->tau0.reset(ctx_->alloc, tb);
+  if (mode_ == ND_SND) m->tau1.reset(ctx_->alloc, tb);
+  m->ring.reset(ctx_->alloc, kBatchRing);
+  init_member_tau(*m);
+  if (ks.nr == 0 || m->max_local == 0) {
+    m->finished = true;
+    m->converged = ks.nr == 0;
+  }
+  Member *raw = m.get();
+  members_.push_back(std::move(m));
+  dirty_ = true;
+  return raw;
+}
+
+void Batch::init_member_tau(Member &m) {
+  const KindState &ks = m.g->ks[kind_];
+  if (ks.nr == 0) return;
+  if (tau16_)
+    init_tau(ks, m.tau0.p, s_);  // ks.tau16 holds (checked in add)
+  else
+    ND_HIP(hipMemcpyAsync(m.tau0.p, ks.ds.p, sizeof(int32_t) * ks.nr,
+                          hipMemcpyDeviceToDevice, s_));
+  if (mode_ == ND_SND)
+    ND_HIP(hipMemcpyAsync(m.tau1.p, m.tau0.p, (tau16_ ? 2 : 4) * ks.nr,
+                          hipMemcpyDeviceToDevice, s_));
+}
+
+std::vector<std::unique_ptr<Member>> Batch::take_finished() {
+  std::vector<std::unique_ptr<Member>> out;
+  std::vector<std::unique_ptr<Member>> keep;
+  for (auto &m : members_)
+    (m->finished ? out : keep).push_back(std::move(m));
+  members_ = std::move(keep);
+  if (!out.empty()) dirty_ = true;
+  return out;
+}
+
+void Batch::rebuild() {
+  StreamScope scope(s_);
+  std::vector<BGraph> hg;
+  std::vector<BTile> ht[kBinZero];  // per bin type; heaviest bins first
+  std::vector<BHub> hh;
+  int64_t work = 0;
+  for (auto &mp : members_) {
+    Member &m = *mp;
+    m.slot = -1;
+    m.ntiles = 0;
+    if (m.finished) continue;
+    const KindState &ks = m.g->ks[kind_];
+    const int32_t gi = (int32_t)hg.size();
+    m.slot = gi;
+    BGraph G{};
+    G.inc_off = ks.inc_off.p;
+    G.inc_ids = ks.inc_ids.p;
+    G.tau[0] = m.tau0.p;
+    G.tau[1] = mode_ == ND_SND ? m.tau1.p : m.tau0.p;
+    G.ring = m.ring.p;
+    G.t0 = m.t0;
+    G.max_local = m.max_local;
+    hg.push_back(G);
+    work += ks.P;
+    for (int64_t R = ks.bin_lo[kBinBlock]; R < ks.bin_hi[kBinBlock]; R++)
+      hh.push_back(BHub{gi, 0, R});
+    for (int b = kBinWave; b < kBinZero; b++) {
+      const int64_t lo = ks.bin_lo[b], hi = ks.bin_hi[b];
+      const int64_t step = (int64_t)rclq_per_pass(b) * cfg_.tile_passes;
+      for (int64_t x = lo; x < hi; x += step) {
+        ht[b].push_back(BTile{gi, b, x, std::min(hi, x + step)});
+        m.ntiles++;
+      }
+    }
+  }
+  std::vector<BTile> all;
+  for (int b = kBinWave; b < kBinZero; b++)
+    all.insert(all.end(), ht[b].begin(), ht[b].end());
+  ntiles_ = (int)all.size();
+  nhubs_ = (int)hh.size();
+  ng_ = (int)hg.size();
+  work_ = work;
+  dead_tiles_ = 0;
+  // Grow device tables (capacity doubles); a new buffer invalidates the
+  // captured graph, whose kernels hold the table pointers.
+  auto ensure = [&](auto &arr, int64_t need, int64_t &cap) {
+    need = std::max<int64_t>(need, 1);
+    if (need > cap) {
+      cap = std::max<int64_t>(need, 2 * cap);
+      arr.reset(ctx_->alloc, cap);
+      drop_graph();
+    }
+  };
+  ensure(gs_, (int64_t)hg.size(), gs_cap_);
+  ensure(tiles_, (int64_t)all.size(), tiles_cap_);
+  ensure(hubs_, (int64_t)hh.size(), hubs_cap_);
+  ensure(poll_buf_, (int64_t)hg.size() * kPollMax, poll_cap_);
+  if (!hg.empty())
+    ND_HIP(hipMemcpyAsync(gs_.p, hg.data(), sizeof(BGraph) * hg.size(),
+                          hipMemcpyHostToDevice, s_));
+  if (!all.empty())
+    ND_HIP(hipMemcpyAsync(tiles_.p, all.data(), sizeof(BTile) * all.size(),
+                          hipMemcpyHostToDevice, s_));
+  if (!hh.empty())
+    ND_HIP(hipMemcpyAsync(hubs_.p, hh.data(), sizeof(BHub) * hh.size(),
+                          hipMemcpyHostToDevice, s_));
+  int32_t counts[3] = {ntiles_, nhubs_, ng_};
+  ND_HIP(hipMemcpyAsync(&state_.p->ntiles, counts, sizeof counts,
+                        hipMemcpyHostToDevice, s_));
+  ND_HIP(hipStreamSynchronize(s_));  // the host vectors go out of scope
+  dirty_ = false;
+}
+
+template <int K, typename T, bool AND>
+void Batch::launch_epoch_t() {
+  k_epoch_begin<<<kBeginGrid, 256, 0, s_>>>(gs_.p, state_.p);
+  ND_LAUNCHED();
+  k_batch_sweep<K, T, AND><<<cfg_.grid, 256, 0, s_>>>(gs_.p, tiles_.p,
+                                                       state_.p);
+  ND_LAUNCHED();
+  k_batch_hubs<K, T, AND><<<kHubGrid, kBlockThreads, 0, s_>>>(gs_.p, hubs_.p,
+                                                              state_.p);
+  ND_LAUNCHED();
+  k_epoch_end<<<1, 1, 0, s_>>>(state_.p);
+  ND_LAUNCHED();
+}
+
+void Batch::launch_epoch() {
+  const int key = (kind_ == ND_KCORE ? 1 : kind_ == ND_KTRUSS ? 2 : 3) * 4 +
+                  (tau16_ ? 2 : 0) + (mode_ == ND_AND ? 1 : 0);
+  switch (key) {
+    case 4: launch_epoch_t<1, int32_t, false>(); break;
+    case 5: launch_epoch_t<1, int32_t, true>(); break;
+    case 6: launch_epoch_t<1, uint16_t, false>(); break;
+    case 7: launch_epoch_t<1, uint16_t, true>(); break;
+    case 8: launch_epoch_t<2, int32_t, false>(); break;
+    case 9: launch_epoch_t<2, int32_t, true>(); break;
+    case 10: launch_epoch_t<2, uint16_t, false>(); break;
+    case 11: launch_epoch_t<2, uint16_t, true>(); break;
+    case 12: launch_epoch_t<3, int32_t, false>(); break;
+    case 13: launch_epoch_t<3, int32_t, true>(); break;
+    case 14: launch_epoch_t<3, uint16_t, false>(); break;
+    default: launch_epoch_t<3, uint16_t, true>(); break;
+  }
+}
+
+void Batch::run_epochs(int count) {
+  if (dirty_) rebuild();
+  if (ng_ == 0) return;
+  if (use_graph && count == kGraphEpochs) {
+    if (!graph_exec_) {
+      hipGraph_t gr;
+      ND_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < kGraphEpochs; i++) launch_epoch();
+      ND_HIP(hipStreamEndCapture(s_, &gr));
+      ND_HIP(hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(gr);
+    }
+    ND_HIP(hipGraphLaunch(graph_exec_, s_));
+  } else {
+    for (int i = 0; i < count; i++) launch_epoch();
+  }
+  epoch_ += count;
+}
+
+void Batch::poll(int epochs_run) {
+  if (ng_ == 0 || epochs_run <= 0) return;
+  ND_REQUIRE(epochs_run <= kPollMax, ND_ERR_INVALID, "poll window too large");
+  k_collect<<<grid_for(ng_, 256), 256, 0, s_>>>(gs_.p, ng_, epoch_, epochs_run,
+                                                 poll_buf_.p);
+  ND_LAUNCHED();
+  std::vector<unsigned long long> h((size_t)ng_ * kPollMax);
+  ND_HIP(hipMemcpyAsync(h.data(), poll_buf_.p, sizeof(unsigned long long) * h.size(),
+                        hipMemcpyDeviceToHost, s_));
+  ND_HIP(hipStreamSynchronize(s_));
+  for (auto &mp : members_) {
+    Member &m = *mp;
+    if (m.finished || m.slot < 0) continue;
+    for (int q = 0; q < epochs_run && !m.finished; q++) {
+      const int64_t local = epoch_ - epochs_run + q - m.t0;
+      const unsigned long long v = h[(size_t)m.slot * kPollMax + q];
+      if (local < 0 || local >= m.max_local || v == ~0ull) continue;
+      m.sweeps = local + 1;
+      if (v == 0) {
+        m.converged = true;
+        m.finished = true;
+      }
+    }
+    if (!m.finished && m.sweeps >= m.max_local) m.finished = true;
+    if (m.finished) dead_tiles_ += m.ntiles;
+  }
+  // drop finished graphs' tiles once they are a quarter of the table
+  if (dead_tiles_ * 4 > ntiles_ && dead_tiles_ > 0) dirty_ = true;
+}
+
+const void *Batch::result_tau(const Member &m) const {
+  if (mode_ == ND_AND) return m.tau0.p;
+  return (m.sweeps & 1) ? m.tau1.p : m.tau0.p;
+}
+
+void Batch::set_config(const BatchConfig &c) {
+  if (c.grid != cfg_.grid || c.tile_passes != cfg_.tile_passes) {
+    cfg_ = c;
+    dirty_ = true;
+    drop_graph();
+  }
+}
+
+// Time one sweep of every member under each candidate, then restore tau_0 and
+// the epoch (the trial sweeps write only buffers that are re-initialised).
+void Batch::autotune() {
+  StreamScope scope(s_);
+  if (dirty_) rebuild();
+  if (ng_ == 0) return;
+  TuneKey key{(int)kind_, (int)mode_, tau16_ ? 1 : 0, work_bucket(work_)};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      set_config(it->second);
+      return;
+    }
+  }
+  const int cus = ctx_->num_cu;
+  std::vector<BatchConfig> cand;
+  for (int gm : {4, 8, 16})
+    for (int tp : {1, 4}) {
+      BatchConfig c;
+      c.grid = cus * gm;
+      c.tile_passes = tp;
+      cand.push_back(c);
+    }
+  hipEvent_t a, b;
+  ND_HIP(hipEventCreate(&a));
+  ND_HIP(hipEventCreate(&b));
+  float best = 1e30f;
+  BatchConfig best_cfg = cfg_;
+  const int64_t e0 = epoch_;
+  for (const BatchConfig &c : cand) {
+    set_config(c);
+    rebuild();
+    BState z{};
+    z.epoch = e0;
+    z.ntiles = ntiles_;
+    z.nhubs = nhubs_;
+    z.ng = ng_;
+    ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
+    ND_HIP(hipEventRecord(a, s_));
+    launch_epoch();
+    ND_HIP(hipEventRecord(b, s_));
+    ND_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    ND_HIP(hipEventElapsedTime(&ms, a, b));
+    if (ms < best) {
+      best = ms;
+      best_cfg = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  for (auto &mp : members_) init_member_tau(*mp);
+  set_config(best_cfg);
+  rebuild();
+  BState z{};
+  z.epoch = e0;
+  z.ntiles = ntiles_;
+  z.nhubs = nhubs_;
+  z.ng = ng_;
+  ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
+  ND_HIP(hipStreamSynchronize(s_));
+  tuned_ms = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best_cfg;
+}
+
+// ------------------------------------------------------- batch ABI
+
+nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
+                          nd_kind kind, const nd_opts *opts_in,
+                          int32_t *const *kappas, int on_device, hipStream_t s,
+                          nd_result *res) {
+  nd_opts opts;
+  nd_opts_init(&opts);
+  if (opts_in) opts = *opts_in;
+  ND_REQUIRE(opts.mode == ND_SND || opts.mode == ND_AND, ND_ERR_INVALID,
+             "unknown mode");
+  ND_REQUIRE(!opts.use_frontier && opts.on_iter == nullptr &&
+                 opts.stop_active_ratio == 0,
+             ND_ERR_UNSUPPORTED,
+             "batched decomposition supports mode and max_iters only");
+  bool all16 = true;
+  std::vector<double> prep(count, 0.0);
+  for (int i = 0; i < count; i++) {
+    ND_REQUIRE(graphs[i] && graphs[i]->ctx == ctx, ND_ERR_INVALID,
+               "graph %d is NULL or from another context", i);
+    const bool was = graphs[i]->ks[kind].ready;
+    prepare(graphs[i], kind, s);
+    prep[i] = was ? 0.0 : graphs[i]->ks[kind].ms_prep;
+    all16 &= graphs[i]->ks[kind].tau16;
+  }
+  Batch batch(ctx, kind, opts.mode, all16, s);
+  hipStream_t bs = batch.stream();
+  std::vector<Member *> ms;
+  for (int i = 0; i < count; i++)
+    ms.push_back(batch.add(graphs[i], opts.max_iters, nullptr));
+  batch.autotune();
+  hipEvent_t a, b;
+  ND_HIP(hipEventCreate(&a));
+  ND_HIP(hipEventCreate(&b));
+  ND_HIP(hipEventRecord(a, bs));
+  int chunk = 2;
+  for (;;) {
+    bool any = false;
+    for (Member *m : ms) any |= !m->finished;
+    if (!any) break;
+    batch.run_epochs(chunk);
+    batch.poll(chunk);
+    chunk = std::min(chunk * 2, Batch::kGraphEpochs);
+  }
+  ND_HIP(hipEventRecord(b, bs));
+  ND_HIP(hipEventSynchronize(b));
+  float ms_total = 0;
+  ND_HIP(hipEventElapsedTime(&ms_total, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  nd_status out = ND_OK;
+  StreamScope scope(bs);
+  for (int i = 0; i < count; i++) {
+    Member &m = *ms[i];
+    const KindState &ks = graphs[i]->ks[kind];
+    if (ks.nr > 0) {
+      ND_REQUIRE(kappas && kappas[i], ND_ERR_INVALID, "kappas[%d] is NULL", i);
+      if (on_device) {
+        to_original(ks, batch.result_tau(m), batch.tau16(), kappas[i], bs);
+      } else {
+        DArr<int32_t> tmp(ctx->alloc, ks.nr);
+        to_original(ks, batch.result_tau(m), batch.tau16(), tmp.p, bs);
+        ND_HIP(hipMemcpyAsync(kappas[i], tmp.p, sizeof(int32_t) * ks.nr,
+                              hipMemcpyDeviceToHost, bs));
+        ND_HIP(hipStreamSynchronize(bs));
+      }
+    }
+    if (res) {
+      nd_result &r = res[i];
+      memset(&r, 0, sizeof r);
+      r.sweeps = (int32_t)m.sweeps;
+      r.converged = m.converged ? 1 : 0;
+      r.n_rcliques = ks.nr;
+      r.n_incidence = ks.P;
+      r.updates = ks.bin_lo[kBinZero] * m.sweeps;
+      r.ms_prep = prep[i];
+      r.ms_iterate = ms_total;  // shared by the whole batch
+      r.max_sdegree = ks.max_ds;
+      r.tau_bytes = batch.tau16() ? 2 : 4;
+    }
+    if (!m.converged) out = ND_ERR_NOT_CONVERGED;
+  }
+  ND_HIP(hipStreamSynchronize(bs));
+  if (out != ND_OK) set_error("a graph of the batch stopped without converging");
+  return out;
+}
+
+}  // namespace nd
 
 using namespace nd;
 
@@ -10,8 +619,18 @@ extern "C" nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
                                         const nd_opts *opts,
                                         int32_t *const *kappas, int on_device,
                                         void *stream, nd_result *res) {
-  (void)ctx; (void)count; (void)graphs; (void)kind; (void)opts; (void)kappas;
-  (void)on_device; (void)stream; (void)res;
-  set_error("nd_batch_decompose: not available in this build");
-  return ND_ERR_UNSUPPORTED;
+  nd_status out = ND_OK;
+  nd_status st = guarded([&] {
+    ND_REQUIRE(ctx, ND_ERR_INVALID, "ctx is NULL");
+    ND_REQUIRE(count >= 0 && (count == 0 || graphs), ND_ERR_INVALID,
+               "bad graph list");
+    ND_REQUIRE(kind == ND_KCORE || kind == ND_KTRUSS || kind == ND_NUCLEUS34,
+               ND_ERR_UNSUPPORTED, "unknown kind");
+    ND_HIP(hipSetDevice(ctx->device));
+    StreamScope scope((hipStream_t)stream);
+    if (count == 0) return;
+    out = batch_decompose(ctx, count, graphs, kind, opts, kappas, on_device,
+                          (hipStream_t)stream, res);
+  });
+  return st != ND_OK ? st : out;
 }

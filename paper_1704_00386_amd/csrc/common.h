@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <exception>
 #include <string>
 
 #include "../../include/nd.h"
@@ -23,9 +24,18 @@ struct Err {
   explicit Err(nd_status c) : code(c) {}
 };
 
+// A HIP runtime call; failures (and C++ exceptions escaping the runtime)
+// become an Err naming the call site.
 #define ND_HIP(call)                                                        \
   do {                                                                      \
-    hipError_t e_ = (call);                                                 \
+    hipError_t e_;                                                          \
+    try {                                                                   \
+      e_ = (call);                                                          \
+    } catch (const std::exception &x_) {                                    \
+      ::nd::set_error("%s threw at %s:%d: %s", #call, __FILE__, __LINE__,  \
+                      x_.what());                                           \
+      throw ::nd::Err(ND_ERR_DEVICE);                                       \
+    }                                                                       \
     if (e_ != hipSuccess) {                                                 \
       ::nd::set_error("%s failed at %s:%d: %s", #call, __FILE__, __LINE__, \
                       hipGetErrorString(e_));                               \

@@ -37,6 +37,9 @@ class Allocator {
   void *alloc(size_t bytes);  // throws Err(ND_ERR_OOM)
   void release(void *p);      // back to the cache, tagged current_stream()
   void trim();                // return cached blocks to the device
+  // Before destroying stream s: wait for it and mark its cached blocks free
+  // for any stream (no handle of a destroyed stream is ever used again).
+  void forget_stream(hipStream_t s);
   size_t live_bytes() const;
   size_t cached_bytes() const;
   size_t budget() const { return budget_; }
@@ -46,6 +49,7 @@ class Allocator {
   struct Cached {
     void *p;
     hipStream_t s;
+    bool idle;  // no pending work may touch it: reusable without a wait
   };
   void trim_locked();
   int device_;

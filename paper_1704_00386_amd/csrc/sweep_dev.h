@@ -1,0 +1,222 @@
+// sweep_dev.h -- device routines of one h-index update, shared by the
+// single-graph sweep kernels (sweep.hip) and the batched persistent kernel
+// (batch.hip).  See sweep.hip for the method and the exactness argument.
+#pragma once
+
+#include "internal.h"
+
+namespace nd {
+namespace dev {
+
+constexpr int kBlockThreads = 256;
+constexpr int kBlockHistBins = 16384;  // 64 KiB of LDS
+
+template <typename T, bool AND>
+__device__ __forceinline__ int32_t load_tau(const T *p) {
+  if constexpr (AND) {
+    return (int32_t)__hip_atomic_load(p, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    return (int32_t)*p;
+  }
+}
+
+template <typename T, bool AND>
+__device__ __forceinline__ void store_tau(T *p, int32_t h, bool changed) {
+  if constexpr (AND) {
+    if (changed)
+      __hip_atomic_store(p, (T)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = (T)h;
+  }
+}
+
+// rho for the s-clique j of the incidence list (k = K ids per s-clique).
+template <int K, typename T, bool AND>
+__device__ __forceinline__ int32_t gather_rho(const int32_t *__restrict__ ids,
+                                              int64_t j, const T *tau) {
+  if constexpr (K == 1) {
+    return load_tau<T, AND>(tau + ids[j]);
+  } else if constexpr (K == 2) {
+    const int2 p = *reinterpret_cast<const int2 *>(ids + 2 * j);
+    return min(load_tau<T, AND>(tau + p.x), load_tau<T, AND>(tau + p.y));
+  } else {
+    const int32_t *q = ids + 3 * j;
+    const int32_t x = q[0], y = q[1], z = q[2];
+    return min(min(load_tau<T, AND>(tau + x), load_tau<T, AND>(tau + y)),
+               load_tau<T, AND>(tau + z));
+  }
+}
+
+template <int G>
+__device__ __forceinline__ int subgroup_sum(int x) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
+  return x;
+}
+
+__device__ __forceinline__ void count_changed(SweepStats *st, bool changed) {
+  const uint64_t m = ballot(changed);
+  if (lane_id() == 0 && m) atomicAdd(&st->changed, (unsigned long long)__popcll(m));
+}
+
+// Largest x in [0, c-1] with #{rho >= x} >= x, given that x = 0 satisfies it;
+// G lanes of a subgroup each hold M values (absent values are -1).
+template <int G, int M>
+__device__ __forceinline__ int32_t hindex_search(const int32_t (&rho)[M],
+                                                 int32_t c) {
+  int32_t lo = 0, hi = c - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    int cm = 0;
+#pragma unroll
+    for (int m = 0; m < M; m++) cm += rho[m] >= mid;
+    cm = subgroup_sum<G>(cm);
+    if (cm >= mid)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// One r-clique per subgroup of G lanes (sl = lane within the subgroup), each
+// lane holding M gathered values: d_s(R) <= G*M.  `active` false for a
+// subgroup with no r-clique.  Returns whether R changed (true on the
+// subgroup's first lane only).
+template <int K, int G, int M, typename T, bool AND>
+__device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
+                                            const int32_t *__restrict__ inc_ids,
+                                            const T *tau_in, T *tau_out,
+                                            int cap_by_tau, int64_t R,
+                                            bool active) {
+  const int sl = lane_id() % G;
+  int32_t told = 0, c = 0;
+  int64_t b = 0, d = 0;
+  if (active) {
+    b = inc_off[R];
+    d = inc_off[R + 1] - b;
+    told = (int32_t)tau_in[R];
+    c = cap_by_tau ? told : (int32_t)d;
+  }
+  int32_t rho[M];
+#pragma unroll
+  for (int m = 0; m < M; m++) {
+    const int64_t j = sl + (int64_t)m * G;
+    rho[m] = (j < d) ? gather_rho<K, T, AND>(inc_ids, b + j, tau_in) : -1;
+  }
+  int cnt = 0;
+#pragma unroll
+  for (int m = 0; m < M; m++) cnt += rho[m] >= c;
+  cnt = subgroup_sum<G>(cnt);
+  const int32_t h = cnt >= c ? c : hindex_search<G, M>(rho, c);
+  const bool lead = active && sl == 0;
+  const bool changed = lead && h != told;
+  if (lead) store_tau<T, AND>(tau_out + R, h, changed);
+  return changed;
+}
+
+// Bins hist[0..nb) count values, bin i standing for the value x0 + i*scale.
+// Returns the largest i with base + sum_{i' >= i} hist[i'] >= x0 + i*scale,
+// or -1 if there is none.  All NT threads of the block call it.
+template <int NT>
+__device__ int suffix_search(const int32_t *hist, int nb, int64_t base,
+                             int64_t x0, int64_t scale) {
+  __shared__ int64_t part[NT];
+  __shared__ int best_s;
+  const int t = threadIdx.x;
+  const int chunk = (nb + NT - 1) / NT;
+  const int lo = min(nb, t * chunk), hi = min(nb, lo + chunk);
+  int64_t mine = 0;
+  for (int i = lo; i < hi; i++) mine += hist[i];
+  part[t] = mine;
+  if (t == 0) best_s = -1;
+  __syncthreads();
+  int64_t above = base;  // the chunks above mine
+  for (int q = t + 1; q < NT; q++) above += part[q];
+  int found = -1;
+  int64_t run = above;
+  for (int i = hi - 1; i >= lo; i--) {
+    run += hist[i];
+    if (run >= x0 + (int64_t)i * scale) {
+      found = i;
+      break;
+    }
+  }
+  if (found >= 0) atomicMax(&best_s, found);
+  __syncthreads();
+  const int r = best_s;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int64_t block_sum(int64_t x) {
+  __shared__ int64_t ws[kBlockThreads / kWave];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  if (lane_id() == 0) ws[threadIdx.x / kWave] = x;
+  __syncthreads();
+  int64_t s = 0;
+#pragma unroll
+  for (int w = 0; w < kBlockThreads / kWave; w++) s += ws[w];
+  __syncthreads();
+  return s;
+}
+
+// One r-clique per 256-thread workgroup, any d_s: LDS histogram of
+// min(rho, c) in up to kBlockHistBins bins; for larger c values are binned
+// coarsely and the coarse bin holding H is refined with a second gather.
+// Returns whether R changed (thread 0 only).
+template <int K, typename T, bool AND>
+__device__ bool update_block(const int64_t *__restrict__ inc_off,
+                             const int32_t *__restrict__ inc_ids,
+                             const T *tau_in, T *tau_out, int cap_by_tau,
+                             int64_t R, int32_t *hist) {
+  const int t = threadIdx.x;
+  const int64_t b = inc_off[R];
+  const int64_t d = inc_off[R + 1] - b;
+  const int32_t told = (int32_t)tau_in[R];
+  const int32_t c = cap_by_tau ? told : (int32_t)d;
+  const int64_t w = ((int64_t)c + kBlockHistBins) / kBlockHistBins;
+  const int nb = (int)(((int64_t)c + w) / w);  // bins for values 0..c
+  for (int x = t; x < nb; x += kBlockThreads) hist[x] = 0;
+  __syncthreads();
+  int64_t ge = 0;
+  for (int64_t j = t; j < d; j += kBlockThreads) {
+    const int32_t rho = gather_rho<K, T, AND>(inc_ids, b + j, tau_in);
+    ge += rho >= c;
+    atomicAdd(&hist[min(rho, c) / w], 1);
+  }
+  ge = block_sum(ge);
+  int32_t h = c;
+  if (ge < c) {
+    const int i = suffix_search<kBlockThreads>(hist, nb, 0, 0, w);
+    if (w == 1) {
+      h = i;
+    } else {
+      const int64_t x0 = (int64_t)i * w;
+      const int64_t x1 = min(x0 + w, (int64_t)c + 1);  // exclusive
+      const int nfine = (int)(x1 - x0);
+      for (int x = t; x < nfine; x += kBlockThreads) hist[x] = 0;
+      __syncthreads();
+      int64_t above = 0;
+      for (int64_t j = t; j < d; j += kBlockThreads) {
+        const int32_t rho = min(gather_rho<K, T, AND>(inc_ids, b + j, tau_in), c);
+        if (rho >= x1)
+          above++;
+        else if (rho >= x0)
+          atomicAdd(&hist[rho - x0], 1);
+      }
+      above = block_sum(above);
+      const int f = suffix_search<kBlockThreads>(hist, nfine, above, x0, 1);
+      h = (int32_t)(x0 + f);
+    }
+  }
+  const bool changed = t == 0 && h != told;
+  if (t == 0) store_tau<T, AND>(tau_out + R, h, changed);
+  __syncthreads();
+  return changed;
+}
+
+}  // namespace dev
+}  // namespace nd

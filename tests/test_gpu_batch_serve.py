@@ -1,0 +1,166 @@
+"""Batched and served decomposition: every result equals the graph's lone
+nd_decompose result and the oracle, whatever else shares the launches."""
+
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import chung_lu, erdos_renyi, sbm
+
+pytestmark = pytest.mark.gpu
+
+KINDS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4)}
+
+
+@pytest.fixture(scope="module")
+def ctx(nd):
+    return nd.Context(0)
+
+
+def mixed_graphs():
+    out = [
+        erdos_renyi(600, 0.02, seed=31),
+        chung_lu(3000, 2.1, 12.0, seed=32),
+        chung_lu(800, 2.4, 8.0, seed=33),
+        sbm(n_comm=20, size_lo=10, size_hi=30, p_in=0.35, p_out=0.004, seed=34),
+        chung_lu(20000, 2.2, 16.0, seed=35),
+    ]
+    # a graph with an edge in 3000 triangles and a triangle in 3000 4-cliques
+    pairs = [(0, 1), (0, 2), (1, 2)] + [(x, 3 + i) for i in range(3000)
+                                        for x in (0, 1, 2)]
+    src = np.array([a for a, b in pairs], np.int32)
+    dst = np.array([b for a, b in pairs], np.int32)
+    from synth import RawGraph
+    out.append(RawGraph(3003, src, dst, "book"))
+    out.append(RawGraph(5, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty"))
+    return out
+
+
+def make(nd, ctx, raw):
+    return nd.Graph.from_edges(ctx, raw.n, torch.from_numpy(raw.src),
+                               torch.from_numpy(raw.dst))
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
+@pytest.mark.parametrize("mode", ["snd", "and"])
+def test_batch_equals_solo_and_oracle(nd, ctx, kind, mode):
+    raws = mixed_graphs()
+    r, s = KINDS[kind]
+    gs = [make(nd, ctx, raw) for raw in raws]
+    solo = [g.decompose(kind, mode) for g in gs]
+    kappas, results = nd.batch_decompose(ctx, gs, kind, mode)
+    for raw, (ks, rs), kb, rb in zip(raws, solo, kappas, results):
+        assert torch.equal(kb, ks), raw.name
+        assert rb["converged"] == 1
+        if mode == "snd":
+            assert rb["sweeps"] == rs["sweeps"], raw.name
+        want = oracle.Graph.from_raw(raw).peel(r, s)
+        assert np.array_equal(kb.cpu().numpy(), want), raw.name
+
+
+def test_batch_replays_with_eager_work_between(nd, ctx):
+    """Repeated batches (the epoch loop replays a captured HIP graph) with
+    eager decompositions and synchronisations in between: every replay
+    matches the eager result."""
+    raws = [chung_lu(2000 + 500 * i, 2.2, 10.0, seed=50 + i) for i in range(12)]
+    gs = [make(nd, ctx, raw) for raw in raws]
+    eager = [g.decompose("truss", "snd")[0] for g in gs]
+    for rep in range(4):
+        kappas, results = nd.batch_decompose(ctx, gs, "truss", "snd")
+        torch.cuda.synchronize()
+        for e, k in zip(eager, kappas):
+            assert torch.equal(e, k), rep
+        # eager work between replays
+        again = gs[rep].decompose("truss", "and")[0]
+        assert torch.equal(again, eager[rep])
+        torch.cuda.synchronize()
+
+
+def test_batch_many_small_graphs(nd, ctx):
+    raws = [chung_lu(int(n), 2.0 + 0.05 * (i % 10), 8.0 + i % 20, seed=100 + i)
+            for i, n in enumerate(np.linspace(200, 4000, 64))]
+    gs = [make(nd, ctx, raw) for raw in raws]
+    kappas, results = nd.batch_decompose(ctx, gs, "core", "snd")
+    for raw, g, k in zip(raws, gs, kappas):
+        assert torch.equal(k, g.decompose("core", "snd")[0]), raw.name
+
+
+def test_batch_max_iters(nd, ctx):
+    raw = chung_lu(4096, 2.1, 16.0, seed=7)
+    og = oracle.Graph.from_raw(raw)
+    seq = og.snd(2, 3)
+    g = make(nd, ctx, raw)
+    with pytest.raises(nd.NdError) as e:
+        nd.batch_decompose(ctx, [g], "truss", "snd", max_iters=2)
+    assert e.value.name == "not_converged"
+
+
+# -------------------------------------------------------------- serving
+
+
+def test_server_results_equal_solo(nd, ctx):
+    raws = mixed_graphs() + [chung_lu(int(n), 2.3, 10.0, seed=200 + i)
+                             for i, n in enumerate(np.linspace(500, 30000, 20))]
+    kinds = ["truss", "core", "truss", "nucleus34", "core", "truss", "core"]
+    kinds += ["truss" if i % 2 else "core" for i in range(20)]
+    modes = ["snd" if i % 3 else "and" for i in range(len(raws))]
+    solo = [make(nd, ctx, raw).decompose(k, m)[0].cpu()
+            for raw, k, m in zip(raws, kinds, modes)]
+    srv = nd.Server(ctx, max_slots=8)
+    tickets = []
+    for raw, k, m in zip(raws, kinds, modes):
+        tickets.append(srv.submit(make(nd, ctx, raw), k, m))
+        time.sleep(0.002)  # staggered arrivals: later ones join a running mix
+    lats = []
+    for t, want in zip(tickets, solo):
+        kappa, res, lat = srv.wait(t)
+        assert torch.equal(kappa, want)
+        assert res["converged"] == 1
+        lats.append(lat)
+    assert all(l > 0 for l in lats)
+    srv.close()
+
+
+def test_server_budget_admission_and_oom(nd):
+    # a budget that holds about one graph at a time: requests wait for memory
+    ctx = nd.Context(0, hbm_budget_bytes=96 << 20)
+    raws = [chung_lu(30000, 2.2, 16.0, seed=300 + i) for i in range(6)]
+    solo_ctx = nd.Context(0)
+    solo = [make(nd, solo_ctx, raw).decompose("truss")[0].cpu() for raw in raws]
+    srv = nd.Server(ctx, max_slots=4)
+    ts = [srv.submit(make(nd, ctx, raw), "truss") for raw in raws]
+    for t, want in zip(ts, solo):
+        kappa, res, lat = srv.wait(t)
+        assert torch.equal(kappa, want)
+    # a graph too large for the whole budget fails with OOM, alone
+    big = chung_lu(300000, 2.1, 32.0, seed=399)
+    try:
+        g = make(nd, ctx, big)
+    except nd.NdError as e:
+        assert e.name == "oom"
+    else:
+        t = srv.submit(g, "truss")
+        with pytest.raises(nd.NdError) as e:
+            srv.wait(t)
+        assert e.value.name == "oom"
+    srv.close()
+
+
+def test_server_cancel_and_busy(nd, ctx):
+    srv = nd.Server(ctx, max_slots=1, max_queue=3)
+    raws = [chung_lu(20000, 2.1, 24.0, seed=400 + i) for i in range(3)]
+    ts = [srv.submit(make(nd, ctx, raw), "truss") for raw in raws]
+    with pytest.raises(nd.NdError) as e:
+        for i in range(4):
+            srv.submit(make(nd, ctx, raws[0]), "truss")
+    assert e.value.name == "busy"
+    srv.cancel(ts[2])
+    got = srv.wait(ts[0])
+    assert got is not None
+    with pytest.raises(nd.NdError) as e:
+        srv.wait(ts[2])
+    assert e.value.name == "cancelled"
+    srv.close()
