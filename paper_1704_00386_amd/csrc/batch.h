@@ -9,7 +9,7 @@
 
 namespace nd {
 
-constexpr int kBatchRing = 64;    // per-graph sweep counters kept
+constexpr int kBatchRing = 32;    // per-graph sweep counters kept
 constexpr int kCounterRing = 64;  // tile counters, one per epoch slot
 constexpr int kPollMax = 16;      // epochs between host polls, at most
 

@@ -46,7 +46,7 @@ __device__ __forceinline__ bool graph_live(const BGraph &G, int64_t e,
                                            int64_t *local) {
   *local = e - G.t0;
   if (*local < 0 || *local >= G.max_local) return false;
-  return *local == 0 || G.ring[(*local - 1) % kBatchRing].changed != 0;
+  return *local == 0 || changed_sum(&G.ring[(*local - 1) % kBatchRing]) != 0;
 }
 
 template <int K, typename T, bool AND>
@@ -72,40 +72,40 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
     SweepStats *sst = &G.ring[local % kBatchRing];
     const int per = rclq_per_pass(tile.type);
     for (int64_t base = tile.lo; base < tile.hi; base += per) {
-      bool ch = false;
+      bool ch = false, ev = false;
       switch (tile.type) {
         case kBinG1: {
           const int64_t R = base + threadIdx.x;
-          ch = update_regs<K, 1, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                            R < tile.hi);
+          ch = update_regs<K, 1, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                            R < tile.hi, nullptr, nullptr, &ev);
           break;
         }
         case kBinG4: {
           const int64_t R = base + threadIdx.x / 4;
-          ch = update_regs<K, 4, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                            R < tile.hi);
+          ch = update_regs<K, 4, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                            R < tile.hi, nullptr, nullptr, &ev);
           break;
         }
         case kBinG16: {
           const int64_t R = base + threadIdx.x / 16;
-          ch = update_regs<K, 16, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
-                                             R, R < tile.hi);
+          ch = update_regs<K, 16, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1,
+                                             R, R < tile.hi, nullptr, nullptr, &ev);
           break;
         }
         case kBinG64: {
           const int64_t R = base + threadIdx.x / 64;
-          ch = update_regs<K, 64, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
-                                             R, R < tile.hi);
+          ch = update_regs<K, 64, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1,
+                                             R, R < tile.hi, nullptr, nullptr, &ev);
           break;
         }
         default: {  // kBinWave
           const int64_t R = base + threadIdx.x / 64;
-          ch = update_regs<K, 64, 32, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
-                                              R, R < tile.hi);
+          ch = update_regs<K, 64, 32, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1,
+                                              R, R < tile.hi, nullptr, nullptr, &ev);
           break;
         }
       }
-      count_changed(sst, ch);
+      stat_add(sst, ch, ev);
     }
   }
 }
@@ -125,9 +125,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch_hubs(
     if (!graph_live(G, e, &local)) continue;
     const T *in = (const T *)G.tau[local & 1];
     T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
-    const bool ch = update_block<K, T, AND>(G.inc_off, G.inc_ids, in, out, 1,
-                                            hb.R, hist);
-    count_changed(&G.ring[local % kBatchRing], ch);
+    bool ev;
+    const bool ch = update_block<K, T, AND, false>(G.inc_off, G.inc_ids, in,
+                                                   out, 1, hb.R, hist, nullptr,
+                                                   nullptr, &ev);
+    stat_add(&G.ring[local % kBatchRing], ch, ev);
   }
 }
 
@@ -142,10 +144,11 @@ __global__ void k_epoch_begin(const BGraph *__restrict__ gs,
     const int64_t local = e - gs[i].t0;
     if (local >= 0 && local < gs[i].max_local) {
       SweepStats &z = gs[i].ring[local % kBatchRing];
-      z.changed = 0;
-      z.evaluated = 0;
-      z.active_next = 0;
-      z.pad = 0;
+      for (int q = 0; q < kStatParts; q++) {
+        z.part[q].changed = 0;
+        z.part[q].evaluated = 0;
+      }
+      z.notified = 0;
     }
   }
 }
@@ -162,7 +165,7 @@ __global__ void k_collect(const BGraph *__restrict__ gs, int ng, int64_t e_end,
     const int64_t local = e_end - n + q - gs[i].t0;
     unsigned long long v = ~0ull;
     if (local >= 0 && local < gs[i].max_local)
-      v = gs[i].ring[local % kBatchRing].changed;
+      v = gs[i].ring[local % kBatchRing].changed_total();
     out[(int64_t)i * kPollMax + q] = v;
   }
 }

@@ -7,6 +7,7 @@
 // at once when it is zero, so sweeps queued past convergence cost only their
 // launch.  For SND the two buffers then hold identical values, so the result
 // is the same whichever was written last.
+#include <stdlib.h>
 #include <string.h>
 
 #include <vector>
@@ -21,14 +22,14 @@ namespace {
 constexpr int kStatsRing = 1024;  // device counters kept per decomposition
 constexpr int kMaxChunk = 16;     // sweeps enqueued per host round trip
 
+// Zero the counters of sweeps first .. first+count-1 (a kernel, not a
+// memset, so that the sequence stays capturable).
 __global__ void k_zero_stats(SweepStats *ring, int64_t first, int count) {
-  int i = threadIdx.x;
-  if (i < count) {
-    SweepStats &z = ring[(first + i) % kStatsRing];
-    z.changed = 0;
-    z.evaluated = 0;
-    z.active_next = 0;
-    z.pad = 0;
+  constexpr int W = sizeof(SweepStats) / sizeof(unsigned long long);
+  for (int i = threadIdx.x; i < count * W; i += blockDim.x) {
+    unsigned long long *z =
+        reinterpret_cast<unsigned long long *>(&ring[(first + i / W) % kStatsRing]);
+    z[i % W] = 0;
   }
 }
 
@@ -64,8 +65,6 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
              "unknown mode %d", (int)opts.mode);
   ND_REQUIRE(opts.stop_active_ratio >= 0 && opts.stop_active_ratio <= 1,
              ND_ERR_INVALID, "stop_active_ratio must be in [0,1]");
-  ND_REQUIRE(!opts.use_frontier, ND_ERR_UNSUPPORTED,
-             "frontier sweeps are not available in this build");
   const bool was_ready = g->ks[kind].ready;
   prepare(g, kind, s);
   const KindState &ks = g->ks[kind];
@@ -95,6 +94,20 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   void *buf[2] = {tau0.p, and_mode ? tau0.p : tau1.p};
   DArr<int32_t> snap;  // callback view, r-clique-id order, int32
   if (opts.on_iter) snap.reset(al, nr);
+  // frontier flags (Section 4.3): act[t & 1] selects the r-cliques of sweep
+  // t; every r-clique takes part in the first sweep
+  DArr<uint8_t> act[2];
+  const bool frontier = opts.use_frontier != 0;
+  // notifications start once a sweep changes at most 1/32 of the swept
+  // r-cliques (ND_FRONTIER_SWITCH overrides the divisor; 0 = from the start)
+  unsigned long long notify_below = 0;
+  if (frontier) {
+    act[0].reset(al, nr);
+    act[1].reset(al, nr);
+    int div = 32;
+    if (const char *v = getenv("ND_FRONTIER_SWITCH")) div = atoi(v);
+    notify_below = div <= 0 ? ~0ull : (unsigned long long)(ks.bin_lo[kBinZero] / div);
+  }
   DArr<SweepStats> ring(al, kStatsRing);
   if (!g->ctx->host_stats)
     ND_HIP(hipHostMalloc(&g->ctx->host_stats, sizeof(SweepStats) * kStatsRing,
@@ -106,7 +119,7 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   const bool step_by_step = opts.on_iter != nullptr || opts.stop_active_ratio > 0;
   int chunk = step_by_step ? 1 : 2;
   int64_t t = 0;  // sweeps enqueued
-  int64_t sweeps = 0;
+  int64_t sweeps = 0, updates = 0;
   bool converged = false, stop_ratio = false, stop_cb = false;
   Timer total, one;
   total.start(s);
@@ -119,7 +132,7 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
     if (t >= opts.max_iters) break;
     int nb = chunk;
     if (t + nb > opts.max_iters) nb = (int)(opts.max_iters - t);
-    k_zero_stats<<<1, kMaxChunk, 0, s>>>(ring.p, t, nb);
+    k_zero_stats<<<1, 256, 0, s>>>(ring.p, t, nb);
     ND_LAUNCHED();
     const int64_t t0 = t;
     for (int i = 0; i < nb; i++, t++) {
@@ -131,6 +144,12 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
       a.stats = ring.p + (t % kStatsRing);
       a.prev = t > 0 ? ring.p + ((t - 1) % kStatsRing) : nullptr;
       a.cap_by_tau = 1;
+      if (frontier) {
+        a.act = act[t & 1].p;
+        a.act_next = act[(t + 1) & 1].p;
+        a.notify_below = notify_below;
+        fill_u8(act[(t + 1) & 1].p, 0, nr, s);
+      }
       if (step_by_step) one.start(s);
       launch_sweep(ks, a, and_mode, s);
       if (step_by_step) one.stop(s);
@@ -148,13 +167,15 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
     for (int64_t j = t0; j < t0 + nb && !done; j++) {
       const SweepStats &st = hst[j % kStatsRing];
       sweeps = j + 1;
-      const int64_t changed = (int64_t)st.changed;
+      const int64_t changed = (int64_t)st.changed_total();
+      const int64_t evald = (int64_t)st.evaluated_total();
+      updates += evald;
       if (opts.on_iter) {
         to_original(ks, buf[(j + 1) & 1], ks.tau16, snap.p, s);
         ND_HIP(hipStreamSynchronize(s));
         nd_iter_info info{};
         info.iter = (int32_t)(j + 1);
-        info.evaluated = evaluated;
+        info.evaluated = evald;
         info.changed = changed;
         info.active_next = evaluated;
         info.tau_dev = snap.p;
@@ -179,7 +200,7 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   r.ms_iterate = total.ms();
   r.sweeps = (int32_t)sweeps;
   r.converged = converged ? 1 : 0;
-  r.updates = evaluated * sweeps;
+  r.updates = updates;
   const void *result = buf[sweeps & 1];
   if (on_device) {
     to_original(ks, result, ks.tau16, kappa, s);

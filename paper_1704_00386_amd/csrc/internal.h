@@ -202,6 +202,7 @@ void partition_by_bin(const uint8_t *bin, int64_t n, int nbins, int32_t *items,
                       int64_t *offsets, hipStream_t s, Allocator &al);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 int64_t read_i64(const int64_t *dev, hipStream_t s);  // synchronous
 
 // ------------------------------------------------------------ graph prep
@@ -236,11 +237,30 @@ void init_tau(const KindState &ks, void *tau, hipStream_t s);
 
 // ---------------------------------------------------------------- sweeps
 
-struct SweepStats {
+// Per-sweep counters.  Every wave adds its counts atomically; with one
+// counter all those atomics would queue on a single L2 channel, so the counts
+// are split over kStatParts parts, one 128-byte line each, and summed by the
+// reader.
+constexpr int kStatParts = 16;
+struct alignas(128) StatPart {
   unsigned long long changed;
   unsigned long long evaluated;
-  unsigned long long active_next;
-  unsigned long long pad;
+  unsigned long long pad[14];
+};
+struct SweepStats {
+  StatPart part[kStatParts];
+  unsigned long long notified;  // 1: this sweep set the next sweep's flags
+  unsigned long long pad[15];
+  __host__ __device__ unsigned long long changed_total() const {
+    unsigned long long s = 0;
+    for (int i = 0; i < kStatParts; i++) s += part[i].changed;
+    return s;
+  }
+  __host__ __device__ unsigned long long evaluated_total() const {
+    unsigned long long s = 0;
+    for (int i = 0; i < kStatParts; i++) s += part[i].evaluated;
+    return s;
+  }
 };
 
 struct SweepArgs {
@@ -251,6 +271,16 @@ struct SweepArgs {
   SweepStats *stats;       // this sweep's counters
   const SweepStats *prev;  // previous sweep's counters (skip when converged)
   int cap_by_tau;          // 1: clamp at tau_in(R) (iterates); 0: at d_s
+  // Frontier (Section 4.3 notifications), both NULL when off: only
+  // r-cliques with act[R] != 0 are recomputed; a changed one sets act_next
+  // for every neighbour whose value is above its new value.
+  const uint8_t *act;
+  uint8_t *act_next;
+  // Notifications start once a sweep changes at most this many r-cliques
+  // (before that nearly everything is active and notifying costs as much as
+  // the gathers it would save); from then on every sweep notifies and the
+  // next one recomputes only flagged r-cliques.
+  unsigned long long notify_below;
 };
 
 // Launch one sweep over every bin of ks (internal numbering, tau of

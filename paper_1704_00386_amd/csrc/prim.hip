@@ -185,6 +185,17 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_u8(uint8_t *p, uint8_t v, int64_t n) {
+  // four bytes per thread where aligned
+  int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i + 3 < n && ((uintptr_t)(p + i) & 3) == 0) {
+    const uint32_t w = 0x01010101u * v;
+    *reinterpret_cast<uint32_t *>(p + i) = w;
+  } else {
+    for (int64_t j = i; j < i + 4 && j < n; j++) p[j] = v;
+  }
+}
+
 __global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -279,6 +290,12 @@ void partition_by_bin(const uint8_t *bin, int64_t n, int nbins, int32_t *items,
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+  ND_LAUNCHED();
+}
+
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill_u8<<<grid_for(ceil_div(n, 4), 256), 256, 0, s>>>(p, v, n);
   ND_LAUNCHED();
 }
 

@@ -42,31 +42,54 @@ namespace {
 using namespace dev;
 
 __device__ __forceinline__ bool converged_before(const SweepStats *prev) {
-  return prev != nullptr && prev->changed == 0;
+  return prev != nullptr && changed_sum(prev) == 0;
 }
 
-template <int K, int G, int M, typename T, bool AND>
+// Frontier state of this sweep (uniform over the launch): flags are read
+// only if the previous sweep wrote them; this sweep notifies once the
+// previous one changed few enough r-cliques, and keeps notifying after.
+__device__ __forceinline__ void frontier_mode(const SweepArgs &a,
+                                              const uint8_t **act,
+                                              uint8_t **act_next) {
+  const bool flags_valid = a.prev != nullptr && a.prev->notified;
+  const bool notify =
+      a.prev != nullptr &&
+      (a.prev->notified || changed_sum(a.prev) <= a.notify_below);
+  *act = flags_valid ? a.act : nullptr;
+  *act_next = notify ? a.act_next : nullptr;
+  if (notify && blockIdx.x == 0 && threadIdx.x == 0) a.stats->notified = 1;
+}
+
+template <int K, int G, int M, typename T, bool AND, bool FR>
 __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
                                                     int64_t hi) {
   if (converged_before(a.prev)) return;
+  const uint8_t *act = nullptr;
+  uint8_t *act_next = nullptr;
+  if (FR) frontier_mode(a, &act, &act_next);
   const int64_t R = lo + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const bool changed = update_regs<K, G, M, T, AND>(
+  bool ev;
+  const bool changed = update_regs<K, G, M, T, AND, FR>(
       a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out, a.cap_by_tau,
-      R, R < hi);
-  count_changed(a.stats, changed);
+      R, R < hi, act, act_next, &ev);
+  stat_add(a.stats, changed, ev);
 }
 
-template <int K, typename T, bool AND>
+template <int K, typename T, bool AND, bool FR>
 __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
                                                                int64_t lo,
                                                                int64_t hi) {
   __shared__ int32_t hist[kBlockHistBins];
   if (converged_before(a.prev)) return;
+  const uint8_t *act = nullptr;
+  uint8_t *act_next = nullptr;
+  if (FR) frontier_mode(a, &act, &act_next);
   for (int64_t R = lo + blockIdx.x; R < hi; R += gridDim.x) {
-    const bool changed = update_block<K, T, AND>(
+    bool ev;
+    const bool changed = update_block<K, T, AND, FR>(
         a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out,
-        a.cap_by_tau, R, hist);
-    count_changed(a.stats, changed);
+        a.cap_by_tau, R, hist, act, act_next, &ev);
+    stat_add(a.stats, changed, ev);
   }
 }
 
@@ -76,35 +99,43 @@ __global__ void k_zero_range(T *__restrict__ tau, int64_t lo, int64_t hi) {
   if (i < hi) tau[i] = 0;
 }
 
-template <int K, typename T, bool AND>
+template <int K, typename T, bool AND, bool FR>
 void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
   for (int bin = kBinBlock; bin < kBinZero; bin++) {
     const int64_t lo = ks.bin_lo[bin], hi = ks.bin_hi[bin], n = hi - lo;
     if (n == 0) continue;
     switch (bin) {
       case kBinG1:
-        k_sweep_regs<K, 1, 4, T, AND><<<grid_for(n, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 1, 4, T, AND, FR><<<grid_for(n, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG4:
-        k_sweep_regs<K, 4, 4, T, AND><<<grid_for(n * 4, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 4, 4, T, AND, FR><<<grid_for(n * 4, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG16:
-        k_sweep_regs<K, 16, 4, T, AND><<<grid_for(n * 16, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 16, 4, T, AND, FR><<<grid_for(n * 16, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG64:
-        k_sweep_regs<K, 64, 4, T, AND><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 64, 4, T, AND, FR><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinWave:
-        k_sweep_regs<K, 64, 32, T, AND><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 64, 32, T, AND, FR><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
         break;
       default: {
         const unsigned grid = (unsigned)(n < 65536 ? n : 65536);
-        k_sweep_block<K, T, AND><<<grid, kBlockThreads, 0, s>>>(a, lo, hi);
+        k_sweep_block<K, T, AND, FR><<<grid, kBlockThreads, 0, s>>>(a, lo, hi);
         break;
       }
     }
     ND_LAUNCHED();
   }
+}
+
+template <int K, typename T, bool AND>
+void launch_fr(const KindState &ks, const SweepArgs &a, hipStream_t s) {
+  if (a.act)
+    launch_bins<K, T, AND, true>(ks, a, s);
+  else
+    launch_bins<K, T, AND, false>(ks, a, s);
 }
 
 template <typename T>
@@ -119,12 +150,12 @@ void launch_typed(const KindState &ks, const SweepArgs &a, bool and_mode,
     }
   }
   switch (ks.k * 2 + (and_mode ? 1 : 0)) {
-    case 2: launch_bins<1, T, false>(ks, a, s); break;
-    case 3: launch_bins<1, T, true>(ks, a, s); break;
-    case 4: launch_bins<2, T, false>(ks, a, s); break;
-    case 5: launch_bins<2, T, true>(ks, a, s); break;
-    case 6: launch_bins<3, T, false>(ks, a, s); break;
-    case 7: launch_bins<3, T, true>(ks, a, s); break;
+    case 2: launch_fr<1, T, false>(ks, a, s); break;
+    case 3: launch_fr<1, T, true>(ks, a, s); break;
+    case 4: launch_fr<2, T, false>(ks, a, s); break;
+    case 5: launch_fr<2, T, true>(ks, a, s); break;
+    case 6: launch_fr<3, T, false>(ks, a, s); break;
+    case 7: launch_fr<3, T, true>(ks, a, s); break;
     default:
       ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "no sweep kernel for k=%d", ks.k);
   }

@@ -55,24 +55,63 @@ __device__ __forceinline__ int subgroup_sum(int x) {
   return x;
 }
 
-__device__ __forceinline__ void count_changed(SweepStats *st, bool changed) {
-  const uint64_t m = ballot(changed);
-  if (lane_id() == 0 && m) atomicAdd(&st->changed, (unsigned long long)__popcll(m));
+// Add this wave's changed / recomputed r-cliques to the sweep's counters
+// (one part per workgroup-and-wave hash, see SweepStats).
+__device__ __forceinline__ void stat_add(SweepStats *st, bool changed,
+                                         bool evald) {
+  const uint64_t mc = ballot(changed), me = ballot(evald);
+  if (lane_id() == 0 && (mc | me)) {
+    StatPart &p = st->part[(blockIdx.x + threadIdx.x / kWave) % kStatParts];
+    if (mc) atomicAdd(&p.changed, (unsigned long long)__popcll(mc));
+    if (me) atomicAdd(&p.evaluated, (unsigned long long)__popcll(me));
+  }
+}
+
+// Total changed count of a finished sweep, the same on every lane of the
+// wave (one part per lane, then a wave sum).
+__device__ __forceinline__ unsigned long long changed_sum(const SweepStats *st) {
+  unsigned long long v = lane_id() < kStatParts ? st->part[lane_id()].changed : 0;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// How many lanes of this lane's G-lane subgroup have p set: one wave ballot
+// and a popcount (scalar for G = 64), no cross-lane data movement.
+template <int G>
+__device__ __forceinline__ int subgroup_count(bool p) {
+  if constexpr (G == 1) {
+    return p ? 1 : 0;
+  } else {
+    const uint64_t b = ballot(p);
+    if constexpr (G == 64) {
+      return __popcll(b);
+    } else {
+      const int sub = lane_id() / G;
+      return __popcll((b >> (sub * G)) & (((uint64_t)1 << G) - 1));
+    }
+  }
+}
+
+// #{rho >= x} over the subgroup (G lanes x M values each).
+template <int G, int M>
+__device__ __forceinline__ int count_ge(const int32_t (&rho)[M], int32_t x) {
+  int n = 0;
+#pragma unroll
+  for (int m = 0; m < M; m++) n += subgroup_count<G>(rho[m] >= x);
+  return n;
 }
 
 // Largest x in [0, c-1] with #{rho >= x} >= x, given that x = 0 satisfies it;
-// G lanes of a subgroup each hold M values (absent values are -1).
+// G lanes of a subgroup each hold M values (absent values are -1).  Binary
+// search; every probe is M ballots.
 template <int G, int M>
 __device__ __forceinline__ int32_t hindex_search(const int32_t (&rho)[M],
                                                  int32_t c) {
   int32_t lo = 0, hi = c - 1;
   while (lo < hi) {
     const int32_t mid = (lo + hi + 1) >> 1;
-    int cm = 0;
-#pragma unroll
-    for (int m = 0; m < M; m++) cm += rho[m] >= mid;
-    cm = subgroup_sum<G>(cm);
-    if (cm >= mid)
+    if (count_ge<G, M>(rho, mid) >= mid)
       lo = mid;
     else
       hi = mid - 1;
@@ -80,24 +119,54 @@ __device__ __forceinline__ int32_t hindex_search(const int32_t (&rho)[M],
   return lo;
 }
 
+// Notification of Section 4.3: R changed to h, so a neighbour R' (any other
+// r-clique of an s-clique containing R) can change at the next sweep only if
+// h < tau(R'); mark those.  SND reads tau_t, so the test uses a value at
+// least tau_{t+1}(R') -- a superset of the neighbours that can change, hence
+// the iterates are exactly those of full sweeps.  Byte stores of the same
+// value race harmlessly.
+template <int K, typename T, bool AND>
+__device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
+                                       int64_t b, int64_t d, int first,
+                                       int stride, int32_t h, const T *tau,
+                                       uint8_t *act_next) {
+  for (int64_t j = first; j < d; j += stride) {
+    const int32_t *q = ids + K * (b + j);
+#pragma unroll
+    for (int x = 0; x < K; x++) {
+      const int32_t r = q[x];
+      if (h < load_tau<T, AND>(tau + r)) act_next[r] = 1;
+    }
+  }
+}
+
 // One r-clique per subgroup of G lanes (sl = lane within the subgroup), each
 // lane holding M gathered values: d_s(R) <= G*M.  `active` false for a
-// subgroup with no r-clique.  Returns whether R changed (true on the
-// subgroup's first lane only).
-template <int K, int G, int M, typename T, bool AND>
+// subgroup with no r-clique.  With a frontier (FR), an r-clique whose flag is
+// clear keeps its value (copied forward for SND) without any gather.
+// Returns (on the subgroup's first lane only) whether R changed; *evald
+// likewise whether it was recomputed.
+template <int K, int G, int M, typename T, bool AND, bool FR>
 __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
                                             const int32_t *__restrict__ inc_ids,
                                             const T *tau_in, T *tau_out,
                                             int cap_by_tau, int64_t R,
-                                            bool active) {
+                                            bool active, const uint8_t *act,
+                                            uint8_t *act_next, bool *evald) {
   const int sl = lane_id() % G;
   int32_t told = 0, c = 0;
   int64_t b = 0, d = 0;
+  bool eval = active;
   if (active) {
-    b = inc_off[R];
-    d = inc_off[R + 1] - b;
     told = (int32_t)tau_in[R];
-    c = cap_by_tau ? told : (int32_t)d;
+    if (FR && act && !act[R]) {
+      eval = false;
+      if (!AND && sl == 0) tau_out[R] = (T)told;
+    } else {
+      b = inc_off[R];
+      d = inc_off[R + 1] - b;
+      c = cap_by_tau ? told : (int32_t)d;
+    }
   }
   int32_t rho[M];
 #pragma unroll
@@ -105,15 +174,15 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
     const int64_t j = sl + (int64_t)m * G;
     rho[m] = (j < d) ? gather_rho<K, T, AND>(inc_ids, b + j, tau_in) : -1;
   }
-  int cnt = 0;
-#pragma unroll
-  for (int m = 0; m < M; m++) cnt += rho[m] >= c;
-  cnt = subgroup_sum<G>(cnt);
+  const int cnt = count_ge<G, M>(rho, c);
   const int32_t h = cnt >= c ? c : hindex_search<G, M>(rho, c);
-  const bool lead = active && sl == 0;
-  const bool changed = lead && h != told;
-  if (lead) store_tau<T, AND>(tau_out + R, h, changed);
-  return changed;
+  const bool ch = eval && h != told;  // uniform within the subgroup
+  const bool lead = sl == 0;
+  if (eval && lead) store_tau<T, AND>(tau_out + R, h, ch);
+  if (FR && ch && act_next)
+    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next);
+  *evald = lead && eval;
+  return lead && ch;
 }
 
 // Bins hist[0..nb) count values, bin i standing for the value x0 + i*scale.
@@ -166,16 +235,22 @@ __device__ __forceinline__ int64_t block_sum(int64_t x) {
 // One r-clique per 256-thread workgroup, any d_s: LDS histogram of
 // min(rho, c) in up to kBlockHistBins bins; for larger c values are binned
 // coarsely and the coarse bin holding H is refined with a second gather.
-// Returns whether R changed (thread 0 only).
-template <int K, typename T, bool AND>
+// Returns whether R changed (thread 0 only); *evald likewise.
+template <int K, typename T, bool AND, bool FR>
 __device__ bool update_block(const int64_t *__restrict__ inc_off,
                              const int32_t *__restrict__ inc_ids,
                              const T *tau_in, T *tau_out, int cap_by_tau,
-                             int64_t R, int32_t *hist) {
+                             int64_t R, int32_t *hist, const uint8_t *act,
+                             uint8_t *act_next, bool *evald) {
   const int t = threadIdx.x;
+  const int32_t told = (int32_t)tau_in[R];
+  if (FR && act && !act[R]) {
+    if (!AND && t == 0) tau_out[R] = (T)told;
+    *evald = false;
+    return false;
+  }
   const int64_t b = inc_off[R];
   const int64_t d = inc_off[R + 1] - b;
-  const int32_t told = (int32_t)tau_in[R];
   const int32_t c = cap_by_tau ? told : (int32_t)d;
   const int64_t w = ((int64_t)c + kBlockHistBins) / kBlockHistBins;
   const int nb = (int)(((int64_t)c + w) / w);  // bins for values 0..c
@@ -212,10 +287,13 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
       h = (int32_t)(x0 + f);
     }
   }
-  const bool changed = t == 0 && h != told;
-  if (t == 0) store_tau<T, AND>(tau_out + R, h, changed);
+  const bool ch = h != told;
+  if (t == 0) store_tau<T, AND>(tau_out + R, h, ch);
+  if (FR && ch && act_next)
+    notify<K, T, AND>(inc_ids, b, d, t, kBlockThreads, h, tau_in, act_next);
   __syncthreads();
-  return changed;
+  *evald = t == 0;
+  return t == 0 && ch;
 }
 
 }  // namespace dev

@@ -114,14 +114,19 @@ def test_update_arbitrary_tau(nd, ctx, name, make, kind):
 
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
 @pytest.mark.parametrize("kind", list(KINDS))
-def test_snd_every_iterate_and_kappa(nd, ctx, name, make, kind):
+@pytest.mark.parametrize("frontier", [False, True], ids=["full", "frontier"])
+def test_snd_every_iterate_and_kappa(nd, ctx, name, make, kind, frontier):
+    """Every SND iterate equals the oracle's; with the notification frontier
+    (Section 4.3) the iterates are the same, only fewer r-cliques are
+    recomputed."""
     raw = make()
     r, s = KINDS[kind]
     g = gpu_graph(nd, ctx, raw)
     og = oracle.Graph.from_raw(raw)
     seq = og.snd(r, s)  # tau_0 .. tau_T, tau_T == tau_{T-1}
     its = []
-    kappa, res = g.decompose(kind, "snd", keep_iterates=its)
+    kappa, res = g.decompose(kind, "snd", keep_iterates=its,
+                             use_frontier=frontier)
     kappa = kappa.cpu().numpy()
     assert res["converged"] == 1
     if og.num_rcliques(r) == 0:
@@ -137,7 +142,8 @@ def test_snd_every_iterate_and_kappa(nd, ctx, name, make, kind):
 
 @pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
 @pytest.mark.parametrize("kind", list(KINDS))
-def test_and_converges_to_kappa(nd, ctx, name, make, kind):
+@pytest.mark.parametrize("frontier", [False, True], ids=["full", "frontier"])
+def test_and_converges_to_kappa(nd, ctx, name, make, kind, frontier):
     raw = make()
     r, s = KINDS[kind]
     g = gpu_graph(nd, ctx, raw)
@@ -147,7 +153,8 @@ def test_and_converges_to_kappa(nd, ctx, name, make, kind):
     seq = og.snd(r, s)
     kref = og.peel(r, s)
     its = []
-    kappa, res = g.decompose(kind, "and", keep_iterates=its)
+    kappa, res = g.decompose(kind, "and", keep_iterates=its,
+                             use_frontier=frontier)
     assert np.array_equal(kappa.cpu().numpy(), kref)
     assert res["converged"] == 1
     # never more sweeps than SND; every AND iterate between kappa and SND's
@@ -168,6 +175,9 @@ def test_snd_deterministic_and_chunked(nd, ctx):
     assert r1["sweeps"] == r2["sweeps"] == r3["sweeps"]
     k4, _ = g.decompose("truss", "and")
     assert torch.equal(k1, k4)
+    k5, r5 = g.decompose("truss", "snd", use_frontier=True)
+    assert torch.equal(k1, k5) and r5["sweeps"] == r1["sweeps"]
+    assert r5["updates"] < r1["updates"]  # the frontier skips idle r-cliques
 
 
 def test_max_iters_returns_iterate(nd, ctx):
@@ -238,10 +248,12 @@ def test_edge_cases(nd, ctx, case, kind):
     r, s = KINDS[kind]
     g, og = edges_graph(nd, ctx, n, pairs)
     nr = og.num_rcliques(r)
+    want = og.peel(r, s)
     for mode in ("snd", "and"):
-        kappa, res = g.decompose(kind, mode)
-        assert res["converged"] == 1
-        assert np.array_equal(kappa.cpu().numpy(), og.peel(r, s)), mode
+        for fr in (False, True):
+            kappa, res = g.decompose(kind, mode, use_frontier=fr)
+            assert res["converged"] == 1
+            assert np.array_equal(kappa.cpu().numpy(), want), (mode, fr)
     assert g.sizes(kind)[0] == nr
     if nr:
         ds = og.sdeg(r, s)
