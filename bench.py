@@ -3,7 +3,7 @@
 
 One step is the whole path on a graph whose raw edge list is already in HBM:
 canonical CSR -> edge numbering -> triangle incidence lists -> d_s -> SND
-sweeps until a sweep changes nothing.  ``value`` is r-clique h-index updates
+sweeps (notification frontier on) until a sweep changes nothing.  ``value`` is r-clique h-index updates
 (the r-cliques with d_s > 0, each sweep; the others are exact from the start)
 per second of step time; the step time itself is the time-to-exact-convergence
 including preparation.
@@ -13,7 +13,11 @@ Also reported on the same line:
     over its average device time per sweep (HIP events on the library's
     stream), against the 8 TB/s HBM peak; ``traffic`` from rocprofv3 counters
     when a summary for the current kernels is present (else null);
-  * ``and``: the same graph decomposed by AND (sweeps, time, updates/s);
+  * ``full_sweeps``: the same graph by SND recomputing every r-clique each
+    sweep (the roofline is taken on these launches);
+  * ``and``: the same graph decomposed by AND (sweeps, time);
+  * ``stream``: batched and served decomposition of a sample of the
+    request-stream workload against one graph per launch;
   * ``cpu_baseline``: the CPU oracle's update operator timed on the host over
     a bounded sample of the same graph's r-cliques.
 
@@ -75,6 +79,107 @@ def cpu_baseline(raw, kind, budget_s=15.0):
                       f"({upd} with d_s > 0, tau = d_s) in {dt:.1f} s"}
 
 
+def sweep_source_hash() -> str:
+    """Hash of the sources that define the sweep kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "sweep_dev.h"):
+        with open(os.path.join(ROOT, "paper_1704_00386_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per full sweep from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on different sweep kernels."""
+    path = os.path.join(ROOT, "profiles", "traffic_sweep_cl20_truss.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("sweep_source_sha256") != sweep_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_sweep")
+
+
+def stream_leg(nd, ctx, count, seed=5):
+    """Batched and served k-truss against one graph per launch, on `count`
+    graphs of the request-stream workload (Chung-Lu, n ~ U{1000..200000},
+    mean degree ~ U[8,64], exponent ~ U[2.0,2.5]).  Edge lists are resident
+    in HBM before timing; every path builds its graphs from them."""
+    import numpy as np
+    import torch
+
+    from synth import chung_lu, request_stream
+
+    specs = request_stream(count=count, seed=seed)
+    raws = [chung_lu(sp["n"], sp["beta"], sp["mean"], sp["seed"]) for sp in specs]
+    dev = [(r.n, torch.from_numpy(r.src).cuda(), torch.from_numpy(r.dst).cuda())
+           for r in raws]
+    updates = 0
+
+    def build():
+        return [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev]
+
+    # warm the allocator and kernels once
+    for g in build()[:4]:
+        g.decompose(KIND, "snd")
+    torch.cuda.synchronize()
+    # one graph per launch sequence: build, prepare, decompose, next
+    t0 = time.perf_counter()
+    solo = []
+    for n, s, d in dev:
+        g = nd.Graph.from_edges(ctx, n, s, d)
+        k, r = g.decompose(KIND, "snd")
+        solo.append(k)
+        updates += r["updates"]
+        g.close()
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    # batched: build and prepare all, then one combined sweep loop
+    t0 = time.perf_counter()
+    gs = build()
+    for g in gs:
+        g.prepare(KIND)
+    ks, rs = nd.batch_decompose(ctx, gs, KIND, "snd")
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    batch_same = all(torch.equal(a, b) for a, b in zip(ks, solo))
+    for g in gs:
+        g.close()
+    # served: Poisson arrivals at 80% of the one-graph-per-launch rate
+    rate = 0.8 * count / t_solo
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
+    arrive = np.cumsum(gaps) - gaps[0]
+    srv = nd.Server(ctx, max_slots=64)
+    tickets = []
+    t0 = time.perf_counter()
+    for i, (n, s, d) in enumerate(dev):
+        while time.perf_counter() - t0 < arrive[i]:
+            time.sleep(0.0002)
+        tickets.append(srv.submit(nd.Graph.from_edges(ctx, n, s, d), KIND))
+    lats, served_same = [], True
+    for t, want in zip(tickets, solo):
+        kappa, r, lat = srv.wait(t)
+        lats.append(lat)
+        served_same &= bool(torch.equal(kappa, want.cpu()))
+    t_srv = time.perf_counter() - t0
+    srv.close()
+    return {
+        "graphs": count,
+        "workload": "request stream of Chung-Lu k-truss graphs, n ~ U{1000.."
+                    "200000}, mean ~ U[8,64], exponent ~ U[2.0,2.5], seed 5",
+        "one_per_launch_graphs_per_s": count / t_solo,
+        "batched_graphs_per_s": count / t_batch,
+        "batched_speedup": t_solo / t_batch,
+        "served": {"arrival_rate_per_s": rate, "graphs_per_s": count / t_srv,
+                   "p50_ms": float(np.percentile(lats, 50)),
+                   "p99_ms": float(np.percentile(lats, 99))},
+        "results_identical": bool(batch_same and served_same),
+        "updates": updates,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +187,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (a known-size "
+                         "kernel for scaling hardware byte counters)")
+    ap.add_argument("--stream-graphs", type=int, default=96,
+                    help="graphs in the batched/served comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU "
@@ -94,15 +204,21 @@ def main():
     import paper_1704_00386_amd as nd
     from synth import workload
 
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     raw = workload(WORKLOAD)
     ctx = nd.Context(0)
     src = torch.from_numpy(raw.src).cuda()
     dst = torch.from_numpy(raw.dst).cuda()
     torch.cuda.synchronize()
 
-    def step(collect=None):
+    def step():
         g = nd.Graph.from_edges(ctx, raw.n, src, dst)
-        kappa, res = g.decompose(KIND, "snd", on_iter=collect)
+        kappa, res = g.decompose(KIND, "snd", use_frontier=True)
         return g, kappa, res
 
     for _ in range(args.warmup):
@@ -110,50 +226,50 @@ def main():
         g.close()
     torch.cuda.synchronize()
 
+    # timed steps: the whole path, SND with the notification frontier
+    times, results = [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, kappa, res = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        results.append(res)
+        if i < args.steps - 1:
+            g.close()
+    ms_per_step = 1e3 * sum(times) / len(times)
+    res = results[-1]
+    nr, P = res["n_rcliques"], res["n_incidence"]
+    k = {"core": 1, "truss": 2, "nucleus34": 3}[KIND]
+    nr_eval = int(np.count_nonzero(g.sdegree(KIND).cpu().numpy()))
+    full_equiv = nr_eval * res["sweeps"]
+
+    # roofline leg: full sweeps (every r-clique with d_s > 0 recomputed each
+    # sweep) on the same prepared graph, per-sweep device time from events
+    # recorded around each sweep's launches on the library's stream
     sweep_ms = []
 
     def collect(info):
         sweep_ms.append(info.ms)
         return 0
 
-    times, results = [], []
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g, kappa, res = step(collect)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        results.append(res)
-        last_kappa = kappa
-        if _ < args.steps - 1:
-            g.close()
-    ms_per_step = 1e3 * sum(times) / len(times)
-    res = results[-1]
-    nr, P = res["n_rcliques"], res["n_incidence"]
-    k = {"core": 1, "truss": 2, "nucleus34": 3}[KIND]
-    updates = res["updates"]
-    nr_eval = updates // max(res["sweeps"], 1)
+    kfull, rfull = g.decompose(KIND, "snd", on_iter=collect)
+    same_full = bool(torch.equal(kfull, kappa))
     B = sweep_bytes(P, nr_eval, k, res["tau_bytes"])
     avg_sweep_ms = sum(sweep_ms) / len(sweep_ms)
     achieved = B / (avg_sweep_ms * 1e-3) / 1e9
 
-    # AND on the prepared graph (same incidence lists)
-    kand, rand = g.decompose(KIND, "and")
-    same = bool(torch.equal(kand, last_kappa))
+    # AND on the prepared graph (same incidence lists), frontier on
+    kand, rand = g.decompose(KIND, "and", use_frontier=True)
+    same_and = bool(torch.equal(kand, kappa))
     g.close()
 
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_sweep_cl20_truss.json")
-    if os.path.exists(tpath):
-        try:
-            traffic = json.load(open(tpath)).get("bytes_per_sweep")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic()
 
     line = {
         "metric": "r-clique h-index updates/sec + time-to-exact-convergence "
                   "vs CPU peeling",
-        "value": updates / (ms_per_step * 1e-3),
+        "value": full_equiv / (ms_per_step * 1e-3),
         "unit": "r-clique h-index updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -167,25 +283,36 @@ def main():
         "config": {"workload": "k-truss (2,3) SND on Chung-Lu n=2^20, "
                                "exponent 2.1, mean degree 32, seed 2",
                    "n": raw.n, "raw_pairs": raw.m, "edges": nr,
-                   "incidence_P": P, "evaluated_per_sweep": nr_eval,
-                   "tau_bytes": res["tau_bytes"], "kind": KIND, "mode": "snd"},
+                   "incidence_P": P, "swept_per_sweep": nr_eval,
+                   "tau_bytes": res["tau_bytes"], "kind": KIND,
+                   "mode": "snd", "frontier": True},
+        "updates_counted": "r-cliques with d_s > 0 per sweep (full-sweep "
+                           "equivalent: the frontier recomputes only notified "
+                           "r-cliques and yields the same iterates)",
         "time_to_exact_ms": ms_per_step,
         "ms_prep": ms_per_step - res["ms_iterate"],
         "ms_iterate": res["ms_iterate"],
         "sweeps": res["sweeps"],
-        "updates_per_s_sweeps": updates / (res["ms_iterate"] * 1e-3),
+        "evaluated_updates": res["updates"],
+        "full_sweeps": {"ms_iterate": rfull["ms_iterate"],
+                        "sweeps": rfull["sweeps"],
+                        "updates_per_s": rfull["updates"] /
+                        (rfull["ms_iterate"] * 1e-3),
+                        "kappa_equals_frontier": same_full},
         "roofline": {"bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "sweep (one full application of U)",
+                     "kernel": "full sweep (one application of U to every "
+                               "r-clique with d_s > 0)",
                      "bytes_per_launch": B, "avg_launch_ms": avg_sweep_ms},
         "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
-                "updates_per_s": rand["updates"] / (rand["ms_iterate"] * 1e-3),
-                "kappa_equals_snd": same},
+                "frontier": True, "kappa_equals_snd": same_and},
     }
+    if args.stream_graphs > 0:
+        line["stream"] = stream_leg(nd, ctx, args.stream_graphs)
     if not args.no_cpu:
         cb = cpu_baseline(raw, KIND, args.cpu_budget)
-        cb["time_to_exact_s_est"] = nr_eval * res["sweeps"] / cb["value"]
+        cb["time_to_exact_s_est"] = full_equiv / cb["value"]
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
