@@ -21,6 +21,8 @@
 // each element of it is binary-searched in the others.  Items are binned by
 // that length and each bin gets a subgroup of G lanes per item (G = 1, 4, 16,
 // 64) that strides over the short list; matches are ordered with a ballot.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace nd {
@@ -104,6 +106,81 @@ __global__ __launch_bounds__(256) void k_edge_isect(EdgeIsectArgs a) {
   }
   if ((MODE == kCountTruss || MODE == kCountTri) && sl == 0)
     a.count[e] = (int32_t)written;
+}
+
+// Edges whose shorter list is long (both endpoints high-degree): one wave
+// per edge streams the longer list through LDS in windows of kIsectWindow
+// entries; the slice of the shorter list whose values fall inside a window is
+// binary-searched in LDS rather than in global memory.  Windows cover
+// increasing value ranges, so matches still come out in ascending order.
+constexpr int kIsectWindow = 2048;
+
+template <int MODE>
+__global__ __launch_bounds__(kWave) void k_edge_isect_lds(EdgeIsectArgs a) {
+  __shared__ int32_t win[kIsectWindow];
+  const int lane = threadIdx.x;
+  for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+    const int32_t e = a.items[it];
+    const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
+    const int64_t bu = a.row_off[u], eu = a.row_off[u + 1];
+    const int64_t bv = a.row_off[v], ev = a.row_off[v + 1];
+    const bool short_is_u = (eu - bu) <= (ev - bv);
+    const int64_t sb = short_is_u ? bu : bv, se = short_is_u ? eu : ev;
+    const int64_t lb = short_is_u ? bv : bu, le = short_is_u ? ev : eu;
+    int64_t start = sb;
+    if (MODE == kCountTri || MODE == kFillTri)
+      start = lower_bound<int32_t>(a.col, sb, se, v + 1);  // only w > v
+    int64_t base = 0;
+    if (MODE == kFillTruss) base = a.off[a.inv[e]];
+    if (MODE == kFillTri) base = a.off[e];
+    int64_t written = 0;
+    int64_t apos = start;  // shorter-list elements before apos are done
+    for (int64_t w0 = lb; w0 < le && apos < se; w0 += kIsectWindow) {
+      const int wn = (int)min((int64_t)kIsectWindow, le - w0);
+      for (int i = lane; i < wn; i += kWave) win[i] = a.col[w0 + i];
+      __syncthreads();
+      const int32_t hi_val = win[wn - 1];
+      // shorter-list elements <= hi_val that are not done yet
+      const int64_t aend = lower_bound<int32_t>(a.col, apos, se, hi_val + 1);
+      for (int64_t j0 = apos; j0 < aend; j0 += kWave) {
+        const int64_t j = j0 + lane;
+        bool found = false;
+        int q = 0;
+        int32_t w = 0;
+        if (j < aend) {
+          w = a.col[j];
+          int lo = 0, hi = wn;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (win[mid] < w)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          q = lo;
+          found = q < wn && win[q] == w;
+        }
+        const uint64_t m = ballot(found);
+        if (MODE == kFillTruss && found) {
+          const int64_t k = base + written + lanes_below(m);
+          const int32_t id_short = a.inv[a.eid[j]];
+          const int32_t id_long = a.inv[a.eid[w0 + q]];
+          a.out_a[2 * k] = short_is_u ? id_short : id_long;
+          a.out_a[2 * k + 1] = short_is_u ? id_long : id_short;
+        }
+        if (MODE == kFillTri && found) {
+          const int64_t k = base + written + lanes_below(m);
+          a.out_a[k] = w;
+          a.out_b[k] = e;
+        }
+        written += __popcll(m);
+      }
+      apos = aend;
+      __syncthreads();  // the window is overwritten next
+    }
+    if ((MODE == kCountTruss || MODE == kCountTri) && lane == 0)
+      a.count[e] = (int32_t)written;
+  }
 }
 
 // ------------------------------------------------------------- (3,4)
@@ -228,7 +305,11 @@ void run_edge_isect(EdgeIsectArgs a, const int32_t *items,
       case 0: k_edge_isect<1, MODE><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
       case 1: k_edge_isect<4, MODE><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
       case 2: k_edge_isect<16, MODE><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
-      default: k_edge_isect<64, MODE><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a); break;
+      default: {
+        const unsigned grid = (unsigned)std::min<int64_t>(a.nitems, 1 << 20);
+        k_edge_isect_lds<MODE><<<grid, kWave, 0, s>>>(a);
+        break;
+      }
     }
     ND_LAUNCHED();
   }
