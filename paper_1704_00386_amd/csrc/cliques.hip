@@ -262,6 +262,142 @@ __global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
   if (!FILL && sl == 0) a.count[t] = (int32_t)written;
 }
 
+// ------------------------------------------- k-truss by orientation
+
+// Orient every edge from the endpoint of lower (degree, id) to the higher one.
+// Each triangle then has exactly one edge u->v whose out-lists N+(u), N+(v)
+// both contain the third vertex, so intersecting out-lists lists every
+// triangle once; out-lists are short (at most about sqrt(2|E|)) even when
+// degrees are not.
+__device__ __forceinline__ bool ranks_below(int64_t du, int32_t u, int64_t dv,
+                                            int32_t v) {
+  return du < dv || (du == dv && u < v);
+}
+
+__global__ void k_orient_flags(const int64_t *__restrict__ row_off,
+                               const int32_t *__restrict__ col,
+                               const int32_t *__restrict__ rowid, int64_t nnz,
+                               int32_t *__restrict__ flag) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t u = rowid[p], v = col[p];
+  const int64_t du = row_off[u + 1] - row_off[u], dv = row_off[v + 1] - row_off[v];
+  flag[p] = ranks_below(du, u, dv, v) ? 1 : 0;
+}
+
+// Out-lists in CSR order (so sorted by vertex id) with each entry's edge id.
+__global__ void k_orient_fill(const int32_t *__restrict__ col,
+                              const int32_t *__restrict__ rowid,
+                              const int32_t *__restrict__ eid,
+                              const int32_t *__restrict__ flag,
+                              const int64_t *__restrict__ pos, int64_t nnz,
+                              int32_t *__restrict__ out_col,
+                              int32_t *__restrict__ out_eid,
+                              int32_t *__restrict__ out_src) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz || !flag[p]) return;
+  const int64_t q = pos[p];
+  out_col[q] = col[p];
+  out_eid[q] = eid[p];
+  out_src[q] = rowid[p];
+}
+
+// out_off[u] = first out-entry of u (entries are grouped by source, in order).
+__global__ void k_orient_off(const int32_t *__restrict__ out_src, int64_t ne,
+                             int32_t n, int64_t *__restrict__ out_off) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x > n) return;
+  out_off[x] = lower_bound<int32_t>(out_src, 0, ne, (int32_t)x);
+}
+
+struct OrientArgs {
+  const int32_t *items;   // oriented edges (out-entry index) of this bin
+  int64_t nitems;
+  const int64_t *out_off;
+  const int32_t *out_col;
+  const int32_t *out_eid;
+  const int32_t *out_src;
+  int32_t *count;         // count pass: per edge id
+  const int32_t *inv;     // fill pass: edge id -> internal id
+  unsigned long long *cursor;  // fill pass: next free s-clique slot, internal
+  int32_t *ids;           // fill pass: 2 ids per (edge, triangle)
+};
+
+template <int G, bool FILL>
+__global__ __launch_bounds__(256) void k_orient_isect(OrientArgs a) {
+  const int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int sl = lane_id() % G;
+  if (gsub >= a.nitems) return;  // uniform within the subgroup
+  const int64_t q = a.items[gsub];
+  const int32_t u = a.out_src[q], v = a.out_col[q];
+  const int32_t euv = a.out_eid[q];
+  const int64_t bu = a.out_off[u], eu = a.out_off[u + 1];
+  const int64_t bv = a.out_off[v], ev = a.out_off[v + 1];
+  const bool short_is_u = (eu - bu) <= (ev - bv);
+  const int64_t sb = short_is_u ? bu : bv, se = short_is_u ? eu : ev;
+  const int64_t lb = short_is_u ? bv : bu, le = short_is_u ? ev : eu;
+  for (int64_t j0 = sb; j0 < se; j0 += G) {
+    const int64_t j = j0 + sl;
+    if (j >= se) break;
+    const int32_t w = a.out_col[j];
+    const int64_t k = lower_bound<int32_t>(a.out_col, lb, le, w);
+    if (k >= le || a.out_col[k] != w) continue;
+    const int32_t e1 = a.out_eid[short_is_u ? j : k];  // (u, w)
+    const int32_t e2 = a.out_eid[short_is_u ? k : j];  // (v, w)
+    if (!FILL) {
+      atomicAdd(&a.count[euv], 1);
+      atomicAdd(&a.count[e1], 1);
+      atomicAdd(&a.count[e2], 1);
+    } else {
+      const int32_t iuv = a.inv[euv], i1 = a.inv[e1], i2 = a.inv[e2];
+      const int64_t p0 = (int64_t)atomicAdd(&a.cursor[iuv], 1ull);
+      const int64_t p1 = (int64_t)atomicAdd(&a.cursor[i1], 1ull);
+      const int64_t p2 = (int64_t)atomicAdd(&a.cursor[i2], 1ull);
+      a.ids[2 * p0] = i1;
+      a.ids[2 * p0 + 1] = i2;
+      a.ids[2 * p1] = iuv;
+      a.ids[2 * p1 + 1] = i2;
+      a.ids[2 * p2] = iuv;
+      a.ids[2 * p2 + 1] = i1;
+    }
+  }
+}
+
+__global__ void k_orient_bins(const int64_t *__restrict__ out_off,
+                              const int32_t *__restrict__ out_col,
+                              const int32_t *__restrict__ out_src, int64_t ne,
+                              uint8_t *__restrict__ bin) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ne) return;
+  const int32_t u = out_src[q], v = out_col[q];
+  const int64_t a = out_off[u + 1] - out_off[u], b = out_off[v + 1] - out_off[v];
+  const int64_t m = min(a, b);
+  bin[q] = m <= 4 ? 0 : m <= 16 ? 1 : m <= 64 ? 2 : 3;
+}
+
+__global__ void k_cursor_init(const int64_t *__restrict__ off, int64_t nr,
+                              unsigned long long *__restrict__ cursor) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nr) cursor[i] = (unsigned long long)off[i];
+}
+
+template <bool FILL>
+void run_orient(OrientArgs a, const int32_t *items, const int64_t *bin_off,
+                hipStream_t s) {
+  for (int b = 0; b < 4; b++) {
+    a.items = items + bin_off[b];
+    a.nitems = bin_off[b + 1] - bin_off[b];
+    if (a.nitems == 0) continue;
+    switch (b) {
+      case 0: k_orient_isect<1, FILL><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
+      case 1: k_orient_isect<4, FILL><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
+      case 2: k_orient_isect<16, FILL><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
+      default: k_orient_isect<64, FILL><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+  }
+}
+
 // ------------------------------------------------------------- binning
 
 constexpr int kIsectBins = 4;  // G = 1, 4, 16, 64
@@ -358,25 +494,70 @@ EdgeIsectArgs edge_args(nd_graph *g) {
 
 }  // namespace
 
+// k-truss incidence: every triangle is listed once by the orientation above
+// and written into the lists of its three edges.  Slots inside a list are
+// taken with atomic cursors, so the order of s-cliques within a list varies
+// from run to run; nothing computed from the lists depends on it (min and H
+// are order-free).
 void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   build_edges(g, s);
   Allocator &al = g->ctx->alloc;
-  const int64_t ne = g->ne;
-  DArr<int32_t> items;
-  int64_t bin_off[kIsectBins + 1];
-  edge_schedule(g, items, bin_off, s);
+  const int64_t ne = g->ne, nnz = g->nnz;
+  const int32_t n = g->n;
+  DArr<int32_t> flag(al, nnz);
+  DArr<int64_t> pos(al, nnz + 1);
+  if (nnz > 0) {
+    k_orient_flags<<<grid_for(nnz, 256), 256, 0, s>>>(g->row_off.p, g->col.p,
+                                                       g->rowid.p, nnz, flag.p);
+    ND_LAUNCHED();
+  }
+  exclusive_scan_i32(flag.p, pos.p, nnz, s, al);  // ne oriented entries
+  DArr<int32_t> out_col(al, ne), out_eid(al, ne), out_src(al, ne);
+  DArr<int64_t> out_off(al, (int64_t)n + 1);
+  if (nnz > 0) {
+    k_orient_fill<<<grid_for(nnz, 256), 256, 0, s>>>(
+        g->col.p, g->rowid.p, g->eid.p, flag.p, pos.p, nnz, out_col.p,
+        out_eid.p, out_src.p);
+    ND_LAUNCHED();
+  }
+  flag.free();
+  pos.free();
+  k_orient_off<<<grid_for((int64_t)n + 1, 256), 256, 0, s>>>(out_src.p, ne, n,
+                                                              out_off.p);
+  ND_LAUNCHED();
+  // oriented edges binned by their shorter out-list
+  DArr<uint8_t> bin(al, ne);
+  DArr<int32_t> items(al, ne);
+  if (ne > 0) {
+    k_orient_bins<<<grid_for(ne, 256), 256, 0, s>>>(out_off.p, out_col.p,
+                                                     out_src.p, ne, bin.p);
+    ND_LAUNCHED();
+  }
+  int64_t bin_off[5];
+  partition_by_bin(bin.p, ne, 4, items.p, bin_off, s, al);
+  bin.free();
+  OrientArgs a{};
+  a.out_off = out_off.p;
+  a.out_col = out_col.p;
+  a.out_eid = out_eid.p;
+  a.out_src = out_src.p;
   DArr<int32_t> cnt(al, ne);
-  EdgeIsectArgs a = edge_args(g);
+  fill_i32(cnt.p, 0, ne, s);
   a.count = cnt.p;
-  run_edge_isect<kCountTruss>(a, items.p, bin_off, s);
+  run_orient<false>(a, items.p, bin_off, s);
   ks.nr = ne;
   build_layout(g, ks, cnt.p, s);
   cnt.free();
   ks.inc_ids.reset(al, 2 * ks.P);
-  a.off = ks.inc_off.p;
+  DArr<unsigned long long> cursor(al, ne);
+  if (ne > 0) {
+    k_cursor_init<<<grid_for(ne, 256), 256, 0, s>>>(ks.inc_off.p, ne, cursor.p);
+    ND_LAUNCHED();
+  }
   a.inv = ks.inv.p;
-  a.out_a = ks.inc_ids.p;
-  run_edge_isect<kFillTruss>(a, items.p, bin_off, s);
+  a.cursor = cursor.p;
+  a.ids = ks.inc_ids.p;
+  run_orient<true>(a, items.p, bin_off, s);
 }
 
 void build_triangles(nd_graph *g, hipStream_t s) {
