@@ -18,6 +18,8 @@ Also reported on the same line:
   * ``and``: the same graph decomposed by AND (sweeps, time);
   * ``stream``: batched and served decomposition of a sample of the
     request-stream workload against one graph per launch;
+  * ``small_graphs``: the same comparison on small graphs only (n <= 5000),
+    where each graph alone is launch-bound;
   * ``cpu_baseline``: the CPU oracle's update operator timed on the host over
     a bounded sample of the same graph's r-cliques.
 
@@ -80,10 +82,11 @@ def cpu_baseline(raw, kind, budget_s=15.0):
 
 
 def sweep_source_hash() -> str:
-    """Hash of the sources that define the sweep kernels."""
+    """Hash of the sources that define the sweep kernels and the r-clique
+    order they gather in."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_dev.h"):
+    for f in ("sweep.hip", "sweep_dev.h", "layout.hip"):
         with open(os.path.join(ROOT, "paper_1704_00386_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -102,82 +105,82 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_sweep")
 
 
-def stream_leg(nd, ctx, count, seed=5):
+def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     """Batched and served k-truss against one graph per launch, on `count`
-    graphs of the request-stream workload (Chung-Lu, n ~ U{1000..200000},
+    graphs of the request-stream workload (Chung-Lu, n ~ U{n_lo..n_hi},
     mean degree ~ U[8,64], exponent ~ U[2.0,2.5]).  Edge lists are resident
-    in HBM before timing; every path builds its graphs from them."""
+    in HBM before timing; every path builds, prepares and decomposes its
+    graphs (frontier SND, the same iterates as plain SND)."""
     import numpy as np
     import torch
 
     from synth import chung_lu, request_stream
 
-    specs = request_stream(count=count, seed=seed)
+    specs = request_stream(count=count, n_lo=n_lo, n_hi=n_hi, seed=seed)
     raws = [chung_lu(sp["n"], sp["beta"], sp["mean"], sp["seed"]) for sp in specs]
     dev = [(r.n, torch.from_numpy(r.src).cuda(), torch.from_numpy(r.dst).cuda())
            for r in raws]
     updates = 0
 
-    def build():
-        return [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev]
-
     # warm the allocator and kernels once
-    for g in build()[:4]:
-        g.decompose(KIND, "snd")
+    for n, s, d in dev[:4]:
+        nd.Graph.from_edges(ctx, n, s, d).decompose(KIND, "snd", use_frontier=True)
     torch.cuda.synchronize()
     # one graph per launch sequence: build, prepare, decompose, next
     t0 = time.perf_counter()
     solo = []
     for n, s, d in dev:
         g = nd.Graph.from_edges(ctx, n, s, d)
-        k, r = g.decompose(KIND, "snd")
+        k, r = g.decompose(KIND, "snd", use_frontier=True)
         solo.append(k)
         updates += r["updates"]
         g.close()
     torch.cuda.synchronize()
     t_solo = time.perf_counter() - t0
-    # batched: build and prepare all, then one combined sweep loop
+    # batched: build all, then one call that prepares them (several host
+    # threads and streams) and sweeps them together
     t0 = time.perf_counter()
-    gs = build()
-    for g in gs:
-        g.prepare(KIND)
-    ks, rs = nd.batch_decompose(ctx, gs, KIND, "snd")
+    gs = [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev]
+    ks, rs = nd.batch_decompose(ctx, gs, KIND, "snd", use_frontier=True)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    batch_same = all(torch.equal(a, b) for a, b in zip(ks, solo))
+    same = all(torch.equal(a, b) for a, b in zip(ks, solo))
     for g in gs:
         g.close()
-    # served: Poisson arrivals at 80% of the one-graph-per-launch rate
-    rate = 0.8 * count / t_solo
-    gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
-    arrive = np.cumsum(gaps) - gaps[0]
-    srv = nd.Server(ctx, max_slots=64)
-    tickets = []
-    t0 = time.perf_counter()
-    for i, (n, s, d) in enumerate(dev):
-        while time.perf_counter() - t0 < arrive[i]:
-            time.sleep(0.0002)
-        tickets.append(srv.submit(nd.Graph.from_edges(ctx, n, s, d), KIND))
-    lats, served_same = [], True
-    for t, want in zip(tickets, solo):
-        kappa, r, lat = srv.wait(t)
-        lats.append(lat)
-        served_same &= bool(torch.equal(kappa, want.cpu()))
-    t_srv = time.perf_counter() - t0
-    srv.close()
-    return {
+    out = {
         "graphs": count,
-        "workload": "request stream of Chung-Lu k-truss graphs, n ~ U{1000.."
-                    "200000}, mean ~ U[8,64], exponent ~ U[2.0,2.5], seed 5",
+        "workload": f"request stream of Chung-Lu k-truss graphs, n ~ U{{{n_lo}.."
+                    f"{n_hi}}}, mean ~ U[8,64], exponent ~ U[2.0,2.5], seed {seed}",
         "one_per_launch_graphs_per_s": count / t_solo,
         "batched_graphs_per_s": count / t_batch,
         "batched_speedup": t_solo / t_batch,
-        "served": {"arrival_rate_per_s": rate, "graphs_per_s": count / t_srv,
-                   "p50_ms": float(np.percentile(lats, 50)),
-                   "p99_ms": float(np.percentile(lats, 99))},
-        "results_identical": bool(batch_same and served_same),
         "updates": updates,
     }
+    if serve:
+        # served: Poisson arrivals at 80% of the one-graph-per-launch rate
+        rate = 0.8 * count / t_solo
+        gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
+        arrive = np.cumsum(gaps) - gaps[0]
+        srv = nd.Server(ctx, max_slots=64)
+        tickets = []
+        t0 = time.perf_counter()
+        for i, (n, s, d) in enumerate(dev):
+            while time.perf_counter() - t0 < arrive[i]:
+                time.sleep(0.0002)
+            tickets.append(srv.submit(nd.Graph.from_edges(ctx, n, s, d), KIND,
+                                      use_frontier=True))
+        lats = []
+        for t, want in zip(tickets, solo):
+            kappa, r, lat = srv.wait(t)
+            lats.append(lat)
+            same &= bool(torch.equal(kappa, want.cpu()))
+        t_srv = time.perf_counter() - t0
+        srv.close()
+        out["served"] = {"arrival_rate_per_s": rate, "graphs_per_s": count / t_srv,
+                         "p50_ms": float(np.percentile(lats, 50)),
+                         "p99_ms": float(np.percentile(lats, 99))}
+    out["results_identical"] = bool(same)
+    return out
 
 
 def main():
@@ -192,6 +195,9 @@ def main():
                          "kernel for scaling hardware byte counters)")
     ap.add_argument("--stream-graphs", type=int, default=96,
                     help="graphs in the batched/served comparison (0: skip)")
+    ap.add_argument("--small-graphs", type=int, default=512,
+                    help="graphs in the small-graph batched comparison "
+                         "(0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU "
@@ -310,6 +316,10 @@ def main():
     }
     if args.stream_graphs > 0:
         line["stream"] = stream_leg(nd, ctx, args.stream_graphs)
+    if args.small_graphs > 0:
+        # the launch-bound end of the stream: n ~ U{1000..5000}
+        line["small_graphs"] = stream_leg(nd, ctx, args.small_graphs, seed=7,
+                                          n_lo=1000, n_hi=5000, serve=False)
     if not args.no_cpu:
         cb = cpu_baseline(raw, KIND, args.cpu_budget)
         cb["time_to_exact_s_est"] = full_equiv / cb["value"]

@@ -210,7 +210,9 @@ nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
  * list swept by each launch; a graph stops being swept once one of its sweeps
  * changes nothing.  kappas[i] receives graph i's result (device pointers if
  * on_device), res[i] its statistics (res may be NULL).  Results equal those
- * of nd_decompose on each graph alone. */
+ * of nd_decompose on each graph alone.  opts: mode, max_iters and
+ * use_frontier apply to every graph; on_iter and stop_active_ratio give
+ * ND_ERR_UNSUPPORTED. */
 nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
                              nd_graph *const *graphs, nd_kind kind,
                              const nd_opts *opts, int32_t *const *kappas,
@@ -229,7 +231,7 @@ nd_status nd_server_create(nd_ctx *ctx, int32_t max_slots, int32_t max_queue,
 /* Submit: the server takes ownership of g (destroyed when the request ends)
  * and writes the result to host buffer kappa[|R|] (caller keeps it alive
  * until nd_server_wait returns for this ticket).  ND_ERR_BUSY when
- * max_queue requests are waiting. */
+ * max_queue requests are waiting.  opts as for nd_batch_decompose. */
 nd_status nd_server_submit(nd_server *srv, nd_graph *g, nd_kind kind,
                            const nd_opts *opts, int32_t *kappa,
                            uint64_t *ticket);

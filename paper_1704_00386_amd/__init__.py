@@ -335,7 +335,8 @@ class Graph:
 
 
 def batch_decompose(ctx: Context, graphs: Sequence[Graph], kind: str,
-                    mode: str = "snd", max_iters: int = -1, stream=None):
+                    mode: str = "snd", max_iters: int = -1,
+                    use_frontier: bool = False, stream=None):
     """Decompose several graphs in one combined sweep; returns ([kappa],
     [result dict])."""
     count = len(graphs)
@@ -347,7 +348,7 @@ def batch_decompose(ctx: Context, graphs: Sequence[Graph], kind: str,
         outs.append(k[:nr])
         ptrs[i] = k.data_ptr()
         hs[i] = g._h
-    o, keep = _make_opts(mode, max_iters)
+    o, keep = _make_opts(mode, max_iters, use_frontier)
     res = (nd_result * max(count, 1))()
     _check(_lib.nd_batch_decompose(ctx._h, count, hs, KIND[kind],
                                    ctypes.byref(o), ptrs, 1, _stream(stream),
@@ -370,8 +371,8 @@ class Server:
         self._bufs = {}
 
     def submit(self, graph: Graph, kind: str, mode: str = "snd",
-               max_iters: int = -1) -> int:
-        o, keep = _make_opts(mode, max_iters)
+               max_iters: int = -1, use_frontier: bool = False) -> int:
+        o, keep = _make_opts(mode, max_iters, use_frontier)
         n_r = _server_rcount(graph, kind)
         buf = torch.empty(max(n_r, 1), dtype=torch.int32, pin_memory=True)
         t = ctypes.c_uint64()

@@ -21,6 +21,8 @@ struct BGraph {
   SweepStats *ring;    // counters of sweep t at ring[t % kBatchRing]
   int64_t t0;          // epoch at which the graph joined
   int64_t max_local;   // sweeps allowed
+  uint8_t *act[2];     // frontier stamps: sweep t reads act[t & 1]
+  unsigned long long notify_below;  // start notifying at <= this many changes
 };
 
 // A run of r-cliques of one graph and one sweep bin.
@@ -48,8 +50,9 @@ struct BState {
 };
 
 struct BatchConfig {
-  int grid = 2048;       // workgroups of the persistent sweep kernel
-  int tile_passes = 1;   // block passes per tile
+  int grid = 2048;          // workgroups of the persistent sweep kernel
+  int tiles_per_group = 8;  // target tiles per workgroup and epoch; sets the
+                            // tile length (block passes per tile)
 };
 
 // One graph taking part in a batch.
@@ -64,6 +67,7 @@ struct Member {
   int slot = -1;          // index in the device descriptor table
   int64_t ntiles = 0;     // tiles it contributes
   DArr<uint8_t> tau0, tau1;
+  DArr<uint8_t> act0, act1;  // frontier batches only
   DArr<SweepStats> ring;
 };
 
@@ -72,7 +76,7 @@ class Batch {
   static constexpr int kGraphEpochs = 8;  // epochs per captured HIP graph
 
   // Work is issued on a private stream ordered after `caller`.
-  Batch(nd_ctx *ctx, nd_kind kind, nd_mode mode, bool tau16,
+  Batch(nd_ctx *ctx, nd_kind kind, nd_mode mode, bool tau16, bool frontier,
         hipStream_t caller);
   ~Batch();
   Batch(const Batch &) = delete;
@@ -85,10 +89,13 @@ class Batch {
   void run_epochs(int count);
   // Update sweeps/converged/finished of every member from the device.
   void poll(int epochs_run);
-  // Pick tile and grid sizes (cached per shape); restores tau_0.
-  void autotune();
+  // Pick tile and grid sizes (cached per shape).  Returns the number of
+  // real epochs it ran (0 or 1), which the caller then polls.
+  int autotune();
+  static constexpr float kTuneSkipMs = 2.0f;
   const void *result_tau(const Member &m) const;
   bool tau16() const { return tau16_; }
+  bool frontier() const { return frontier_; }
   nd_kind kind() const { return kind_; }
   nd_mode mode() const { return mode_; }
   hipStream_t stream() const { return s_; }
@@ -103,7 +110,7 @@ class Batch {
   void rebuild();
   void set_config(const BatchConfig &c);
   void launch_epoch();
-  template <int K, typename T, bool AND>
+  template <int K, typename T, bool AND, bool FR>
   void launch_epoch_t();
   void drop_graph();
 
@@ -111,6 +118,8 @@ class Batch {
   nd_kind kind_;
   nd_mode mode_;
   bool tau16_;
+  bool frontier_;
+  int notify_div_ = 32;
   hipStream_t s_ = nullptr;
   BatchConfig cfg_;
   std::vector<std::unique_ptr<Member>> members_;

@@ -13,14 +13,19 @@
 // table sizes live in device memory -- so a chunk of epochs is captured once
 // in a HIP graph and replayed until the table outgrows its buffers.
 //
-// Tile and grid sizes come from a small autotuner: the first batch of a given
-// shape times one sweep under each candidate on scratch state, keeps the
-// fastest, and caches it by (kind, mode, tau width, work bucket).
+// Tile and grid sizes come from a small autotuner, cached by (kind, mode,
+// tau width, frontier, work bucket): a batch whose first sweep is short
+// (launch-bound) times one trial sweep per candidate on scratch state and
+// keeps the fastest; a longer one keeps the default, since there the
+// configuration hardly matters and each trial would cost a whole sweep.
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -42,6 +47,11 @@ __host__ __device__ constexpr int rclq_per_pass(int type) {
   return type == kBinG1 ? 256 : type == kBinG4 ? 64 : type == kBinG16 ? 16 : 4;
 }
 
+// Largest incidence count of one pass, in units of 1024: passes of the
+// G-bins cover at most 1024 incidences (R per pass x largest d_s of the
+// bin); a pass of the wave bin (4 R of d_s < 2048) up to 8x that.
+constexpr int pass_units(int type) { return type == kBinWave ? 8 : 1; }
+
 __device__ __forceinline__ bool graph_live(const BGraph &G, int64_t e,
                                            int64_t *local) {
   *local = e - G.t0;
@@ -49,7 +59,29 @@ __device__ __forceinline__ bool graph_live(const BGraph &G, int64_t e,
   return *local == 0 || changed_sum(&G.ring[(*local - 1) % kBatchRing]) != 0;
 }
 
-template <int K, typename T, bool AND>
+// Frontier state of graph G's sweep `local` (the rule of the one-graph
+// sweep, per graph): flags are read only if the previous sweep wrote them,
+// and notifications start once a sweep changed at most G.notify_below.
+template <bool FR>
+__device__ __forceinline__ void graph_frontier(const BGraph &G, int64_t local,
+                                               SweepStats *sst,
+                                               const uint8_t **act,
+                                               uint8_t **act_next,
+                                               uint8_t *stamp) {
+  *act = nullptr;
+  *act_next = nullptr;
+  *stamp = 0;
+  if (!FR || local == 0) return;
+  const SweepStats *prev = &G.ring[(local - 1) % kBatchRing];
+  const bool valid = prev->notified != 0;
+  const bool notify = valid || changed_sum(prev) <= G.notify_below;
+  *act = valid ? G.act[local & 1] : nullptr;
+  *act_next = notify ? G.act[(local + 1) & 1] : nullptr;
+  *stamp = sweep_stamp(local);
+  if (notify && threadIdx.x == 0) sst->notified = 1;
+}
+
+template <int K, typename T, bool AND, bool FR>
 __global__ __launch_bounds__(256) void k_batch_sweep(
     const BGraph *__restrict__ gs, const BTile *__restrict__ tiles,
     BState *__restrict__ st) {
@@ -70,38 +102,41 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
     const T *in = (const T *)G.tau[local & 1];
     T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
     SweepStats *sst = &G.ring[local % kBatchRing];
+    const uint8_t *act;
+    uint8_t *act_next, stamp;
+    graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp);
     const int per = rclq_per_pass(tile.type);
     for (int64_t base = tile.lo; base < tile.hi; base += per) {
       bool ch = false, ev = false;
       switch (tile.type) {
         case kBinG1: {
           const int64_t R = base + threadIdx.x;
-          ch = update_regs<K, 1, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                            R < tile.hi, nullptr, nullptr, &ev);
+          ch = update_regs<K, 1, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                            R < tile.hi, act, act_next, stamp, &ev);
           break;
         }
         case kBinG4: {
           const int64_t R = base + threadIdx.x / 4;
-          ch = update_regs<K, 4, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                            R < tile.hi, nullptr, nullptr, &ev);
+          ch = update_regs<K, 4, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                            R < tile.hi, act, act_next, stamp, &ev);
           break;
         }
         case kBinG16: {
           const int64_t R = base + threadIdx.x / 16;
-          ch = update_regs<K, 16, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1,
-                                             R, R < tile.hi, nullptr, nullptr, &ev);
+          ch = update_regs<K, 16, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                             R, R < tile.hi, act, act_next, stamp, &ev);
           break;
         }
         case kBinG64: {
           const int64_t R = base + threadIdx.x / 64;
-          ch = update_regs<K, 64, 4, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1,
-                                             R, R < tile.hi, nullptr, nullptr, &ev);
+          ch = update_regs<K, 64, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                             R, R < tile.hi, act, act_next, stamp, &ev);
           break;
         }
         default: {  // kBinWave
           const int64_t R = base + threadIdx.x / 64;
-          ch = update_regs<K, 64, 32, T, AND, false>(G.inc_off, G.inc_ids, in, out, 1,
-                                              R, R < tile.hi, nullptr, nullptr, &ev);
+          ch = update_regs<K, 64, 32, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                              R, R < tile.hi, act, act_next, stamp, &ev);
           break;
         }
       }
@@ -111,7 +146,7 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
 }
 
 // r-cliques with d_s >= 2048: one workgroup each, grid-stride over the list.
-template <int K, typename T, bool AND>
+template <int K, typename T, bool AND, bool FR>
 __global__ __launch_bounds__(kBlockThreads) void k_batch_hubs(
     const BGraph *__restrict__ gs, const BHub *__restrict__ hubs,
     const BState *__restrict__ st) {
@@ -125,11 +160,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch_hubs(
     if (!graph_live(G, e, &local)) continue;
     const T *in = (const T *)G.tau[local & 1];
     T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
+    SweepStats *sst = &G.ring[local % kBatchRing];
+    const uint8_t *act;
+    uint8_t *act_next, stamp;
+    graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp);
     bool ev;
-    const bool ch = update_block<K, T, AND, false>(G.inc_off, G.inc_ids, in,
-                                                   out, 1, hb.R, hist, nullptr,
-                                                   nullptr, &ev);
-    stat_add(&G.ring[local % kBatchRing], ch, ev);
+    const bool ch = update_block<K, T, AND, FR>(G.inc_off, G.inc_ids, in, out,
+                                                1, hb.R, hist, act, act_next,
+                                                stamp, &ev);
+    stat_add(sst, ch, ev);
   }
 }
 
@@ -171,10 +210,10 @@ __global__ void k_collect(const BGraph *__restrict__ gs, int ng, int64_t e_end,
 }
 
 struct TuneKey {
-  int kind, mode, t16, bucket;
+  int kind, mode, t16, fr, bucket;
   bool operator<(const TuneKey &o) const {
-    return std::tie(kind, mode, t16, bucket) <
-           std::tie(o.kind, o.mode, o.t16, o.bucket);
+    return std::tie(kind, mode, t16, fr, bucket) <
+           std::tie(o.kind, o.mode, o.t16, o.fr, o.bucket);
   }
 };
 std::mutex g_tune_mu;
@@ -194,9 +233,10 @@ int work_bucket(int64_t P) {
 // ------------------------------------------------------------ Batch
 
 Batch::Batch(nd_ctx *ctx, nd_kind kind, nd_mode mode, bool tau16,
-             hipStream_t caller)
-    : ctx_(ctx), kind_(kind), mode_(mode), tau16_(tau16) {
+             bool frontier, hipStream_t caller)
+    : ctx_(ctx), kind_(kind), mode_(mode), tau16_(tau16), frontier_(frontier) {
   cfg_ = default_config(ctx);
+  if (const char *v = getenv("ND_FRONTIER_SWITCH")) notify_div_ = atoi(v);
   if (const char *v = getenv("ND_BATCH_NO_GRAPH")) use_graph = v[0] != '1';
   ND_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
   hipEvent_t ev;
@@ -237,7 +277,7 @@ void Batch::drop_graph() {
 BatchConfig Batch::default_config(nd_ctx *ctx) {
   BatchConfig c;
   c.grid = ctx->num_cu * 8;
-  c.tile_passes = 1;
+  c.tiles_per_group = 8;
   return c;
 }
 
@@ -257,6 +297,10 @@ Member *Batch::add(nd_graph *g, int32_t max_iters, void *user) {
   m->tau0.reset(ctx_->alloc, tb);
   if (mode_ == ND_SND) m->tau1.reset(ctx_->alloc, tb);
   m->ring.reset(ctx_->alloc, kBatchRing);
+  if (frontier_) {
+    m->act0.reset(ctx_->alloc, std::max<int64_t>(ks.nr, 1));
+    m->act1.reset(ctx_->alloc, std::max<int64_t>(ks.nr, 1));
+  }
   init_member_tau(*m);
   if (ks.nr == 0 || m->max_local == 0) {
     m->finished = true;
@@ -279,6 +323,10 @@ void Batch::init_member_tau(Member &m) {
   if (mode_ == ND_SND)
     ND_HIP(hipMemcpyAsync(m.tau1.p, m.tau0.p, (tau16_ ? 2 : 4) * ks.nr,
                           hipMemcpyDeviceToDevice, s_));
+  if (frontier_) {  // no stamps yet
+    fill_u8(m.act0.p, 0, ks.nr, s_);
+    fill_u8(m.act1.p, 0, ks.nr, s_);
+  }
 }
 
 std::vector<std::unique_ptr<Member>> Batch::take_finished() {
@@ -297,6 +345,19 @@ void Batch::rebuild() {
   std::vector<BTile> ht[kBinZero];  // per bin type; heaviest bins first
   std::vector<BHub> hh;
   int64_t work = 0;
+  // Tile length: tiles hold about equal work bounds (pass_units) and an
+  // epoch has about grid * tiles_per_group of them -- each costs one atomic
+  // on the shared tile counter -- but never less than one block pass.
+  int64_t units_total = 0;
+  for (auto &mp : members_) {
+    if (mp->finished) continue;
+    const KindState &ks = mp->g->ks[kind_];
+    for (int b = kBinWave; b < kBinZero; b++)
+      units_total += (ks.bin_hi[b] - ks.bin_lo[b] + rclq_per_pass(b) - 1) /
+                     rclq_per_pass(b) * pass_units(b);
+  }
+  const int64_t target = (int64_t)cfg_.grid * cfg_.tiles_per_group;
+  const int64_t units = std::max<int64_t>(1, units_total / std::max<int64_t>(target, 1));
   for (auto &mp : members_) {
     Member &m = *mp;
     m.slot = -1;
@@ -313,13 +374,21 @@ void Batch::rebuild() {
     G.ring = m.ring.p;
     G.t0 = m.t0;
     G.max_local = m.max_local;
+    if (frontier_) {
+      G.act[0] = m.act0.p;
+      G.act[1] = m.act1.p;
+      G.notify_below = notify_div_ <= 0
+                           ? ~0ull
+                           : (unsigned long long)(ks.bin_lo[kBinZero] / notify_div_);
+    }
     hg.push_back(G);
     work += ks.P;
     for (int64_t R = ks.bin_lo[kBinBlock]; R < ks.bin_hi[kBinBlock]; R++)
       hh.push_back(BHub{gi, 0, R});
     for (int b = kBinWave; b < kBinZero; b++) {
       const int64_t lo = ks.bin_lo[b], hi = ks.bin_hi[b];
-      const int64_t step = (int64_t)rclq_per_pass(b) * cfg_.tile_passes;
+      const int64_t passes = std::max<int64_t>(1, units / pass_units(b));
+      const int64_t step = (int64_t)rclq_per_pass(b) * passes;
       for (int64_t x = lo; x < hi; x += step) {
         ht[b].push_back(BTile{gi, b, x, std::min(hi, x + step)});
         m.ntiles++;
@@ -364,37 +433,39 @@ void Batch::rebuild() {
   dirty_ = false;
 }
 
-template <int K, typename T, bool AND>
+template <int K, typename T, bool AND, bool FR>
 void Batch::launch_epoch_t() {
   k_epoch_begin<<<kBeginGrid, 256, 0, s_>>>(gs_.p, state_.p);
   ND_LAUNCHED();
-  k_batch_sweep<K, T, AND><<<cfg_.grid, 256, 0, s_>>>(gs_.p, tiles_.p,
-                                                       state_.p);
+  k_batch_sweep<K, T, AND, FR><<<cfg_.grid, 256, 0, s_>>>(gs_.p, tiles_.p,
+                                                           state_.p);
   ND_LAUNCHED();
-  k_batch_hubs<K, T, AND><<<kHubGrid, kBlockThreads, 0, s_>>>(gs_.p, hubs_.p,
-                                                              state_.p);
+  k_batch_hubs<K, T, AND, FR><<<kHubGrid, kBlockThreads, 0, s_>>>(
+      gs_.p, hubs_.p, state_.p);
   ND_LAUNCHED();
   k_epoch_end<<<1, 1, 0, s_>>>(state_.p);
   ND_LAUNCHED();
 }
 
 void Batch::launch_epoch() {
-  const int key = (kind_ == ND_KCORE ? 1 : kind_ == ND_KTRUSS ? 2 : 3) * 4 +
-                  (tau16_ ? 2 : 0) + (mode_ == ND_AND ? 1 : 0);
+  const int k = kind_ == ND_KCORE ? 1 : kind_ == ND_KTRUSS ? 2 : 3;
+  const int key = (k * 2 + (tau16_ ? 1 : 0)) * 4 + (mode_ == ND_AND ? 2 : 0) +
+                  (frontier_ ? 1 : 0);
+#define ND_EPOCH_CASES(KK, T, BASE)                                   \
+  case BASE + 0: launch_epoch_t<KK, T, false, false>(); break;       \
+  case BASE + 1: launch_epoch_t<KK, T, false, true>(); break;        \
+  case BASE + 2: launch_epoch_t<KK, T, true, false>(); break;        \
+  case BASE + 3: launch_epoch_t<KK, T, true, true>(); break;
   switch (key) {
-    case 4: launch_epoch_t<1, int32_t, false>(); break;
-    case 5: launch_epoch_t<1, int32_t, true>(); break;
-    case 6: launch_epoch_t<1, uint16_t, false>(); break;
-    case 7: launch_epoch_t<1, uint16_t, true>(); break;
-    case 8: launch_epoch_t<2, int32_t, false>(); break;
-    case 9: launch_epoch_t<2, int32_t, true>(); break;
-    case 10: launch_epoch_t<2, uint16_t, false>(); break;
-    case 11: launch_epoch_t<2, uint16_t, true>(); break;
-    case 12: launch_epoch_t<3, int32_t, false>(); break;
-    case 13: launch_epoch_t<3, int32_t, true>(); break;
-    case 14: launch_epoch_t<3, uint16_t, false>(); break;
-    default: launch_epoch_t<3, uint16_t, true>(); break;
+    ND_EPOCH_CASES(1, int32_t, 8)
+    ND_EPOCH_CASES(1, uint16_t, 12)
+    ND_EPOCH_CASES(2, int32_t, 16)
+    ND_EPOCH_CASES(2, uint16_t, 20)
+    ND_EPOCH_CASES(3, int32_t, 24)
+    ND_EPOCH_CASES(3, uint16_t, 28)
+    default: ND_REQUIRE(false, ND_ERR_INVALID, "bad batch key %d", key);
   }
+#undef ND_EPOCH_CASES
 }
 
 void Batch::run_epochs(int count) {
@@ -452,45 +523,80 @@ const void *Batch::result_tau(const Member &m) const {
 }
 
 void Batch::set_config(const BatchConfig &c) {
-  if (c.grid != cfg_.grid || c.tile_passes != cfg_.tile_passes) {
+  if (c.grid != cfg_.grid || c.tiles_per_group != cfg_.tiles_per_group) {
     cfg_ = c;
     dirty_ = true;
     drop_graph();
   }
 }
 
-// Time one sweep of every member under each candidate, then restore tau_0 and
-// the epoch (the trial sweeps write only buffers that are re-initialised).
-void Batch::autotune() {
+// Pick the launch configuration.  The first epoch runs under the default
+// configuration and counts as a real sweep; if it took kTuneSkipMs or more
+// the batch is in the bandwidth-bound regime where the configuration hardly
+// matters, and the default is kept (trials would cost whole sweeps).  A
+// shorter (launch-bound) batch times one trial epoch per candidate on
+// scratch state, then restores tau_0 and the epoch, so no epoch counts.
+// Returns the real epochs run (0 or 1); the caller polls them.
+int Batch::autotune() {
   StreamScope scope(s_);
   if (dirty_) rebuild();
-  if (ng_ == 0) return;
-  TuneKey key{(int)kind_, (int)mode_, tau16_ ? 1 : 0, work_bucket(work_)};
+  if (ng_ == 0) return 0;
+  TuneKey key{(int)kind_, (int)mode_, tau16_ ? 1 : 0, frontier_ ? 1 : 0,
+              work_bucket(work_)};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       set_config(it->second);
-      return;
+      return 0;
     }
   }
-  const int cus = ctx_->num_cu;
-  std::vector<BatchConfig> cand;
-  for (int gm : {4, 8, 16})
-    for (int tp : {1, 4}) {
-      BatchConfig c;
-      c.grid = cus * gm;
-      c.tile_passes = tp;
-      cand.push_back(c);
-    }
   hipEvent_t a, b;
   ND_HIP(hipEventCreate(&a));
   ND_HIP(hipEventCreate(&b));
-  float best = 1e30f;
-  BatchConfig best_cfg = cfg_;
+  auto time_epoch = [&]() {
+    ND_HIP(hipEventRecord(a, s_));
+    launch_epoch();
+    ND_HIP(hipEventRecord(b, s_));
+    ND_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    ND_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  };
   const int64_t e0 = epoch_;
-  for (const BatchConfig &c : cand) {
-    set_config(c);
+  const BatchConfig dflt = default_config(ctx_);
+  set_config(dflt);
+  if (dirty_) rebuild();
+  const float first = time_epoch();
+  int real = 0;
+  BatchConfig best_cfg = dflt;
+  float best = first;
+  if (first >= kTuneSkipMs) {
+    epoch_ += 1;
+    real = 1;
+  } else {
+    const int cus = ctx_->num_cu;
+    for (int gm : {4, 8, 16})
+      for (int tpg : {4, 16}) {
+        BatchConfig c;
+        c.grid = cus * gm;
+        c.tiles_per_group = tpg;
+        set_config(c);
+        rebuild();
+        BState z{};
+        z.epoch = e0;
+        z.ntiles = ntiles_;
+        z.nhubs = nhubs_;
+        z.ng = ng_;
+        ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
+        const float ms = time_epoch();
+        if (ms < best) {
+          best = ms;
+          best_cfg = c;
+        }
+      }
+    for (auto &mp : members_) init_member_tau(*mp);
+    set_config(best_cfg);
     rebuild();
     BState z{};
     z.epoch = e0;
@@ -498,35 +604,87 @@ void Batch::autotune() {
     z.nhubs = nhubs_;
     z.ng = ng_;
     ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
-    ND_HIP(hipEventRecord(a, s_));
-    launch_epoch();
-    ND_HIP(hipEventRecord(b, s_));
-    ND_HIP(hipEventSynchronize(b));
-    float ms = 0;
-    ND_HIP(hipEventElapsedTime(&ms, a, b));
-    if (ms < best) {
-      best = ms;
-      best_cfg = c;
-    }
+    ND_HIP(hipStreamSynchronize(s_));
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  for (auto &mp : members_) init_member_tau(*mp);
-  set_config(best_cfg);
-  rebuild();
-  BState z{};
-  z.epoch = e0;
-  z.ntiles = ntiles_;
-  z.nhubs = nhubs_;
-  z.ng = ng_;
-  ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
-  ND_HIP(hipStreamSynchronize(s_));
   tuned_ms = best;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best_cfg;
+  return real;
 }
 
 // ------------------------------------------------------- batch ABI
+
+namespace {
+
+constexpr int kPrepThreads = 4;
+
+// Prepare the graphs that are not yet prepared for `kind`, on up to
+// kPrepThreads host threads with a stream each (ordered after s), so that
+// the short, launch-bound build phases of different graphs overlap; s then
+// waits for every prep stream.  The first failure is rethrown.
+void prepare_all(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
+                 nd_kind kind, hipStream_t s) {
+  std::vector<nd_graph *> todo;
+  for (int i = 0; i < count; i++)
+    if (!graphs[i]->ks[kind].ready &&
+        std::find(todo.begin(), todo.end(), graphs[i]) == todo.end())
+      todo.push_back(graphs[i]);
+  if (todo.size() <= 1) {
+    for (nd_graph *g : todo) prepare(g, kind, s);
+    return;
+  }
+  const int nt = (int)std::min<size_t>(kPrepThreads, todo.size());
+  hipEvent_t start;
+  ND_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  ND_HIP(hipEventRecord(start, s));
+  std::vector<hipStream_t> streams(nt, nullptr);
+  for (int t = 0; t < nt; t++) {
+    ND_HIP(hipStreamCreateWithFlags(&streams[t], hipStreamNonBlocking));
+    ND_HIP(hipStreamWaitEvent(streams[t], start, 0));
+  }
+  (void)hipEventDestroy(start);
+  std::atomic<size_t> next{0};
+  std::atomic<bool> failed{false};
+  std::vector<nd_status> codes(nt, ND_OK);
+  std::vector<std::string> msgs(nt);
+  std::vector<std::thread> threads;
+  for (int t = 0; t < nt; t++)
+    threads.emplace_back([&, t] {
+      try {
+        ND_HIP(hipSetDevice(ctx->device));
+        StreamScope scope(streams[t]);
+        for (size_t i; !failed && (i = next++) < todo.size();)
+          prepare(todo[i], kind, streams[t]);
+      } catch (const Err &e) {
+        codes[t] = e.code;
+        msgs[t] = nd_last_error();
+        failed = true;
+      } catch (const std::exception &e) {
+        codes[t] = ND_ERR_DEVICE;
+        msgs[t] = e.what();
+        failed = true;
+      }
+    });
+  for (auto &th : threads) th.join();
+  for (int t = 0; t < nt; t++) {
+    hipEvent_t done;
+    ND_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    ND_HIP(hipEventRecord(done, streams[t]));
+    ND_HIP(hipStreamWaitEvent(s, done, 0));
+    (void)hipEventDestroy(done);
+    ctx->alloc.forget_stream(streams[t]);
+    (void)hipStreamDestroy(streams[t]);
+  }
+  for (int t = 0; t < nt; t++)
+    if (codes[t] != ND_OK) {
+      set_error("%s", msgs[t].c_str());
+      throw Err(codes[t]);
+    }
+}
+
+}  // namespace
 
 nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
                           nd_kind kind, const nd_opts *opts_in,
@@ -537,30 +695,32 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
   if (opts_in) opts = *opts_in;
   ND_REQUIRE(opts.mode == ND_SND || opts.mode == ND_AND, ND_ERR_INVALID,
              "unknown mode");
-  ND_REQUIRE(!opts.use_frontier && opts.on_iter == nullptr &&
-                 opts.stop_active_ratio == 0,
+  ND_REQUIRE(opts.on_iter == nullptr && opts.stop_active_ratio == 0,
              ND_ERR_UNSUPPORTED,
-             "batched decomposition supports mode and max_iters only");
+             "batched decomposition supports mode, max_iters and use_frontier");
   bool all16 = true;
   std::vector<double> prep(count, 0.0);
+  std::vector<bool> was(count);
   for (int i = 0; i < count; i++) {
     ND_REQUIRE(graphs[i] && graphs[i]->ctx == ctx, ND_ERR_INVALID,
                "graph %d is NULL or from another context", i);
-    const bool was = graphs[i]->ks[kind].ready;
-    prepare(graphs[i], kind, s);
-    prep[i] = was ? 0.0 : graphs[i]->ks[kind].ms_prep;
+    was[i] = graphs[i]->ks[kind].ready;
+  }
+  prepare_all(ctx, count, graphs, kind, s);
+  for (int i = 0; i < count; i++) {
+    prep[i] = was[i] ? 0.0 : graphs[i]->ks[kind].ms_prep;
     all16 &= graphs[i]->ks[kind].tau16;
   }
-  Batch batch(ctx, kind, opts.mode, all16, s);
+  Batch batch(ctx, kind, opts.mode, all16, opts.use_frontier != 0, s);
   hipStream_t bs = batch.stream();
   std::vector<Member *> ms;
   for (int i = 0; i < count; i++)
     ms.push_back(batch.add(graphs[i], opts.max_iters, nullptr));
-  batch.autotune();
   hipEvent_t a, b;
   ND_HIP(hipEventCreate(&a));
   ND_HIP(hipEventCreate(&b));
   ND_HIP(hipEventRecord(a, bs));
+  batch.poll(batch.autotune());
   int chunk = 2;
   for (;;) {
     bool any = false;

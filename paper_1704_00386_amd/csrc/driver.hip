@@ -14,6 +14,7 @@
 
 #include "api_util.h"
 #include "internal.h"
+#include "sweep_dev.h"
 
 namespace nd {
 
@@ -104,6 +105,8 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   if (frontier) {
     act[0].reset(al, nr);
     act[1].reset(al, nr);
+    fill_u8(act[0].p, 0, nr, s);  // no stamps yet
+    fill_u8(act[1].p, 0, nr, s);
     int div = 32;
     if (const char *v = getenv("ND_FRONTIER_SWITCH")) div = atoi(v);
     notify_below = div <= 0 ? ~0ull : (unsigned long long)(ks.bin_lo[kBinZero] / div);
@@ -147,8 +150,8 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
       if (frontier) {
         a.act = act[t & 1].p;
         a.act_next = act[(t + 1) & 1].p;
+        a.stamp = dev::sweep_stamp(t);
         a.notify_below = notify_below;
-        fill_u8(act[(t + 1) & 1].p, 0, nr, s);
       }
       if (step_by_step) one.start(s);
       launch_sweep(ks, a, and_mode, s);

@@ -120,11 +120,11 @@ namespace nd {
 
 // ---------------------------------------------------------- sweep bins
 
-// r-cliques are numbered internally by descending S-degree (ties by id), so
-// every sweep bin is a contiguous range of internal ids, hot tau values (those
-// gathered most often: a tau value is read once per s-clique it shares) sit
-// together at the front, and zero-degree r-cliques (never swept) sit at the
-// end.  Bins in internal order, with their d_s ranges:
+// r-cliques are numbered internally by sweep bin, ascending id within a bin,
+// so every sweep bin is a contiguous range of internal ids, r-cliques that
+// share vertices stay close together (their gathers hit nearby cache lines),
+// and zero-degree r-cliques (never swept) sit at the end.  Bins in internal
+// order, with their d_s ranges:
 enum SweepBin : int {
   kBinBlock = 0,  // d_s >= 2048:  one workgroup per r-clique, LDS histogram
   kBinWave,       // 257..2047:    one wave, 32 values per lane in registers
@@ -274,8 +274,9 @@ struct SweepArgs {
   // Frontier (Section 4.3 notifications), both NULL when off: only
   // r-cliques with act[R] != 0 are recomputed; a changed one sets act_next
   // for every neighbour whose value is above its new value.
-  const uint8_t *act;
+  const uint8_t *act;       // flags of this sweep (stamps, see sweep_dev.h)
   uint8_t *act_next;
+  uint8_t stamp;            // this sweep's stamp
   // Notifications start once a sweep changes at most this many r-cliques
   // (before that nearly everything is active and notifying costs as much as
   // the gathers it would save); from then on every sweep notifies and the

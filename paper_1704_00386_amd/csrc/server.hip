@@ -55,8 +55,8 @@ struct nd_server {
   int active = 0;
   uint64_t next_ticket = 1;
   hipStream_t stream = nullptr;
-  // one batch per (kind, mode, tau width)
-  std::unique_ptr<nd::Batch> batches[3][2][2];
+  // one batch per (kind, mode, tau width, frontier)
+  std::unique_ptr<nd::Batch> batches[3][2][2][2];
 };
 
 namespace nd {
@@ -126,10 +126,11 @@ bool admit(nd_server *srv, Request *r) {
     const KindState &ks = r->g->ks[r->kind];
     const int mi = r->opts.mode == ND_AND ? 1 : 0;
     const int wi = ks.tau16 ? 1 : 0;
-    auto &slot = srv->batches[r->kind][mi][wi];
+    const int fi = r->opts.use_frontier ? 1 : 0;
+    auto &slot = srv->batches[r->kind][mi][wi][fi];
     if (!slot)
       slot = std::make_unique<Batch>(srv->ctx, r->kind, r->opts.mode, ks.tau16,
-                                     srv->stream);
+                                     fi != 0, srv->stream);
     r->member = slot->add(r->g, r->opts.max_iters, r);
     r->batch = slot.get();
     return true;
@@ -184,7 +185,8 @@ void worker_main(nd_server *srv) {
     bool any = false;
     for (auto &bk : srv->batches)
       for (auto &bm : bk)
-        for (auto &b : bm) {
+        for (auto &bw : bm)
+          for (auto &b : bw) {
           if (!b || b->size() == 0) continue;
           any = true;
           try {
@@ -258,8 +260,8 @@ nd_status nd_server_submit(nd_server *srv, nd_graph *g, nd_kind kind,
     if (opts) o = *opts;
     ND_REQUIRE(o.mode == ND_SND || o.mode == ND_AND, ND_ERR_INVALID,
                "unknown mode");
-    ND_REQUIRE(!o.use_frontier && !o.on_iter && o.stop_active_ratio == 0,
-               ND_ERR_UNSUPPORTED, "served requests support mode and max_iters");
+    ND_REQUIRE(!o.on_iter && o.stop_active_ratio == 0, ND_ERR_UNSUPPORTED,
+               "served requests support mode, max_iters and use_frontier");
     auto r = std::make_unique<Request>();
     r->g = g;
     r->kind = kind;
@@ -335,7 +337,8 @@ void nd_server_destroy(nd_server *srv) {
   (void)hipSetDevice(srv->ctx->device);
   for (auto &bk : srv->batches)
     for (auto &bm : bk)
-      for (auto &b : bm) b.reset();
+      for (auto &bw : bm)
+        for (auto &b : bw) b.reset();
   for (auto &kv : srv->reqs) release_graph(kv.second.get());
   srv->reqs.clear();
   srv->ctx->alloc.forget_stream(srv->stream);

@@ -5,7 +5,7 @@
 //   tau'(R)   = H({rho(S,R)} over the d_s(R) s-cliques S containing R)
 //   changed  += (tau'(R) != tau(R))                         (convergence flag)
 //
-// r-cliques are in the internal numbering (descending d_s), so each bin is a
+// r-cliques are in the internal numbering (grouped by bin), so each bin is a
 // contiguous id range and the incidence lists are read in one sequential,
 // coalesced stream; the tau reads are the random part.  tau is stored as
 // uint16 when every d_s fits (then every tau does: tau <= d_s), halving the
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
   bool ev;
   const bool changed = update_regs<K, G, M, T, AND, FR>(
       a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out, a.cap_by_tau,
-      R, R < hi, act, act_next, &ev);
+      R, R < hi, act, act_next, a.stamp, &ev);
   stat_add(a.stats, changed, ev);
 }
 
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
     bool ev;
     const bool changed = update_block<K, T, AND, FR>(
         a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out,
-        a.cap_by_tau, R, hist, act, act_next, &ev);
+        a.cap_by_tau, R, hist, act, act_next, a.stamp, &ev);
     stat_add(a.stats, changed, ev);
   }
 }

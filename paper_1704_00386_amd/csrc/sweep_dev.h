@@ -129,15 +129,24 @@ template <int K, typename T, bool AND>
 __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
                                        int64_t b, int64_t d, int first,
                                        int stride, int32_t h, const T *tau,
-                                       uint8_t *act_next) {
+                                       uint8_t *act_next, uint8_t stamp_next) {
   for (int64_t j = first; j < d; j += stride) {
     const int32_t *q = ids + K * (b + j);
 #pragma unroll
     for (int x = 0; x < K; x++) {
       const int32_t r = q[x];
-      if (h < load_tau<T, AND>(tau + r)) act_next[r] = 1;
+      if (h < load_tau<T, AND>(tau + r)) act_next[r] = stamp_next;
     }
   }
+}
+
+// Frontier flags hold sweep stamps instead of booleans: sweep t takes part
+// for r-cliques whose flag equals stamp(t) = t mod 255 + 1, and notifies by
+// writing stamp(t+1) into the other array of the pair.  Old stamps never need
+// clearing: a value left from sweep t' matches stamp(t) only when
+// t' = t - 254k (harmless extra work; never a skipped r-clique).
+__host__ __device__ __forceinline__ uint8_t sweep_stamp(int64_t t) {
+  return (uint8_t)(t % 255 + 1);
 }
 
 // One r-clique per subgroup of G lanes (sl = lane within the subgroup), each
@@ -152,14 +161,15 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
                                             const T *tau_in, T *tau_out,
                                             int cap_by_tau, int64_t R,
                                             bool active, const uint8_t *act,
-                                            uint8_t *act_next, bool *evald) {
+                                            uint8_t *act_next, uint8_t stamp,
+                                            bool *evald) {
   const int sl = lane_id() % G;
   int32_t told = 0, c = 0;
   int64_t b = 0, d = 0;
   bool eval = active;
   if (active) {
     told = (int32_t)tau_in[R];
-    if (FR && act && !act[R]) {
+    if (FR && act && act[R] != stamp) {
       eval = false;
       if (!AND && sl == 0) tau_out[R] = (T)told;
     } else {
@@ -180,7 +190,8 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
   const bool lead = sl == 0;
   if (eval && lead) store_tau<T, AND>(tau_out + R, h, ch);
   if (FR && ch && act_next)
-    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next);
+    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next,
+                      stamp == 255 ? 1 : stamp + 1);
   *evald = lead && eval;
   return lead && ch;
 }
@@ -241,10 +252,10 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
                              const int32_t *__restrict__ inc_ids,
                              const T *tau_in, T *tau_out, int cap_by_tau,
                              int64_t R, int32_t *hist, const uint8_t *act,
-                             uint8_t *act_next, bool *evald) {
+                             uint8_t *act_next, uint8_t stamp, bool *evald) {
   const int t = threadIdx.x;
   const int32_t told = (int32_t)tau_in[R];
-  if (FR && act && !act[R]) {
+  if (FR && act && act[R] != stamp) {
     if (!AND && t == 0) tau_out[R] = (T)told;
     *evald = false;
     return false;
@@ -290,7 +301,8 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
   const bool ch = h != told;
   if (t == 0) store_tau<T, AND>(tau_out + R, h, ch);
   if (FR && ch && act_next)
-    notify<K, T, AND>(inc_ids, b, d, t, kBlockThreads, h, tau_in, act_next);
+    notify<K, T, AND>(inc_ids, b, d, t, kBlockThreads, h, tau_in, act_next,
+                      stamp == 255 ? 1 : stamp + 1);
   __syncthreads();
   *evald = t == 0;
   return t == 0 && ch;

@@ -46,12 +46,14 @@ def make(nd, ctx, raw):
 
 @pytest.mark.parametrize("kind", list(KINDS))
 @pytest.mark.parametrize("mode", ["snd", "and"])
-def test_batch_equals_solo_and_oracle(nd, ctx, kind, mode):
+@pytest.mark.parametrize("frontier", [False, True])
+def test_batch_equals_solo_and_oracle(nd, ctx, kind, mode, frontier):
     raws = mixed_graphs()
     r, s = KINDS[kind]
     gs = [make(nd, ctx, raw) for raw in raws]
     solo = [g.decompose(kind, mode) for g in gs]
-    kappas, results = nd.batch_decompose(ctx, gs, kind, mode)
+    kappas, results = nd.batch_decompose(ctx, gs, kind, mode,
+                                         use_frontier=frontier)
     for raw, (ks, rs), kb, rb in zip(raws, solo, kappas, results):
         assert torch.equal(kb, ks), raw.name
         assert rb["converged"] == 1
@@ -79,13 +81,41 @@ def test_batch_replays_with_eager_work_between(nd, ctx):
         torch.cuda.synchronize()
 
 
-def test_batch_many_small_graphs(nd, ctx):
+@pytest.mark.parametrize("frontier", [False, True])
+def test_batch_many_small_graphs(nd, ctx, frontier):
     raws = [chung_lu(int(n), 2.0 + 0.05 * (i % 10), 8.0 + i % 20, seed=100 + i)
             for i, n in enumerate(np.linspace(200, 4000, 64))]
     gs = [make(nd, ctx, raw) for raw in raws]
-    kappas, results = nd.batch_decompose(ctx, gs, "core", "snd")
-    for raw, g, k in zip(raws, gs, kappas):
-        assert torch.equal(k, g.decompose("core", "snd")[0]), raw.name
+    kappas, results = nd.batch_decompose(ctx, gs, "core", "snd",
+                                         use_frontier=frontier)
+    for raw, g, k, rb in zip(raws, gs, kappas, results):
+        want, rs = g.decompose("core", "snd")
+        assert torch.equal(k, want), raw.name
+        # frontier SND computes the same iterates, so the same sweep count
+        assert rb["sweeps"] == rs["sweeps"], raw.name
+
+
+def test_batch_frontier_stamps_wrap(nd, ctx):
+    """More sweeps than the frontier stamps repeat after (510): on a path the
+    k-core iteration lowers one vertex per end per sweep, so SND takes about
+    n/2 sweeps; the frontier results, alone and batched, equal the plain one
+    and the sweep counts agree."""
+    from synth import RawGraph
+    n = 1400
+    raw = RawGraph(n, np.arange(n - 1, dtype=np.int32),
+                   np.arange(1, n, dtype=np.int32), "path")
+    g = make(nd, ctx, raw)
+    want, rs = g.decompose("core", "snd")
+    assert rs["sweeps"] == len(oracle.Graph.from_raw(raw).snd(1, 2)) - 1 > 600
+    k1, r1 = g.decompose("core", "snd", use_frontier=True)
+    assert torch.equal(k1, want) and r1["sweeps"] == rs["sweeps"]
+    kb, rb = nd.batch_decompose(ctx, [g], "core", "snd", use_frontier=True)
+    assert torch.equal(kb[0], want) and rb[0]["sweeps"] == rs["sweeps"]
+    for mode in ("and",):
+        k2, _ = g.decompose("core", mode, use_frontier=True)
+        kb2, _ = nd.batch_decompose(ctx, [g], "core", mode, use_frontier=True)
+        assert torch.equal(k2, want) and torch.equal(kb2[0], want)
+    assert np.array_equal(want.cpu().numpy(), np.ones(n, np.int32))
 
 
 def test_batch_max_iters(nd, ctx):
@@ -111,8 +141,9 @@ def test_server_results_equal_solo(nd, ctx):
             for raw, k, m in zip(raws, kinds, modes)]
     srv = nd.Server(ctx, max_slots=8)
     tickets = []
-    for raw, k, m in zip(raws, kinds, modes):
-        tickets.append(srv.submit(make(nd, ctx, raw), k, m))
+    for i, (raw, k, m) in enumerate(zip(raws, kinds, modes)):
+        tickets.append(srv.submit(make(nd, ctx, raw), k, m,
+                                  use_frontier=i % 2 == 0))
         time.sleep(0.002)  # staggered arrivals: later ones join a running mix
     lats = []
     for t, want in zip(tickets, solo):
