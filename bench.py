@@ -183,6 +183,61 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     return out
 
 
+def quality_leg(nd, name, sample=1_000_000, seed=9):
+    """Per-sweep accuracy of the iterates against the exact result (the
+    approximation trade-off of Sections 5.2-5.3): fraction of r-cliques whose
+    tau_t equals kappa (all of them) and the Kendall-Tau similarity of tau_t
+    and kappa (scipy's tau-b on a uniform sample of r-cliques), with each
+    sweep's device time, for SND and AND on one of the named workloads.
+    Also the stop points of the active-ratio control (stop once fewer than
+    40% / 10% / 1% of the r-cliques changed in a sweep)."""
+    import numpy as np
+    import scipy.stats
+    import torch
+
+    from synth import WORKLOADS, workload
+
+    kind = WORKLOADS[name]["kind"]
+    raw = workload(name)
+    ctx = nd.Context(0)
+    g = nd.Graph.from_edges(ctx, raw.n, torch.from_numpy(raw.src).cuda(),
+                            torch.from_numpy(raw.dst).cuda())
+    g.prepare(kind)
+    kappa, _ = g.decompose(kind, "snd", use_frontier=True)
+    kap = kappa.cpu().numpy()
+    nr = kap.size
+    idx = np.random.default_rng(seed).choice(nr, size=min(sample, nr),
+                                             replace=False)
+    out = {"workload": name, "kind": kind, "n_rcliques": int(nr),
+           "kendall_sample": int(idx.size)}
+    for mode in ("snd", "and"):
+        its, ms = [], []
+
+        def on_iter(info):
+            ms.append(info.ms)
+            return 0
+
+        g.decompose(kind, mode, keep_iterates=its, on_iter=on_iter)
+        tau0 = g.sdegree(kind).cpu().numpy()
+        rows, t_cum = [], 0.0
+        seq = [(None, tau0)] + [(c, t.cpu().numpy()) for c, t in its]
+        for t, (changed, tau) in enumerate(seq):
+            if t > 0:
+                t_cum += ms[t - 1]
+            exact = float(np.count_nonzero(tau == kap)) / max(nr, 1)
+            kt = float(scipy.stats.kendalltau(tau[idx], kap[idx]).statistic)
+            rows.append({"sweep": t, "changed": changed, "ms_cum": t_cum,
+                         "fraction_exact": exact, "kendall_tau": kt})
+        stops = {}
+        for ratio in (0.4, 0.1, 0.01):
+            hit = next((r for r in rows[1:] if r["changed"] < ratio * nr), rows[-1])
+            stops[str(ratio)] = {k: hit[k] for k in ("sweep", "ms_cum",
+                                                     "fraction_exact", "kendall_tau")}
+        out[mode] = {"rows": rows, "active_ratio_stops": stops}
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +250,9 @@ def main():
                          "kernel for scaling hardware byte counters)")
     ap.add_argument("--stream-graphs", type=int, default=96,
                     help="graphs in the batched/served comparison (0: skip)")
+    ap.add_argument("--quality", default=None,
+                    help="only run the per-sweep accuracy leg on this "
+                         "workload (e.g. cl23) and print its JSON")
     ap.add_argument("--small-graphs", type=int, default=512,
                     help="graphs in the small-graph batched comparison "
                          "(0: skip)")
@@ -209,6 +267,10 @@ def main():
 
     import paper_1704_00386_amd as nd
     from synth import workload
+
+    if args.quality:
+        print(json.dumps(quality_leg(nd, args.quality)), flush=True)
+        return
 
     if args.calib_copy:
         a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")

@@ -33,6 +33,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -79,6 +80,24 @@ def erdos_renyi(n: int, p: float, seed: int = 1) -> RawGraph:
     return RawGraph(n, src, dst, f"er(n={n},p={p},seed={seed})")
 
 
+def _searchsorted_threads(cdf: np.ndarray, keys: np.ndarray) -> np.ndarray:
+    """np.searchsorted(cdf, keys, side="right"), over chunks of keys on a
+    thread pool (numpy releases the GIL inside the search)."""
+    if keys.size < (1 << 20):
+        return np.searchsorted(cdf, keys, side="right")
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty(keys.size, dtype=np.int64)
+    bounds = np.linspace(0, keys.size, 65).astype(np.int64)
+
+    def run(i):
+        a, b = bounds[i], bounds[i + 1]
+        out[a:b] = np.searchsorted(cdf, keys[a:b], side="right")
+
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(run, range(64)))
+    return out
+
+
 def chung_lu_weights(n: int, beta: float, mean: float) -> np.ndarray:
     """Capped power-law weights with the requested mean (see module doc)."""
     cap = math.sqrt(n * mean)
@@ -105,9 +124,10 @@ def chung_lu(n: int, beta: float, mean: float, seed: int) -> RawGraph:
     w = chung_lu_weights(n, beta, mean)
     cdf = np.cumsum(w)
     m = int(round(n * mean / 2.0))
-    # Endpoints drawn with probability proportional to w, by inverting the CDF.
+    # Endpoints drawn with probability proportional to w, by inverting the CDF
+    # (the searches run in chunks on a few threads; the result is the same).
     draws = rng.random(2 * m) * cdf[-1]
-    ends = np.searchsorted(cdf, draws, side="right")
+    ends = _searchsorted_threads(cdf, draws)
     np.minimum(ends, n - 1, out=ends)
     perm = rng.permutation(n).astype(np.int32)
     src = perm[ends[:m]]
