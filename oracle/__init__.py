@@ -81,6 +81,9 @@ def _load():
     lib.og_update.restype = ctypes.c_int
     lib.og_update.argtypes = [P, ctypes.c_int, ctypes.c_int, i32p, i32p,
                               ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    lib.og_update_set.restype = ctypes.c_int
+    lib.og_update_set.argtypes = [P, ctypes.c_int, ctypes.c_int, i32p, i32p,
+                                  i32p, ctypes.c_int64, ctypes.c_int]
     lib.og_and_sweep.restype = ctypes.c_int64
     lib.og_and_sweep.argtypes = [P, ctypes.c_int, ctypes.c_int, i32p, i64p]
     lib.og_levels.restype = ctypes.c_int32
@@ -205,6 +208,62 @@ class Graph:
                 break
             tau = nxt
         return seq
+
+    def update_set(self, r: int, s: int, tau, ids,
+                   threads: int | None = None) -> np.ndarray:
+        """U tau on the listed ids only; other entries copy tau."""
+        nr = self.num_rcliques(r)
+        tau = np.ascontiguousarray(tau, dtype=np.int32)
+        if tau.size != nr:
+            raise ValueError("tau has the wrong length")
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        res = tau.copy()
+        if ids.size:
+            self._check(self._lib.og_update_set(self._h, r, s, _i32(tau),
+                                                _i32(res), _i32(ids), ids.size,
+                                                threads or default_threads()))
+        return res
+
+    def partial_and(self, r: int, s: int, ids, max_iters: int = 1 << 30,
+                    threads: int | None = None):
+        """PartialAND (Section 4.3, end): the update operator applied only to
+        the r-cliques in the set P = ids until none of them changes; every
+        other r-clique keeps tau_0 = d_s.  Returns (tau, sweeps, converged)
+        with tau over all r-cliques.
+
+        Taken here as synchronous sweeps over P.  U restricted to P is
+        monotone and tau_0 is above its image, so synchronous and in-place
+        sweeps (in any order) descend to the same limit: the largest fixed
+        point of the restricted operator below tau_0."""
+        tau = self.sdeg(r, s, threads)
+        P = np.unique(np.asarray(ids, dtype=np.int32))
+        sweeps = 0
+        while sweeps < max_iters:
+            nxt = self.update_set(r, s, tau, P, threads)
+            sweeps += 1
+            if np.array_equal(nxt[P], tau[P]):
+                return nxt, sweeps, True
+            tau = nxt
+        return tau, sweeps, P.size == 0
+
+    def ego_set(self, r: int, s: int, q: int) -> np.ndarray:
+        """The ego network of r-clique q used for its PartialAND estimate
+        (Section 6 application): q and every r-clique sharing an s-clique
+        with q (its neighbours for r = 1, the edges of its triangles for
+        r = 2, ...), sorted."""
+        m = self.members(r, s, q).reshape(-1)
+        return np.unique(np.concatenate([np.array([q], np.int32), m]))
+
+    def ego_estimate(self, r: int, s: int, queries, threads: int | None = None):
+        """PartialAND on each query's ego network; the estimate is the
+        query's own resulting tau.  Returns (estimates, sweeps)."""
+        est, sw = [], []
+        for q in np.asarray(queries, dtype=np.int64):
+            tau, n, _ = self.partial_and(r, s, self.ego_set(r, s, int(q)),
+                                         threads=threads)
+            est.append(int(tau[q]))
+            sw.append(n)
+        return np.array(est, np.int32), np.array(sw, np.int32)
 
     def and_sweep(self, r: int, s: int, tau, order=None) -> int:
         """One in-place Alg. AND sweep over tau (modified); returns #changed."""

@@ -533,6 +533,32 @@ int og_update(og *g, int r, int s, const int32_t *tau_in, int32_t *tau_out,
   return 0;
 }
 
+/* U on a list of r-clique ids (any order, repeats allowed). */
+typedef struct {
+  upd_arg u;
+  const int32_t *ids;
+} upd_set_arg;
+
+static void update_set_body(void *arg, int64_t i, void *wv) {
+  upd_set_arg *a = (upd_set_arg *)arg;
+  update_body(&a->u, a->ids[i], wv);
+}
+
+int og_update_set(og *g, int r, int s, const int32_t *tau_in, int32_t *tau_out,
+                  const int32_t *ids, int64_t count, int threads) {
+  if (check_rs(g, r, s)) return -1;
+  for (int64_t i = 0; i < count; i++)
+    if (ids[i] < 0 || ids[i] >= g->nr[r]) {
+      set_err("r-clique id %d out of range", ids[i]);
+      return -1;
+    }
+  upd_set_arg a = {.u = {.tau_in = tau_in, .tau_out = tau_out,
+                         .k = choose(s, r) - 1},
+                   .ids = ids};
+  if (count > 0) par_for(0, count, threads, g, r, s, update_set_body, &a);
+  return 0;
+}
+
 /* ------------------------------------------------- asynchronous sweep */
 
 int64_t og_and_sweep(og *g, int r, int s, int32_t *tau, const int64_t *order) {

@@ -74,6 +74,12 @@ int og_peel(og *g, int r, int s, int32_t *kappa, int threads);
 int og_update(og *g, int r, int s, const int32_t *tau_in, int32_t *tau_out,
               int64_t lo, int64_t hi, int threads);
 
+/* U applied to the r-cliques listed in ids[count] only (repeats allowed):
+ * tau_out[R] = (U tau_in)(R) for each listed R; other entries untouched.
+ * The step of PartialAND (Section 4.3, end), taken synchronously. */
+int og_update_set(og *g, int r, int s, const int32_t *tau_in, int32_t *tau_out,
+                  const int32_t *ids, int64_t count, int threads);
+
 /* One in-place asynchronous sweep (Alg. AND without the notification lines):
  * visits r-cliques in the given order (NULL = id order), each time reading
  * the current tau.  Returns the number of r-cliques whose tau changed, or -1.

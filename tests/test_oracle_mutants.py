@@ -37,13 +37,17 @@ MUTANTS = {
     # degree levels: one decrement per removed s-clique
     "levels_double_count": ("if (gone_before || counted_by_other) continue;",
                             "if (gone_before) continue;"),
+    # PartialAND: U on the listed r-cliques, not on the first |P| ids
+    "update_set_index": ("update_body(&a->u, a->ids[i], wv);",
+                         "update_body(&a->u, i, wv);"),
     # s-clique extension vertices must be pairwise adjacent
     "ext_not_clique": (
         "for (int j = 0; j < depth && ok; j++) ok = adjacent(c->g, c->ext[j], x);",
         ";"),
 }
 
-PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py"]
+PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py",
+             "tests/test_oracle_partial.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
