@@ -20,6 +20,8 @@ Also reported on the same line:
     request-stream workload against one graph per launch;
   * ``small_graphs``: the same comparison on small graphs only (n <= 5000),
     where each graph alone is launch-bound;
+  * ``ego``: PartialAND estimates on the ego networks of random edges of the
+    same graph, one call for all queries, with their accuracy;
   * ``cpu_baseline``: the CPU oracle's update operator timed on the host over
     a bounded sample of the same graph's r-cliques.
 
@@ -183,6 +185,33 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     return out
 
 
+def ego_leg(g, kappa, count, seed=13):
+    """PartialAND estimates on the ego networks of `count` random r-cliques
+    of the prepared graph, all in one call: throughput, and accuracy against
+    the exact kappa (share exact, mean relative error) -- the comparison of
+    the Section 6 application."""
+    import numpy as np
+    import torch
+
+    nr = kappa.numel()
+    q = torch.from_numpy(np.random.default_rng(seed).integers(
+        0, nr, size=count).astype(np.int32)).cuda()
+    g.ego_estimate(KIND, q[:64])  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est, sw = g.ego_estimate(KIND, q)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k = kappa[q.long()].to(torch.float64)
+    e = est.to(torch.float64)
+    rel = ((e - k) / torch.clamp(k, min=1.0)).mean().item()
+    return {"queries": count, "ms": 1e3 * dt, "queries_per_s": count / dt,
+            "fraction_exact": (est == kappa[q.long()]).double().mean().item(),
+            "mean_relative_error": rel,
+            "mean_sweeps": sw.double().mean().item(),
+            "max_sweeps": int(sw.max().item())}
+
+
 def quality_leg(nd, name, sample=1_000_000, seed=9):
     """Per-sweep accuracy of the iterates against the exact result (the
     approximation trade-off of Sections 5.2-5.3): fraction of r-cliques whose
@@ -250,6 +279,8 @@ def main():
                          "kernel for scaling hardware byte counters)")
     ap.add_argument("--stream-graphs", type=int, default=96,
                     help="graphs in the batched/served comparison (0: skip)")
+    ap.add_argument("--ego-queries", type=int, default=4096,
+                    help="random r-cliques for the ego-estimate leg (0: skip)")
     ap.add_argument("--quality", default=None,
                     help="only run the per-sweep accuracy leg on this "
                          "workload (e.g. cl23) and print its JSON")
@@ -330,6 +361,9 @@ def main():
     # AND on the prepared graph (same incidence lists), frontier on
     kand, rand = g.decompose(KIND, "and", use_frontier=True)
     same_and = bool(torch.equal(kand, kappa))
+
+    # ego-network estimates (PartialAND per query) for random edges
+    ego = ego_leg(g, kappa, args.ego_queries) if args.ego_queries > 0 else None
     g.close()
 
     traffic = measured_traffic()
@@ -376,6 +410,8 @@ def main():
         "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
                 "frontier": True, "kappa_equals_snd": same_and},
     }
+    if ego is not None:
+        line["ego"] = ego
     if args.stream_graphs > 0:
         line["stream"] = stream_leg(nd, ctx, args.stream_graphs)
     if args.small_graphs > 0:

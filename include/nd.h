@@ -206,6 +206,36 @@ nd_status nd_decompose(nd_graph *g, nd_kind kind, const nd_opts *opts,
 nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
                     int32_t *tau_out, int on_device, void *stream);
 
+/* PartialAND (Section 4.3, end): AND sweeps that recompute only the
+ * r-cliques listed in ids[count] (original ids; repeats allowed), every other
+ * r-clique keeping tau_0 = d_s, until a sweep changes none of them (or
+ * opts->max_iters sweeps; opts may be NULL).  out[i] receives the final
+ * value of ids[i].  The limit is the largest fixed point, below d_s, of the
+ * update operator restricted to the set -- the same for any sweep order --
+ * and an upper bound on kappa_s there.  ids and out: device pointers if
+ * on_device, else host.  opts->mode and use_frontier are ignored (AND, no
+ * notifications).  ND_ERR_INVALID for an id outside [0, |R|);
+ * ND_ERR_NOT_CONVERGED (out then holds the current values) when max_iters
+ * stopped it.  res (may be NULL): sweeps, and updates = members x sweeps. */
+nd_status nd_partial_and(nd_graph *g, nd_kind kind, const int32_t *ids,
+                         int64_t count, const nd_opts *opts, int32_t *out,
+                         int on_device, void *stream, nd_result *res);
+
+/* Ego-network estimates (the Section 6 application of PartialAND): for
+ * every query r-clique q = queries[i] (original ids), PartialAND on
+ * P(q) = {q} and every r-clique sharing an s-clique with q -- for k-core q
+ * and its neighbours, for k-truss q and the other edges of its triangles --
+ * each query independently; est[i] = q's resulting value (an upper bound on
+ * kappa_s(q), usually equal), sweeps[i] (sweeps may be NULL) the sweeps it
+ * took.  max_iters < 0: until convergence.  All queries whose P(q) has at
+ * most 4096 r-cliques run in one launch, a workgroup each; larger ones run
+ * one at a time as nd_partial_and.  Pointers are device pointers if
+ * on_device, else host.  ND_ERR_INVALID for a query outside [0, |R|);
+ * ND_ERR_NOT_CONVERGED if some query hit max_iters. */
+nd_status nd_ego_estimate(nd_graph *g, nd_kind kind, const int32_t *queries,
+                          int64_t count, int32_t max_iters, int32_t *est,
+                          int32_t *sweeps, int on_device, void *stream);
+
 /* Decompose `count` graphs together: their r-cliques form one combined work
  * list swept by each launch; a graph stops being swept once one of its sweeps
  * changes nothing.  kappas[i] receives graph i's result (device pointers if

@@ -115,6 +115,10 @@ _sig("nd_sdegree", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int, _P)
 _sig("nd_decompose", ctypes.c_int, _P, ctypes.c_int, ctypes.POINTER(nd_opts),
      _P, ctypes.c_int, _P, ctypes.POINTER(nd_result))
 _sig("nd_update", ctypes.c_int, _P, ctypes.c_int, _P, _P, ctypes.c_int, _P)
+_sig("nd_partial_and", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int64,
+     ctypes.POINTER(nd_opts), _P, ctypes.c_int, _P, ctypes.POINTER(nd_result))
+_sig("nd_ego_estimate", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int64,
+     _I32, _P, _P, ctypes.c_int, _P)
 _sig("nd_batch_decompose", ctypes.c_int, _P, _I32, ctypes.POINTER(_P),
      ctypes.c_int, ctypes.POINTER(nd_opts), ctypes.POINTER(_P), ctypes.c_int,
      _P, ctypes.POINTER(nd_result))
@@ -298,6 +302,39 @@ class Graph:
                               _P(out.data_ptr()), 1, _stream(stream)),
                "nd_update")
         return out
+
+    def partial_and(self, kind: str, ids, max_iters: int = -1, stream=None,
+                    allow_not_converged: bool = False):
+        """PartialAND on the r-cliques `ids` (nd_partial_and): their final
+        values (int32 tensor on the device, one per id) and the result dict."""
+        t = _dev_i32(ids, self.ctx.device)
+        out = torch.empty(max(t.numel(), 1), dtype=torch.int32,
+                          device=self.ctx.device)
+        o, keep = _make_opts("and", max_iters)
+        res = nd_result()
+        st = _lib.nd_partial_and(self._h, KIND[kind], _P(t.data_ptr()),
+                                 t.numel(), ctypes.byref(o),
+                                 _P(out.data_ptr()), 1, _stream(stream),
+                                 ctypes.byref(res))
+        del keep
+        if not (st == 0 or (st == 5 and allow_not_converged)):
+            _check(st, "nd_partial_and")
+        return out[:t.numel()], res.as_dict()
+
+    def ego_estimate(self, kind: str, queries, max_iters: int = -1,
+                     stream=None):
+        """PartialAND estimates on the queries' ego networks
+        (nd_ego_estimate): (estimates, sweeps), int32 tensors on the
+        device."""
+        q = _dev_i32(queries, self.ctx.device)
+        n = q.numel()
+        est = torch.empty(max(n, 1), dtype=torch.int32, device=self.ctx.device)
+        sw = torch.empty(max(n, 1), dtype=torch.int32, device=self.ctx.device)
+        _check(_lib.nd_ego_estimate(self._h, KIND[kind], _P(q.data_ptr()), n,
+                                    int(max_iters), _P(est.data_ptr()),
+                                    _P(sw.data_ptr()), 1, _stream(stream)),
+               "nd_ego_estimate")
+        return est[:n], sw[:n]
 
     def decompose(self, kind: str, mode: str = "snd", max_iters: int = -1,
                   use_frontier: bool = False, stop_active_ratio: float = 0.0,

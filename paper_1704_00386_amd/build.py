@@ -19,7 +19,7 @@ OBJ = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libnd.so")
 
 SOURCES = ["api.hip", "prim.hip", "graph.hip", "cliques.hip", "layout.hip",
-           "sweep.hip", "driver.hip", "batch.hip", "server.hip"]
+           "sweep.hip", "driver.hip", "partial.hip", "batch.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

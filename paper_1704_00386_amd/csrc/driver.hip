@@ -10,6 +10,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "api_util.h"
@@ -56,12 +57,19 @@ struct Timer {
 
 }  // namespace
 
-nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
-                    int32_t *kappa, int on_device, hipStream_t s,
-                    nd_result *res) {
+// The sweep loop.  fixed_set (device, internal numbering, 1 = member) turns
+// it into PartialAND: AND sweeps that recompute only the members, every
+// other r-clique keeping tau_0 = d_s.
+nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
+                         int32_t *kappa, int on_device, hipStream_t s,
+                         nd_result *res, const uint8_t *fixed_set) {
   nd_opts opts;
   nd_opts_init(&opts);
   if (opts_in) opts = *opts_in;
+  if (fixed_set) {
+    opts.mode = ND_AND;
+    opts.use_frontier = 0;
+  }
   ND_REQUIRE(opts.mode == ND_SND || opts.mode == ND_AND, ND_ERR_INVALID,
              "unknown mode %d", (int)opts.mode);
   ND_REQUIRE(opts.stop_active_ratio >= 0 && opts.stop_active_ratio <= 1,
@@ -128,9 +136,14 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   total.start(s);
   // Lemma 2: the iteration is exact after at most (number of degree levels)
   // <= |R| sweeps, so |R| + 1 sweeps always observe convergence; the cap only
-  // guards against a defect turning into an endless loop.
-  if (opts.max_iters < 0 || opts.max_iters > nr + 1)
+  // guards against a defect turning into an endless loop.  A restricted
+  // iteration ends too (some member drops by at least one in every sweep
+  // but the last), without that bound.
+  if (fixed_set) {
+    if (opts.max_iters < 0) opts.max_iters = 0x7fffffff;
+  } else if (opts.max_iters < 0 || opts.max_iters > nr + 1) {
     opts.max_iters = (int32_t)std::min<int64_t>(nr + 1, 0x7fffffff);
+  }
   while (true) {
     if (t >= opts.max_iters) break;
     int nb = chunk;
@@ -152,6 +165,10 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
         a.act_next = act[(t + 1) & 1].p;
         a.stamp = dev::sweep_stamp(t);
         a.notify_below = notify_below;
+      } else if (fixed_set) {
+        a.act = fixed_set;
+        a.stamp = 1;
+        a.fixed_set = 1;
       }
       if (step_by_step) one.start(s);
       launch_sweep(ks, a, and_mode, s);
@@ -221,9 +238,101 @@ nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   return ND_ERR_NOT_CONVERGED;
 }
 
+nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts,
+                    int32_t *kappa, int on_device, hipStream_t s,
+                    nd_result *res) {
+  return decompose_impl(g, kind, opts, kappa, on_device, s, res, nullptr);
+}
+
+namespace {
+
+// err = 1 if some id is outside [0, nr); else mark[inv[id]] = 1.
+__global__ void k_mark_set(const int32_t *__restrict__ ids, int64_t count,
+                           int64_t nr, const int32_t *__restrict__ inv,
+                           uint8_t *__restrict__ mark, int32_t *__restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int32_t id = ids[i];
+  if (id < 0 || id >= nr) {
+    *err = 1;
+    return;
+  }
+  mark[inv[id]] = 1;
+}
+
+__global__ void k_gather_ids(const int32_t *__restrict__ full,
+                             const int32_t *__restrict__ ids, int64_t count,
+                             int32_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = full[ids[i]];
+}
+
+}  // namespace
+
+nd_status partial_and(nd_graph *g, nd_kind kind, const int32_t *ids,
+                      int64_t count, const nd_opts *opts, int32_t *out,
+                      int on_device, hipStream_t s, nd_result *res) {
+  ND_REQUIRE(count >= 0 && (count == 0 || (ids && out)), ND_ERR_INVALID,
+             "bad id list");
+  prepare(g, kind, s);
+  const KindState &ks = g->ks[kind];
+  Allocator &al = g->ctx->alloc;
+  const int64_t nr = ks.nr;
+  DArr<int32_t> dids(al, std::max<int64_t>(count, 1));
+  if (count > 0)
+    ND_HIP(hipMemcpyAsync(dids.p, ids, sizeof(int32_t) * count,
+                          on_device ? hipMemcpyDeviceToDevice
+                                    : hipMemcpyHostToDevice, s));
+  DArr<uint8_t> mark(al, std::max<int64_t>(nr, 1));
+  DArr<int32_t> err(al, 1);
+  fill_u8(mark.p, 0, std::max<int64_t>(nr, 1), s);
+  fill_i32(err.p, 0, 1, s);
+  if (count > 0) {
+    k_mark_set<<<grid_for(count, 256), 256, 0, s>>>(dids.p, count, nr,
+                                                     ks.inv.p, mark.p, err.p);
+    ND_LAUNCHED();
+  }
+  int32_t herr = 0;
+  ND_HIP(hipMemcpyAsync(&herr, err.p, sizeof herr, hipMemcpyDeviceToHost, s));
+  ND_HIP(hipStreamSynchronize(s));
+  ND_REQUIRE(herr == 0, ND_ERR_INVALID, "an r-clique id is outside [0, %lld)",
+             (long long)nr);
+  DArr<int32_t> full(al, std::max<int64_t>(nr, 1));
+  const nd_status st =
+      decompose_impl(g, kind, opts, full.p, 1, s, res, mark.p);
+  if (st != ND_OK && st != ND_ERR_NOT_CONVERGED) return st;
+  if (count > 0) {
+    DArr<int32_t> got(al, count);
+    k_gather_ids<<<grid_for(count, 256), 256, 0, s>>>(full.p, dids.p, count,
+                                                       on_device ? out : got.p);
+    ND_LAUNCHED();
+    if (!on_device)
+      ND_HIP(hipMemcpyAsync(out, got.p, sizeof(int32_t) * count,
+                            hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+  }
+  return st;
+}
+
 }  // namespace nd
 
 using namespace nd;
+
+extern "C" nd_status nd_partial_and(nd_graph *g, nd_kind kind,
+                                    const int32_t *ids, int64_t count,
+                                    const nd_opts *opts, int32_t *out,
+                                    int on_device, void *stream,
+                                    nd_result *res) {
+  nd_status outst = ND_OK;
+  nd_status st = guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    StreamScope scope((hipStream_t)stream);
+    outst = partial_and(g, kind, ids, count, opts, out, on_device,
+                        (hipStream_t)stream, res);
+  });
+  return st != ND_OK ? st : outst;
+}
 
 extern "C" nd_status nd_decompose(nd_graph *g, nd_kind kind,
                                   const nd_opts *opts, int32_t *kappa,

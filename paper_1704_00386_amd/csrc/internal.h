@@ -282,6 +282,9 @@ struct SweepArgs {
   // the gathers it would save); from then on every sweep notifies and the
   // next one recomputes only flagged r-cliques.
   unsigned long long notify_below;
+  // PartialAND (Section 4.3, end): act marks a fixed set (stamp 1) that is
+  // the only thing recomputed, every sweep, and nothing notifies.
+  int fixed_set;
 };
 
 // Launch one sweep over every bin of ks (internal numbering, tau of

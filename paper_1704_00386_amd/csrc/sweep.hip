@@ -51,6 +51,11 @@ __device__ __forceinline__ bool converged_before(const SweepStats *prev) {
 __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
                                               const uint8_t **act,
                                               uint8_t **act_next) {
+  if (a.fixed_set) {
+    *act = a.act;
+    *act_next = nullptr;
+    return;
+  }
   const bool flags_valid = a.prev != nullptr && a.prev->notified;
   const bool notify =
       a.prev != nullptr &&
