@@ -20,6 +20,8 @@ Also reported on the same line:
     request-stream workload against one graph per launch;
   * ``small_graphs``: the same comparison on small graphs only (n <= 5000),
     where each graph alone is launch-bound;
+  * ``degree_levels``: the number of degree levels of the same graph (the
+    bound on SND sweeps) beside the SND and AND sweep counts;
   * ``ego``: PartialAND estimates on the ego networks of random edges of the
     same graph, one call for all queries, with their accuracy;
   * ``cpu_baseline``: the CPU oracle's update operator timed on the host over
@@ -232,13 +234,14 @@ def quality_leg(nd, name, sample=1_000_000, seed=9):
     g = nd.Graph.from_edges(ctx, raw.n, torch.from_numpy(raw.src).cuda(),
                             torch.from_numpy(raw.dst).cuda())
     g.prepare(kind)
+    _, n_levels = g.levels(kind)
     kappa, _ = g.decompose(kind, "snd", use_frontier=True)
     kap = kappa.cpu().numpy()
     nr = kap.size
     idx = np.random.default_rng(seed).choice(nr, size=min(sample, nr),
                                              replace=False)
     out = {"workload": name, "kind": kind, "n_rcliques": int(nr),
-           "kendall_sample": int(idx.size)}
+           "kendall_sample": int(idx.size), "degree_levels": n_levels}
     for mode in ("snd", "and"):
         its, ms = [], []
 
@@ -364,6 +367,13 @@ def main():
 
     # ego-network estimates (PartialAND per query) for random edges
     ego = ego_leg(g, kappa, args.ego_queries) if args.ego_queries > 0 else None
+
+    # degree levels: the bound on SND sweeps (the DL row of Table 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, n_levels = g.levels(KIND)
+    torch.cuda.synchronize()
+    levels_ms = 1e3 * (time.perf_counter() - t0)
     g.close()
 
     traffic = measured_traffic()
@@ -410,6 +420,9 @@ def main():
         "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
                 "frontier": True, "kappa_equals_snd": same_and},
     }
+    line["degree_levels"] = {"levels": n_levels, "ms": levels_ms,
+                             "snd_sweeps": res["sweeps"],
+                             "and_sweeps": rand["sweeps"]}
     if ego is not None:
         line["ego"] = ego
     if args.stream_graphs > 0:

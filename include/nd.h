@@ -236,6 +236,17 @@ nd_status nd_ego_estimate(nd_graph *g, nd_kind kind, const int32_t *queries,
                           int64_t count, int32_t max_iters, int32_t *est,
                           int32_t *sweeps, int on_device, void *stream);
 
+/* Degree levels (Defn. 4): level[R] = i for every r-clique R of L_i, in
+ * r-clique id order (device pointer if on_device, else host; |R| entries);
+ * *num_levels (host) = the number of non-empty levels, which bounds the SND
+ * sweeps (the level-i r-cliques are exact after i sweeps; the DL row of
+ * Table 3).  L_0 = r-cliques of minimum S-degree; removing an r-clique
+ * removes every s-clique containing it; L_i = the minimum-degree r-cliques
+ * of what remains.  One device step per level (three kernels and a 16-byte
+ * read-back). */
+nd_status nd_levels(nd_graph *g, nd_kind kind, int32_t *level,
+                    int32_t *num_levels, int on_device, void *stream);
+
 /* Decompose `count` graphs together: their r-cliques form one combined work
  * list swept by each launch; a graph stops being swept once one of its sweeps
  * changes nothing.  kappas[i] receives graph i's result (device pointers if

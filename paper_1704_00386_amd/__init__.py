@@ -24,8 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libnd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m "
-        "paper_1704_00386_amd.build` (there is no fallback path)")
+        f"{LIB_PATH} is missing: build it with `python "
+        "paper_1704_00386_amd/build.py` (there is no fallback path)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 # The HIP runtime the library links; used only to copy per-sweep snapshots
@@ -115,6 +115,8 @@ _sig("nd_sdegree", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int, _P)
 _sig("nd_decompose", ctypes.c_int, _P, ctypes.c_int, ctypes.POINTER(nd_opts),
      _P, ctypes.c_int, _P, ctypes.POINTER(nd_result))
 _sig("nd_update", ctypes.c_int, _P, ctypes.c_int, _P, _P, ctypes.c_int, _P)
+_sig("nd_levels", ctypes.c_int, _P, ctypes.c_int, _P,
+     ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _P)
 _sig("nd_partial_and", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int64,
      ctypes.POINTER(nd_opts), _P, ctypes.c_int, _P, ctypes.POINTER(nd_result))
 _sig("nd_ego_estimate", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int64,
@@ -302,6 +304,17 @@ class Graph:
                               _P(out.data_ptr()), 1, _stream(stream)),
                "nd_update")
         return out
+
+    def levels(self, kind: str, stream=None):
+        """Degree levels (nd_levels): (level per r-clique as an int32 tensor
+        on the device, number of levels)."""
+        nr, _, _ = self.sizes(kind)
+        out = torch.empty(max(nr, 1), dtype=torch.int32, device=self.ctx.device)
+        nl = ctypes.c_int32()
+        _check(_lib.nd_levels(self._h, KIND[kind], _P(out.data_ptr()),
+                              ctypes.byref(nl), 1, _stream(stream)),
+               "nd_levels")
+        return out[:nr], int(nl.value)
 
     def partial_and(self, kind: str, ids, max_iters: int = -1, stream=None,
                     allow_not_converged: bool = False):

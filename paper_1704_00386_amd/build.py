@@ -2,7 +2,8 @@
 
 Every source in ``csrc/`` is compiled with hipcc for gfx950 only, then linked
 into one shared library next to this file.  Usage:
-``python -m paper_1704_00386_amd.build [--jobs N]``.
+``python paper_1704_00386_amd/build.py [--jobs N]`` (run as a script: importing
+the package itself needs the library).
 """
 
 from __future__ import annotations
@@ -19,7 +20,7 @@ OBJ = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libnd.so")
 
 SOURCES = ["api.hip", "prim.hip", "graph.hip", "cliques.hip", "layout.hip",
-           "sweep.hip", "driver.hip", "partial.hip", "batch.hip", "server.hip"]
+           "sweep.hip", "driver.hip", "partial.hip", "levels.hip", "batch.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

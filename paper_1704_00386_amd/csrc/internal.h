@@ -203,6 +203,7 @@ void partition_by_bin(const uint8_t *bin, int64_t n, int nbins, int32_t *items,
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void iota_i32(int32_t *p, int64_t n, hipStream_t s);  // p[i] = i
 int64_t read_i64(const int64_t *dev, hipStream_t s);  // synchronous
 
 // ------------------------------------------------------------ graph prep

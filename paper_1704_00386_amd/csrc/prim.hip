@@ -293,6 +293,19 @@ void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
   ND_LAUNCHED();
 }
 
+namespace {
+__global__ void k_iota_i32(int32_t *__restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+}  // namespace
+
+void iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_iota_i32<<<grid_for(n, 256), 256, 0, s>>>(p, n);
+  ND_LAUNCHED();
+}
+
 void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_fill_u8<<<grid_for(ceil_div(n, 4), 256), 256, 0, s>>>(p, v, n);

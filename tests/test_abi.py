@@ -30,7 +30,7 @@ def test_header_declares_expected_surface():
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(LIB):
-        pytest.fail("libnd.so is not built (python -m paper_1704_00386_amd.build)")
+        pytest.fail("libnd.so is not built (python paper_1704_00386_amd/build.py)")
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
