@@ -282,6 +282,8 @@ def main():
                          "kernel for scaling hardware byte counters)")
     ap.add_argument("--stream-graphs", type=int, default=96,
                     help="graphs in the batched/served comparison (0: skip)")
+    ap.add_argument("--levels", action="store_true",
+                    help="also count the degree levels of the graph")
     ap.add_argument("--ego-queries", type=int, default=4096,
                     help="random r-cliques for the ego-estimate leg (0: skip)")
     ap.add_argument("--quality", default=None,
@@ -369,11 +371,13 @@ def main():
     ego = ego_leg(g, kappa, args.ego_queries) if args.ego_queries > 0 else None
 
     # degree levels: the bound on SND sweeps (the DL row of Table 3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, n_levels = g.levels(KIND)
-    torch.cuda.synchronize()
-    levels_ms = 1e3 * (time.perf_counter() - t0)
+    n_levels = levels_ms = None
+    if args.levels:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, n_levels = g.levels(KIND)
+        torch.cuda.synchronize()
+        levels_ms = 1e3 * (time.perf_counter() - t0)
     g.close()
 
     traffic = measured_traffic()
@@ -420,9 +424,10 @@ def main():
         "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
                 "frontier": True, "kappa_equals_snd": same_and},
     }
-    line["degree_levels"] = {"levels": n_levels, "ms": levels_ms,
-                             "snd_sweeps": res["sweeps"],
-                             "and_sweeps": rand["sweeps"]}
+    if n_levels is not None:
+        line["degree_levels"] = {"levels": n_levels, "ms": levels_ms,
+                                 "snd_sweeps": res["sweeps"],
+                                 "and_sweeps": rand["sweeps"]}
     if ego is not None:
         line["ego"] = ego
     if args.stream_graphs > 0:
