@@ -4,20 +4,33 @@
 // number bounds the sweeps SND needs (level i is exact after i sweeps), the
 // DL row of Table 3.
 //
-// One level per step, all on the device except a 3-integer read-back:
-//   1. minimum current degree over the r-cliques still present (a compact
-//      list of them, rebuilt every step),
-//   2. split the list: degree == minimum -> this level (frontier), the rest
-//      -> next list,
-//   3. one wave per frontier r-clique walks its incidence list; an s-clique
-//      still present (no member removed at an earlier level) is counted once,
-//      by its frontier member of smallest id, and lowers the degree of each
-//      member still present by one.
-// The levels are fully determined by the definition, so the result is the
-// same on every run.
+// Levels form a chain (each depends on the previous removal) and power-law
+// graphs have hundreds of thousands of small ones, so a level must cost
+// microseconds, not a scan of everything still present.  Degree buckets make
+// each level proportional to its own work:
+//   * I[d]: the r-cliques whose initial degree is d (one sort, up front);
+//   * B[d]: r-cliques whose degree dropped to d at the end of some level,
+//     appended then.  A degree only falls, so an r-clique enters B[d] at most
+//     once for each d below its initial degree: B[d] needs at most
+//     #{R : d_s(R) > d} slots, P slots in all;
+//   * hist[d]: how many r-cliques still present have degree d.
+// Level i with minimum m: the members of I[m] (first visit of m only) and of
+// B[m] past what earlier visits of m consumed that are still present with
+// degree m form L_i -- every present r-clique of degree m is there, and stale
+// entries (degree fell further, or removed) are skipped.  Peeling L_i walks
+// its incidence lists: an s-clique still present (no member removed at an
+// earlier level) is counted once, by its L_i member of smallest id, and
+// lowers the degree of each member still present by one.  The next minimum
+// is the first non-empty bucket of hist from min(lowest new degree, m + 1):
+// everything not lowered in level i has degree above m.
+//
+// The loop over levels runs in one workgroup (barriers between the phases of
+// a level cost far less than kernel launches); every loop has a hard bound
+// and an inconsistency ends it with an error flag rather than a hang.
 #include <limits.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "api_util.h"
 #include "internal.h"
@@ -26,85 +39,185 @@ namespace nd {
 
 namespace {
 
-struct LevelCounters {
-  int32_t min_deg;
-  int32_t n_frontier;
-  int32_t n_next;
-  int32_t pad;
+constexpr int kLvThreads = 1024;
+constexpr int kLvWaves = kLvThreads / kWave;
+
+struct LevelArgs {
+  const int64_t *inc_off;  // internal numbering
+  const int32_t *inc_ids;
+  int64_t nr;
+  int32_t maxd;
+  int32_t m0;             // minimum initial degree
+  int32_t *deg;           // current degree (starts at d_s)
+  int32_t *lvl;           // level, -1 while present
+  int32_t *hist;          // [maxd + 1] present r-cliques per degree
+  const int32_t *I;       // r-cliques by initial degree
+  const int64_t *Ioff;    // [maxd + 2]
+  int32_t *B;             // re-bucketed r-cliques
+  const int64_t *Boff;    // [maxd + 1]
+  int64_t *Bcnt;          // [maxd + 1] entries appended
+  int64_t *Bused;         // [maxd + 1] entries consumed
+  uint8_t *Iused;         // [maxd + 1] I[d] consumed
+  int32_t *moved_at;      // per r-clique: last level that lowered it
+  int32_t *F;             // frontier (this level), nr slots
+  int32_t *MV;            // r-cliques lowered in this level, nr slots
+  int32_t *out;           // [0] = number of levels, [1] = error code
 };
 
-__global__ void k_level_reset(LevelCounters *c) {
-  c->min_deg = INT_MAX;
-  c->n_frontier = 0;
-  c->n_next = 0;
-}
-
-__global__ __launch_bounds__(256) void k_level_min(
-    const int32_t *__restrict__ alive, int64_t n, const int32_t *__restrict__ deg,
-    LevelCounters *c) {
-  int32_t m = INT_MAX;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    m = min(m, deg[alive[i]]);
-  for (int o = kWave / 2; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, kWave));
-  if (lane_id() == 0 && m != INT_MAX) atomicMin(&c->min_deg, m);
-}
-
-// Wave-aggregated append of the lanes with `take` to list[*count ...].
-__device__ __forceinline__ void wave_append(bool take, int32_t v, int32_t *list,
-                                            int32_t *count) {
-  const uint64_t b = ballot(take);
-  if (!b) return;
-  int32_t base = 0;
-  if (lane_id() == __ffsll((long long)b) - 1)
-    base = atomicAdd(count, (int32_t)__popcll(b));
-  base = __shfl(base, __ffsll((long long)b) - 1, kWave);
-  if (take) list[base + lanes_below(b)] = v;
-}
-
-__global__ __launch_bounds__(256) void k_level_split(
-    const int32_t *__restrict__ alive, int64_t n, const int32_t *__restrict__ deg,
-    int32_t level, int32_t *__restrict__ lvl, int32_t *__restrict__ frontier,
-    int32_t *__restrict__ next, LevelCounters *c) {
-  const int32_t m = c->min_deg;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // whole waves iterate together so that the ballots see every lane
-  const int64_t n_up = (n + kWave - 1) / kWave * kWave;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_up;
-       i += stride) {
-    const bool valid = i < n;
-    const int32_t R = valid ? alive[i] : 0;
-    const bool now = valid && deg[R] == m;
-    if (now) lvl[R] = level;
-    wave_append(now, R, frontier, &c->n_frontier);
-    wave_append(valid && !now, R, next, &c->n_next);
-  }
-}
-
 template <int K>
-__global__ __launch_bounds__(256) void k_level_peel(
-    const int32_t *__restrict__ frontier, int64_t nf,
-    const int64_t *__restrict__ inc_off, const int32_t *__restrict__ inc_ids,
-    const int32_t *__restrict__ lvl, int32_t level, int32_t *__restrict__ deg) {
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t f = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-       f < nf; f += waves) {
-    const int32_t R = frontier[f];
-    const int64_t b = inc_off[R], d = inc_off[R + 1] - b;
-    for (int64_t j = lane_id(); j < d; j += kWave) {
-      const int32_t *o = inc_ids + (int64_t)K * (b + j);
-      bool skip = false;
-#pragma unroll
-      for (int x = 0; x < K; x++) {
-        const int32_t l = lvl[o[x]];
-        skip |= (l >= 0 && l < level) || (l == level && o[x] < R);
-      }
-      if (skip) continue;
-#pragma unroll
-      for (int x = 0; x < K; x++)
-        if (lvl[o[x]] < 0) atomicSub(&deg[o[x]], 1);
-    }
+__global__ __launch_bounds__(kLvThreads) void k_levels(LevelArgs a) {
+  __shared__ int32_t s_m, s_nf, s_nmv, s_dmin, s_err, s_level;
+  __shared__ int64_t s_alive, s_ilo, s_ilen, s_blo, s_blen;
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  if (t == 0) {
+    s_m = a.m0;
+    s_alive = a.nr;
+    s_err = 0;
+    s_level = 0;
   }
+  __syncthreads();
+  for (int64_t guard = 0; guard <= a.nr; guard++) {
+    if (s_alive <= 0 || s_err) break;  // uniform: read after a barrier
+    const int32_t m = s_m, level = s_level;
+    // ---- collect L_level
+    if (t == 0) {
+      s_ilo = a.Ioff[m];
+      s_ilen = a.Iused[m] ? 0 : a.Ioff[m + 1] - a.Ioff[m];
+      s_blo = a.Boff[m] + a.Bused[m];
+      s_blen = a.Bcnt[m] - a.Bused[m];
+      s_nf = 0;
+      s_nmv = 0;
+      s_dmin = INT_MAX;
+    }
+    __syncthreads();
+    const int64_t ilo = s_ilo, ilen = s_ilen, blo = s_blo, blen = s_blen;
+    for (int64_t x = t; x < ilen + blen; x += kLvThreads) {
+      const int32_t R = x < ilen ? a.I[ilo + x] : a.B[blo + (x - ilen)];
+      if (a.deg[R] == m && atomicCAS(&a.lvl[R], -1, level) == -1)
+        a.F[atomicAdd(&s_nf, 1)] = R;
+    }
+    __syncthreads();
+    const int32_t nf = s_nf;
+    if (nf == 0) {  // the minimum bucket must hold a present r-clique
+      if (t == 0) s_err = 1;
+      __syncthreads();
+      break;
+    }
+    if (t == 0) {
+      a.Iused[m] = 1;
+      a.Bused[m] += blen;
+    }
+    // ---- peel: one wave per r-clique of L_level
+    for (int f = w; f < nf; f += kLvWaves) {
+      const int32_t R = a.F[f];
+      const int64_t b = a.inc_off[R], d = a.inc_off[R + 1] - b;
+      for (int64_t j = lane; j < d; j += kWave) {
+        const int32_t *o = a.inc_ids + (int64_t)K * (b + j);
+        bool skip = false;
+#pragma unroll
+        for (int x = 0; x < K; x++) {
+          const int32_t l = a.lvl[o[x]];
+          skip |= (l >= 0 && l < level) || (l == level && o[x] < R);
+        }
+        if (skip) continue;
+#pragma unroll
+        for (int x = 0; x < K; x++) {
+          const int32_t q = o[x];
+          if (a.lvl[q] >= 0) continue;
+          const int32_t old = atomicSub(&a.deg[q], 1);
+          if (old < 1 || old > a.maxd) {  // a present s-clique counts in deg
+            s_err = 4;
+            continue;
+          }
+          atomicSub(&a.hist[old], 1);
+          atomicAdd(&a.hist[old - 1], 1);
+          atomicMin(&s_dmin, old - 1);
+          if (atomicExch(&a.moved_at[q], level) != level)
+            a.MV[atomicAdd(&s_nmv, 1)] = q;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- re-bucket what was lowered, at its final degree of this level
+    const int32_t nmv = s_nmv;
+    for (int x = t; x < nmv; x += kLvThreads) {
+      const int32_t q = a.MV[x];
+      const int32_t dq = a.deg[q];
+      if (dq < 0 || dq > a.maxd) {
+        s_err = 5;
+        continue;
+      }
+      const int64_t p = (int64_t)atomicAdd((unsigned long long *)&a.Bcnt[dq], 1ull);
+      if (a.Boff[dq] + p < a.Boff[dq + 1])  // a bucket never overflows
+        a.B[a.Boff[dq] + p] = q;
+      else
+        s_err = 6;
+    }
+    if (t == 0) {
+      atomicSub(&a.hist[m], nf);
+      s_alive -= nf;
+      s_level = level + 1;
+    }
+    __syncthreads();
+    // ---- next minimum: first non-empty bucket from min(dmin, m + 1)
+    if (w == 0 && s_alive > 0) {
+      const int32_t lo = min(s_dmin, m + 1);
+      int32_t found = -1;
+      for (int32_t base = lo; base <= a.maxd && found < 0; base += kWave) {
+        const int32_t dd = base + lane;
+        const bool hit = dd <= a.maxd && a.hist[dd] > 0;
+        const uint64_t bal = ballot(hit);
+        if (bal) found = base + __ffsll((long long)bal) - 1;
+      }
+      if (lane == 0) {
+        if (found < 0)
+          s_err = 2;
+        else
+          s_m = found;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    a.out[0] = s_level;
+    a.out[1] = s_err ? s_err : (s_alive > 0 ? 3 : 0);
+  }
+}
+
+// keys[i] = d_s(i) << rb | i
+__global__ void k_deg_keys(const int32_t *__restrict__ ds, int64_t nr, int rb,
+                           uint64_t *__restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nr) keys[i] = ((uint64_t)ds[i] << rb) | (uint64_t)i;
+}
+
+// From the degree-sorted keys: I (ids), and Ioff[d] = first position of
+// degree >= d, for d = 0 .. maxd + 1.
+__global__ void k_deg_buckets(const uint64_t *__restrict__ keys, int64_t nr,
+                              int rb, int32_t maxd, int32_t *__restrict__ I,
+                              int64_t *__restrict__ Ioff) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > nr) return;
+  const int32_t dj = j < nr ? (int32_t)(keys[j] >> rb) : maxd + 1;
+  const int32_t dp = j > 0 ? (int32_t)(keys[j - 1] >> rb) : -1;
+  for (int32_t d = dp + 1; d <= dj; d++) Ioff[d] = j;
+  if (j < nr) I[j] = (int32_t)(keys[j] & (((uint64_t)1 << rb) - 1));
+}
+
+// hist[d] = |I[d]|; cap[d] = #{R : d_s(R) > d} = nr - Ioff[d + 1].
+__global__ void k_deg_hist(const int64_t *__restrict__ Ioff, int64_t nr,
+                           int32_t maxd, int32_t *__restrict__ hist,
+                           int64_t *__restrict__ cap) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d > maxd) return;
+  hist[d] = (int32_t)(Ioff[d + 1] - Ioff[d]);
+  cap[d] = nr - Ioff[d + 1];
+}
+
+int bits_for(int64_t x) {
+  int b = 1;
+  while (b < 62 && ((int64_t)1 << b) <= x) b++;
+  return b;
 }
 
 }  // namespace
@@ -121,50 +234,85 @@ nd_status levels(nd_graph *g, nd_kind kind, int32_t *level_out,
     *num_levels = 0;
     return ND_OK;
   }
-  DArr<int32_t> deg(al, nr), lvl(al, nr), a0(al, nr), a1(al, nr), fr(al, nr);
-  DArr<LevelCounters> cnt(al, 1);
+  const int32_t maxd = ks.max_ds;
+  const int rb = bits_for(nr - 1);
+  ND_REQUIRE(rb + bits_for(maxd + 1) <= 64, ND_ERR_UNSUPPORTED,
+             "degree-level keys do not fit 64 bits");
+  DArr<int32_t> deg(al, nr), lvl(al, nr), I(al, nr), moved(al, nr), F(al, nr),
+      MV(al, nr), hist(al, maxd + 1), out(al, 2);
+  DArr<int64_t> Ioff(al, maxd + 2), cap(al, maxd + 1), Boff(al, maxd + 2),
+      Bcnt(al, maxd + 1), Bused(al, maxd + 1);
+  DArr<uint8_t> Iused(al, maxd + 1);
+  {
+    DArr<uint64_t> keys(al, nr), tmp(al, nr);
+    k_deg_keys<<<grid_for(nr, 256), 256, 0, s>>>(ks.ds.p, nr, rb, keys.p);
+    ND_LAUNCHED();
+    const uint64_t *sorted =
+        radix_sort_u64(keys.p, tmp.p, nr, rb, rb + bits_for(maxd + 1), s, al);
+    k_deg_buckets<<<grid_for(nr + 1, 256), 256, 0, s>>>(sorted, nr, rb, maxd,
+                                                         I.p, Ioff.p);
+    ND_LAUNCHED();
+  }
+  k_deg_hist<<<grid_for(maxd + 1, 256), 256, 0, s>>>(Ioff.p, nr, maxd, hist.p,
+                                                      cap.p);
+  ND_LAUNCHED();
+  exclusive_scan_i64(cap.p, Boff.p, maxd + 1, s, al);
+  const int64_t btotal = read_i64(Boff.p + maxd + 1, s);  // = P
+  DArr<int32_t> B(al, std::max<int64_t>(btotal, 1));
   ND_HIP(hipMemcpyAsync(deg.p, ks.ds.p, sizeof(int32_t) * nr,
                         hipMemcpyDeviceToDevice, s));
   fill_i32(lvl.p, -1, nr, s);
-  iota_i32(a0.p, nr, s);
-  int32_t *alive = a0.p, *next = a1.p;
-  int64_t nalive = nr;
-  int32_t level = 0;
-  const int max_grid = g->ctx->num_cu * 8;
-  LevelCounters h{};
-  while (nalive > 0) {
-    const unsigned grid = (unsigned)std::min<int64_t>(grid_for(nalive, 256), max_grid);
-    k_level_reset<<<1, 1, 0, s>>>(cnt.p);
-    ND_LAUNCHED();
-    k_level_min<<<grid, 256, 0, s>>>(alive, nalive, deg.p, cnt.p);
-    ND_LAUNCHED();
-    k_level_split<<<grid, 256, 0, s>>>(alive, nalive, deg.p, level, lvl.p, fr.p,
-                                       next, cnt.p);
-    ND_LAUNCHED();
-    ND_HIP(hipMemcpyAsync(&h, cnt.p, sizeof h, hipMemcpyDeviceToHost, s));
-    ND_HIP(hipStreamSynchronize(s));
-    ND_REQUIRE(h.n_frontier > 0 && h.n_frontier + h.n_next == nalive,
-               ND_ERR_DEVICE, "degree levels: inconsistent split");
-    const unsigned pgrid =
-        (unsigned)std::min<int64_t>(grid_for((int64_t)h.n_frontier * kWave, 256),
-                                    max_grid);
-    switch (ks.k) {
-      case 1: k_level_peel<1><<<pgrid, 256, 0, s>>>(fr.p, h.n_frontier, ks.inc_off.p, ks.inc_ids.p, lvl.p, level, deg.p); break;
-      case 2: k_level_peel<2><<<pgrid, 256, 0, s>>>(fr.p, h.n_frontier, ks.inc_off.p, ks.inc_ids.p, lvl.p, level, deg.p); break;
-      default: k_level_peel<3><<<pgrid, 256, 0, s>>>(fr.p, h.n_frontier, ks.inc_off.p, ks.inc_ids.p, lvl.p, level, deg.p); break;
-    }
-    ND_LAUNCHED();
-    std::swap(alive, next);
-    nalive = h.n_next;
-    level++;
+  fill_i32(moved.p, -1, nr, s);
+  fill_u64((uint64_t *)Bcnt.p, 0, maxd + 1, s);
+  fill_u64((uint64_t *)Bused.p, 0, maxd + 1, s);
+  fill_u8(Iused.p, 0, maxd + 1, s);
+  fill_i32(out.p, 0, 2, s);
+  // minimum initial degree: the first non-empty bucket
+  std::vector<int64_t> hoff(maxd + 2);
+  ND_HIP(hipMemcpyAsync(hoff.data(), Ioff.p, sizeof(int64_t) * (maxd + 2),
+                        hipMemcpyDeviceToHost, s));
+  ND_HIP(hipStreamSynchronize(s));
+  int32_t m0 = 0;
+  while (m0 <= maxd && hoff[m0 + 1] == hoff[m0]) m0++;
+  ND_REQUIRE(m0 <= maxd, ND_ERR_DEVICE, "degree buckets are empty");
+  LevelArgs a{};
+  a.inc_off = ks.inc_off.p;
+  a.inc_ids = ks.inc_ids.p;
+  a.nr = nr;
+  a.maxd = maxd;
+  a.m0 = m0;
+  a.deg = deg.p;
+  a.lvl = lvl.p;
+  a.hist = hist.p;
+  a.I = I.p;
+  a.Ioff = Ioff.p;
+  a.B = B.p;
+  a.Boff = Boff.p;
+  a.Bcnt = Bcnt.p;
+  a.Bused = Bused.p;
+  a.Iused = Iused.p;
+  a.moved_at = moved.p;
+  a.F = F.p;
+  a.MV = MV.p;
+  a.out = out.p;
+  switch (ks.k) {
+    case 1: k_levels<1><<<1, kLvThreads, 0, s>>>(a); break;
+    case 2: k_levels<2><<<1, kLvThreads, 0, s>>>(a); break;
+    default: k_levels<3><<<1, kLvThreads, 0, s>>>(a); break;
   }
-  *num_levels = level;
+  ND_LAUNCHED();
+  int32_t res[2] = {0, 0};
+  ND_HIP(hipMemcpyAsync(res, out.p, sizeof res, hipMemcpyDeviceToHost, s));
+  ND_HIP(hipStreamSynchronize(s));
+  ND_REQUIRE(res[1] == 0, ND_ERR_DEVICE,
+             "degree levels: inconsistent buckets (code %d)", res[1]);
+  *num_levels = res[0];
   if (on_device) {
     to_original(ks, lvl.p, false, level_out, s);
   } else {
-    DArr<int32_t> out(al, nr);
-    to_original(ks, lvl.p, false, out.p, s);
-    ND_HIP(hipMemcpyAsync(level_out, out.p, sizeof(int32_t) * nr,
+    DArr<int32_t> o(al, nr);
+    to_original(ks, lvl.p, false, o.p, s);
+    ND_HIP(hipMemcpyAsync(level_out, o.p, sizeof(int32_t) * nr,
                           hipMemcpyDeviceToHost, s));
   }
   ND_HIP(hipStreamSynchronize(s));
