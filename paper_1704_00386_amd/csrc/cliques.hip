@@ -319,9 +319,48 @@ struct OrientArgs {
   const int32_t *out_src;
   int32_t *count;         // count pass: per edge id
   const int32_t *inv;     // fill pass: edge id -> internal id
-  unsigned long long *cursor;  // fill pass: next free s-clique slot, internal
+  unsigned long long *cursor;  // fill pass: next free side slot, internal
   int32_t *ids;           // fill pass: 2 ids per (edge, triangle)
+  int32_t *count_base;    // count pass: base triangles per edge id
+  const int64_t *base_off;  // fill pass: list start per internal id
+  int lds_cap;            // k_orient_heavy: out-list entries held in LDS
 };
+
+// One triangle (euv, e1 = (u,w), e2 = (v,w)) found from the oriented edge
+// u->v.  Each edge's list holds first the triangles found from the edge
+// itself (its "base" entries: their count and their places come from the
+// subgroup that owns the edge, without atomics), then those where it is a
+// side e1 or e2 (counted and placed with atomics).  Count pass: the side
+// counts; fill pass: the three entries, the base one at base_pos.
+template <bool FILL>
+__device__ __forceinline__ void orient_emit(const OrientArgs &a, int32_t euv,
+                                            int32_t e1, int32_t e2,
+                                            int64_t base_pos) {
+  if (!FILL) {
+    atomicAdd(&a.count[e1], 1);
+    atomicAdd(&a.count[e2], 1);
+  } else {
+    const int32_t iuv = a.inv[euv], i1 = a.inv[e1], i2 = a.inv[e2];
+    const int64_t p1 = (int64_t)atomicAdd(&a.cursor[i1], 1ull);
+    const int64_t p2 = (int64_t)atomicAdd(&a.cursor[i2], 1ull);
+    a.ids[2 * base_pos] = i1;
+    a.ids[2 * base_pos + 1] = i2;
+    a.ids[2 * p1] = iuv;
+    a.ids[2 * p1 + 1] = i2;
+    a.ids[2 * p2] = iuv;
+    a.ids[2 * p2 + 1] = i1;
+  }
+}
+
+// After an edge's subgroup has found `run` base triangles: record them.
+template <bool FILL>
+__device__ __forceinline__ void orient_base_done(const OrientArgs &a,
+                                                 int32_t euv, int run) {
+  if (!FILL) {
+    a.count_base[euv] = run;
+    if (run) atomicAdd(&a.count[euv], run);
+  }
+}
 
 template <int G, bool FILL>
 __global__ __launch_bounds__(256) void k_orient_isect(OrientArgs a) {
@@ -336,31 +375,114 @@ __global__ __launch_bounds__(256) void k_orient_isect(OrientArgs a) {
   const bool short_is_u = (eu - bu) <= (ev - bv);
   const int64_t sb = short_is_u ? bu : bv, se = short_is_u ? eu : ev;
   const int64_t lb = short_is_u ? bv : bu, le = short_is_u ? ev : eu;
-  for (int64_t j0 = sb; j0 < se; j0 += G) {
+  const uint64_t smask = subgroup_mask<G>();
+  const int64_t base = FILL ? a.base_off[a.inv[euv]] : 0;
+  int run = 0;
+  for (int64_t j0 = sb; j0 < se; j0 += G) {  // uniform within the subgroup
     const int64_t j = j0 + sl;
-    if (j >= se) break;
-    const int32_t w = a.out_col[j];
-    const int64_t k = lower_bound<int32_t>(a.out_col, lb, le, w);
-    if (k >= le || a.out_col[k] != w) continue;
-    const int32_t e1 = a.out_eid[short_is_u ? j : k];  // (u, w)
-    const int32_t e2 = a.out_eid[short_is_u ? k : j];  // (v, w)
-    if (!FILL) {
-      atomicAdd(&a.count[euv], 1);
-      atomicAdd(&a.count[e1], 1);
-      atomicAdd(&a.count[e2], 1);
-    } else {
-      const int32_t iuv = a.inv[euv], i1 = a.inv[e1], i2 = a.inv[e2];
-      const int64_t p0 = (int64_t)atomicAdd(&a.cursor[iuv], 1ull);
-      const int64_t p1 = (int64_t)atomicAdd(&a.cursor[i1], 1ull);
-      const int64_t p2 = (int64_t)atomicAdd(&a.cursor[i2], 1ull);
-      a.ids[2 * p0] = i1;
-      a.ids[2 * p0 + 1] = i2;
-      a.ids[2 * p1] = iuv;
-      a.ids[2 * p1 + 1] = i2;
-      a.ids[2 * p2] = iuv;
-      a.ids[2 * p2 + 1] = i1;
+    bool found = false;
+    int64_t k = 0;
+    if (j < se) {
+      const int32_t w = a.out_col[j];
+      k = lower_bound<int32_t>(a.out_col, lb, le, w);
+      found = k < le && a.out_col[k] == w;
+    }
+    const uint64_t m = ballot(found) & smask;
+    if (found) {
+      const int32_t e1 = a.out_eid[short_is_u ? j : k];  // (u, w)
+      const int32_t e2 = a.out_eid[short_is_u ? k : j];  // (v, w)
+      orient_emit<FILL>(a, euv, e1, e2, base + run + lanes_below(m));
+    }
+    run += __popcll(m);
+  }
+  if (sl == 0) orient_base_done<FILL>(a, euv, run);
+}
+
+// The oriented edges whose both out-lists are long (the 64-lane bin) are
+// grouped by source u (they are sorted by it): one workgroup loads out(u)
+// into LDS once, then each wave takes an edge u->v, streams out(v) from HBM
+// (coalesced) and binary-searches each entry in the LDS copy of out(u).
+// Degree orientation keeps out-lists short (at most sqrt(2|E|) entries), so
+// out(u) fits LDS; the host falls back to k_orient_isect<64> otherwise.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_orient_heavy(OrientArgs a,
+                                                      const int32_t *__restrict__ seg_lo,
+                                                      int64_t nseg) {
+  extern __shared__ int32_t lds[];
+  const int cap = a.lds_cap;
+  int32_t *lc = lds, *le = lds + cap;
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  constexpr int kWaves = 256 / kWave;
+  for (int64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    const int64_t lo = seg_lo[sg];
+    const int64_t hi = sg + 1 < nseg ? seg_lo[sg + 1] : a.nitems;
+    const int32_t u = a.out_src[a.items[lo]];
+    const int64_t bu = a.out_off[u];
+    const int du = (int)(a.out_off[u + 1] - bu);  // <= cap (host-checked)
+    __syncthreads();  // the previous segment is done with the LDS copy
+    for (int i = t; i < du; i += 256) {
+      lc[i] = a.out_col[bu + i];
+      le[i] = a.out_eid[bu + i];
+    }
+    __syncthreads();
+    for (int64_t e = lo + w; e < hi; e += kWaves) {  // one edge per wave
+      const int64_t q = a.items[e];
+      const int32_t v = a.out_col[q];
+      const int32_t euv = a.out_eid[q];
+      const int64_t bv = a.out_off[v], ev = a.out_off[v + 1];
+      const int64_t base = FILL ? a.base_off[a.inv[euv]] : 0;
+      int run = 0;
+      for (int64_t j0 = bv; j0 < ev; j0 += kWave) {  // uniform over the wave
+        const int64_t j = j0 + lane;
+        bool found = false;
+        int l = 0;
+        if (j < ev) {
+          const int32_t x = a.out_col[j];
+          int r = du;
+          while (l < r) {
+            const int mid = (l + r) >> 1;
+            if (lc[mid] < x)
+              l = mid + 1;
+            else
+              r = mid;
+          }
+          found = l < du && lc[l] == x;
+        }
+        const uint64_t m = ballot(found);
+        if (found)
+          orient_emit<FILL>(a, euv, le[l], a.out_eid[j],
+                            base + run + lanes_below(m));
+        run += __popcll(m);
+      }
+      if (lane == 0) orient_base_done<FILL>(a, euv, run);
     }
   }
+}
+
+// Start of every run of equal source among the items: flag[i] = 1 there.
+__global__ void k_seg_flags(const int32_t *__restrict__ items, int64_t n,
+                            const int32_t *__restrict__ out_src,
+                            int32_t *__restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n)
+    flag[i] = (i == 0 || out_src[items[i]] != out_src[items[i - 1]]) ? 1 : 0;
+}
+
+__global__ void k_seg_fill(const int32_t *__restrict__ flag,
+                           const int64_t *__restrict__ pos, int64_t n,
+                           int32_t *__restrict__ seg_lo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) seg_lo[pos[i]] = (int32_t)i;
+}
+
+__global__ void k_max_outdeg(const int64_t *__restrict__ out_off, int32_t n,
+                             int32_t *__restrict__ mx) {
+  int32_t m = 0;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, (int32_t)(out_off[u + 1] - out_off[u]));
+  for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+  if (lane_id() == 0) atomicMax(mx, m);
 }
 
 __global__ void k_orient_bins(const int64_t *__restrict__ out_off,
@@ -375,15 +497,25 @@ __global__ void k_orient_bins(const int64_t *__restrict__ out_off,
   bin[q] = m <= 4 ? 0 : m <= 16 ? 1 : m <= 64 ? 2 : 3;
 }
 
-__global__ void k_cursor_init(const int64_t *__restrict__ off, int64_t nr,
+// Side entries of internal r-clique i start after its base entries.
+__global__ void k_cursor_init(const int64_t *__restrict__ off,
+                              const int32_t *__restrict__ perm,
+                              const int32_t *__restrict__ count_base, int64_t nr,
                               unsigned long long *__restrict__ cursor) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nr) cursor[i] = (unsigned long long)off[i];
+  if (i < nr)
+    cursor[i] = (unsigned long long)(off[i] + (count_base ? count_base[perm[i]] : 0));
 }
+
+// Segments of equal source in the 64-lane bin (for k_orient_heavy).
+struct HeavySegs {
+  DArr<int32_t> lo;
+  int64_t n = 0;
+};
 
 template <bool FILL>
 void run_orient(OrientArgs a, const int32_t *items, const int64_t *bin_off,
-                hipStream_t s) {
+                const HeavySegs &hs, hipStream_t s) {
   for (int b = 0; b < 4; b++) {
     a.items = items + bin_off[b];
     a.nitems = bin_off[b + 1] - bin_off[b];
@@ -392,7 +524,15 @@ void run_orient(OrientArgs a, const int32_t *items, const int64_t *bin_off,
       case 0: k_orient_isect<1, FILL><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
       case 1: k_orient_isect<4, FILL><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
       case 2: k_orient_isect<16, FILL><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
-      default: k_orient_isect<64, FILL><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a); break;
+      default:
+        if (a.lds_cap > 0) {
+          const unsigned grid = (unsigned)std::min<int64_t>(hs.n, 65536);
+          k_orient_heavy<FILL><<<grid, 256, sizeof(int32_t) * 2 * a.lds_cap, s>>>(
+              a, hs.lo.p, hs.n);
+        } else {
+          k_orient_isect<64, FILL><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a);
+        }
+        break;
     }
     ND_LAUNCHED();
   }
@@ -541,23 +681,53 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   a.out_col = out_col.p;
   a.out_eid = out_eid.p;
   a.out_src = out_src.p;
-  DArr<int32_t> cnt(al, ne);
+  // the 64-lane bin by source, when every out-list fits the LDS copy
+  HeavySegs hs;
+  const int64_t n3 = bin_off[4] - bin_off[3];
+  if (n3 > 0) {
+    DArr<int32_t> mx(al, 1);
+    fill_i32(mx.p, 0, 1, s);
+    k_max_outdeg<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(
+        out_off.p, n, mx.p);
+    ND_LAUNCHED();
+    int32_t hmax = 0;
+    ND_HIP(hipMemcpyAsync(&hmax, mx.p, sizeof hmax, hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+    constexpr int kMaxLdsEntries = 8192;  // 64 KiB: two int32 arrays
+    if (hmax <= kMaxLdsEntries) {
+      a.lds_cap = std::max(hmax, 1);
+      const int32_t *it3 = items.p + bin_off[3];
+      DArr<int32_t> flag3(al, n3);
+      DArr<int64_t> pos3(al, n3 + 1);
+      k_seg_flags<<<grid_for(n3, 256), 256, 0, s>>>(it3, n3, out_src.p, flag3.p);
+      ND_LAUNCHED();
+      exclusive_scan_i32(flag3.p, pos3.p, n3, s, al);
+      hs.n = read_i64(pos3.p + n3, s);
+      hs.lo.reset(al, std::max<int64_t>(hs.n, 1));
+      k_seg_fill<<<grid_for(n3, 256), 256, 0, s>>>(flag3.p, pos3.p, n3, hs.lo.p);
+      ND_LAUNCHED();
+    }
+  }
+  DArr<int32_t> cnt(al, ne), cbase(al, ne);
   fill_i32(cnt.p, 0, ne, s);
   a.count = cnt.p;
-  run_orient<false>(a, items.p, bin_off, s);
+  a.count_base = cbase.p;  // every oriented edge stores its own
+  run_orient<false>(a, items.p, bin_off, hs, s);
   ks.nr = ne;
   build_layout(g, ks, cnt.p, s);
   cnt.free();
   ks.inc_ids.reset(al, 2 * ks.P);
   DArr<unsigned long long> cursor(al, ne);
   if (ne > 0) {
-    k_cursor_init<<<grid_for(ne, 256), 256, 0, s>>>(ks.inc_off.p, ne, cursor.p);
+    k_cursor_init<<<grid_for(ne, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
+                                                     cbase.p, ne, cursor.p);
     ND_LAUNCHED();
   }
   a.inv = ks.inv.p;
   a.cursor = cursor.p;
   a.ids = ks.inc_ids.p;
-  run_orient<true>(a, items.p, bin_off, s);
+  a.base_off = ks.inc_off.p;
+  run_orient<true>(a, items.p, bin_off, hs, s);
 }
 
 void build_triangles(nd_graph *g, hipStream_t s) {
