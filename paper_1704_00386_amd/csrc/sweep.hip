@@ -41,14 +41,16 @@ namespace {
 
 using namespace dev;
 
-__device__ __forceinline__ bool converged_before(const SweepStats *prev) {
-  return prev != nullptr && changed_sum(prev) == 0;
+// The previous sweep's changed count (1 for the first sweep: not converged).
+__device__ __forceinline__ unsigned long long prev_changed(const SweepArgs &a) {
+  return a.prev != nullptr ? changed_sum(a.prev) : 1ull;
 }
 
 // Frontier state of this sweep (uniform over the launch): flags are read
 // only if the previous sweep wrote them; this sweep notifies once the
 // previous one changed few enough r-cliques, and keeps notifying after.
 __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
+                                              unsigned long long prev_changed,
                                               const uint8_t **act,
                                               uint8_t **act_next) {
   if (a.fixed_set) {
@@ -59,7 +61,7 @@ __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
   const bool flags_valid = a.prev != nullptr && a.prev->notified;
   const bool notify =
       a.prev != nullptr &&
-      (a.prev->notified || changed_sum(a.prev) <= a.notify_below);
+      (a.prev->notified || prev_changed <= a.notify_below);
   *act = flags_valid ? a.act : nullptr;
   *act_next = notify ? a.act_next : nullptr;
   if (notify && blockIdx.x == 0 && threadIdx.x == 0) a.stats->notified = 1;
@@ -68,10 +70,11 @@ __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
 template <int K, int G, int M, typename T, bool AND, bool FR>
 __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
                                                     int64_t hi) {
-  if (converged_before(a.prev)) return;
+  const unsigned long long pc = prev_changed(a);
+  if (pc == 0) return;  // converged: a sweep queued past the end
   const uint8_t *act = nullptr;
   uint8_t *act_next = nullptr;
-  if (FR) frontier_mode(a, &act, &act_next);
+  if (FR) frontier_mode(a, pc, &act, &act_next);
   const int64_t R = lo + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   bool ev;
   const bool changed = update_regs<K, G, M, T, AND, FR>(
@@ -85,10 +88,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
                                                                int64_t lo,
                                                                int64_t hi) {
   __shared__ int32_t hist[kBlockHistBins];
-  if (converged_before(a.prev)) return;
+  const unsigned long long pc = prev_changed(a);
+  if (pc == 0) return;  // converged: a sweep queued past the end
   const uint8_t *act = nullptr;
   uint8_t *act_next = nullptr;
-  if (FR) frontier_mode(a, &act, &act_next);
+  if (FR) frontier_mode(a, pc, &act, &act_next);
   for (int64_t R = lo + blockIdx.x; R < hi; R += gridDim.x) {
     bool ev;
     const bool changed = update_block<K, T, AND, FR>(

@@ -67,12 +67,13 @@ __device__ __forceinline__ void stat_add(SweepStats *st, bool changed,
   }
 }
 
-// Total changed count of a finished sweep, the same on every lane of the
-// wave (one part per lane, then a wave sum).
+// Total changed count of a finished sweep.  Every lane reads the same 16
+// words (uniform addresses: scalar or broadcast loads), which costs far less
+// at every wave's start than a cross-lane reduction.
 __device__ __forceinline__ unsigned long long changed_sum(const SweepStats *st) {
-  unsigned long long v = lane_id() < kStatParts ? st->part[lane_id()].changed : 0;
+  unsigned long long v = 0;
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  for (int q = 0; q < kStatParts; q++) v += st->part[q].changed;
   return v;
 }
 
