@@ -286,6 +286,9 @@ struct SweepArgs {
   // PartialAND (Section 4.3, end): act marks a fixed set (stamp 1) that is
   // the only thing recomputed, every sweep, and nothing notifies.
   int fixed_set;
+  // At most this many workgroups per lanes-per-r-clique kernel (they stride
+  // over the rest of the bin); 0: one pass, no cap.
+  int grid_cap;
 };
 
 // Launch one sweep over every bin of ks (internal numbering, tau of

@@ -33,6 +33,8 @@
 // iterate is deterministic).  AND reads and writes one array in place; its
 // neighbour reads bypass the per-CU cache so that they see other workgroups'
 // recent writes, which only ever lower values (Section 4.2).
+#include <algorithm>
+
 #include "sweep_dev.h"
 
 namespace nd {
@@ -75,12 +77,24 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
   const uint8_t *act = nullptr;
   uint8_t *act_next = nullptr;
   if (FR) frontier_mode(a, pc, &act, &act_next);
-  const int64_t R = lo + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  bool ev;
-  const bool changed = update_regs<K, G, M, T, AND, FR>(
-      a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out, a.cap_by_tau,
-      R, R < hi, act, act_next, a.stamp, &ev);
-  stat_add(a.stats, changed, ev);
+  // Each wave takes kWave/G consecutive r-cliques per step and strides over
+  // the bin, so a grid of a few waves per SIMD covers any bin: an r-clique
+  // the frontier skips costs a flag test, not a wave dispatch.
+  constexpr int kPerWave = kWave / G;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kWave) * kPerWave;
+  const int sub = lane_id() / G;
+  unsigned long long n_ch = 0, n_ev = 0;  // wave totals, from ballots
+  for (int64_t base = lo + wave * kPerWave; base < hi; base += stride) {
+    const int64_t R = base + sub;
+    bool ev;
+    const bool changed = update_regs<K, G, M, T, AND, FR>(
+        a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out,
+        a.cap_by_tau, R, R < hi, act, act_next, a.stamp, &ev);
+    n_ch += __popcll(ballot(changed));
+    n_ev += __popcll(ballot(ev));
+  }
+  stat_add_counts(a.stats, n_ch, n_ev);
 }
 
 template <int K, typename T, bool AND, bool FR>
@@ -108,6 +122,14 @@ __global__ void k_zero_range(T *__restrict__ tau, int64_t lo, int64_t hi) {
   if (i < hi) tau[i] = 0;
 }
 
+// Blocks for a bin of n r-cliques at G lanes each, at most a.grid_cap
+// (the kernels stride over the rest).
+inline unsigned regs_grid(const SweepArgs &a, int64_t n, int G) {
+  const int64_t blocks = (n * G + 255) / 256;
+  return (unsigned)std::max<int64_t>(
+      1, a.grid_cap > 0 ? std::min<int64_t>(blocks, a.grid_cap) : blocks);
+}
+
 template <int K, typename T, bool AND, bool FR>
 void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
   for (int bin = kBinBlock; bin < kBinZero; bin++) {
@@ -115,19 +137,19 @@ void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
     if (n == 0) continue;
     switch (bin) {
       case kBinG1:
-        k_sweep_regs<K, 1, 4, T, AND, FR><<<grid_for(n, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 1, 4, T, AND, FR><<<regs_grid(a, n, 1), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG4:
-        k_sweep_regs<K, 4, 4, T, AND, FR><<<grid_for(n * 4, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 4, 4, T, AND, FR><<<regs_grid(a, n, 4), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG16:
-        k_sweep_regs<K, 16, 4, T, AND, FR><<<grid_for(n * 16, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 16, 4, T, AND, FR><<<regs_grid(a, n, 16), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinG64:
-        k_sweep_regs<K, 64, 4, T, AND, FR><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 64, 4, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
         break;
       case kBinWave:
-        k_sweep_regs<K, 64, 32, T, AND, FR><<<grid_for(n * 64, 256), 256, 0, s>>>(a, lo, hi);
+        k_sweep_regs<K, 64, 32, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
         break;
       default: {
         const unsigned grid = (unsigned)(n < 65536 ? n : 65536);

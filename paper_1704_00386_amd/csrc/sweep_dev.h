@@ -67,6 +67,18 @@ __device__ __forceinline__ void stat_add(SweepStats *st, bool changed,
   }
 }
 
+// Add wave-wide totals (the same on every lane, summed from ballots) to the
+// sweep's counters: one atomic per wave and counter.
+__device__ __forceinline__ void stat_add_counts(SweepStats *st,
+                                                unsigned long long ch,
+                                                unsigned long long ev) {
+  if (lane_id() == 0 && (ch | ev)) {
+    StatPart &p = st->part[(blockIdx.x + threadIdx.x / kWave) % kStatParts];
+    if (ch) atomicAdd(&p.changed, ch);
+    if (ev) atomicAdd(&p.evaluated, ev);
+  }
+}
+
 // Total changed count of a finished sweep.  Every lane reads the same 16
 // words (uniform addresses: scalar or broadcast loads), which costs far less
 // at every wave's start than a cross-lane reduction.
