@@ -132,12 +132,18 @@ __device__ __forceinline__ int32_t hindex_search(const int32_t (&rho)[M],
   return lo;
 }
 
-// Notification of Section 4.3: R changed to h, so a neighbour R' (any other
-// r-clique of an s-clique containing R) can change at the next sweep only if
-// h < tau(R'); mark those.  SND reads tau_t, so the test uses a value at
-// least tau_{t+1}(R') -- a superset of the neighbours that can change, hence
-// the iterates are exactly those of full sweeps.  Byte stores of the same
-// value race harmlessly.
+// Notification of Section 4.3: R changed to h.  A neighbour R' (another
+// r-clique of an s-clique S containing R) can change at the next sweep only
+// if some rho(S,R') falls from at least its next cap c' = tau_{t+1}(R') to
+// below it.  Through S that needs rho_t(S,R') >= c' > h, i.e. both
+//   h < tau(R')                 (tau_t(R') >= c'), and
+//   h <= tau(Q) for every other member Q of S besides R and R'
+// (rho_t(S,R') is a minimum over them and R).  Mark exactly those R'.  SND
+// reads tau_t, so every R' that can change is marked and the iterates are
+// those of full sweeps.  In place (AND) the values read may already be
+// newer; of several members of S that fell in one sweep, the one with the
+// lowest new value still passes the test (<= keeps ties), so the s-clique is
+// never lost.  Byte stores of the same stamp race harmlessly.
 template <int K, typename T, bool AND>
 __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
                                        int64_t b, int64_t d, int first,
@@ -145,10 +151,19 @@ __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
                                        uint8_t *act_next, uint8_t stamp_next) {
   for (int64_t j = first; j < d; j += stride) {
     const int32_t *q = ids + K * (b + j);
+    int32_t r[K], v[K];
 #pragma unroll
     for (int x = 0; x < K; x++) {
-      const int32_t r = q[x];
-      if (h < load_tau<T, AND>(tau + r)) act_next[r] = stamp_next;
+      r[x] = q[x];
+      v[x] = load_tau<T, AND>(tau + r[x]);
+    }
+#pragma unroll
+    for (int x = 0; x < K; x++) {
+      bool others_ok = true;
+#pragma unroll
+      for (int y = 0; y < K; y++)
+        if (y != x) others_ok &= h <= v[y];
+      if (h < v[x] && others_ok) act_next[r[x]] = stamp_next;
     }
   }
 }
