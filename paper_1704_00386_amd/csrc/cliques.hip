@@ -62,9 +62,10 @@ __device__ __forceinline__ uint64_t subgroup_mask() {
 
 template <int G, int MODE>
 __global__ __launch_bounds__(256) void k_edge_isect(EdgeIsectArgs a) {
-  const int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sl = lane_id() % G;
-  if (gsub >= a.nitems) return;  // uniform within the subgroup
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       gsub < a.nitems; gsub += nsub) {  // uniform within the subgroup
   const int32_t e = a.items[gsub];
   const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
   const int64_t bu = a.row_off[u], eu = a.row_off[u + 1];
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(256) void k_edge_isect(EdgeIsectArgs a) {
   }
   if ((MODE == kCountTruss || MODE == kCountTri) && sl == 0)
     a.count[e] = (int32_t)written;
+  }
 }
 
 // Edges whose shorter list is long (both endpoints high-degree): one wave
@@ -225,9 +227,10 @@ __device__ __forceinline__ int32_t tri_id(const TriIsectArgs &t, int32_t a,
 
 template <int G, bool FILL>
 __global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
-  const int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sl = lane_id() % G;
-  if (gsub >= a.nitems) return;
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       gsub < a.nitems; gsub += nsub) {  // uniform within the subgroup
   const int32_t t = a.items[gsub];
   const int32_t e = a.tri_e[t];
   const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
@@ -260,6 +263,7 @@ __global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
     written += __popcll(m);
   }
   if (!FILL && sl == 0) a.count[t] = (int32_t)written;
+  }
 }
 
 // ------------------------------------------- k-truss by orientation
@@ -364,9 +368,10 @@ __device__ __forceinline__ void orient_base_done(const OrientArgs &a,
 
 template <int G, bool FILL>
 __global__ __launch_bounds__(256) void k_orient_isect(OrientArgs a) {
-  const int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sl = lane_id() % G;
-  if (gsub >= a.nitems) return;  // uniform within the subgroup
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       gsub < a.nitems; gsub += nsub) {  // uniform within the subgroup
   const int64_t q = a.items[gsub];
   const int32_t u = a.out_src[q], v = a.out_col[q];
   const int32_t euv = a.out_eid[q];
@@ -396,6 +401,7 @@ __global__ __launch_bounds__(256) void k_orient_isect(OrientArgs a) {
     run += __popcll(m);
   }
   if (sl == 0) orient_base_done<FILL>(a, euv, run);
+  }
 }
 
 // The oriented edges whose both out-lists are long (the 64-lane bin) are
@@ -521,16 +527,16 @@ void run_orient(OrientArgs a, const int32_t *items, const int64_t *bin_off,
     a.nitems = bin_off[b + 1] - bin_off[b];
     if (a.nitems == 0) continue;
     switch (b) {
-      case 0: k_orient_isect<1, FILL><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
-      case 1: k_orient_isect<4, FILL><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
-      case 2: k_orient_isect<16, FILL><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
+      case 0: k_orient_isect<1, FILL><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
+      case 1: k_orient_isect<4, FILL><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
+      case 2: k_orient_isect<16, FILL><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
       default:
         if (a.lds_cap > 0) {
           const unsigned grid = (unsigned)std::min<int64_t>(hs.n, 65536);
           k_orient_heavy<FILL><<<grid, 256, sizeof(int32_t) * 2 * a.lds_cap, s>>>(
               a, hs.lo.p, hs.n);
         } else {
-          k_orient_isect<64, FILL><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a);
+          k_orient_isect<64, FILL><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a);
         }
         break;
     }
@@ -578,9 +584,9 @@ void run_edge_isect(EdgeIsectArgs a, const int32_t *items,
     a.nitems = bin_off[b + 1] - bin_off[b];
     if (a.nitems == 0) continue;
     switch (b) {
-      case 0: k_edge_isect<1, MODE><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
-      case 1: k_edge_isect<4, MODE><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
-      case 2: k_edge_isect<16, MODE><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
+      case 0: k_edge_isect<1, MODE><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
+      case 1: k_edge_isect<4, MODE><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
+      case 2: k_edge_isect<16, MODE><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
       default: {
         const unsigned grid = (unsigned)std::min<int64_t>(a.nitems, 1 << 20);
         k_edge_isect_lds<MODE><<<grid, kWave, 0, s>>>(a);
@@ -599,10 +605,10 @@ void run_tri_isect(TriIsectArgs a, const int32_t *items, const int64_t *bin_off,
     a.nitems = bin_off[b + 1] - bin_off[b];
     if (a.nitems == 0) continue;
     switch (b) {
-      case 0: k_tri_isect<1, FILL><<<grid_for(a.nitems, 256), 256, 0, s>>>(a); break;
-      case 1: k_tri_isect<4, FILL><<<grid_for(a.nitems * 4, 256), 256, 0, s>>>(a); break;
-      case 2: k_tri_isect<16, FILL><<<grid_for(a.nitems * 16, 256), 256, 0, s>>>(a); break;
-      default: k_tri_isect<64, FILL><<<grid_for(a.nitems * 64, 256), 256, 0, s>>>(a); break;
+      case 0: k_tri_isect<1, FILL><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
+      case 1: k_tri_isect<4, FILL><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
+      case 2: k_tri_isect<16, FILL><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
+      default: k_tri_isect<64, FILL><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a); break;
     }
     ND_LAUNCHED();
   }
@@ -809,12 +815,14 @@ __global__ __launch_bounds__(256) void k_csr_fill(
     const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
     const int64_t *__restrict__ off, int64_t lo, int64_t hi,
     int32_t *__restrict__ out) {
-  const int64_t i = lo + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sl = lane_id() % G;
-  if (i >= hi) return;
-  const int32_t u = perm[i];
-  const int64_t b = row_off[u], d = row_off[u + 1] - b, o = off[i];
-  for (int64_t j = sl; j < d; j += G) out[o + j] = inv[col[b + j]];
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t i = lo + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       i < hi; i += nsub) {
+    const int32_t u = perm[i];
+    const int64_t b = row_off[u], d = row_off[u + 1] - b, o = off[i];
+    for (int64_t j = sl; j < d; j += G) out[o + j] = inv[col[b + j]];
+  }
 }
 
 }  // namespace
@@ -835,13 +843,13 @@ void build_incidence_core(nd_graph *g, KindState &ks, hipStream_t s) {
   // four lanes each
   const int64_t split = ks.bin_hi[kBinG64];
   if (split > 0) {
-    k_csr_fill<64><<<grid_for(split * 64, 256), 256, 0, s>>>(
+    k_csr_fill<64><<<grid_stride(split, 64), 256, 0, s>>>(
         g->row_off.p, g->col.p, ks.perm.p, ks.inv.p, ks.inc_off.p, 0, split,
         ks.inc_ids.p);
     ND_LAUNCHED();
   }
   if (n > split) {
-    k_csr_fill<4><<<grid_for((n - split) * 4, 256), 256, 0, s>>>(
+    k_csr_fill<4><<<grid_stride(n - split, 4), 256, 0, s>>>(
         g->row_off.p, g->col.p, ks.perm.p, ks.inv.p, ks.inc_off.p, split, n,
         ks.inc_ids.p);
     ND_LAUNCHED();

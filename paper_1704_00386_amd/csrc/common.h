@@ -63,6 +63,16 @@ inline unsigned grid_for(int64_t items, int64_t per_block) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// Workgroups of 256 threads for `items` work items of `lanes` lanes each,
+// at most kMaxStrideBlocks (2^28 threads).  Kernels launched with it stride
+// over the items, so no launch exceeds the 32-bit dispatch size however many
+// items there are (the (3,4) builders reach 4*10^8 triangles x 64 lanes).
+constexpr int64_t kMaxStrideBlocks = 1 << 20;
+inline unsigned grid_stride(int64_t items, int64_t lanes) {
+  const int64_t g = ceil_div(items * lanes, 256);
+  return (unsigned)(g < 1 ? 1 : g > kMaxStrideBlocks ? kMaxStrideBlocks : g);
+}
+
 // --------------------------------------------------------- device helpers
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -104,12 +104,14 @@ __global__ __launch_bounds__(256) void k_incidence_original(
     const int32_t *__restrict__ inv, const int32_t *__restrict__ perm, int k,
     int64_t nr, const int64_t *__restrict__ out_off,
     int32_t *__restrict__ out_ids) {
-  const int64_t R = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int sl = lane_id() % G;
-  if (R >= nr) return;
-  const int32_t i = inv[R];
-  const int64_t b = in_off[i] * k, e = in_off[i + 1] * k, o = out_off[R] * k;
-  for (int64_t j = b + sl; j < e; j += G) out_ids[o + (j - b)] = perm[in_ids[j]];
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t R = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       R < nr; R += nsub) {
+    const int32_t i = inv[R];
+    const int64_t b = in_off[i] * k, e = in_off[i + 1] * k, o = out_off[R] * k;
+    for (int64_t j = b + sl; j < e; j += G) out_ids[o + (j - b)] = perm[in_ids[j]];
+  }
 }
 
 template <typename T>
@@ -215,7 +217,7 @@ void incidence_original(nd_graph *g, const KindState &ks, int64_t *off,
   sdegree_original(ks, dso.p, s);
   exclusive_scan_i32(dso.p, off, ks.nr, s, al);
   if (ks.nr == 0 || ks.P == 0) return;
-  k_incidence_original<16><<<grid_for(ks.nr * 16, 256), 256, 0, s>>>(
+  k_incidence_original<16><<<grid_stride(ks.nr, 16), 256, 0, s>>>(
       ks.inc_off.p, ks.inc_ids.p, ks.inv.p, ks.perm.p, ks.k, ks.nr, off, ids);
   ND_LAUNCHED();
 }

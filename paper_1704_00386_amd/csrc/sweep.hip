@@ -122,12 +122,12 @@ __global__ void k_zero_range(T *__restrict__ tau, int64_t lo, int64_t hi) {
   if (i < hi) tau[i] = 0;
 }
 
-// Blocks for a bin of n r-cliques at G lanes each, at most a.grid_cap
-// (the kernels stride over the rest).
+// Blocks for a bin of n r-cliques at G lanes each, at most a.grid_cap, and
+// never more than grid_stride allows (the kernels stride over the rest).
 inline unsigned regs_grid(const SweepArgs &a, int64_t n, int G) {
-  const int64_t blocks = (n * G + 255) / 256;
-  return (unsigned)std::max<int64_t>(
-      1, a.grid_cap > 0 ? std::min<int64_t>(blocks, a.grid_cap) : blocks);
+  const int64_t blocks = grid_stride(n, G);
+  return (unsigned)(a.grid_cap > 0 ? std::min<int64_t>(blocks, a.grid_cap)
+                                   : blocks);
 }
 
 template <int K, typename T, bool AND, bool FR>
