@@ -109,6 +109,107 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_sweep")
 
 
+FULL_SWEEP_SUFFIX = ", false, false>"  # k_sweep_regs<..., AND, frontier>
+
+
+def _short_kernel(name: str) -> str:
+    name = name.replace("void ", "").replace("nd::(anonymous namespace)::", "")
+    i = name.find(">(")
+    return name[:i + 1] if i >= 0 else name
+
+
+def _profile_command(args_extra: str, out: str) -> str:
+    return (f"rocprofv3 {args_extra} --output-format csv -d $R/gpurun_out/{out} -o {out} "
+            "-- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu --stream-graphs 0 "
+            "--small-graphs 0 --ego-queries 0 --calib-copy")
+
+
+def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
+    """Write the committed profile summaries from the CSV output of three
+    rocprofv3 runs of this script (see the commands recorded in them): the
+    kernel trace statistics of one bench run, and FETCH_SIZE / WRITE_SIZE per
+    dispatch, scaled by what the same counters read for the 1 GiB device copy
+    that --calib-copy makes first in the same run."""
+    import csv
+    import statistics
+
+    out_dir = os.path.join(ROOT, "profiles")
+    # kernel trace statistics
+    rows = list(csv.DictReader(open(trace_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# Kernel trace: one bench step (k-truss SND on Chung-Lu 2^20, beta 2.1, mean 32)", "",
+             "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`):", "", "```",
+             _profile_command("--kernel-trace --stats", "kt"), "```", "",
+             "The run holds one timed step (prep + SND with the notification frontier), the full-sweep",
+             "roofline leg (SND, every r-clique recomputed each sweep) and the AND leg (frontier), after a",
+             "1 GiB device copy. Template arguments of `k_sweep_regs<k, lanes, values/lane, tau type, AND,",
+             "frontier>`.", "", "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
+    full_avg = 0.0
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:32]:
+        name = _short_kernel(r["Name"])
+        avg = float(r["AverageNs"]) / 1e3
+        if name.startswith("k_sweep_regs") and name.endswith(FULL_SWEEP_SUFFIX):
+            full_avg += avg
+        lines.append(f"| {100 * float(r['TotalDurationNs']) / tot:.1f} | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {avg:.1f} | `{name}` |")
+    lines += ["", f"Full sweep = the `k_sweep_regs<..., false, false>` launches (one per sweep bin): "
+              f"{full_avg:.0f} us per sweep (sum of their averages)."]
+    open(os.path.join(out_dir, "kernel_trace_cl20_truss.md"), "w").write("\n".join(lines) + "\n")
+
+    # calibrated HBM-side traffic of one full sweep
+    def per_kernel(path, counter):
+        vals, copy = {}, []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = _short_kernel(r["Kernel_Name"])
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                copy.append(v)
+            vals.setdefault(name, []).append(v)
+        return vals, max(copy)
+
+    fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    gib_kib = float(1 << 20)  # the copy moves 1 GiB each way
+    fscale, wscale = gib_kib / fcopy, gib_kib / wcopy
+    full = sorted(k for k in fetch if k.startswith("k_sweep_regs") and k.endswith(FULL_SWEEP_SUFFIX))
+    f_kib = sum(statistics.mean(fetch[k]) for k in full)
+    w_kib = sum(statistics.mean(write.get(k, [0.0])) for k in full)
+    rec = {
+        "workload": "k-truss SND, full sweeps, Chung-Lu n=2^20 beta 2.1 mean 32 seed 2",
+        "kernels": full,
+        "fetch_bytes_per_sweep": f_kib * 1024 * fscale,
+        "write_bytes_per_sweep": w_kib * 1024 * wscale,
+        "hbm_bytes_per_sweep": (f_kib * fscale + w_kib * wscale) * 1024,
+        "fetch_scale": fscale, "write_scale": wscale,
+        "scale_from": "1 GiB device-to-device copy (__amd_rocclr_copyBuffer) in the same run",
+        "sweep_source_sha256": sweep_source_hash(),
+        "commands": [_profile_command("--pmc FETCH_SIZE", "pf"),
+                     _profile_command("--pmc WRITE_SIZE", "pw")],
+    }
+    json.dump(rec, open(os.path.join(out_dir, "traffic_sweep_cl20_truss.json"), "w"), indent=1)
+    md = ["# HBM-side traffic of one full sweep (k-truss SND, Chung-Lu 2^20)", "",
+          "Counters per dispatch (KiB), averaged over the full sweeps of the roofline leg and summed over",
+          "the bin kernels of a sweep, then scaled by what the same counter reads for a 1 GiB",
+          f"device-to-device copy in the same run (FETCH_SIZE reads {fcopy / 1024:.0f} MiB for it, "
+          f"WRITE_SIZE {wcopy / 1024:.0f} MiB):", "",
+          f"- fetch scale {fscale:.3f}, write scale {wscale:.3f}",
+          f"- FETCH per sweep: {rec['fetch_bytes_per_sweep'] / 2**30:.2f} GiB",
+          f"- WRITE per sweep: {rec['write_bytes_per_sweep'] / 2**30:.3f} GiB", "",
+          "Per kernel (unscaled KiB averages):", "", "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |",
+          "|---|---:|---:|"]
+    for k in full:
+        md.append(f"| `{k}` | {statistics.mean(fetch[k]):.0f} | {statistics.mean(write.get(k, [0.0])):.0f} |")
+    md += ["", "Commands (run from /tmp, `TMPDIR=/tmp`, repo at `$R`), then "
+           "`python bench.py --summarize-profiles <trace stats csv> <fetch csv> <write csv>`:", "", "```",
+           *rec["commands"], "```", "",
+           "These counters measure L2-to-fabric traffic, which includes Infinity Cache (MALL) hits; the",
+           "tau array (33 MB as uint16) fits in the MALL, so this is an upper bound on DRAM bytes."]
+    open(os.path.join(out_dir, "traffic_sweep_cl20_truss.md"), "w").write("\n".join(md) + "\n")
+    print(f"full sweep {full_avg:.0f} us; HBM-side {rec['hbm_bytes_per_sweep'] / 1e9:.2f} GB per sweep")
+
+
 def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     """Batched and served k-truss against one graph per launch, on `count`
     graphs of the request-stream workload (Chung-Lu, n ~ U{n_lo..n_hi},
@@ -292,7 +393,14 @@ def main():
     ap.add_argument("--small-graphs", type=int, default=512,
                     help="graphs in the small-graph batched comparison "
                          "(0: skip)")
+    ap.add_argument("--summarize-profiles", nargs=3, default=None,
+                    metavar=("TRACE_STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="write the profiles/ summaries from rocprofv3 output "
+                         "and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU "
               "sharding is a design note, not a measured path", file=sys.stderr)
