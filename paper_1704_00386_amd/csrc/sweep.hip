@@ -77,22 +77,54 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
   const uint8_t *act = nullptr;
   uint8_t *act_next = nullptr;
   if (FR) frontier_mode(a, pc, &act, &act_next);
-  // Each wave takes kWave/G consecutive r-cliques per step and strides over
-  // the bin, so a grid of a few waves per SIMD covers any bin: an r-clique
-  // the frontier skips costs a flag test, not a wave dispatch.
   constexpr int kPerWave = kWave / G;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kWave) * kPerWave;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   const int sub = lane_id() / G;
+  const T *tin = (const T *)a.tau_in;
+  T *tout = (T *)a.tau_out;
   unsigned long long n_ch = 0, n_ev = 0;  // wave totals, from ballots
-  for (int64_t base = lo + wave * kPerWave; base < hi; base += stride) {
-    const int64_t R = base + sub;
-    bool ev;
-    const bool changed = update_regs<K, G, M, T, AND, FR>(
-        a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out,
-        a.cap_by_tau, R, R < hi, act, act_next, a.stamp, &ev);
-    n_ch += __popcll(ballot(changed));
-    n_ev += __popcll(ballot(ev));
+  if (FR && G > 1 && act != nullptr) {
+    // Sparse sweep: the wave tests the flags of kChunk consecutive r-cliques
+    // at once (one lane each, coalesced; SND copies the skipped values
+    // forward there) and runs only the flagged ones, kPerWave at a time.  A
+    // chunk holds at most 8 rounds of r-cliques, so a run of flagged hubs
+    // is not serialised on one wave for long.
+    constexpr int kChunk = kPerWave * 8 < kWave ? kPerWave * 8 : kWave;
+    for (int64_t base = lo + wave * kChunk; base < hi; base += waves * kChunk) {
+      const int64_t Rl = base + lane_id();
+      bool on = false;
+      if (lane_id() < kChunk && Rl < hi) {
+        on = act[Rl] == a.stamp;
+        if (!AND && !on) tout[Rl] = tin[Rl];
+      }
+      const uint64_t m = ballot(on);
+      const int na = __popcll(m);
+      for (int r0 = 0; r0 < na; r0 += kPerWave) {  // uniform over the wave
+        const int t = r0 + sub;
+        const bool has = t < na;
+        const int64_t R = base + (has ? nth_set_bit(m, t) : 0);
+        bool ev;
+        const bool changed = update_regs<K, G, M, T, AND, FR>(
+            a.inc_off, a.inc_ids, tin, tout, a.cap_by_tau, R, has, nullptr,
+            act_next, a.stamp, &ev);
+        n_ch += __popcll(ballot(changed));
+        n_ev += __popcll(ballot(ev));
+      }
+    }
+  } else {
+    // Each wave takes kPerWave consecutive r-cliques per step and strides
+    // over the bin, so a grid of a few waves per SIMD covers any bin.
+    for (int64_t base = lo + wave * kPerWave; base < hi;
+         base += waves * kPerWave) {
+      const int64_t R = base + sub;
+      bool ev;
+      const bool changed = update_regs<K, G, M, T, AND, FR>(
+          a.inc_off, a.inc_ids, tin, tout, a.cap_by_tau, R, R < hi, act,
+          act_next, a.stamp, &ev);
+      n_ch += __popcll(ballot(changed));
+      n_ev += __popcll(ballot(ev));
+    }
   }
   stat_add_counts(a.stats, n_ch, n_ev);
 }

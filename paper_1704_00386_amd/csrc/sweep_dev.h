@@ -168,6 +168,18 @@ __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
   }
 }
 
+// Bit position of the t-th set bit (t counted from 0) of m; t < popc(m).
+// Binary lifting: the largest p with popc(m below bit p) <= t is that bit.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int t) {
+  int p = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1) {
+    const uint64_t below = m & ((((uint64_t)1) << (p + w)) - 1);
+    if (__popcll(below) <= t) p += w;
+  }
+  return p;
+}
+
 // Frontier flags hold sweep stamps instead of booleans: sweep t takes part
 // for r-cliques whose flag equals stamp(t) = t mod 255 + 1, and notifies by
 // writing stamp(t+1) into the other array of the pair.  Old stamps never need
