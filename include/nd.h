@@ -10,12 +10,15 @@
  *     U tau(R) = H({rho(S,R)} over all S containing R),
  * H being the h-index (Section 2.2).  The iteration stops at the first sweep
  * that changes nothing; the result is then exactly kappa_s (Theorem 3 and
- * Lemma 2).  Three instances are supported (Section 5):
+ * Lemma 2).  Five instances are supported (Section 5 evaluates the first
+ * three; the definitions hold for any r < s, Section 2.1):
  *     ND_KCORE      (r,s) = (1,2)  core number of every vertex
  *     ND_KTRUSS     (r,s) = (2,3)  truss number of every edge, counted in
  *                                  triangles (Section 2.1; Cohen's k-truss
  *                                  number is this value + 2)
  *     ND_NUCLEUS34  (r,s) = (3,4)  kappa_4 of every triangle
+ *     ND_NUCLEUS13  (r,s) = (1,3)  kappa_3 of every vertex (its triangles)
+ *     ND_NUCLEUS24  (r,s) = (2,4)  kappa_4 of every edge (its 4-cliques)
  * under synchronous (SND, Alg. 2) or asynchronous (AND, Alg. 3) updates.
  *
  * Output order.  r-cliques are numbered by the lexicographic order of their
@@ -64,7 +67,13 @@ typedef enum {
   ND_ERR_TIMEOUT = 8        /* nd_server_wait timed out; request still live */
 } nd_status;
 
-typedef enum { ND_KCORE = 0, ND_KTRUSS = 1, ND_NUCLEUS34 = 2 } nd_kind;
+typedef enum {
+  ND_KCORE = 0,
+  ND_KTRUSS = 1,
+  ND_NUCLEUS34 = 2,
+  ND_NUCLEUS13 = 3,
+  ND_NUCLEUS24 = 4
+} nd_kind;
 
 /* ND_SND: Jacobi-style sweeps, tau_{t+1} = U tau_t from a snapshot (Alg. 2);
  *         every iterate is deterministic.
@@ -175,7 +184,7 @@ nd_status nd_sizes(nd_graph *g, nd_kind kind, int64_t *n_rcliques,
                    int64_t *n_incidence, size_t *dev_bytes);
 
 /* Copy out the r-clique list: verts[i*r + j] = j-th smallest vertex of
- * r-clique i (r = 1, 2, 3 for the three kinds), lexicographic order. */
+ * r-clique i (r = 1, 2, 3, 1, 2 for the five kinds), lexicographic order. */
 nd_status nd_rcliques(nd_graph *g, nd_kind kind, int32_t *verts, int on_device,
                       void *stream);
 

@@ -31,7 +31,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
-KINDS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4)}
+KINDS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4), "nucleus13": (1, 3),
+         "nucleus24": (2, 4)}
 
 
 def build(force: bool = False) -> str:

@@ -7,7 +7,8 @@ fallback.
 
 Kinds (Section 5 of Sariyuce, Seshadhri, Pinar): ``"core"`` = (1,2),
 ``"truss"`` = (2,3) with truss numbers counted in triangles, ``"nucleus34"`` =
-(3,4).  Modes: ``"snd"`` (Alg. 2) and ``"and"`` (Alg. 3).
+(3,4), and the generic variants ``"nucleus13"`` = (1,3) and ``"nucleus24"`` =
+(2,4).  Modes: ``"snd"`` (Alg. 2) and ``"and"`` (Alg. 3).
 """
 
 from __future__ import annotations
@@ -36,8 +37,9 @@ _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                            ctypes.c_int]
 _HIP_D2D = 3
 
-KIND = {"core": 0, "truss": 1, "nucleus34": 2}
-RS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4)}
+KIND = {"core": 0, "truss": 1, "nucleus34": 2, "nucleus13": 3, "nucleus24": 4}
+RS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4), "nucleus13": (1, 3),
+      "nucleus24": (2, 4)}
 MODE = {"snd": 0, "and": 1}
 
 STATUS = {0: "ok", 1: "invalid", 2: "oom", 3: "device", 4: "unsupported",

@@ -205,20 +205,25 @@ static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
   ND_HIP(hipEventCreate(&e0));
   ND_HIP(hipEventCreate(&e1));
   ND_HIP(hipEventRecord(e0, s));
+  const KindRS rs = kind_rs(kind);
+  ks.r = rs.r; ks.s = rs.s; ks.k = rs.k;
   switch (kind) {
     case ND_KCORE:
       // (1,2): the s-cliques containing vertex u are its edges and the other
       // r-clique of each is the neighbour: the incidence is the CSR.
-      ks.r = 1; ks.s = 2; ks.k = 1;
       build_incidence_core(g, ks, s);
       break;
     case ND_KTRUSS:
-      ks.r = 2; ks.s = 3; ks.k = 2;
       build_incidence_truss(g, ks, s);
       break;
     case ND_NUCLEUS34:
-      ks.r = 3; ks.s = 4; ks.k = 3;
       build_incidence_n34(g, ks, s);
+      break;
+    case ND_NUCLEUS13:
+      build_incidence_n13(g, ks, s);
+      break;
+    case ND_NUCLEUS24:
+      build_incidence_n24(g, ks, s);
       break;
     default:
       ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "unknown kind %d", (int)kind);
@@ -252,8 +257,8 @@ static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
 }
 
 void prepare(nd_graph *g, nd_kind kind, hipStream_t s) {
-  ND_REQUIRE(kind == ND_KCORE || kind == ND_KTRUSS || kind == ND_NUCLEUS34,
-             ND_ERR_UNSUPPORTED, "unknown kind %d", (int)kind);
+  ND_REQUIRE(kind_valid(kind), ND_ERR_UNSUPPORTED, "unknown kind %d",
+             (int)kind);
   prepare_kind(g, kind, s);
 }
 
@@ -490,10 +495,10 @@ nd_status nd_rcliques(nd_graph *g, nd_kind kind, int32_t *verts, int on_device,
     if (cnt == 0) return;
     DArr<int32_t> tmp(g->ctx->alloc, cnt);
     const int32_t *src = tmp.p;
-    if (kind == ND_KCORE) {
+    if (r == 1) {
       k_iota<<<grid_for(cnt, 256), 256, 0, s>>>(tmp.p, cnt);
       ND_LAUNCHED();
-    } else if (kind == ND_KTRUSS) {
+    } else if (r == 2) {
       src = g->ev.p;
     } else {
       k_tri_verts<<<grid_for(ks.nr, 256), 256, 0, s>>>(

@@ -448,7 +448,7 @@ void Batch::launch_epoch_t() {
 }
 
 void Batch::launch_epoch() {
-  const int k = kind_ == ND_KCORE ? 1 : kind_ == ND_KTRUSS ? 2 : 3;
+  const int k = kind_rs(kind_).k;
   const int key = (k * 2 + (tau16_ ? 1 : 0)) * 4 + (mode_ == ND_AND ? 2 : 0) +
                   (frontier_ ? 1 : 0);
 #define ND_EPOCH_CASES(KK, T, BASE)                                   \
@@ -463,6 +463,8 @@ void Batch::launch_epoch() {
     ND_EPOCH_CASES(2, uint16_t, 20)
     ND_EPOCH_CASES(3, int32_t, 24)
     ND_EPOCH_CASES(3, uint16_t, 28)
+    ND_EPOCH_CASES(5, int32_t, 40)
+    ND_EPOCH_CASES(5, uint16_t, 44)
     default: ND_REQUIRE(false, ND_ERR_INVALID, "bad batch key %d", key);
   }
 #undef ND_EPOCH_CASES
@@ -787,7 +789,7 @@ extern "C" nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
     ND_REQUIRE(ctx, ND_ERR_INVALID, "ctx is NULL");
     ND_REQUIRE(count >= 0 && (count == 0 || graphs), ND_ERR_INVALID,
                "bad graph list");
-    ND_REQUIRE(kind == ND_KCORE || kind == ND_KTRUSS || kind == ND_NUCLEUS34,
+    ND_REQUIRE(kind_valid(kind),
                ND_ERR_UNSUPPORTED, "unknown kind");
     ND_HIP(hipSetDevice(ctx->device));
     StreamScope scope((hipStream_t)stream);

@@ -798,6 +798,213 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   run_tri_isect<true>(a, items.p, bin_off, s);
 }
 
+// ------------------------------------------------------- (1,3) and (2,4)
+//
+// The generic variants of Section 5 listed from the triangles: for (1,3) a
+// vertex's s-cliques are its triangles (the other two vertices listed); for
+// (2,4) an edge's s-cliques are its 4-cliques (the other five edges listed).
+// Counts and slots come from atomics, so list order varies from run to run.
+
+namespace {
+
+__global__ void k_n13_count(const int32_t *__restrict__ ev,
+                            const int32_t *__restrict__ tri_e,
+                            const int32_t *__restrict__ tri_w, int64_t nt,
+                            int32_t *__restrict__ cnt) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = tri_e[t];
+    atomicAdd(&cnt[ev[2 * e]], 1);
+    atomicAdd(&cnt[ev[2 * e + 1]], 1);
+    atomicAdd(&cnt[tri_w[t]], 1);
+  }
+}
+
+// Triangle (u,v,w) into the lists of u, v and w, each entry the two other
+// vertices (internal ids).
+__global__ void k_n13_fill(const int32_t *__restrict__ ev,
+                           const int32_t *__restrict__ tri_e,
+                           const int32_t *__restrict__ tri_w, int64_t nt,
+                           const int32_t *__restrict__ inv,
+                           unsigned long long *__restrict__ cursor,
+                           int32_t *__restrict__ ids) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = tri_e[t];
+    const int32_t x[3] = {inv[ev[2 * e]], inv[ev[2 * e + 1]], inv[tri_w[t]]};
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      const int64_t p = (int64_t)atomicAdd(&cursor[x[i]], 1ull);
+      ids[2 * p] = x[(i + 1) % 3];
+      ids[2 * p + 1] = x[(i + 2) % 3];
+    }
+  }
+}
+
+struct K4Args {
+  const int32_t *items;  // triangle ids of this bin
+  int64_t nitems;
+  const int32_t *ev;
+  const int64_t *row_off;
+  const int32_t *col;
+  const int32_t *eid;
+  const int32_t *tri_e;
+  const int32_t *tri_w;
+  int32_t *count;               // count pass: 4-cliques per edge id
+  const int32_t *inv;           // fill pass: edge id -> internal id
+  unsigned long long *cursor;   // fill pass: next slot per internal id
+  int32_t *ids;                 // fill pass: 5 ids per (edge, 4-clique)
+};
+
+// Every 4-clique {u,v,w,x}, u<v<w<x, is found once, from its lowest
+// triangle (u,v,w): x runs over the common neighbours of u, v and w above w.
+// G lanes per triangle stride over the shortest of the three lists (from its
+// first entry above w) and binary-search the other two.
+template <int G, bool FILL>
+__global__ __launch_bounds__(256) void k_k4_list(K4Args a) {
+  const int sl = lane_id() % G;
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       gsub < a.nitems; gsub += nsub) {
+    const int32_t t = a.items[gsub];
+    const int32_t euv = a.tri_e[t];
+    const int32_t u = a.ev[2 * (int64_t)euv], v = a.ev[2 * (int64_t)euv + 1];
+    const int32_t w = a.tri_w[t];
+    const int64_t b[3] = {a.row_off[u], a.row_off[v], a.row_off[w]};
+    const int64_t en[3] = {a.row_off[u + 1], a.row_off[v + 1], a.row_off[w + 1]};
+    int sh = 0;
+    if (en[1] - b[1] < en[sh] - b[sh]) sh = 1;
+    if (en[2] - b[2] < en[sh] - b[sh]) sh = 2;
+    const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
+    const int64_t start = lower_bound<int32_t>(a.col, b[sh], en[sh], w + 1);
+    if (start >= en[sh]) continue;  // uniform within the subgroup
+    const int32_t euw = a.eid[lower_bound<int32_t>(a.col, b[0], en[0], w)];
+    const int32_t evw = a.eid[lower_bound<int32_t>(a.col, b[1], en[1], w)];
+    for (int64_t j = start + sl; j < en[sh]; j += G) {
+      const int32_t x = a.col[j];
+      const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
+      if (q1 >= en[o1] || a.col[q1] != x) continue;
+      const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
+      if (q2 >= en[o2] || a.col[q2] != x) continue;
+      int64_t pos[3];
+      pos[sh] = j;
+      pos[o1] = q1;
+      pos[o2] = q2;
+      // the six edges: uv, uw, vw, ux, vx, wx
+      const int32_t e6[6] = {euv, euw, evw, a.eid[pos[0]], a.eid[pos[1]],
+                             a.eid[pos[2]]};
+      if (!FILL) {
+#pragma unroll
+        for (int i = 0; i < 6; i++) atomicAdd(&a.count[e6[i]], 1);
+      } else {
+        int32_t ie[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) ie[i] = a.inv[e6[i]];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+          const int64_t p = (int64_t)atomicAdd(&a.cursor[ie[i]], 1ull);
+          int32_t *o = a.ids + 5 * p;
+          int c = 0;
+#pragma unroll
+          for (int q = 0; q < 6; q++)
+            if (q != i) o[c++] = ie[q];
+        }
+      }
+    }
+  }
+}
+
+template <bool FILL>
+void run_k4(K4Args a, const int32_t *items, const int64_t *bin_off,
+            hipStream_t s) {
+  for (int b = 0; b < kIsectBins; b++) {
+    a.items = items + bin_off[b];
+    a.nitems = bin_off[b + 1] - bin_off[b];
+    if (a.nitems == 0) continue;
+    switch (b) {
+      case 0: k_k4_list<1, FILL><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
+      case 1: k_k4_list<4, FILL><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
+      case 2: k_k4_list<16, FILL><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
+      default: k_k4_list<64, FILL><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+  }
+}
+
+}  // namespace
+
+void build_incidence_n13(nd_graph *g, KindState &ks, hipStream_t s) {
+  build_triangles(g, s);
+  Allocator &al = g->ctx->alloc;
+  const int64_t nt = g->nt;
+  const int32_t n = g->n;
+  DArr<int32_t> cnt(al, n);
+  fill_i32(cnt.p, 0, n, s);
+  if (nt > 0) {
+    k_n13_count<<<grid_stride(nt, 1), 256, 0, s>>>(g->ev.p, g->tri_e.p,
+                                                   g->tri_w.p, nt, cnt.p);
+    ND_LAUNCHED();
+  }
+  ks.nr = n;
+  build_layout(g, ks, cnt.p, s);
+  cnt.free();
+  ks.inc_ids.reset(al, 2 * ks.P);
+  DArr<unsigned long long> cursor(al, n);
+  if (n > 0) {
+    k_cursor_init<<<grid_for(n, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
+                                                    nullptr, n, cursor.p);
+    ND_LAUNCHED();
+  }
+  if (nt > 0) {
+    k_n13_fill<<<grid_stride(nt, 1), 256, 0, s>>>(g->ev.p, g->tri_e.p,
+                                                  g->tri_w.p, nt, ks.inv.p,
+                                                  cursor.p, ks.inc_ids.p);
+    ND_LAUNCHED();
+  }
+}
+
+void build_incidence_n24(nd_graph *g, KindState &ks, hipStream_t s) {
+  build_triangles(g, s);
+  Allocator &al = g->ctx->alloc;
+  const int64_t nt = g->nt, ne = g->ne;
+  DArr<uint8_t> bin(al, nt);
+  DArr<int32_t> items(al, nt);
+  if (nt > 0) {
+    k_tri_bins<<<grid_for(nt, 256), 256, 0, s>>>(g->ev.p, g->tri_e.p,
+                                                  g->tri_w.p, g->row_off.p, nt,
+                                                  bin.p);
+    ND_LAUNCHED();
+  }
+  int64_t bin_off[kIsectBins + 1];
+  partition_by_bin(bin.p, nt, kIsectBins, items.p, bin_off, s, al);
+  bin.free();
+  DArr<int32_t> cnt(al, ne);
+  fill_i32(cnt.p, 0, ne, s);
+  K4Args a{};
+  a.ev = g->ev.p;
+  a.row_off = g->row_off.p;
+  a.col = g->col.p;
+  a.eid = g->eid.p;
+  a.tri_e = g->tri_e.p;
+  a.tri_w = g->tri_w.p;
+  a.count = cnt.p;
+  run_k4<false>(a, items.p, bin_off, s);
+  ks.nr = ne;
+  build_layout(g, ks, cnt.p, s);
+  cnt.free();
+  ks.inc_ids.reset(al, 5 * ks.P);
+  DArr<unsigned long long> cursor(al, ne);
+  if (ne > 0) {
+    k_cursor_init<<<grid_for(ne, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
+                                                     nullptr, ne, cursor.p);
+    ND_LAUNCHED();
+  }
+  a.inv = ks.inv.p;
+  a.cursor = cursor.p;
+  a.ids = ks.inc_ids.p;
+  run_k4<true>(a, items.p, bin_off, s);
+}
+
 // ------------------------------------------------------------- (1,2)
 
 namespace {

@@ -57,6 +57,24 @@ struct Err {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The (r,s) of every nd_kind and k = C(s,r) - 1, the number of other
+// r-cliques listed per s-clique.
+constexpr int kNumKinds = 5;
+struct KindRS {
+  int r, s, k;
+};
+inline bool kind_valid(int kind) { return kind >= 0 && kind < kNumKinds; }
+inline KindRS kind_rs(int kind) {
+  constexpr KindRS t[kNumKinds] = {
+      {1, 2, 1},  // ND_KCORE
+      {2, 3, 2},  // ND_KTRUSS
+      {3, 4, 3},  // ND_NUCLEUS34
+      {1, 3, 2},  // ND_NUCLEUS13
+      {2, 4, 5},  // ND_NUCLEUS24
+  };
+  return t[kind];
+}
+
 // Grid size for `items` work items at `per_block` items per block, at least 1.
 inline unsigned grid_for(int64_t items, int64_t per_block) {
   int64_t g = ceil_div(items, per_block);

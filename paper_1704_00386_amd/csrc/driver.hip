@@ -76,6 +76,8 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
              "unknown mode %d", (int)opts.mode);
   ND_REQUIRE(opts.stop_active_ratio >= 0 && opts.stop_active_ratio <= 1,
              ND_ERR_INVALID, "stop_active_ratio must be in [0,1]");
+  ND_REQUIRE(kind_valid(kind), ND_ERR_UNSUPPORTED, "unknown kind %d",
+             (int)kind);
   const bool was_ready = g->ks[kind].ready;
   prepare(g, kind, s);
   const KindState &ks = g->ks[kind];

@@ -178,7 +178,7 @@ struct nd_graph {
   nd::DArr<int64_t> toff;     // ne+1: first triangle id of edge (u,v)
   nd::DArr<int32_t> tri_w;    // nt: third vertex w
   nd::DArr<int32_t> tri_e;    // nt: edge id of (u,v)
-  nd::KindState ks[3];
+  nd::KindState ks[nd::kNumKinds];
   double ms_build = 0;
   size_t bytes() const;
 };
@@ -221,6 +221,8 @@ void build_triangles(nd_graph *g, hipStream_t s);
 void build_incidence_core(nd_graph *g, KindState &ks, hipStream_t s);
 void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s);
 void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s);
+void build_incidence_n13(nd_graph *g, KindState &ks, hipStream_t s);
+void build_incidence_n24(nd_graph *g, KindState &ks, hipStream_t s);
 // From S-degrees in r-clique-id order: perm, inv, ds, inc_off, bins.
 void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
                   hipStream_t s);

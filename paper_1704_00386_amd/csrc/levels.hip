@@ -298,7 +298,9 @@ nd_status levels(nd_graph *g, nd_kind kind, int32_t *level_out,
   switch (ks.k) {
     case 1: k_levels<1><<<1, kLvThreads, 0, s>>>(a); break;
     case 2: k_levels<2><<<1, kLvThreads, 0, s>>>(a); break;
-    default: k_levels<3><<<1, kLvThreads, 0, s>>>(a); break;
+    case 3: k_levels<3><<<1, kLvThreads, 0, s>>>(a); break;
+    case 5: k_levels<5><<<1, kLvThreads, 0, s>>>(a); break;
+    default: ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "no level kernel for k=%d", ks.k);
   }
   ND_LAUNCHED();
   int32_t res[2] = {0, 0};

@@ -294,7 +294,9 @@ nd_status ego_estimate(nd_graph *g, nd_kind kind, const int32_t *queries,
   switch (ks.k) {
     case 1: k_ego<1><<<grid, kEgoThreads, 0, s>>>(a); break;
     case 2: k_ego<2><<<grid, kEgoThreads, 0, s>>>(a); break;
-    default: k_ego<3><<<grid, kEgoThreads, 0, s>>>(a); break;
+    case 3: k_ego<3><<<grid, kEgoThreads, 0, s>>>(a); break;
+    case 5: k_ego<5><<<grid, kEgoThreads, 0, s>>>(a); break;
+    default: ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "no ego kernel for k=%d", ks.k);
   }
   ND_LAUNCHED();
   std::vector<int32_t> hq(count), he(count), hs(count);

@@ -253,7 +253,7 @@ nd_status nd_server_submit(nd_server *srv, nd_graph *g, nd_kind kind,
     ND_REQUIRE(srv && g && ticket, ND_ERR_INVALID, "NULL argument");
     ND_REQUIRE(g->ctx == srv->ctx, ND_ERR_INVALID,
                "graph belongs to another context");
-    ND_REQUIRE(kind == ND_KCORE || kind == ND_KTRUSS || kind == ND_NUCLEUS34,
+    ND_REQUIRE(kind_valid(kind),
                ND_ERR_UNSUPPORTED, "unknown kind");
     nd_opts o;
     nd_opts_init(&o);

@@ -219,6 +219,8 @@ void launch_typed(const KindState &ks, const SweepArgs &a, bool and_mode,
     case 5: launch_fr<2, T, true>(ks, a, s); break;
     case 6: launch_fr<3, T, false>(ks, a, s); break;
     case 7: launch_fr<3, T, true>(ks, a, s); break;
+    case 10: launch_fr<5, T, false>(ks, a, s); break;
+    case 11: launch_fr<5, T, true>(ks, a, s); break;
     default:
       ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "no sweep kernel for k=%d", ks.k);
   }

@@ -40,11 +40,20 @@ __device__ __forceinline__ int32_t gather_rho(const int32_t *__restrict__ ids,
   } else if constexpr (K == 2) {
     const int2 p = *reinterpret_cast<const int2 *>(ids + 2 * j);
     return min(load_tau<T, AND>(tau + p.x), load_tau<T, AND>(tau + p.y));
-  } else {
+  } else if constexpr (K == 3) {
     const int32_t *q = ids + 3 * j;
     const int32_t x = q[0], y = q[1], z = q[2];
     return min(min(load_tau<T, AND>(tau + x), load_tau<T, AND>(tau + y)),
                load_tau<T, AND>(tau + z));
+  } else {
+    const int32_t *q = ids + (int64_t)K * j;
+    int32_t id[K];
+#pragma unroll
+    for (int x = 0; x < K; x++) id[x] = q[x];
+    int32_t v = load_tau<T, AND>(tau + id[0]);
+#pragma unroll
+    for (int x = 1; x < K; x++) v = min(v, load_tau<T, AND>(tau + id[x]));
+    return v;
   }
 }
 

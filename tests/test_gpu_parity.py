@@ -16,7 +16,8 @@ from synth import chung_lu, erdos_renyi, sbm
 
 pytestmark = pytest.mark.gpu
 
-KINDS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4)}
+KINDS = {"core": (1, 2), "truss": (2, 3), "nucleus34": (3, 4), "nucleus13": (1, 3),
+         "nucleus24": (2, 4)}
 
 
 @pytest.fixture(scope="module")
