@@ -328,6 +328,10 @@ struct OrientArgs {
   int32_t *count_base;    // count pass: base triangles per edge id
   const int64_t *base_off;  // fill pass: list start per internal id
   int lds_cap;            // k_orient_heavy: out-list entries held in LDS
+  // count pass, when set: the triangles found from oriented edge q go to
+  // tri_buf[tri_off[q] ...] as (e1, e2) pairs, for k_orient_scatter
+  const int64_t *tri_off;
+  int2 *tri_buf;
 };
 
 // One triangle (euv, e1 = (u,w), e2 = (v,w)) found from the oriented edge
@@ -343,6 +347,7 @@ __device__ __forceinline__ void orient_emit(const OrientArgs &a, int32_t euv,
   if (!FILL) {
     atomicAdd(&a.count[e1], 1);
     atomicAdd(&a.count[e2], 1);
+    if (a.tri_buf) a.tri_buf[base_pos] = make_int2(e1, e2);
   } else {
     const int32_t iuv = a.inv[euv], i1 = a.inv[e1], i2 = a.inv[e2];
     const int64_t p1 = (int64_t)atomicAdd(&a.cursor[i1], 1ull);
@@ -381,7 +386,8 @@ __global__ __launch_bounds__(256) void k_orient_isect(OrientArgs a) {
   const int64_t sb = short_is_u ? bu : bv, se = short_is_u ? eu : ev;
   const int64_t lb = short_is_u ? bv : bu, le = short_is_u ? ev : eu;
   const uint64_t smask = subgroup_mask<G>();
-  const int64_t base = FILL ? a.base_off[a.inv[euv]] : 0;
+  const int64_t base = FILL ? a.base_off[a.inv[euv]]
+                            : (a.tri_buf ? a.tri_off[q] : 0);
   int run = 0;
   for (int64_t j0 = sb; j0 < se; j0 += G) {  // uniform within the subgroup
     const int64_t j = j0 + sl;
@@ -436,7 +442,8 @@ __global__ __launch_bounds__(256) void k_orient_heavy(OrientArgs a,
       const int32_t v = a.out_col[q];
       const int32_t euv = a.out_eid[q];
       const int64_t bv = a.out_off[v], ev = a.out_off[v + 1];
-      const int64_t base = FILL ? a.base_off[a.inv[euv]] : 0;
+      const int64_t base = FILL ? a.base_off[a.inv[euv]]
+                                : (a.tri_buf ? a.tri_off[q] : 0);
       int run = 0;
       for (int64_t j0 = bv; j0 < ev; j0 += kWave) {  // uniform over the wave
         const int64_t j = j0 + lane;
@@ -461,6 +468,29 @@ __global__ __launch_bounds__(256) void k_orient_heavy(OrientArgs a,
         run += __popcll(m);
       }
       if (lane == 0) orient_base_done<FILL>(a, euv, run);
+    }
+  }
+}
+
+// Fill pass from the triangles the count pass recorded: oriented edge q
+// found count_base[euv] triangles, kept at tri_buf[tri_off[q] ...] in the
+// order it found them; each goes into the lists of its three edges exactly as
+// orient_emit places it, without intersecting the out-lists again.
+template <int G>
+__global__ __launch_bounds__(256) void k_orient_scatter(OrientArgs a) {
+  const int sl = lane_id() % G;
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       gsub < a.nitems; gsub += nsub) {
+    const int64_t q = a.items[gsub];
+    const int32_t euv = a.out_eid[q];
+    const int32_t n = a.count_base[euv];
+    if (n == 0) continue;
+    const int64_t base = a.base_off[a.inv[euv]];
+    const int2 *tb = a.tri_buf + a.tri_off[q];
+    for (int i = sl; i < n; i += G) {
+      const int2 p = tb[i];
+      orient_emit<true>(a, euv, p.x, p.y, base + i);
     }
   }
 }
@@ -491,16 +521,20 @@ __global__ void k_max_outdeg(const int64_t *__restrict__ out_off, int32_t n,
   if (lane_id() == 0) atomicMax(mx, m);
 }
 
+// Bin of oriented edge q by its shorter out-list, whose length also bounds
+// the triangles found from q (cap).
 __global__ void k_orient_bins(const int64_t *__restrict__ out_off,
                               const int32_t *__restrict__ out_col,
                               const int32_t *__restrict__ out_src, int64_t ne,
-                              uint8_t *__restrict__ bin) {
+                              uint8_t *__restrict__ bin,
+                              int32_t *__restrict__ cap) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ne) return;
   const int32_t u = out_src[q], v = out_col[q];
   const int64_t a = out_off[u + 1] - out_off[u], b = out_off[v + 1] - out_off[v];
   const int64_t m = min(a, b);
   bin[q] = m <= 4 ? 0 : m <= 16 ? 1 : m <= 64 ? 2 : 3;
+  cap[q] = (int32_t)m;
 }
 
 // Side entries of internal r-clique i start after its base entries.
@@ -539,6 +573,22 @@ void run_orient(OrientArgs a, const int32_t *items, const int64_t *bin_off,
           k_orient_isect<64, FILL><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a);
         }
         break;
+    }
+    ND_LAUNCHED();
+  }
+}
+
+void run_scatter(OrientArgs a, const int32_t *items, const int64_t *bin_off,
+                 hipStream_t s) {
+  for (int b = 0; b < 4; b++) {
+    a.items = items + bin_off[b];
+    a.nitems = bin_off[b + 1] - bin_off[b];
+    if (a.nitems == 0) continue;
+    switch (b) {
+      case 0: k_orient_scatter<1><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
+      case 1: k_orient_scatter<4><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
+      case 2: k_orient_scatter<16><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
+      default: k_orient_scatter<64><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a); break;
     }
     ND_LAUNCHED();
   }
@@ -673,15 +723,35 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   ND_LAUNCHED();
   // oriented edges binned by their shorter out-list
   DArr<uint8_t> bin(al, ne);
-  DArr<int32_t> items(al, ne);
+  DArr<int32_t> items(al, ne), cap(al, ne);
   if (ne > 0) {
     k_orient_bins<<<grid_for(ne, 256), 256, 0, s>>>(out_off.p, out_col.p,
-                                                     out_src.p, ne, bin.p);
+                                                     out_src.p, ne, bin.p,
+                                                     cap.p);
     ND_LAUNCHED();
   }
   int64_t bin_off[5];
   partition_by_bin(bin.p, ne, 4, items.p, bin_off, s, al);
   bin.free();
+  // Room for every triangle the count pass can find (the shorter out-list
+  // bounds each edge's), so that the fill pass reads them back instead of
+  // intersecting again; above kTriBufMax the fill intersects again.
+  constexpr int64_t kTriBufMax = (int64_t)1 << 32;  // entries (32 GiB)
+  DArr<int64_t> tri_off(al, ne + 1);
+  exclusive_scan_i32(cap.p, tri_off.p, ne, s, al);
+  cap.free();
+  const int64_t tri_cap = read_i64(tri_off.p + ne, s);
+  DArr<int2> tri_buf;
+  const size_t tri_bytes = sizeof(int2) * (size_t)std::max<int64_t>(tri_cap, 1);
+  if (tri_cap <= kTriBufMax &&
+      (al.budget() == 0 || al.live_bytes() + tri_bytes <= al.budget())) {
+    try {
+      tri_buf.reset(al, tri_cap);
+    } catch (const Err &) {  // the device is short of memory: intersect twice
+      tri_buf.p = nullptr;
+    }
+  }
+  if (!tri_buf.p) tri_off.free();
   OrientArgs a{};
   a.out_off = out_off.p;
   a.out_col = out_col.p;
@@ -718,6 +788,8 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   fill_i32(cnt.p, 0, ne, s);
   a.count = cnt.p;
   a.count_base = cbase.p;  // every oriented edge stores its own
+  a.tri_off = tri_buf.p ? tri_off.p : nullptr;
+  a.tri_buf = tri_buf.p;
   run_orient<false>(a, items.p, bin_off, hs, s);
   ks.nr = ne;
   build_layout(g, ks, cnt.p, s);
@@ -733,7 +805,10 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   a.cursor = cursor.p;
   a.ids = ks.inc_ids.p;
   a.base_off = ks.inc_off.p;
-  run_orient<true>(a, items.p, bin_off, hs, s);
+  if (tri_buf.p)
+    run_scatter(a, items.p, bin_off, s);
+  else
+    run_orient<true>(a, items.p, bin_off, hs, s);
 }
 
 void build_triangles(nd_graph *g, hipStream_t s) {
