@@ -288,6 +288,67 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     return out
 
 
+def nucleus34_leg(nd, ctx, full_sweeps=4):
+    """(3,4)-nucleus decomposition of the stochastic block model workload
+    (5000 communities of U{50..400} vertices, p_in 0.3, p_out 2e-6, seed 4;
+    triangles as r-cliques, 4-clique incidence lists): the edge list already
+    in HBM, build + prepare, then SND and AND with the notification frontier
+    until exact, and a few full sweeps (every r-clique with d_s > 0
+    recomputed) for the roofline of the k = 3 sweep kernels."""
+    import numpy as np
+    import torch
+
+    from synth import workload
+
+    raw = workload("sbm")
+    src = torch.from_numpy(raw.src).cuda()
+    dst = torch.from_numpy(raw.dst).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = nd.Graph.from_edges(ctx, raw.n, src, dst)
+    g.prepare("nucleus34")
+    torch.cuda.synchronize()
+    ms_prep = 1e3 * (time.perf_counter() - t0)
+    del src, dst
+    nr, P, dev_bytes = g.sizes("nucleus34")
+    out = {"workload": "(3,4)-nucleus on the stochastic block model: 5000 "
+                       "communities of U{50..400} vertices, p_in 0.3, "
+                       "p_out 2e-6, seed 4",
+           "n": raw.n, "raw_pairs": raw.m, "triangles": nr, "incidence_P": P,
+           "device_bytes": dev_bytes, "ms_build_prepare": ms_prep}
+    kappa = None
+    for mode in ("snd", "and"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k, r = g.decompose("nucleus34", mode, use_frontier=True)
+        torch.cuda.synchronize()
+        out[mode] = {"sweeps": r["sweeps"], "ms": 1e3 * (time.perf_counter() - t0),
+                     "ms_iterate": r["ms_iterate"], "updates": r["updates"]}
+        tau_bytes = r["tau_bytes"]
+        if kappa is None:
+            kappa = k
+        else:
+            out["kappa_and_equals_snd"] = bool(torch.equal(k, kappa))
+    nr_eval = int(np.count_nonzero(g.sdegree("nucleus34").cpu().numpy()))
+    sweep_ms = []
+
+    def collect(info):
+        sweep_ms.append(info.ms)
+        return 0
+
+    g.decompose("nucleus34", "snd", max_iters=full_sweeps, on_iter=collect,
+                allow_not_converged=True)
+    avg = sum(sweep_ms) / len(sweep_ms)
+    B = sweep_bytes(P, nr_eval, 3, tau_bytes)
+    out["full_sweep"] = {"sweeps_timed": len(sweep_ms), "avg_ms": avg,
+                         "bytes_per_sweep": B,
+                         "achieved_GBs": B / (avg * 1e-3) / 1e9,
+                         "frac_of_hbm_peak": B / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out["kappa_max"] = int(kappa.max()) if kappa.numel() else 0
+    g.close()
+    return out
+
+
 def ego_leg(g, kappa, count, seed=13):
     """PartialAND estimates on the ego networks of `count` random r-cliques
     of the prepared graph, all in one call: throughput, and accuracy against
@@ -393,6 +454,8 @@ def main():
     ap.add_argument("--small-graphs", type=int, default=512,
                     help="graphs in the small-graph batched comparison "
                          "(0: skip)")
+    ap.add_argument("--no-nucleus34", action="store_true",
+                    help="skip the (3,4)-nucleus leg on the block model")
     ap.add_argument("--summarize-profiles", nargs=3, default=None,
                     metavar=("TRACE_STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="write the profiles/ summaries from rocprofv3 output "
@@ -544,6 +607,8 @@ def main():
         # the launch-bound end of the stream: n ~ U{1000..5000}
         line["small_graphs"] = stream_leg(nd, ctx, args.small_graphs, seed=7,
                                           n_lo=1000, n_hi=5000, serve=False)
+    if not args.no_nucleus34:
+        line["nucleus34"] = nucleus34_leg(nd, ctx)
     if not args.no_cpu:
         cb = cpu_baseline(raw, KIND, args.cpu_budget)
         cb["time_to_exact_s_est"] = full_equiv / cb["value"]
