@@ -735,7 +735,10 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   bin.free();
   // Room for every triangle the count pass can find (the shorter out-list
   // bounds each edge's), so that the fill pass reads them back instead of
-  // intersecting again; above kTriBufMax the fill intersects again.
+  // intersecting again.  The fill intersects again above kTriBufMax, or
+  // under a device-memory budget when the buffer would take more than a
+  // quarter of what is left of it (other work on the context, such as a
+  // server preparing graphs while its caller builds more, keeps room).
   constexpr int64_t kTriBufMax = (int64_t)1 << 32;  // entries (32 GiB)
   DArr<int64_t> tri_off(al, ne + 1);
   exclusive_scan_i32(cap.p, tri_off.p, ne, s, al);
@@ -743,8 +746,10 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   const int64_t tri_cap = read_i64(tri_off.p + ne, s);
   DArr<int2> tri_buf;
   const size_t tri_bytes = sizeof(int2) * (size_t)std::max<int64_t>(tri_cap, 1);
+  const size_t live = al.live_bytes();
   if (tri_cap <= kTriBufMax &&
-      (al.budget() == 0 || al.live_bytes() + tri_bytes <= al.budget())) {
+      (al.budget() == 0 ||
+       (live < al.budget() && tri_bytes <= (al.budget() - live) / 4))) {
     try {
       tri_buf.reset(al, tri_cap);
     } catch (const Err &) {  // the device is short of memory: intersect twice
