@@ -86,18 +86,15 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
   unsigned long long n_ch = 0, n_ev = 0;  // wave totals, from ballots
   if (FR && G > 1 && act != nullptr) {
     // Sparse sweep: the wave tests the flags of kChunk consecutive r-cliques
-    // at once (one lane each, coalesced; SND copies the skipped values
-    // forward there) and runs only the flagged ones, kPerWave at a time.  A
+    // at once (one lane each, coalesced) and runs only the flagged ones,
+    // kPerWave at a time; skipped ones need no write (see update_regs).  A
     // chunk holds at most 8 rounds of r-cliques, so a run of flagged hubs
     // is not serialised on one wave for long.
     constexpr int kChunk = kPerWave * 8 < kWave ? kPerWave * 8 : kWave;
     for (int64_t base = lo + wave * kChunk; base < hi; base += waves * kChunk) {
       const int64_t Rl = base + lane_id();
       bool on = false;
-      if (lane_id() < kChunk && Rl < hi) {
-        on = act[Rl] == a.stamp;
-        if (!AND && !on) tout[Rl] = tin[Rl];
-      }
+      if (lane_id() < kChunk && Rl < hi) on = act[Rl] == a.stamp;
       const uint64_t m = ballot(on);
       const int na = __popcll(m);
       for (int r0 = 0; r0 < na; r0 += kPerWave) {  // uniform over the wave

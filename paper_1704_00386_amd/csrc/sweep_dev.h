@@ -210,9 +210,12 @@ __host__ __device__ __forceinline__ uint8_t sweep_stamp(int64_t t) {
 // One r-clique per subgroup of G lanes (sl = lane within the subgroup), each
 // lane holding M gathered values: d_s(R) <= G*M.  `active` false for a
 // subgroup with no r-clique.  With a frontier (FR), an r-clique whose flag is
-// clear keeps its value (copied forward for SND) without any gather.
-// Returns (on the subgroup's first lane only) whether R changed; *evald
-// likewise whether it was recomputed.
+// clear is skipped: it cannot change.  SND writes only what it recomputes:
+// a changed r-clique also flags itself for the next sweep (the self-activation
+// of Alg. 3), so an r-clique skipped in sweep t+1 did not change in sweep t,
+// and the output buffer of sweep t+1 (the input of sweep t) already holds
+// its value.  Returns (on the subgroup's first lane only) whether R changed;
+// *evald likewise whether it was recomputed.
 template <int K, int G, int M, typename T, bool AND, bool FR>
 __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
                                             const int32_t *__restrict__ inc_ids,
@@ -226,11 +229,10 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
   int64_t b = 0, d = 0;
   bool eval = active;
   if (active) {
-    told = (int32_t)tau_in[R];
     if (FR && act && act[R] != stamp) {
       eval = false;
-      if (!AND && sl == 0) tau_out[R] = (T)told;
     } else {
+      told = (int32_t)tau_in[R];
       b = inc_off[R];
       d = inc_off[R + 1] - b;
       c = cap_by_tau ? told : (int32_t)d;
@@ -247,9 +249,11 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
   const bool ch = eval && h != told;  // uniform within the subgroup
   const bool lead = sl == 0;
   if (eval && lead) store_tau<T, AND>(tau_out + R, h, ch);
-  if (FR && ch && act_next)
-    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next,
-                      stamp == 255 ? 1 : stamp + 1);
+  if (FR && ch && act_next) {
+    const uint8_t next = stamp == 255 ? 1 : stamp + 1;
+    if (!AND && lead) act_next[R] = next;
+    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next, next);
+  }
   *evald = lead && eval;
   return lead && ch;
 }
@@ -312,12 +316,11 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
                              int64_t R, int32_t *hist, const uint8_t *act,
                              uint8_t *act_next, uint8_t stamp, bool *evald) {
   const int t = threadIdx.x;
-  const int32_t told = (int32_t)tau_in[R];
-  if (FR && act && act[R] != stamp) {
-    if (!AND && t == 0) tau_out[R] = (T)told;
+  if (FR && act && act[R] != stamp) {  // skipped: see update_regs
     *evald = false;
     return false;
   }
+  const int32_t told = (int32_t)tau_in[R];
   const int64_t b = inc_off[R];
   const int64_t d = inc_off[R + 1] - b;
   const int32_t c = cap_by_tau ? told : (int32_t)d;
@@ -358,9 +361,12 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
   }
   const bool ch = h != told;
   if (t == 0) store_tau<T, AND>(tau_out + R, h, ch);
-  if (FR && ch && act_next)
+  if (FR && ch && act_next) {
+    const uint8_t next = stamp == 255 ? 1 : stamp + 1;
+    if (!AND && t == 0) act_next[R] = next;
     notify<K, T, AND>(inc_ids, b, d, t, kBlockThreads, h, tau_in, act_next,
-                      stamp == 255 ? 1 : stamp + 1);
+                      next);
+  }
   __syncthreads();
   *evald = t == 0;
   return t == 0 && ch;
