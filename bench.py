@@ -121,7 +121,7 @@ def _short_kernel(name: str) -> str:
 def _profile_command(args_extra: str, out: str) -> str:
     return (f"rocprofv3 {args_extra} --output-format csv -d $R/gpurun_out/{out} -o {out} "
             "-- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu --stream-graphs 0 "
-            "--small-graphs 0 --ego-queries 0 --calib-copy")
+            "--small-graphs 0 --ego-queries 0 --no-nucleus34 --calib-copy")
 
 
 def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:

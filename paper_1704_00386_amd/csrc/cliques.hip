@@ -203,26 +203,11 @@ struct TriIsectArgs {
   int32_t *out;          // fill pass: 3 ids per 4-clique
 };
 
-__device__ __forceinline__ bool in_list(const int32_t *__restrict__ col,
-                                        int64_t b, int64_t e, int32_t x) {
-  int64_t q = lower_bound<int32_t>(col, b, e, x);
-  return q < e && col[q] == x;
-}
-
-// Id of the triangle with vertices {a, b, c} (any order).
-__device__ __forceinline__ int32_t tri_id(const TriIsectArgs &t, int32_t a,
-                                          int32_t b, int32_t c) {
-  // sort three values
-  int32_t x = min(a, b), y = max(a, b);
-  int32_t z = max(y, c);
-  y = min(y, c);
-  int32_t w = min(x, y);
-  y = max(x, y);
-  x = w;
-  // edge (x, y)
-  const int64_t q = lower_bound<int32_t>(t.col, t.row_off[x], t.row_off[x + 1], y);
-  const int32_t e = t.eid[q];
-  return (int32_t)lower_bound<int32_t>(t.tri_w, t.toff[e], t.toff[e + 1], z);
+// Id of the triangle whose lowest edge (lexicographically) is e and whose
+// third vertex is c: triangles are numbered by (lowest edge, third vertex).
+__device__ __forceinline__ int32_t tri_in(const TriIsectArgs &t, int32_t e,
+                                          int32_t c) {
+  return (int32_t)lower_bound<int32_t>(t.tri_w, t.toff[e], t.toff[e + 1], c);
 }
 
 template <int G, bool FILL>
@@ -244,21 +229,38 @@ __global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
   const int o1 = s == 0 ? 1 : 0, o2 = s == 2 ? 1 : 2;
   const uint64_t smask = subgroup_mask<G>();
   const int64_t base = FILL ? a.off[a.inv[t]] : 0;
+  // fill: the edges (u,w) and (v,w) once per triangle; the three edges to
+  // x come from the positions the intersection finds x at
+  int32_t euw = 0, evw = 0;
+  if (FILL) {
+    euw = a.eid[lower_bound<int32_t>(a.col, b[0], en[0], w)];
+    evw = a.eid[lower_bound<int32_t>(a.col, b[1], en[1], w)];
+  }
   int64_t written = 0;
   for (int64_t j0 = b[s]; j0 < en[s]; j0 += G) {
     const int64_t j = j0 + sl;
     bool found = false;
     int32_t x = 0;
+    int64_t pos[3] = {0, 0, 0};
     if (j < en[s]) {
       x = a.col[j];
-      found = in_list(a.col, b[o1], en[o1], x) && in_list(a.col, b[o2], en[o2], x);
+      pos[s] = j;
+      pos[o1] = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
+      found = pos[o1] < en[o1] && a.col[pos[o1]] == x;
+      if (found) {
+        pos[o2] = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
+        found = pos[o2] < en[o2] && a.col[pos[o2]] == x;
+      }
     }
     const uint64_t m = ballot(found) & smask;
     if (FILL && found) {
       const int64_t k = base + written + lanes_below(m);
-      a.out[3 * k] = a.inv[tri_id(a, u, v, x)];
-      a.out[3 * k + 1] = a.inv[tri_id(a, u, w, x)];
-      a.out[3 * k + 2] = a.inv[tri_id(a, v, w, x)];
+      const int32_t eux = a.eid[pos[0]], evx = a.eid[pos[1]], ewx = a.eid[pos[2]];
+      // a triangle {p<q<r} is the entry for r in the list of its lowest
+      // edge (p,q); u < v < w, so the lowest edge of each is known
+      a.out[3 * k] = a.inv[tri_in(a, x > v ? e : eux, x > v ? x : v)];      // {u,v,x}
+      a.out[3 * k + 1] = a.inv[tri_in(a, x > w ? euw : eux, x > w ? x : w)];  // {u,w,x}
+      a.out[3 * k + 2] = a.inv[tri_in(a, x > w ? evw : evx, x > w ? x : w)];  // {v,w,x}
     }
     written += __popcll(m);
   }
