@@ -580,6 +580,7 @@ def main():
         "ms_prep": ms_per_step - res["ms_iterate"],
         "ms_iterate": res["ms_iterate"],
         "sweeps": res["sweeps"],
+        "t_star": res["sweeps"] - 1,  # first t with tau_t = kappa
         "evaluated_updates": res["updates"],
         "full_sweeps": {"ms_iterate": rfull["ms_iterate"],
                         "sweeps": rfull["sweeps"],
@@ -594,6 +595,17 @@ def main():
                      "bytes_per_launch": B, "avg_launch_ms": avg_sweep_ms},
         "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
                 "frontier": True, "kappa_equals_snd": same_and},
+    }
+    # the paper's own figures, other hardware and real graphs: context only
+    line["paper_context"] = {
+        "hardware": "2 x 12-core Intel Ivy Bridge at 2.4 GHz, 24 threads, "
+                    "C++/OpenMP (Section 5)",
+        "published_updates_per_s": None,
+        "derived_and_updates_per_s": {
+            "k_truss": [3.7e6, 1.5e7], "nucleus34": [1.1e6, 3.1e6]},
+        "derived_from": "|R| x AND iterations (Table 3, sequential runs) / "
+                        "AND time on 24 threads (Table 4) for the facebook and "
+                        "web-Google graphs (Table 2); order of magnitude only",
     }
     if n_levels is not None:
         line["degree_levels"] = {"levels": n_levels, "ms": levels_ms,
