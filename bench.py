@@ -210,6 +210,37 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
     print(f"full sweep {full_avg:.0f} us; HBM-side {rec['hbm_bytes_per_sweep'] / 1e9:.2f} GB per sweep")
 
 
+TRACE_RUNS = {
+    "sbm_nucleus34": ("(3,4)-nucleus on the stochastic block model (5000 communities of "
+                      "U{50..400} vertices, p_in 0.3, p_out 2e-6, seed 4): build + prepare, "
+                      "SND and AND with the frontier until exact, 4 full sweeps",
+                      "--only-nucleus34"),
+}
+
+
+def summarize_trace(stats_csv: str, name: str) -> None:
+    """profiles/kernel_trace_<name>.md from the kernel-stats CSV of
+    `rocprofv3 --kernel-trace --stats -- python3 bench.py <flags>`."""
+    import csv
+
+    what, flags = TRACE_RUNS[name]
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# Kernel trace: {name}", "", what + ".", "",
+             "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`):", "", "```",
+             f"rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/{name} "
+             f"-o {name} -- python3 $R/bench.py {flags}", "```", "",
+             f"Total kernel time {tot / 1e6:.1f} ms.", "",
+             "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:30]:
+        lines.append(f"| {100 * float(r['TotalDurationNs']) / tot:.1f} | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | `{_short_kernel(r['Name'])}` |")
+    path = os.path.join(ROOT, "profiles", f"kernel_trace_{name}.md")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print(path)
+
+
 def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     """Batched and served k-truss against one graph per launch, on `count`
     graphs of the request-stream workload (Chung-Lu, n ~ U{n_lo..n_hi},
@@ -456,6 +487,12 @@ def main():
                          "(0: skip)")
     ap.add_argument("--no-nucleus34", action="store_true",
                     help="skip the (3,4)-nucleus leg on the block model")
+    ap.add_argument("--only-nucleus34", action="store_true",
+                    help="run only the (3,4)-nucleus leg and print its JSON")
+    ap.add_argument("--summarize-trace", nargs=2, default=None,
+                    metavar=("STATS_CSV", "NAME"),
+                    help="write profiles/kernel_trace_NAME.md from a "
+                         "rocprofv3 kernel-stats CSV and exit")
     ap.add_argument("--summarize-profiles", nargs=3, default=None,
                     metavar=("TRACE_STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="write the profiles/ summaries from rocprofv3 output "
@@ -463,6 +500,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU "
@@ -477,6 +517,10 @@ def main():
 
     if args.quality:
         print(json.dumps(quality_leg(nd, args.quality)), flush=True)
+        return
+    if args.only_nucleus34:
+        print(json.dumps({"nucleus34": nucleus34_leg(nd, nd.Context(0))}),
+              flush=True)
         return
 
     if args.calib_copy:
