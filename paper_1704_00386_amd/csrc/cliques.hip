@@ -198,7 +198,6 @@ struct TriIsectArgs {
   const int32_t *tri_w;
   const int32_t *tri_e;
   int32_t *count;        // count pass
-  const int64_t *off;    // fill pass: output offset, internal order
   const int32_t *inv;    // fill pass: triangle id -> internal id
   int32_t *out;          // fill pass: 3 ids per 4-clique
 };
@@ -210,61 +209,36 @@ __device__ __forceinline__ int32_t tri_in(const TriIsectArgs &t, int32_t e,
   return (int32_t)lower_bound<int32_t>(t.tri_w, t.toff[e], t.toff[e + 1], c);
 }
 
-template <int G, bool FILL>
-__global__ __launch_bounds__(256) void k_tri_isect(TriIsectArgs a) {
+// (3,4) count pass: the 4-cliques containing triangle (u,v,w), i.e. the x
+// in N(u) & N(v) & N(w); G lanes stride over the shortest of the three
+// lists and binary-search the other two.
+template <int G>
+__global__ __launch_bounds__(256) void k_n34_count(TriIsectArgs a) {
   const int sl = lane_id() % G;
   const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
   for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
        gsub < a.nitems; gsub += nsub) {  // uniform within the subgroup
-  const int32_t t = a.items[gsub];
-  const int32_t e = a.tri_e[t];
-  const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
-  const int32_t w = a.tri_w[t];
-  int64_t b[3] = {a.row_off[u], a.row_off[v], a.row_off[w]};
-  int64_t en[3] = {a.row_off[u + 1], a.row_off[v + 1], a.row_off[w + 1]};
-  // iterate the shortest list, search the other two
-  int s = 0;
-  if (en[1] - b[1] < en[s] - b[s]) s = 1;
-  if (en[2] - b[2] < en[s] - b[s]) s = 2;
-  const int o1 = s == 0 ? 1 : 0, o2 = s == 2 ? 1 : 2;
-  const uint64_t smask = subgroup_mask<G>();
-  const int64_t base = FILL ? a.off[a.inv[t]] : 0;
-  // fill: the edges (u,w) and (v,w) once per triangle; the three edges to
-  // x come from the positions the intersection finds x at
-  int32_t euw = 0, evw = 0;
-  if (FILL) {
-    euw = a.eid[lower_bound<int32_t>(a.col, b[0], en[0], w)];
-    evw = a.eid[lower_bound<int32_t>(a.col, b[1], en[1], w)];
-  }
-  int64_t written = 0;
-  for (int64_t j0 = b[s]; j0 < en[s]; j0 += G) {
-    const int64_t j = j0 + sl;
-    bool found = false;
-    int32_t x = 0;
-    int64_t pos[3] = {0, 0, 0};
-    if (j < en[s]) {
-      x = a.col[j];
-      pos[s] = j;
-      pos[o1] = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
-      found = pos[o1] < en[o1] && a.col[pos[o1]] == x;
-      if (found) {
-        pos[o2] = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
-        found = pos[o2] < en[o2] && a.col[pos[o2]] == x;
-      }
+    const int32_t t = a.items[gsub];
+    const int32_t e = a.tri_e[t];
+    const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
+    const int32_t w = a.tri_w[t];
+    const int64_t b[3] = {a.row_off[u], a.row_off[v], a.row_off[w]};
+    const int64_t en[3] = {a.row_off[u + 1], a.row_off[v + 1], a.row_off[w + 1]};
+    int sh = 0;
+    if (en[1] - b[1] < en[sh] - b[sh]) sh = 1;
+    if (en[2] - b[2] < en[sh] - b[sh]) sh = 2;
+    const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
+    int found = 0;
+    for (int64_t j = b[sh] + sl; j < en[sh]; j += G) {
+      const int32_t x = a.col[j];
+      const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
+      if (q1 >= en[o1] || a.col[q1] != x) continue;
+      const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
+      found += q2 < en[o2] && a.col[q2] == x;
     }
-    const uint64_t m = ballot(found) & smask;
-    if (FILL && found) {
-      const int64_t k = base + written + lanes_below(m);
-      const int32_t eux = a.eid[pos[0]], evx = a.eid[pos[1]], ewx = a.eid[pos[2]];
-      // a triangle {p<q<r} is the entry for r in the list of its lowest
-      // edge (p,q); u < v < w, so the lowest edge of each is known
-      a.out[3 * k] = a.inv[tri_in(a, x > v ? e : eux, x > v ? x : v)];      // {u,v,x}
-      a.out[3 * k + 1] = a.inv[tri_in(a, x > w ? euw : eux, x > w ? x : w)];  // {u,w,x}
-      a.out[3 * k + 2] = a.inv[tri_in(a, x > w ? evw : evx, x > w ? x : w)];  // {v,w,x}
-    }
-    written += __popcll(m);
-  }
-  if (!FILL && sl == 0) a.count[t] = (int32_t)written;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) found += __shfl_xor(found, off, G);
+    if (sl == 0) a.count[t] = found;
   }
 }
 
@@ -649,18 +623,82 @@ void run_edge_isect(EdgeIsectArgs a, const int32_t *items,
   }
 }
 
-template <bool FILL>
-void run_tri_isect(TriIsectArgs a, const int32_t *items, const int64_t *bin_off,
+void run_n34_count(TriIsectArgs a, const int32_t *items, const int64_t *bin_off,
                    hipStream_t s) {
   for (int b = 0; b < kIsectBins; b++) {
     a.items = items + bin_off[b];
     a.nitems = bin_off[b + 1] - bin_off[b];
     if (a.nitems == 0) continue;
     switch (b) {
-      case 0: k_tri_isect<1, FILL><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
-      case 1: k_tri_isect<4, FILL><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
-      case 2: k_tri_isect<16, FILL><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
-      default: k_tri_isect<64, FILL><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a); break;
+      case 0: k_n34_count<1><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
+      case 1: k_n34_count<4><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
+      case 2: k_n34_count<16><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
+      default: k_n34_count<64><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+  }
+}
+
+// (3,4) fill pass, each 4-clique once: from its lowest triangle (u,v,w),
+// with x > w in all three lists (as k_k4_list), the four triangles
+// {u,v,w}, {u,v,x}, {u,w,x}, {v,w,x} -- whose lowest edges are (u,v), (u,v),
+// (u,w), (v,w) -- each receive the other three at a slot taken from their
+// list's cursor.  A quarter of the intersections and searches of filling
+// every triangle's list from its own intersection; list order varies.
+template <int G>
+__global__ __launch_bounds__(256) void k_n34_fill(TriIsectArgs a,
+                                                  unsigned long long *cursor) {
+  const int sl = lane_id() % G;
+  const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
+  for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+       gsub < a.nitems; gsub += nsub) {
+    const int32_t t = a.items[gsub];
+    const int32_t e = a.tri_e[t];
+    const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
+    const int32_t w = a.tri_w[t];
+    const int64_t b[3] = {a.row_off[u], a.row_off[v], a.row_off[w]};
+    const int64_t en[3] = {a.row_off[u + 1], a.row_off[v + 1], a.row_off[w + 1]};
+    int sh = 0;
+    if (en[1] - b[1] < en[sh] - b[sh]) sh = 1;
+    if (en[2] - b[2] < en[sh] - b[sh]) sh = 2;
+    const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
+    const int64_t start = lower_bound<int32_t>(a.col, b[sh], en[sh], w + 1);
+    if (start >= en[sh]) continue;  // uniform within the subgroup
+    const int32_t euw = a.eid[lower_bound<int32_t>(a.col, b[0], en[0], w)];
+    const int32_t evw = a.eid[lower_bound<int32_t>(a.col, b[1], en[1], w)];
+    const int32_t it = a.inv[t];
+    for (int64_t j = start + sl; j < en[sh]; j += G) {
+      const int32_t x = a.col[j];
+      const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
+      if (q1 >= en[o1] || a.col[q1] != x) continue;
+      const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
+      if (q2 >= en[o2] || a.col[q2] != x) continue;
+      const int32_t id[4] = {it, a.inv[tri_in(a, e, x)], a.inv[tri_in(a, euw, x)],
+                             a.inv[tri_in(a, evw, x)]};
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int64_t p = (int64_t)atomicAdd(&cursor[id[i]], 1ull);
+        int32_t *o = a.out + 3 * p;
+        int c = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          if (q != i) o[c++] = id[q];
+      }
+    }
+  }
+}
+
+void run_n34_fill(TriIsectArgs a, unsigned long long *cursor,
+                  const int32_t *items, const int64_t *bin_off, hipStream_t s) {
+  for (int b = 0; b < kIsectBins; b++) {
+    a.items = items + bin_off[b];
+    a.nitems = bin_off[b + 1] - bin_off[b];
+    if (a.nitems == 0) continue;
+    switch (b) {
+      case 0: k_n34_fill<1><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a, cursor); break;
+      case 1: k_n34_fill<4><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a, cursor); break;
+      case 2: k_n34_fill<16><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a, cursor); break;
+      default: k_n34_fill<64><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a, cursor); break;
     }
     ND_LAUNCHED();
   }
@@ -869,15 +907,20 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   a.tri_w = g->tri_w.p;
   a.tri_e = g->tri_e.p;
   a.count = cnt.p;
-  run_tri_isect<false>(a, items.p, bin_off, s);
+  run_n34_count(a, items.p, bin_off, s);
   ks.nr = nt;
   build_layout(g, ks, cnt.p, s);
   cnt.free();
   ks.inc_ids.reset(al, 3 * ks.P);
-  a.off = ks.inc_off.p;
   a.inv = ks.inv.p;
   a.out = ks.inc_ids.p;
-  run_tri_isect<true>(a, items.p, bin_off, s);
+  DArr<unsigned long long> cursor(al, nt);
+  if (nt > 0) {
+    k_cursor_init<<<grid_for(nt, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
+                                                     nullptr, nt, cursor.p);
+    ND_LAUNCHED();
+  }
+  run_n34_fill(a, cursor.p, items.p, bin_off, s);
 }
 
 // ------------------------------------------------------- (1,3) and (2,4)
