@@ -137,13 +137,16 @@ def chung_lu(n: int, beta: float, mean: float, seed: int) -> RawGraph:
 
 
 def sbm(n_comm: int = 5000, size_lo: int = 50, size_hi: int = 400,
-        p_in: float = 0.3, p_out: float = 2e-6, seed: int = 4) -> RawGraph:
+        p_in: float = 0.3, p_out: float = 2e-6, seed: int = 4,
+        with_communities: bool = False):
     """Stochastic block model with uniform community sizes.
 
     Intra-community pairs get one Bernoulli(p_in) draw each.  The number of
     inter-community edges is drawn as Binomial(#inter pairs, p_out) and that
     many uniformly random cross-community pairs are sampled (a repeated pair,
     which is vanishingly rare at these densities, is left in the raw list).
+    With ``with_communities`` the result is ``(graph, labels)``, labels[v]
+    being the community of (relabelled) vertex v; the graph is the same.
     """
     rng = _rng(seed)
     sizes = rng.integers(size_lo, size_hi + 1, size=n_comm)
@@ -175,9 +178,14 @@ def sbm(n_comm: int = 5000, size_lo: int = 50, size_hi: int = 400,
     src = np.concatenate(src_parts).astype(np.int32)
     dst = np.concatenate(dst_parts).astype(np.int32)
     perm = rng.permutation(n).astype(np.int32)
-    return RawGraph(n, perm[src], perm[dst],
-                    f"sbm(c={n_comm},sizes={size_lo}..{size_hi},p_in={p_in},"
-                    f"p_out={p_out},seed={seed})")
+    g = RawGraph(n, perm[src], perm[dst],
+                 f"sbm(c={n_comm},sizes={size_lo}..{size_hi},p_in={p_in},"
+                 f"p_out={p_out},seed={seed})")
+    if not with_communities:
+        return g
+    labels = np.empty(n, np.int32)
+    labels[perm] = comm
+    return g, labels
 
 
 def request_stream(count: int = 4096, n_lo: int = 1000, n_hi: int = 200000,
