@@ -11,15 +11,16 @@ namespace dev {
 constexpr int kBlockThreads = 256;
 constexpr int kBlockHistBins = 16384;  // 64 KiB of LDS
 
-// AND reads tau in place while other waves write it.  The reads are relaxed
-// atomics at workgroup scope, so they may be served by this CU's L1, which
-// holds only values read during the current launch (the L1 is invalidated
-// when a kernel starts): a value read may be older than the latest write but
-// never older than the sweep's start.  That keeps AND exact: values only
-// fall, every value read lies between kappa and the previous iterate, so
-// kappa <= AND_t <= SND_t still holds (H is monotone), and a sweep that
-// changes nothing read only unchanged values, i.e. it certifies a fixed
-// point.  Agent-scope loads (bypassing the L1) cost 60% more per sweep.
+// AND reads and writes tau in place.  Reads and writes are relaxed atomics
+// at workgroup scope: they may be served by (and stay in) this CU's L1 and
+// this XCD's L2, which hold only values of the current launch (caches are
+// made coherent at every kernel boundary), so a value read may be older than
+// the latest write but never older than the sweep's start.  That keeps AND
+// exact: values only fall, every value read lies between kappa and the
+// previous iterate, so kappa <= AND_t <= SND_t still holds (H is monotone),
+// and a sweep that changes nothing read only unchanged values, i.e. it
+// certifies a fixed point.  Each value has one writer (the r-clique's own
+// subgroup), so no write is lost.
 template <typename T, bool AND>
 __device__ __forceinline__ int32_t load_tau(const T *p) {
   if constexpr (AND) {
@@ -34,7 +35,8 @@ template <typename T, bool AND>
 __device__ __forceinline__ void store_tau(T *p, int32_t h, bool changed) {
   if constexpr (AND) {
     if (changed)
-      __hip_atomic_store(p, (T)h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p, (T)h, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
     *p = (T)h;
   }
