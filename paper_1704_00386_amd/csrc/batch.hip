@@ -105,6 +105,35 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
     const uint8_t *act;
     uint8_t *act_next, stamp;
     graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp);
+    if (FR && act != nullptr && tile.type != kBinG1) {
+      // sparse sweep of the tile: flags tested a chunk at a time per wave
+      unsigned long long n_ch = 0, n_ev = 0;
+      const int64_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+      switch (tile.type) {
+        case kBinG4:
+          sweep_sparse<K, 4, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                        tile.hi, wv, nw, act, act_next, stamp,
+                                        &n_ch, &n_ev);
+          break;
+        case kBinG16:
+          sweep_sparse<K, 16, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                         tile.hi, wv, nw, act, act_next, stamp,
+                                         &n_ch, &n_ev);
+          break;
+        case kBinG64:
+          sweep_sparse<K, 64, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                         tile.hi, wv, nw, act, act_next, stamp,
+                                         &n_ch, &n_ev);
+          break;
+        default:  // kBinWave
+          sweep_sparse<K, 64, 32, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                          tile.hi, wv, nw, act, act_next, stamp,
+                                          &n_ch, &n_ev);
+          break;
+      }
+      stat_add_counts(sst, n_ch, n_ev);
+      continue;
+    }
     const int per = rclq_per_pass(tile.type);
     for (int64_t base = tile.lo; base < tile.hi; base += per) {
       bool ch = false, ev = false;

@@ -85,30 +85,9 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
   T *tout = (T *)a.tau_out;
   unsigned long long n_ch = 0, n_ev = 0;  // wave totals, from ballots
   if (FR && G > 1 && act != nullptr) {
-    // Sparse sweep: the wave tests the flags of kChunk consecutive r-cliques
-    // at once (one lane each, coalesced) and runs only the flagged ones,
-    // kPerWave at a time; skipped ones need no write (see update_regs).  A
-    // chunk holds at most 8 rounds of r-cliques, so a run of flagged hubs
-    // is not serialised on one wave for long.
-    constexpr int kChunk = kPerWave * 8 < kWave ? kPerWave * 8 : kWave;
-    for (int64_t base = lo + wave * kChunk; base < hi; base += waves * kChunk) {
-      const int64_t Rl = base + lane_id();
-      bool on = false;
-      if (lane_id() < kChunk && Rl < hi) on = act[Rl] == a.stamp;
-      const uint64_t m = ballot(on);
-      const int na = __popcll(m);
-      for (int r0 = 0; r0 < na; r0 += kPerWave) {  // uniform over the wave
-        const int t = r0 + sub;
-        const bool has = t < na;
-        const int64_t R = base + (has ? nth_set_bit(m, t) : 0);
-        bool ev;
-        const bool changed = update_regs<K, G, M, T, AND, FR>(
-            a.inc_off, a.inc_ids, tin, tout, a.cap_by_tau, R, has, nullptr,
-            act_next, a.stamp, &ev);
-        n_ch += __popcll(ballot(changed));
-        n_ev += __popcll(ballot(ev));
-      }
-    }
+    sweep_sparse<K, G, M, T, AND>(a.inc_off, a.inc_ids, tin, tout, a.cap_by_tau,
+                                  lo, hi, wave, waves, act, act_next, a.stamp,
+                                  &n_ch, &n_ev);
   } else {
     // Each wave takes kPerWave consecutive r-cliques per step and strides
     // over the bin, so a grid of a few waves per SIMD covers any bin.

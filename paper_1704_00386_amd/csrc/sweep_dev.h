@@ -260,6 +260,43 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
   return lead && ch;
 }
 
+// Sparse sweep of the r-cliques [lo, hi) of one bin of G lanes per
+// r-clique, the frontier's flags being valid: the calling wave (number
+// `wave` of `nwaves`) tests the flags of kChunk consecutive r-cliques at
+// once (one lane each, coalesced) and runs only the flagged ones, 64/G at a
+// time, the t-th flagged lane found by nth_set_bit; skipped ones need no
+// write (see update_regs).  A chunk holds at most 8 rounds of r-cliques, so
+// a run of flagged hubs is not serialised on one wave for long.  Adds the
+// wave's changed / recomputed counts to *n_ch / *n_ev.
+template <int K, int G, int M, typename T, bool AND>
+__device__ __forceinline__ void sweep_sparse(
+    const int64_t *__restrict__ inc_off, const int32_t *__restrict__ inc_ids,
+    const T *tin, T *tout, int cap_by_tau, int64_t lo, int64_t hi,
+    int64_t wave, int64_t nwaves, const uint8_t *act, uint8_t *act_next,
+    uint8_t stamp, unsigned long long *n_ch, unsigned long long *n_ev) {
+  constexpr int kPerWave = kWave / G;
+  constexpr int kChunk = kPerWave * 8 < kWave ? kPerWave * 8 : kWave;
+  const int sub = lane_id() / G;
+  for (int64_t base = lo + wave * kChunk; base < hi; base += nwaves * kChunk) {
+    const int64_t Rl = base + lane_id();
+    bool on = false;
+    if (lane_id() < kChunk && Rl < hi) on = act[Rl] == stamp;
+    const uint64_t m = ballot(on);
+    const int na = __popcll(m);
+    for (int r0 = 0; r0 < na; r0 += kPerWave) {  // uniform over the wave
+      const int t = r0 + sub;
+      const bool has = t < na;
+      const int64_t R = base + (has ? nth_set_bit(m, t) : 0);
+      bool ev;
+      const bool changed = update_regs<K, G, M, T, AND, true>(
+          inc_off, inc_ids, tin, tout, cap_by_tau, R, has, nullptr, act_next,
+          stamp, &ev);
+      *n_ch += __popcll(ballot(changed));
+      *n_ev += __popcll(ballot(ev));
+    }
+  }
+}
+
 // Bins hist[0..nb) count values, bin i standing for the value x0 + i*scale.
 // Returns the largest i with base + sum_{i' >= i} hist[i'] >= x0 + i*scale,
 // or -1 if there is none.  All NT threads of the block call it.
