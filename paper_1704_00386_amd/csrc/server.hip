@@ -56,7 +56,7 @@ struct nd_server {
   uint64_t next_ticket = 1;
   hipStream_t stream = nullptr;
   // one batch per (kind, mode, tau width, frontier)
-  std::unique_ptr<nd::Batch> batches[3][2][2][2];
+  std::unique_ptr<nd::Batch> batches[nd::kNumKinds][2][2][2];
 };
 
 namespace nd {

@@ -135,7 +135,7 @@ def test_batch_max_iters(nd, ctx):
 def test_server_results_equal_solo(nd, ctx):
     raws = mixed_graphs() + [chung_lu(int(n), 2.3, 10.0, seed=200 + i)
                              for i, n in enumerate(np.linspace(500, 30000, 20))]
-    kinds = ["truss", "core", "truss", "nucleus34", "core", "truss", "core"]
+    kinds = ["truss", "core", "nucleus13", "nucleus34", "nucleus24", "truss", "core"]
     kinds += ["truss" if i % 2 else "core" for i in range(20)]
     modes = ["snd" if i % 3 else "and" for i in range(len(raws))]
     solo = [make(nd, ctx, raw).decompose(k, m)[0].cpu()
