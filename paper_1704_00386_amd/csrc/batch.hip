@@ -105,11 +105,16 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
     const uint8_t *act;
     uint8_t *act_next, stamp;
     graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp);
-    if (FR && act != nullptr && tile.type != kBinG1) {
+    if (FR && act != nullptr) {
       // sparse sweep of the tile: flags tested a chunk at a time per wave
       unsigned long long n_ch = 0, n_ev = 0;
       const int64_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
       switch (tile.type) {
+        case kBinG1:
+          sweep_sparse<K, 1, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                        tile.hi, wv, nw, act, act_next, stamp,
+                                        &n_ch, &n_ev);
+          break;
         case kBinG4:
           sweep_sparse<K, 4, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                         tile.hi, wv, nw, act, act_next, stamp,

@@ -109,7 +109,7 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   if (opts.on_iter) snap.reset(al, nr);
   // frontier flags (Section 4.3): act[t & 1] selects the r-cliques of sweep
   // t; every r-clique takes part in the first sweep
-  DArr<uint8_t> act[2];
+  DArr<uint8_t> act[2], act_sum[2];  // flags; one stamp per 64 r-cliques
   const bool frontier = opts.use_frontier != 0;
   // notifications start once a sweep changes at most 1/32 of the swept
   // r-cliques (ND_FRONTIER_SWITCH overrides the divisor; 0 = from the start)
@@ -119,6 +119,11 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
     act[1].reset(al, nr);
     fill_u8(act[0].p, 0, nr, s);  // no stamps yet
     fill_u8(act[1].p, 0, nr, s);
+    const int64_t ng = (nr + (1 << dev::kGroupShift) - 1) >> dev::kGroupShift;
+    act_sum[0].reset(al, ng);
+    act_sum[1].reset(al, ng);
+    fill_u8(act_sum[0].p, 0, ng, s);
+    fill_u8(act_sum[1].p, 0, ng, s);
     int div = 32;
     if (const char *v = getenv("ND_FRONTIER_SWITCH")) div = atoi(v);
     notify_below = div <= 0 ? ~0ull : (unsigned long long)(ks.bin_lo[kBinZero] / div);
@@ -168,6 +173,8 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
       if (frontier) {
         a.act = act[t & 1].p;
         a.act_next = act[(t + 1) & 1].p;
+        a.act_sum = act_sum[t & 1].p;
+        a.act_sum_next = act_sum[(t + 1) & 1].p;
         a.stamp = dev::sweep_stamp(t);
         a.notify_below = notify_below;
       } else if (fixed_set) {

@@ -279,6 +279,9 @@ struct SweepArgs {
   // for every neighbour whose value is above its new value.
   const uint8_t *act;       // flags of this sweep (stamps, see sweep_dev.h)
   uint8_t *act_next;
+  // one stamp per 64 r-cliques, set with any flag of the group (NULL: none)
+  const uint8_t *act_sum;
+  uint8_t *act_sum_next;
   uint8_t stamp;            // this sweep's stamp
   // Notifications start once a sweep changes at most this many r-cliques
   // (before that nearly everything is active and notifying costs as much as

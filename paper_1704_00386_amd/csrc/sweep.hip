@@ -54,7 +54,11 @@ __device__ __forceinline__ unsigned long long prev_changed(const SweepArgs &a) {
 __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
                                               unsigned long long prev_changed,
                                               const uint8_t **act,
-                                              uint8_t **act_next) {
+                                              uint8_t **act_next,
+                                              const uint8_t **act_sum,
+                                              uint8_t **sum_next) {
+  *act_sum = nullptr;
+  *sum_next = nullptr;
   if (a.fixed_set) {
     *act = a.act;
     *act_next = nullptr;
@@ -66,6 +70,8 @@ __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
       (a.prev->notified || prev_changed <= a.notify_below);
   *act = flags_valid ? a.act : nullptr;
   *act_next = notify ? a.act_next : nullptr;
+  *act_sum = flags_valid ? a.act_sum : nullptr;
+  *sum_next = notify ? a.act_sum_next : nullptr;
   if (notify && blockIdx.x == 0 && threadIdx.x == 0) a.stats->notified = 1;
 }
 
@@ -74,9 +80,9 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
                                                     int64_t hi) {
   const unsigned long long pc = prev_changed(a);
   if (pc == 0) return;  // converged: a sweep queued past the end
-  const uint8_t *act = nullptr;
-  uint8_t *act_next = nullptr;
-  if (FR) frontier_mode(a, pc, &act, &act_next);
+  const uint8_t *act = nullptr, *act_sum = nullptr;
+  uint8_t *act_next = nullptr, *sum_next = nullptr;
+  if (FR) frontier_mode(a, pc, &act, &act_next, &act_sum, &sum_next);
   constexpr int kPerWave = kWave / G;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -84,10 +90,10 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
   const T *tin = (const T *)a.tau_in;
   T *tout = (T *)a.tau_out;
   unsigned long long n_ch = 0, n_ev = 0;  // wave totals, from ballots
-  if (FR && G > 1 && act != nullptr) {
+  if (FR && act != nullptr) {
     sweep_sparse<K, G, M, T, AND>(a.inc_off, a.inc_ids, tin, tout, a.cap_by_tau,
                                   lo, hi, wave, waves, act, act_next, a.stamp,
-                                  &n_ch, &n_ev);
+                                  &n_ch, &n_ev, act_sum, sum_next);
   } else {
     // Each wave takes kPerWave consecutive r-cliques per step and strides
     // over the bin, so a grid of a few waves per SIMD covers any bin.
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
       bool ev;
       const bool changed = update_regs<K, G, M, T, AND, FR>(
           a.inc_off, a.inc_ids, tin, tout, a.cap_by_tau, R, R < hi, act,
-          act_next, a.stamp, &ev);
+          act_next, a.stamp, &ev, sum_next);
       n_ch += __popcll(ballot(changed));
       n_ev += __popcll(ballot(ev));
     }
@@ -112,14 +118,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_sweep_block(SweepArgs a,
   __shared__ int32_t hist[kBlockHistBins];
   const unsigned long long pc = prev_changed(a);
   if (pc == 0) return;  // converged: a sweep queued past the end
-  const uint8_t *act = nullptr;
-  uint8_t *act_next = nullptr;
-  if (FR) frontier_mode(a, pc, &act, &act_next);
+  const uint8_t *act = nullptr, *act_sum = nullptr;
+  uint8_t *act_next = nullptr, *sum_next = nullptr;
+  if (FR) frontier_mode(a, pc, &act, &act_next, &act_sum, &sum_next);
   for (int64_t R = lo + blockIdx.x; R < hi; R += gridDim.x) {
     bool ev;
     const bool changed = update_block<K, T, AND, FR>(
         a.inc_off, a.inc_ids, (const T *)a.tau_in, (T *)a.tau_out,
-        a.cap_by_tau, R, hist, act, act_next, a.stamp, &ev);
+        a.cap_by_tau, R, hist, act, act_next, a.stamp, &ev, sum_next);
     stat_add(a.stats, changed, ev);
   }
 }

@@ -9,6 +9,9 @@ namespace nd {
 namespace dev {
 
 constexpr int kBlockThreads = 256;
+// Frontier group summaries: one stamp per 64 consecutive r-cliques, set
+// whenever a flag of the group is (see sweep_sparse).
+constexpr int kGroupShift = 6;
 constexpr int kBlockHistBins = 16384;  // 64 KiB of LDS
 
 // AND reads and writes tau in place.  Reads and writes are relaxed atomics
@@ -168,7 +171,8 @@ template <int K, typename T, bool AND>
 __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
                                        int64_t b, int64_t d, int first,
                                        int stride, int32_t h, const T *tau,
-                                       uint8_t *act_next, uint8_t stamp_next) {
+                                       uint8_t *act_next, uint8_t stamp_next,
+                                       uint8_t *sum_next) {
   for (int64_t j = first; j < d; j += stride) {
     const int32_t *q = ids + K * (b + j);
     int32_t r[K], v[K];
@@ -183,7 +187,10 @@ __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
 #pragma unroll
       for (int y = 0; y < K; y++)
         if (y != x) others_ok &= h <= v[y];
-      if (h < v[x] && others_ok) act_next[r[x]] = stamp_next;
+      if (h < v[x] && others_ok) {
+        act_next[r[x]] = stamp_next;
+        if (sum_next) sum_next[r[x] >> kGroupShift] = stamp_next;
+      }
     }
   }
 }
@@ -225,7 +232,8 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
                                             int cap_by_tau, int64_t R,
                                             bool active, const uint8_t *act,
                                             uint8_t *act_next, uint8_t stamp,
-                                            bool *evald) {
+                                            bool *evald,
+                                            uint8_t *sum_next = nullptr) {
   const int sl = lane_id() % G;
   int32_t told = 0, c = 0;
   int64_t b = 0, d = 0;
@@ -253,47 +261,89 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
   if (eval && lead) store_tau<T, AND>(tau_out + R, h, ch);
   if (FR && ch && act_next) {
     const uint8_t next = stamp == 255 ? 1 : stamp + 1;
-    if (!AND && lead) act_next[R] = next;
-    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next, next);
+    if (!AND && lead) {
+      act_next[R] = next;
+      if (sum_next) sum_next[R >> kGroupShift] = next;
+    }
+    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next, next,
+                      sum_next);
   }
   *evald = lead && eval;
   return lead && ch;
 }
 
 // Sparse sweep of the r-cliques [lo, hi) of one bin of G lanes per
-// r-clique, the frontier's flags being valid: the calling wave (number
-// `wave` of `nwaves`) tests the flags of kChunk consecutive r-cliques at
-// once (one lane each, coalesced) and runs only the flagged ones, 64/G at a
-// time, the t-th flagged lane found by nth_set_bit; skipped ones need no
-// write (see update_regs).  A chunk holds at most 8 rounds of r-cliques, so
-// a run of flagged hubs is not serialised on one wave for long.  Adds the
-// wave's changed / recomputed counts to *n_ch / *n_ev.
+// r-clique, the frontier's flags being valid.  The calling wave (number
+// `wave` of `nwaves`) runs only flagged r-cliques, 64/G at a time, the t-th
+// flagged lane of a ballot found by nth_set_bit; skipped ones need no write
+// (see update_regs).  It finds them either through the group summaries
+// (act_sum: one stamp per 64 r-cliques, for the big bins, G <= 4: a step
+// tests 64 groups, then loads the flags of flagged groups only), or by
+// loading the flags of kU chunks of kChunk consecutive r-cliques at once
+// (one lane per flag, coalesced, the loads in flight together).  A chunk
+// holds at most 8 rounds of r-cliques, so a run of flagged hubs is not
+// serialised on one wave for long.  Adds the wave's changed / recomputed
+// counts to *n_ch / *n_ev.
 template <int K, int G, int M, typename T, bool AND>
 __device__ __forceinline__ void sweep_sparse(
     const int64_t *__restrict__ inc_off, const int32_t *__restrict__ inc_ids,
     const T *tin, T *tout, int cap_by_tau, int64_t lo, int64_t hi,
     int64_t wave, int64_t nwaves, const uint8_t *act, uint8_t *act_next,
-    uint8_t stamp, unsigned long long *n_ch, unsigned long long *n_ev) {
+    uint8_t stamp, unsigned long long *n_ch, unsigned long long *n_ev,
+    const uint8_t *act_sum = nullptr, uint8_t *sum_next = nullptr) {
   constexpr int kPerWave = kWave / G;
-  constexpr int kChunk = kPerWave * 8 < kWave ? kPerWave * 8 : kWave;
   const int sub = lane_id() / G;
-  for (int64_t base = lo + wave * kChunk; base < hi; base += nwaves * kChunk) {
-    const int64_t Rl = base + lane_id();
-    bool on = false;
-    if (lane_id() < kChunk && Rl < hi) on = act[Rl] == stamp;
-    const uint64_t m = ballot(on);
+  // runs the flagged r-cliques of mask m (bit i: r-clique cb + i), 64/G at a
+  // time
+  auto run = [&](uint64_t m, int64_t cb) {
     const int na = __popcll(m);
     for (int r0 = 0; r0 < na; r0 += kPerWave) {  // uniform over the wave
       const int t = r0 + sub;
       const bool has = t < na;
-      const int64_t R = base + (has ? nth_set_bit(m, t) : 0);
+      const int64_t R = cb + (has ? nth_set_bit(m, t) : 0);
       bool ev;
       const bool changed = update_regs<K, G, M, T, AND, true>(
           inc_off, inc_ids, tin, tout, cap_by_tau, R, has, nullptr, act_next,
-          stamp, &ev);
+          stamp, &ev, sum_next);
       *n_ch += __popcll(ballot(changed));
       *n_ev += __popcll(ballot(ev));
     }
+  };
+  if (G <= 4 && act_sum != nullptr) {
+    // Big bins: test 64 group summaries per step (one lane each), then the
+    // flags of each flagged group only.  A sweep with few flagged r-cliques
+    // reads 1/64 of the flags.
+    const int64_t g_lo = lo >> kGroupShift;
+    const int64_t g_hi = (hi + (1 << kGroupShift) - 1) >> kGroupShift;
+    for (int64_t gb = g_lo + wave * kWave; gb < g_hi; gb += nwaves * kWave) {
+      const int64_t gi = gb + lane_id();
+      uint64_t gm = ballot(gi < g_hi && act_sum[gi] == stamp);
+      while (gm) {  // uniform over the wave
+        const int q = __ffsll((unsigned long long)gm) - 1;
+        gm &= gm - 1;
+        const int64_t cb = (gb + q) << kGroupShift;
+        const int64_t Rl = cb + lane_id();
+        run(ballot(Rl >= lo && Rl < hi && act[Rl] == stamp), cb);
+      }
+    }
+    return;
+  }
+  constexpr int kChunk = kPerWave * 8 < kWave ? kPerWave * 8 : kWave;
+  // Several chunks per step only where a chunk is narrow work (G <= 4: the
+  // big bins, where the flag scan dominates a sparse sweep); for wide
+  // mappings a step of kU chunks would serialise up to 8 kU hub r-cliques
+  // on one wave.
+  constexpr int kU = G <= 4 ? 8 : 1;
+  constexpr int64_t kStep = (int64_t)kChunk * kU;
+  for (int64_t base = lo + wave * kStep; base < hi; base += nwaves * kStep) {
+    bool on[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int64_t Rl = base + (int64_t)u * kChunk + lane_id();
+      on[u] = lane_id() < kChunk && Rl < hi && act[Rl] == stamp;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) run(ballot(on[u]), base + (int64_t)u * kChunk);
   }
 }
 
@@ -353,7 +403,8 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
                              const int32_t *__restrict__ inc_ids,
                              const T *tau_in, T *tau_out, int cap_by_tau,
                              int64_t R, int32_t *hist, const uint8_t *act,
-                             uint8_t *act_next, uint8_t stamp, bool *evald) {
+                             uint8_t *act_next, uint8_t stamp, bool *evald,
+                             uint8_t *sum_next = nullptr) {
   const int t = threadIdx.x;
   if (FR && act && act[R] != stamp) {  // skipped: see update_regs
     *evald = false;
@@ -402,9 +453,12 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
   if (t == 0) store_tau<T, AND>(tau_out + R, h, ch);
   if (FR && ch && act_next) {
     const uint8_t next = stamp == 255 ? 1 : stamp + 1;
-    if (!AND && t == 0) act_next[R] = next;
+    if (!AND && t == 0) {
+      act_next[R] = next;
+      if (sum_next) sum_next[R >> kGroupShift] = next;
+    }
     notify<K, T, AND>(inc_ids, b, d, t, kBlockThreads, h, tau_in, act_next,
-                      next);
+                      next, sum_next);
   }
   __syncthreads();
   *evald = t == 0;
