@@ -111,7 +111,7 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   // t; every r-clique takes part in the first sweep
   DArr<uint8_t> act[2], act_sum[2];  // flags; one stamp per 64 r-cliques
   const bool frontier = opts.use_frontier != 0;
-  // notifications start once a sweep changes at most 1/32 of the swept
+  // notifications start once a sweep changes at most 1/16 of the swept
   // r-cliques (ND_FRONTIER_SWITCH overrides the divisor; 0 = from the start)
   unsigned long long notify_below = 0;
   if (frontier) {
@@ -124,7 +124,7 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
     act_sum[1].reset(al, ng);
     fill_u8(act_sum[0].p, 0, ng, s);
     fill_u8(act_sum[1].p, 0, ng, s);
-    int div = 32;
+    int div = 16;
     if (const char *v = getenv("ND_FRONTIER_SWITCH")) div = atoi(v);
     notify_below = div <= 0 ? ~0ull : (unsigned long long)(ks.bin_lo[kBinZero] / div);
   }
