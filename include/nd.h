@@ -44,6 +44,13 @@
  *     int64.
  *   - Objects are not thread-safe: calls on one nd_ctx (and its graphs) must
  *     not overlap, except the nd_server_* calls, which are.
+ *
+ * Environment (tuning only; results never depend on them).
+ *   ND_FRONTIER_SWITCH=d  with use_frontier, notifications start once a sweep
+ *                         changes at most 1/d of the swept r-cliques
+ *                         (default 16; 0: from the second sweep on).
+ *   ND_BATCH_NO_GRAPH=1   batched epochs are launched one by one instead of
+ *                         through captured HIP graphs.
  */
 #ifndef ND_H
 #define ND_H
