@@ -119,7 +119,7 @@ def _short_kernel(name: str) -> str:
 
 
 def _profile_command(args_extra: str, out: str) -> str:
-    return (f"rocprofv3 {args_extra} --output-format csv -d $R/gpurun_out/{out} -o {out} "
+    return (f"rocprofv3 {args_extra} --output-format csv -d $OUT/{out} -o {out} "
             "-- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu --stream-graphs 0 "
             "--small-graphs 0 --ego-queries 0 --no-nucleus34 --calib-copy")
 
@@ -138,7 +138,7 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
     rows = list(csv.DictReader(open(trace_csv)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = ["# Kernel trace: one bench step (k-truss SND on Chung-Lu 2^20, beta 2.1, mean 32)", "",
-             "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`):", "", "```",
+             "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`, output under `$OUT`):", "", "```",
              _profile_command("--kernel-trace --stats", "kt"), "```", "",
              "The run holds one timed step (prep + SND with the notification frontier), the full-sweep",
              "roofline leg (SND, every r-clique recomputed each sweep) and the AND leg (frontier), after a",
@@ -201,7 +201,7 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
           "|---|---:|---:|"]
     for k in full:
         md.append(f"| `{k}` | {statistics.mean(fetch[k]):.0f} | {statistics.mean(write.get(k, [0.0])):.0f} |")
-    md += ["", "Commands (run from /tmp, `TMPDIR=/tmp`, repo at `$R`), then "
+    md += ["", "Commands (run from /tmp, `TMPDIR=/tmp`, repo at `$R`, output under `$OUT`), then "
            "`python bench.py --summarize-profiles <trace stats csv> <fetch csv> <write csv>`:", "", "```",
            *rec["commands"], "```", "",
            "These counters measure L2-to-fabric traffic, which includes Infinity Cache (MALL) hits; the",
@@ -227,8 +227,8 @@ def summarize_trace(stats_csv: str, name: str) -> None:
     rows = list(csv.DictReader(open(stats_csv)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = [f"# Kernel trace: {name}", "", what + ".", "",
-             "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`):", "", "```",
-             f"rocprofv3 --kernel-trace --stats --output-format csv -d $R/gpurun_out/{name} "
+             "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`, output under `$OUT`):", "", "```",
+             f"rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/{name} "
              f"-o {name} -- python3 $R/bench.py {flags}", "```", "",
              f"Total kernel time {tot / 1e6:.1f} ms.", "",
              "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
@@ -505,7 +505,7 @@ def main():
         summarize_trace(*args.summarize_trace)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU "
+        print("bench.py: measures one GPU only; the multi-GPU "
               "sharding is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
 
