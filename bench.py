@@ -578,6 +578,22 @@ def main():
     avg_sweep_ms = sum(sweep_ms) / len(sweep_ms)
     achieved = B / (avg_sweep_ms * 1e-3) / 1e9
 
+    # the same step from host memory: pinned host edge list in, kappa back
+    # to host memory (PCIe both ways; never the bench value)
+    hsrc = torch.from_numpy(raw.src).pin_memory()
+    hdst = torch.from_numpy(raw.dst).pin_memory()
+    host_ms = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gh = nd.Graph.from_edges(ctx, raw.n, hsrc, hdst)
+        kh, _ = gh.decompose(KIND, "snd", use_frontier=True)
+        kh = kh.cpu()
+        host_ms.append(1e3 * (time.perf_counter() - t0))
+        gh.close()
+    same_host = bool(torch.equal(kh, kappa.cpu()))
+    del hsrc, hdst, kh
+
     # AND on the prepared graph (same incidence lists), frontier on
     kand, rand = g.decompose(KIND, "and", use_frontier=True)
     same_and = bool(torch.equal(kand, kappa))
@@ -639,6 +655,9 @@ def main():
                      "bytes_per_launch": B, "avg_launch_ms": avg_sweep_ms},
         "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
                 "frontier": True, "kappa_equals_snd": same_and},
+        "host_io": {"ms_per_step": min(host_ms), "kappa_equals": same_host,
+                    "what": "the same step from a pinned host edge list to "
+                            "kappa in host memory (PCIe both ways)"},
     }
     # the paper's own figures, other hardware and real graphs: context only
     line["paper_context"] = {
