@@ -210,6 +210,37 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
     print(f"full sweep {full_avg:.0f} us; HBM-side {rec['hbm_bytes_per_sweep'] / 1e9:.2f} GB per sweep")
 
 
+def summarize_quality(json_path: str) -> None:
+    """profiles/quality_<workload>_<kind>.md from the JSON line printed by
+    `python bench.py --quality <workload>`."""
+    q = json.loads(open(json_path).read().strip().splitlines()[-1])
+    name, kind = q["workload"], q["kind"]
+    L = [f"# Accuracy per sweep: {kind} on the `{name}` workload ({q['n_rcliques']} r-cliques)", "",
+         f"Command (repo root): `python bench.py --quality {name}`", "",
+         "`fraction_exact`: share of all r-cliques with tau_t = kappa.  `kendall_tau`: scipy's tau-b of",
+         f"tau_t against kappa on a uniform sample of {q['kendall_sample']} r-cliques.  `ms_cum`: summed device",
+         "time of sweeps 1..t (events around each sweep's launches; sweeps run one at a time here).", "",
+         f"Degree levels (Defn. 4; the bound on SND sweeps): {q['degree_levels']}.  "
+         f"SND sweeps: {len(q['snd']['rows']) - 1}; AND sweeps: {len(q['and']['rows']) - 1}."]
+    for mode in ("snd", "and"):
+        m = q[mode]
+        L += ["", f"## {mode.upper()}", "",
+              "Active-ratio stop (stop once fewer than this share of r-cliques changed):", "",
+              "| ratio | sweep | ms | fraction exact | Kendall-Tau |", "|---:|---:|---:|---:|---:|"]
+        for ratio, st in m["active_ratio_stops"].items():
+            L.append(f"| {ratio} | {st['sweep']} | {st['ms_cum']:.2f} | "
+                     f"{st['fraction_exact']:.4f} | {st['kendall_tau']:.4f} |")
+        L += ["", "| sweep | changed | ms (cum.) | fraction exact | Kendall-Tau |",
+              "|---:|---:|---:|---:|---:|"]
+        for r in m["rows"]:
+            ch = "" if r["changed"] is None else r["changed"]
+            L.append(f"| {r['sweep']} | {ch} | {r['ms_cum']:.2f} | {r['fraction_exact']:.5f} | "
+                     f"{r['kendall_tau']:.5f} |")
+    path = os.path.join(ROOT, "profiles", f"quality_{name}_{kind}.md")
+    open(path, "w").write("\n".join(L) + "\n")
+    print(path)
+
+
 TRACE_RUNS = {
     "sbm_nucleus34": ("(3,4)-nucleus on the stochastic block model (5000 communities of "
                       "U{50..400} vertices, p_in 0.3, p_out 2e-6, seed 4): build + prepare, "
@@ -489,6 +520,9 @@ def main():
                     help="skip the (3,4)-nucleus leg on the block model")
     ap.add_argument("--only-nucleus34", action="store_true",
                     help="run only the (3,4)-nucleus leg and print its JSON")
+    ap.add_argument("--summarize-quality", default=None, metavar="JSON",
+                    help="write profiles/quality_*.md from the output of "
+                         "--quality and exit")
     ap.add_argument("--summarize-trace", nargs=2, default=None,
                     metavar=("STATS_CSV", "NAME"),
                     help="write profiles/kernel_trace_NAME.md from a "
@@ -503,6 +537,9 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_quality:
+        summarize_quality(args.summarize_quality)
         return
     if args.gpus != 1:
         print("bench.py: measures one GPU only; the multi-GPU "
