@@ -355,24 +355,35 @@ class Graph:
                   use_frontier: bool = False, stop_active_ratio: float = 0.0,
                   on_iter: Optional[Callable] = None, out=None, stream=None,
                   allow_not_converged: bool = False,
-                  keep_iterates: Optional[list] = None):
+                  keep_iterates: Optional[list] = None,
+                  keep_index: Optional[torch.Tensor] = None):
         """kappa for every r-clique (int32 tensor on the device) and the
         nd_result statistics as a dict.  With keep_iterates=[] the list
-        receives (changed, tau_t) for every sweep t = 1, 2, ..."""
+        receives (changed, tau_t) for every sweep t = 1, 2, ...; with
+        keep_index (r-clique ids, a device tensor) only tau_t[keep_index]
+        is kept, so that big graphs can keep many sweeps."""
         nr, _, _ = self.sizes(kind)
         kappa = out if out is not None else torch.empty(
             max(nr, 1), dtype=torch.int32, device=self.ctx.device)
         if keep_iterates is not None:
             user_cb = on_iter
             dev = self.ctx.device
+            full = None if keep_index is None else torch.empty(
+                max(nr, 1), dtype=torch.int32, device=dev)
 
             def on_iter(info):
-                snap = torch.empty(max(nr, 1), dtype=torch.int32, device=dev)
+                snap = full if full is not None else torch.empty(
+                    max(nr, 1), dtype=torch.int32, device=dev)
                 rc = _hip.hipMemcpy(snap.data_ptr(), info.tau_dev, 4 * nr,
                                     _HIP_D2D)
                 if rc != 0:
                     raise RuntimeError(f"hipMemcpy failed ({rc})")
-                keep_iterates.append((int(info.changed), snap[:nr]))
+                if keep_index is None:
+                    kept = snap[:nr]
+                else:
+                    kept = snap[keep_index]
+                    torch.cuda.synchronize()  # before the next sweep's copy
+                keep_iterates.append((int(info.changed), kept))
                 return user_cb(info) if user_cb else 0
         o, keep = _make_opts(mode, max_iters, use_frontier, stop_active_ratio,
                              on_iter)
