@@ -328,12 +328,10 @@ __device__ __forceinline__ void orient_emit(const OrientArgs &a, int32_t euv,
     const int32_t iuv = a.inv[euv], i1 = a.inv[e1], i2 = a.inv[e2];
     const int64_t p1 = (int64_t)atomicAdd(&a.cursor[i1], 1ull);
     const int64_t p2 = (int64_t)atomicAdd(&a.cursor[i2], 1ull);
-    a.ids[2 * base_pos] = i1;
-    a.ids[2 * base_pos + 1] = i2;
-    a.ids[2 * p1] = iuv;
-    a.ids[2 * p1 + 1] = i2;
-    a.ids[2 * p2] = iuv;
-    a.ids[2 * p2 + 1] = i1;
+    int2 *ids2 = reinterpret_cast<int2 *>(a.ids);  // one 8-byte store per entry
+    ids2[base_pos] = make_int2(i1, i2);
+    ids2[p1] = make_int2(iuv, i2);
+    ids2[p2] = make_int2(iuv, i1);
   }
 }
 

@@ -155,24 +155,29 @@ __device__ __forceinline__ int32_t hindex_search(const int32_t (&rho)[M],
   return lo;
 }
 
-// Notification of Section 4.3: R changed to h.  A neighbour R' (another
-// r-clique of an s-clique S containing R) can change at the next sweep only
-// if some rho(S,R') falls from at least its next cap c' = tau_{t+1}(R') to
-// below it.  Through S that needs rho_t(S,R') >= c' > h, i.e. both
+// Notification of Section 4.3: R changed from told to h.  A neighbour R'
+// (another r-clique of an s-clique S containing R) can change at the next
+// sweep only if some rho(S,R') falls from at least its next cap
+// c' = tau_{t+1}(R') to below it.  Through S that needs rho_t(S,R') >= c' > h,
+// i.e. both
 //   h < tau(R')                 (tau_t(R') >= c'), and
 //   h <= tau(Q) for every other member Q of S besides R and R'
-// (rho_t(S,R') is a minimum over them and R).  Mark exactly those R'.  SND
-// reads tau_t, so every R' that can change is marked and the iterates are
-// those of full sweeps.  In place (AND) the values read may already be
-// newer; of several members of S that fell in one sweep, the one with the
-// lowest new value still passes the test (<= keeps ties), so the s-clique is
-// never lost.  Byte stores of the same stamp race harmlessly.
+// (rho_t(S,R') is a minimum over them and R).  In place (AND) the values read
+// may already be newer; of several members of S that fell in one sweep, the
+// one with the lowest new value still passes the test (<= keeps ties), so the
+// s-clique is never lost.  SND reads tau_t exactly and self-activates every R
+// that changed, so it only has to reach the R' that keep their value through
+// sweep t+1: for those c' = tau_t(R'), and rho_t(S,R') >= c' also needs
+// told >= c' and tau_t(Q) >= c' for the other members.  SND marks R' when
+//   h < tau_t(R') <= told  and  tau_t(Q) >= tau_t(R') for every other Q,
+// which keeps every R' that can change, so the iterates are those of full
+// sweeps.  Byte stores of the same stamp race harmlessly.
 template <int K, typename T, bool AND>
 __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
                                        int64_t b, int64_t d, int first,
-                                       int stride, int32_t h, const T *tau,
-                                       uint8_t *act_next, uint8_t stamp_next,
-                                       uint8_t *sum_next) {
+                                       int stride, int32_t told, int32_t h,
+                                       const T *tau, uint8_t *act_next,
+                                       uint8_t stamp_next, uint8_t *sum_next) {
   for (int64_t j = first; j < d; j += stride) {
     const int32_t *q = ids + K * (b + j);
     int32_t r[K], v[K];
@@ -186,8 +191,8 @@ __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
       bool others_ok = true;
 #pragma unroll
       for (int y = 0; y < K; y++)
-        if (y != x) others_ok &= h <= v[y];
-      if (h < v[x] && others_ok) {
+        if (y != x) others_ok &= AND ? h <= v[y] : v[x] <= v[y];
+      if (h < v[x] && (AND || v[x] <= told) && others_ok) {
         act_next[r[x]] = stamp_next;
         if (sum_next) sum_next[r[x] >> kGroupShift] = stamp_next;
       }
@@ -265,7 +270,7 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
       act_next[R] = next;
       if (sum_next) sum_next[R >> kGroupShift] = next;
     }
-    notify<K, T, AND>(inc_ids, b, d, sl, G, h, tau_in, act_next, next,
+    notify<K, T, AND>(inc_ids, b, d, sl, G, told, h, tau_in, act_next, next,
                       sum_next);
   }
   *evald = lead && eval;
@@ -457,8 +462,8 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
       act_next[R] = next;
       if (sum_next) sum_next[R >> kGroupShift] = next;
     }
-    notify<K, T, AND>(inc_ids, b, d, t, kBlockThreads, h, tau_in, act_next,
-                      next, sum_next);
+    notify<K, T, AND>(inc_ids, b, d, t, kBlockThreads, told, h, tau_in,
+                      act_next, next, sum_next);
   }
   __syncthreads();
   *evald = t == 0;
