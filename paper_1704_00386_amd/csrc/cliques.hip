@@ -308,6 +308,9 @@ struct OrientArgs {
   // tri_buf[tri_off[q] ...] as (e1, e2) pairs, for k_orient_scatter
   const int64_t *tri_off;
   int2 *tri_buf;
+  // k_orient_heavy, count pass: side counts of the edges of out(u), summed
+  // per source u (each edge lies in one out-list, so one source writes each)
+  int32_t *hcount;
 };
 
 // One triangle (euv, e1 = (u,w), e2 = (v,w)) found from the oriented edge
@@ -389,14 +392,19 @@ __global__ __launch_bounds__(256) void k_orient_isect(OrientArgs a) {
 // into LDS once, then each wave takes an edge u->v, streams out(v) from HBM
 // (coalesced) and binary-searches each entry in the LDS copy of out(u).
 // Degree orientation keeps out-lists short (at most sqrt(2|E|) entries), so
-// out(u) fits LDS; the host falls back to k_orient_isect<64> otherwise.
+// out(u) fits LDS; the host falls back to k_orient_isect<64> otherwise.  In
+// the count pass the side counts of the edges (u,w) of out(u) are summed in
+// LDS and stored to hcount once per source (an edge lies in one out-list
+// only), so only the (v,w) sides take a global atomic per triangle.  The
+// triangle buffer then holds (index of (u,w) in out(u), edge (v,w)), for
+// k_orient_scatter_heavy.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_orient_heavy(OrientArgs a,
                                                       const int32_t *__restrict__ seg_lo,
                                                       int64_t nseg) {
   extern __shared__ int32_t lds[];
   const int cap = a.lds_cap;
-  int32_t *lc = lds, *le = lds + cap;
+  int32_t *lc = lds, *le = lds + cap, *lcnt = lds + 2 * cap;  // lcnt: count pass
   const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
   constexpr int kWaves = 256 / kWave;
   for (int64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
@@ -409,6 +417,7 @@ __global__ __launch_bounds__(256) void k_orient_heavy(OrientArgs a,
     for (int i = t; i < du; i += 256) {
       lc[i] = a.out_col[bu + i];
       le[i] = a.out_eid[bu + i];
+      if (!FILL) lcnt[i] = 0;
     }
     __syncthreads();
     for (int64_t e = lo + w; e < hi; e += kWaves) {  // one edge per wave
@@ -436,12 +445,24 @@ __global__ __launch_bounds__(256) void k_orient_heavy(OrientArgs a,
           found = l < du && lc[l] == x;
         }
         const uint64_t m = ballot(found);
-        if (found)
-          orient_emit<FILL>(a, euv, le[l], a.out_eid[j],
-                            base + run + lanes_below(m));
+        if (found) {
+          const int32_t e2 = a.out_eid[j];
+          const int64_t bp = base + run + lanes_below(m);
+          if (FILL) {
+            orient_emit<true>(a, euv, le[l], e2, bp);
+          } else {
+            atomicAdd(&lcnt[l], 1);
+            atomicAdd(&a.count[e2], 1);
+            if (a.tri_buf) a.tri_buf[bp] = make_int2(l, e2);
+          }
+        }
         run += __popcll(m);
       }
       if (lane == 0) orient_base_done<FILL>(a, euv, run);
+    }
+    if (!FILL) {
+      __syncthreads();  // every wave is done with this source
+      for (int i = t; i < du; i += 256) a.hcount[le[i]] = lcnt[i];
     }
   }
 }
@@ -465,6 +486,54 @@ __global__ __launch_bounds__(256) void k_orient_scatter(OrientArgs a) {
     for (int i = sl; i < n; i += G) {
       const int2 p = tb[i];
       orient_emit<true>(a, euv, p.x, p.y, base + i);
+    }
+  }
+}
+
+// Fill pass of the 64-lane bin from the triangle buffer, one workgroup per
+// source u as in the count pass.  The list of each edge (u,w) of out(u)
+// keeps, right after its base entries, the hcount slots of the triangles
+// where it is the (u,w) side, all found from this source: they are placed
+// with LDS cursors; only the (v,w) sides take global atomic cursors.
+__global__ __launch_bounds__(256) void k_orient_scatter_heavy(
+    OrientArgs a, const int32_t *__restrict__ seg_lo, int64_t nseg) {
+  extern __shared__ unsigned long long lds64[];
+  const int cap = a.lds_cap;
+  unsigned long long *lcur = lds64;                          // cap entries
+  int32_t *linv = reinterpret_cast<int32_t *>(lds64 + cap);  // cap entries
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  constexpr int kWaves = 256 / kWave;
+  int2 *ids2 = reinterpret_cast<int2 *>(a.ids);
+  for (int64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    const int64_t lo = seg_lo[sg];
+    const int64_t hi = sg + 1 < nseg ? seg_lo[sg + 1] : a.nitems;
+    const int32_t u = a.out_src[a.items[lo]];
+    const int64_t bu = a.out_off[u];
+    const int du = (int)(a.out_off[u + 1] - bu);  // <= cap (host-checked)
+    __syncthreads();  // the previous source is done with the LDS cursors
+    for (int i = t; i < du; i += 256) {
+      const int32_t e = a.out_eid[bu + i];
+      const int32_t ie = a.inv[e];
+      linv[i] = ie;
+      lcur[i] = (unsigned long long)(a.base_off[ie] + a.count_base[e]);
+    }
+    __syncthreads();
+    for (int64_t e = lo + w; e < hi; e += kWaves) {  // one edge per wave
+      const int64_t q = a.items[e];
+      const int32_t euv = a.out_eid[q];
+      const int32_t n = a.count_base[euv];
+      const int32_t iuv = a.inv[euv];
+      const int64_t base = a.base_off[iuv];
+      const int2 *tb = a.tri_buf + a.tri_off[q];
+      for (int i = lane; i < n; i += kWave) {
+        const int2 p = tb[i];  // (index of (u,w) in out(u), edge (v,w))
+        const int32_t i1 = linv[p.x], i2 = a.inv[p.y];
+        const int64_t p1 = (int64_t)atomicAdd(&lcur[p.x], 1ull);
+        const int64_t p2 = (int64_t)atomicAdd(&a.cursor[i2], 1ull);
+        ids2[base + i] = make_int2(i1, i2);
+        ids2[p1] = make_int2(iuv, i2);
+        ids2[p2] = make_int2(iuv, i1);
+      }
     }
   }
 }
@@ -511,14 +580,23 @@ __global__ void k_orient_bins(const int64_t *__restrict__ out_off,
   cap[q] = (int32_t)m;
 }
 
-// Side entries of internal r-clique i start after its base entries.
+// Side entries of internal r-clique i start after its base entries and, when
+// given, after the blocks reserved per source (skip, by edge id).
 __global__ void k_cursor_init(const int64_t *__restrict__ off,
                               const int32_t *__restrict__ perm,
-                              const int32_t *__restrict__ count_base, int64_t nr,
+                              const int32_t *__restrict__ count_base,
+                              const int32_t *__restrict__ skip, int64_t nr,
                               unsigned long long *__restrict__ cursor) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nr)
-    cursor[i] = (unsigned long long)(off[i] + (count_base ? count_base[perm[i]] : 0));
+    cursor[i] = (unsigned long long)(off[i] + (count_base ? count_base[perm[i]] : 0) +
+                                     (skip ? skip[perm[i]] : 0));
+}
+
+__global__ void k_add_i32(int32_t *__restrict__ x, const int32_t *__restrict__ y,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += y[i];
 }
 
 // Segments of equal source in the 64-lane bin (for k_orient_heavy).
@@ -541,8 +619,8 @@ void run_orient(OrientArgs a, const int32_t *items, const int64_t *bin_off,
       default:
         if (a.lds_cap > 0) {
           const unsigned grid = (unsigned)std::min<int64_t>(hs.n, 65536);
-          k_orient_heavy<FILL><<<grid, 256, sizeof(int32_t) * 2 * a.lds_cap, s>>>(
-              a, hs.lo.p, hs.n);
+          const size_t lds = sizeof(int32_t) * (FILL ? 2 : 3) * a.lds_cap;
+          k_orient_heavy<FILL><<<grid, 256, lds, s>>>(a, hs.lo.p, hs.n);
         } else {
           k_orient_isect<64, FILL><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a);
         }
@@ -553,7 +631,7 @@ void run_orient(OrientArgs a, const int32_t *items, const int64_t *bin_off,
 }
 
 void run_scatter(OrientArgs a, const int32_t *items, const int64_t *bin_off,
-                 hipStream_t s) {
+                 const HeavySegs &hs, hipStream_t s) {
   for (int b = 0; b < 4; b++) {
     a.items = items + bin_off[b];
     a.nitems = bin_off[b + 1] - bin_off[b];
@@ -562,7 +640,15 @@ void run_scatter(OrientArgs a, const int32_t *items, const int64_t *bin_off,
       case 0: k_orient_scatter<1><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
       case 1: k_orient_scatter<4><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
       case 2: k_orient_scatter<16><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
-      default: k_orient_scatter<64><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a); break;
+      default:
+        if (a.lds_cap > 0) {  // the count pass ran k_orient_heavy
+          const unsigned grid = (unsigned)std::min<int64_t>(hs.n, 65536);
+          const size_t lds = (sizeof(unsigned long long) + sizeof(int32_t)) * a.lds_cap;
+          k_orient_scatter_heavy<<<grid, 256, lds, s>>>(a, hs.lo.p, hs.n);
+        } else {
+          k_orient_scatter<64><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a);
+        }
+        break;
     }
     ND_LAUNCHED();
   }
@@ -812,7 +898,7 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
     int32_t hmax = 0;
     ND_HIP(hipMemcpyAsync(&hmax, mx.p, sizeof hmax, hipMemcpyDeviceToHost, s));
     ND_HIP(hipStreamSynchronize(s));
-    constexpr int kMaxLdsEntries = 8192;  // 64 KiB: two int32 arrays
+    constexpr int kMaxLdsEntries = 5120;  // 60 KiB: three int32 arrays
     if (hmax <= kMaxLdsEntries) {
       a.lds_cap = std::max(hmax, 1);
       const int32_t *it3 = items.p + bin_off[3];
@@ -833,15 +919,28 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   a.count_base = cbase.p;  // every oriented edge stores its own
   a.tri_off = tri_buf.p ? tri_off.p : nullptr;
   a.tri_buf = tri_buf.p;
+  // per-source side counts of k_orient_heavy; with the triangle buffer each
+  // edge's list keeps those slots right after its base entries
+  DArr<int32_t> hcount;
+  if (a.lds_cap > 0) {
+    hcount.reset(al, ne);
+    fill_i32(hcount.p, 0, ne, s);
+    a.hcount = hcount.p;
+  }
   run_orient<false>(a, items.p, bin_off, hs, s);
+  if (hcount.p) {
+    k_add_i32<<<grid_for(ne, 256), 256, 0, s>>>(cnt.p, hcount.p, ne);
+    ND_LAUNCHED();
+  }
   ks.nr = ne;
   build_layout(g, ks, cnt.p, s);
   cnt.free();
   ks.inc_ids.reset(al, 2 * ks.P);
   DArr<unsigned long long> cursor(al, ne);
   if (ne > 0) {
-    k_cursor_init<<<grid_for(ne, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
-                                                     cbase.p, ne, cursor.p);
+    k_cursor_init<<<grid_for(ne, 256), 256, 0, s>>>(
+        ks.inc_off.p, ks.perm.p, cbase.p, tri_buf.p ? hcount.p : nullptr, ne,
+        cursor.p);
     ND_LAUNCHED();
   }
   a.inv = ks.inv.p;
@@ -849,7 +948,7 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   a.ids = ks.inc_ids.p;
   a.base_off = ks.inc_off.p;
   if (tri_buf.p)
-    run_scatter(a, items.p, bin_off, s);
+    run_scatter(a, items.p, bin_off, hs, s);
   else
     run_orient<true>(a, items.p, bin_off, hs, s);
 }
@@ -915,7 +1014,7 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   DArr<unsigned long long> cursor(al, nt);
   if (nt > 0) {
     k_cursor_init<<<grid_for(nt, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
-                                                     nullptr, nt, cursor.p);
+                                                     nullptr, nullptr, nt, cursor.p);
     ND_LAUNCHED();
   }
   run_n34_fill(a, cursor.p, items.p, bin_off, s);
@@ -1075,7 +1174,7 @@ void build_incidence_n13(nd_graph *g, KindState &ks, hipStream_t s) {
   DArr<unsigned long long> cursor(al, n);
   if (n > 0) {
     k_cursor_init<<<grid_for(n, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
-                                                    nullptr, n, cursor.p);
+                                                    nullptr, nullptr, n, cursor.p);
     ND_LAUNCHED();
   }
   if (nt > 0) {
@@ -1119,7 +1218,7 @@ void build_incidence_n24(nd_graph *g, KindState &ks, hipStream_t s) {
   DArr<unsigned long long> cursor(al, ne);
   if (ne > 0) {
     k_cursor_init<<<grid_for(ne, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
-                                                     nullptr, ne, cursor.p);
+                                                     nullptr, nullptr, ne, cursor.p);
     ND_LAUNCHED();
   }
   a.inv = ks.inv.p;
