@@ -323,17 +323,50 @@ static void emit_s(scl_ctx *c) {
   }
 }
 
+/* First index i >= lo of the sorted list a[0..len) with a[i] >= v. */
+static int64_t first_ge(const int32_t *a, int64_t lo, int64_t len, int32_t v) {
+  int64_t hi = len;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 /* Pick the extension vertices ext[depth..] from cn[start..], increasing,
- * each adjacent to the ones already picked. */
+ * each adjacent to the ones already picked.  Past the first pick the
+ * candidates are also neighbours of the last one, so when that vertex has
+ * fewer neighbours than cn has candidates left, its (ascending) list is
+ * walked instead and each entry looked up in cn: the same vertices in the
+ * same increasing order. */
 static void extend_s(scl_ctx *c, int depth, int64_t start) {
   if (depth == c->s - c->r) {
     emit_s(c);
     return;
   }
+  const og *g = c->g;
+  if (depth > 0) {
+    const int32_t last = c->ext[depth - 1];
+    const int64_t b = g->row_off[last], e = g->row_off[last + 1];
+    if (e - b < c->cn.len - start) {
+      for (int64_t p = b; p < e; p++) {
+        const int32_t x = g->col[p];
+        const int64_t i = first_ge(c->cn.a, start, c->cn.len, x);
+        if (i == c->cn.len || c->cn.a[i] != x) continue;
+        int ok = 1;
+        for (int j = 0; j < depth - 1 && ok; j++) ok = adjacent(g, c->ext[j], x);
+        if (!ok) continue;
+        c->ext[depth] = x;
+        extend_s(c, depth + 1, i + 1);
+      }
+      return;
+    }
+  }
   for (int64_t i = start; i < c->cn.len; i++) {
     int32_t x = c->cn.a[i];
     int ok = 1;
-    for (int j = 0; j < depth && ok; j++) ok = adjacent(c->g, c->ext[j], x);
+    for (int j = 0; j < depth && ok; j++) ok = adjacent(g, c->ext[j], x);
     if (!ok) continue;
     c->ext[depth] = x;
     extend_s(c, depth + 1, i + 1);
