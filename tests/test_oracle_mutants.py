@@ -42,7 +42,7 @@ MUTANTS = {
                          "update_body(&a->u, i, wv);"),
     # s-clique extension vertices must be pairwise adjacent
     "ext_not_clique": (
-        "for (int j = 0; j < depth && ok; j++) ok = adjacent(c->g, c->ext[j], x);",
+        "for (int j = 0; j < depth && ok; j++) ok = adjacent(g, c->ext[j], x);",
         ";"),
 }
 
