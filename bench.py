@@ -140,10 +140,13 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
     lines = ["# Kernel trace: one bench step (k-truss SND on Chung-Lu 2^20, beta 2.1, mean 32)", "",
              "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`, output under `$OUT`):", "", "```",
              _profile_command("--kernel-trace --stats", "kt"), "```", "",
-             "The run holds one timed step (prep + SND with the notification frontier), the full-sweep",
-             "roofline leg (SND, every r-clique recomputed each sweep) and the AND leg (frontier), after a",
-             "1 GiB device copy. Template arguments of `k_sweep_regs<k, lanes, values/lane, tau type, AND,",
-             "frontier>`.", "", "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
+             "The run holds one timed step (build + prep + SND with the notification frontier), the",
+             "full-sweep roofline leg (SND, every r-clique recomputed each sweep), two more steps from a",
+             "pinned host edge list (host_io leg) and the AND leg (frontier), after a 1 GiB device copy.",
+             "Each SND decompose enqueues sweeps in doubling chunks, so its last chunk also launches a few",
+             "sweeps past convergence that return at once (62 launches per bin for 47 sweeps).",
+             "Template arguments of `k_sweep_regs<k, lanes, values/lane, tau type, AND, frontier>`.", "",
+             "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
     full_avg = 0.0
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:32]:
         name = _short_kernel(r["Name"])
