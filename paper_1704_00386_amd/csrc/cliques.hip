@@ -209,12 +209,42 @@ __device__ __forceinline__ int32_t tri_in(const TriIsectArgs &t, int32_t e,
   return (int32_t)lower_bound<int32_t>(t.tri_w, t.toff[e], t.toff[e + 1], c);
 }
 
+// Orders this wave's LDS accesses around it: the lanes of a subgroup (never
+// wider than a wave) write a list into LDS that all of them then read.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copies the two lists searched for every candidate into the subgroup's LDS
+// slots when both fit (CAP entries each); returns whether they did.
+template <int G, int CAP>
+__device__ __forceinline__ bool n34_stage(const int32_t *__restrict__ col,
+                                          int64_t b1, int64_t n1, int64_t b2,
+                                          int64_t n2, int32_t *l1, int32_t *l2,
+                                          int sl) {
+  if (CAP == 0 || n1 > CAP || n2 > CAP) return false;
+  wave_lds_sync();  // the subgroup's previous searches are done
+  for (int i = sl; i < n1; i += G) l1[i] = col[b1 + i];
+  for (int i = sl; i < n2; i += G) l2[i] = col[b2 + i];
+  wave_lds_sync();
+  return true;
+}
+
+// Binary searches of the (3,4) intersection take one dependent load per
+// step; from LDS instead of the L2 they are several times shorter.
+constexpr int n34_cap(int G) { return G == 16 ? 128 : G == 64 ? 512 : 0; }
+
 // (3,4) count pass: the 4-cliques containing triangle (u,v,w), i.e. the x
 // in N(u) & N(v) & N(w); G lanes stride over the shortest of the three
-// lists and binary-search the other two.
+// lists and binary-search the other two (held in LDS when they fit).
 template <int G>
 __global__ __launch_bounds__(256) void k_n34_count(TriIsectArgs a) {
+  constexpr int CAP = n34_cap(G);
+  __shared__ int32_t lds[256 / G][2][CAP > 0 ? CAP : 1];
   const int sl = lane_id() % G;
+  int32_t *l1 = lds[threadIdx.x / G][0], *l2 = lds[threadIdx.x / G][1];
   const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
   for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
        gsub < a.nitems; gsub += nsub) {  // uniform within the subgroup
@@ -228,13 +258,24 @@ __global__ __launch_bounds__(256) void k_n34_count(TriIsectArgs a) {
     if (en[1] - b[1] < en[sh] - b[sh]) sh = 1;
     if (en[2] - b[2] < en[sh] - b[sh]) sh = 2;
     const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
+    const int64_t n1 = en[o1] - b[o1], n2 = en[o2] - b[o2];
     int found = 0;
-    for (int64_t j = b[sh] + sl; j < en[sh]; j += G) {
-      const int32_t x = a.col[j];
-      const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
-      if (q1 >= en[o1] || a.col[q1] != x) continue;
-      const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
-      found += q2 < en[o2] && a.col[q2] == x;
+    if (n34_stage<G, CAP>(a.col, b[o1], n1, b[o2], n2, l1, l2, sl)) {
+      for (int64_t j = b[sh] + sl; j < en[sh]; j += G) {
+        const int32_t x = a.col[j];
+        const int64_t q1 = lower_bound<int32_t>(l1, 0, n1, x);
+        if (q1 >= n1 || l1[q1] != x) continue;
+        const int64_t q2 = lower_bound<int32_t>(l2, 0, n2, x);
+        found += q2 < n2 && l2[q2] == x;
+      }
+    } else {
+      for (int64_t j = b[sh] + sl; j < en[sh]; j += G) {
+        const int32_t x = a.col[j];
+        const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
+        if (q1 >= en[o1] || a.col[q1] != x) continue;
+        const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
+        found += q2 < en[o2] && a.col[q2] == x;
+      }
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) found += __shfl_xor(found, off, G);
@@ -732,7 +773,10 @@ void run_n34_count(TriIsectArgs a, const int32_t *items, const int64_t *bin_off,
 template <int G>
 __global__ __launch_bounds__(256) void k_n34_fill(TriIsectArgs a,
                                                   unsigned long long *cursor) {
+  constexpr int CAP = n34_cap(G);
+  __shared__ int32_t lds[256 / G][2][CAP > 0 ? CAP : 1];
   const int sl = lane_id() % G;
+  int32_t *l1 = lds[threadIdx.x / G][0], *l2 = lds[threadIdx.x / G][1];
   const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
   for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
        gsub < a.nitems; gsub += nsub) {
@@ -751,12 +795,21 @@ __global__ __launch_bounds__(256) void k_n34_fill(TriIsectArgs a,
     const int32_t euw = a.eid[lower_bound<int32_t>(a.col, b[0], en[0], w)];
     const int32_t evw = a.eid[lower_bound<int32_t>(a.col, b[1], en[1], w)];
     const int32_t it = a.inv[t];
+    const int64_t n1 = en[o1] - b[o1], n2 = en[o2] - b[o2];
+    const bool staged = n34_stage<G, CAP>(a.col, b[o1], n1, b[o2], n2, l1, l2, sl);
     for (int64_t j = start + sl; j < en[sh]; j += G) {
       const int32_t x = a.col[j];
-      const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
-      if (q1 >= en[o1] || a.col[q1] != x) continue;
-      const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
-      if (q2 >= en[o2] || a.col[q2] != x) continue;
+      if (staged) {
+        const int64_t q1 = lower_bound<int32_t>(l1, 0, n1, x);
+        if (q1 >= n1 || l1[q1] != x) continue;
+        const int64_t q2 = lower_bound<int32_t>(l2, 0, n2, x);
+        if (q2 >= n2 || l2[q2] != x) continue;
+      } else {
+        const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
+        if (q1 >= en[o1] || a.col[q1] != x) continue;
+        const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
+        if (q2 >= en[o2] || a.col[q2] != x) continue;
+      }
       const int32_t id[4] = {it, a.inv[tri_in(a, e, x)], a.inv[tri_in(a, euw, x)],
                              a.inv[tri_in(a, evw, x)]};
 #pragma unroll
