@@ -51,6 +51,12 @@
  *                         (default 16; 0: from the second sweep on).
  *   ND_BATCH_NO_GRAPH=1   batched epochs are launched one by one instead of
  *                         through captured HIP graphs.
+ *   ND_TRUSS_NO_LDS=1     the k-truss builder intersects the 64-lane bin
+ *                         without the per-source LDS copy (the path taken
+ *                         when an out-list exceeds 5120 entries).
+ *   ND_TRUSS_NO_TRIBUF=1  the k-truss builder intersects twice instead of
+ *                         recording the triangles (the path taken when the
+ *                         buffer does not fit the memory budget).
  */
 #ifndef ND_H
 #define ND_H

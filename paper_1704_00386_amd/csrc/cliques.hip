@@ -924,7 +924,8 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   DArr<int2> tri_buf;
   const size_t tri_bytes = sizeof(int2) * (size_t)std::max<int64_t>(tri_cap, 1);
   const size_t live = al.live_bytes();
-  if (tri_cap <= kTriBufMax &&
+  const char *no_buf = getenv("ND_TRUSS_NO_TRIBUF");
+  if (!(no_buf && no_buf[0] == '1') && tri_cap <= kTriBufMax &&
       (al.budget() == 0 ||
        (live < al.budget() && tri_bytes <= (al.budget() - live) / 4))) {
     try {
@@ -952,7 +953,8 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
     ND_HIP(hipMemcpyAsync(&hmax, mx.p, sizeof hmax, hipMemcpyDeviceToHost, s));
     ND_HIP(hipStreamSynchronize(s));
     constexpr int kMaxLdsEntries = 5120;  // 60 KiB: three int32 arrays
-    if (hmax <= kMaxLdsEntries) {
+    const char *no_lds = getenv("ND_TRUSS_NO_LDS");
+    if (hmax <= kMaxLdsEntries && !(no_lds && no_lds[0] == '1')) {
       a.lds_cap = std::max(hmax, 1);
       const int32_t *it3 = items.p + bin_off[3];
       DArr<int32_t> flag3(al, n3);
