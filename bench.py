@@ -728,7 +728,27 @@ def main():
         cb = cpu_baseline(raw, KIND, args.cpu_budget)
         cb["time_to_exact_s_est"] = full_equiv / cb["value"]
         line["cpu_baseline"] = cb
+    peel = recorded_peeling("cl20")
+    if peel is not None:
+        line["cpu_peeling_recorded"] = {
+            "s": peel, "step_speedup": peel / (ms_per_step * 1e-3),
+            "what": "the oracle's Alg. Peeling on this workload (parallel "
+                    "S-degree count, sequential peeling), timed when the "
+                    "full-size kappa digests in tests/golden/full_size.json "
+                    "were written, on that machine's cores (not this run's "
+                    "host): context, not the baseline"}
     print(json.dumps(line), flush=True)
+
+
+def recorded_peeling(name: str):
+    """Seconds the oracle's peeling took on a workload when its full-size
+    digest was recorded, or None."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                          "full_size.json")))
+        return float(rec[name]["oracle_seconds"])
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 if __name__ == "__main__":
