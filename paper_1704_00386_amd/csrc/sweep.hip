@@ -30,9 +30,10 @@
 //                  are binned coarsely and the coarse bin holding H is refined
 //                  with a second gather.
 // SND reads tau_t and writes tau_{t+1} (double buffer, race free, so every
-// iterate is deterministic).  AND reads and writes one array in place; its
-// neighbour reads bypass the per-CU cache so that they see other workgroups'
-// recent writes, which only ever lower values (Section 4.2).
+// iterate is deterministic).  AND reads and writes one array in place with
+// relaxed workgroup-scope atomics: a value read may predate another
+// workgroup's write in the same sweep but never the sweep's start, and
+// writes only ever lower values (Section 4.2; see load_tau).
 #include <algorithm>
 
 #include "sweep_dev.h"
