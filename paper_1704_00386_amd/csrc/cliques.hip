@@ -9,13 +9,17 @@
 //   (3,4):         first the triangles (u,v,w), u<v<w, numbered
 //                  lexicographically; then for triangle (u,v,w) and every x
 //                  in N(u) & N(v) & N(w), the ids of the triangles {u,v,x},
-//                  {u,w,x} and {v,w,x}.
-// Both use two passes: count, then (once every S-degree is known and the
-// internal numbering is fixed, see build_layout) fill, which writes each list
-// straight into its place in the internal order, with internal ids, and no
-// atomics.  Each list is in ascending order of its extension vertex, so the
-// output is deterministic.  The k-core incidence is the CSR itself,
-// re-indexed the same way.
+//                  {u,w,x} and {v,w,x};
+//   (1,3), (2,4):  from the triangle list (see below).
+// Each is two passes: count, then (once every S-degree is known and the
+// internal numbering is fixed, see build_layout) fill, which writes the lists
+// in the internal order with internal ids.  The k-truss builder finds every
+// triangle once, from its edge oriented by degree, and the (3,4) fill every
+// 4-clique once, from its lowest triangle; entries that go to other lists
+// take their slots from cursors (atomic, or per workgroup in LDS), so the
+// order inside a list varies from run to run.  Nothing computed from a list
+// depends on its order (min and H are order-free).  The k-core incidence is
+// the CSR itself, re-indexed the same way.
 //
 // Work per item is proportional to the shortest adjacency list involved:
 // each element of it is binary-searched in the others.  Items are binned by
