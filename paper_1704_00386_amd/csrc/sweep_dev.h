@@ -423,16 +423,31 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
   const int nb = (int)(((int64_t)c + w) / w);  // bins for values 0..c
   for (int x = t; x < nb; x += kBlockThreads) hist[x] = 0;
   __syncthreads();
+  // One workgroup walks a long list: each thread keeps kU gathers in flight
+  // (the ids, then the tau values, of kU list entries), or the walk is a
+  // chain of dependent loads.  Values >= c are only counted (they enter the
+  // search below as its starting suffix).
+  constexpr int kU = 8;
   int64_t ge = 0;
-  for (int64_t j = t; j < d; j += kBlockThreads) {
-    const int32_t rho = gather_rho<K, T, AND>(inc_ids, b + j, tau_in);
-    ge += rho >= c;
-    atomicAdd(&hist[min(rho, c) / w], 1);
+  for (int64_t j0 = t; j0 < d; j0 += (int64_t)kBlockThreads * kU) {
+    int32_t rho[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int64_t j = j0 + (int64_t)u * kBlockThreads;
+      rho[u] = j < d ? gather_rho<K, T, AND>(inc_ids, b + j, tau_in) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      if (rho[u] >= c)
+        ge++;
+      else if (rho[u] >= 0)
+        atomicAdd(&hist[rho[u] / w], 1);
+    }
   }
   ge = block_sum(ge);
   int32_t h = c;
   if (ge < c) {
-    const int i = suffix_search<kBlockThreads>(hist, nb, 0, 0, w);
+    const int i = suffix_search<kBlockThreads>(hist, nb, ge, 0, w);
     if (w == 1) {
       h = i;
     } else {
@@ -442,12 +457,20 @@ __device__ bool update_block(const int64_t *__restrict__ inc_off,
       for (int x = t; x < nfine; x += kBlockThreads) hist[x] = 0;
       __syncthreads();
       int64_t above = 0;
-      for (int64_t j = t; j < d; j += kBlockThreads) {
-        const int32_t rho = min(gather_rho<K, T, AND>(inc_ids, b + j, tau_in), c);
-        if (rho >= x1)
-          above++;
-        else if (rho >= x0)
-          atomicAdd(&hist[rho - x0], 1);
+      for (int64_t j0 = t; j0 < d; j0 += (int64_t)kBlockThreads * kU) {
+        int32_t rho[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+          const int64_t j = j0 + (int64_t)u * kBlockThreads;
+          rho[u] = j < d ? min(gather_rho<K, T, AND>(inc_ids, b + j, tau_in), c) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+          if (rho[u] >= x1)
+            above++;
+          else if (rho[u] >= x0)
+            atomicAdd(&hist[rho[u] - x0], 1);
+        }
       }
       above = block_sum(above);
       const int f = suffix_search<kBlockThreads>(hist, nfine, above, x0, 1);
