@@ -71,6 +71,32 @@ __device__ __forceinline__ int32_t gather_rho(const int32_t *__restrict__ ids,
   }
 }
 
+// gather_rho for SND with the frontier: also the members of the s-clique
+// that hold the minimum (bit x set when the x-th listed id has tau = rho).
+template <int K, typename T>
+__device__ __forceinline__ int32_t gather_rho_arg(const int32_t *__restrict__ ids,
+                                                  int64_t j, const T *tau,
+                                                  uint32_t *arg) {
+  int32_t v[K];
+  if constexpr (K == 2) {
+    const int2 p = *reinterpret_cast<const int2 *>(ids + 2 * j);
+    v[0] = load_tau<T, false>(tau + p.x);
+    v[1] = load_tau<T, false>(tau + p.y);
+  } else {
+    const int32_t *q = ids + (int64_t)K * j;
+#pragma unroll
+    for (int x = 0; x < K; x++) v[x] = load_tau<T, false>(tau + q[x]);
+  }
+  int32_t r = v[0];
+#pragma unroll
+  for (int x = 1; x < K; x++) r = min(r, v[x]);
+  uint32_t a = 0;
+#pragma unroll
+  for (int x = 0; x < K; x++) a |= (uint32_t)(v[x] == r) << x;
+  *arg = a;
+  return r;
+}
+
 template <int G>
 __device__ __forceinline__ int subgroup_sum(int x) {
 #pragma unroll
@@ -200,6 +226,64 @@ __device__ __forceinline__ void notify(const int32_t *__restrict__ ids,
   }
 }
 
+// The SND test of notify() from the values the update already gathered: R'
+// passes it exactly when it holds the minimum rho of S and h < rho <= told,
+// so the members to mark are those of the slots with rho in (h, told] whose
+// bit is set in the argmin mask (bit m*K + x for slot m, member x; K = 1
+// needs no mask).  Only their ids are read again, no tau.
+template <int K, int G, int M>
+__device__ __forceinline__ void notify_kept(const int32_t *__restrict__ ids,
+                                            int64_t b, int64_t d, int sl,
+                                            const int32_t *rho,
+                                            const uint32_t *amask, int32_t told,
+                                            int32_t h, uint8_t *act_next,
+                                            uint8_t stamp_next,
+                                            uint8_t *sum_next) {
+#pragma unroll
+  for (int m = 0; m < M; m++) {
+    const int64_t j = sl + (int64_t)m * G;
+    if (j < d && h < rho[m] && rho[m] <= told) {
+      const int32_t *q = ids + K * (b + j);
+#pragma unroll
+      for (int x = 0; x < K; x++) {
+        const int bit = m * K + x;
+        if (K == 1 || ((amask[bit >> 5] >> (bit & 31)) & 1u)) {
+          const int32_t r = q[x];
+          act_next[r] = stamp_next;
+          if (sum_next) sum_next[r >> kGroupShift] = stamp_next;
+        }
+      }
+    }
+  }
+}
+
+// The same test for lanes holding many values (no argmin mask kept): only the
+// slots with rho in (h, told] read their members' tau again.
+template <int K, int G, int M, typename T>
+__device__ __forceinline__ void notify_slots(const int32_t *__restrict__ ids,
+                                             int64_t b, int64_t d, int sl,
+                                             const int32_t *rho, int32_t told,
+                                             int32_t h, const T *tau,
+                                             uint8_t *act_next,
+                                             uint8_t stamp_next,
+                                             uint8_t *sum_next) {
+#pragma unroll
+  for (int m = 0; m < M; m++) {
+    const int64_t j = sl + (int64_t)m * G;
+    if (j < d && h < rho[m] && rho[m] <= told) {
+      const int32_t *q = ids + K * (b + j);
+#pragma unroll
+      for (int x = 0; x < K; x++) {
+        const int32_t r = q[x];
+        if (K == 1 || load_tau<T, false>(tau + r) == rho[m]) {
+          act_next[r] = stamp_next;
+          if (sum_next) sum_next[r >> kGroupShift] = stamp_next;
+        }
+      }
+    }
+  }
+}
+
 // Bit position of the t-th set bit (t counted from 0) of m; t < popc(m).
 // Binary lifting: the largest p with popc(m below bit p) <= t is that bit.
 __device__ __forceinline__ int nth_set_bit(uint64_t m, int t) {
@@ -253,11 +337,30 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
       c = cap_by_tau ? told : (int32_t)d;
     }
   }
+  // SND with the frontier keeps which members hold each minimum, so that
+  // notifying needs no second gather (notify_kept).  Not with 32 values per
+  // lane: keeping them past the search costs that kernel occupancy.
+  constexpr bool kKept = FR && !AND && M <= 4;
+  constexpr bool kKeep = kKept && K > 1;
+  constexpr int kMaskWords = kKeep ? (K * M + 31) / 32 : 1;
   int32_t rho[M];
+  uint32_t amask[kMaskWords];
+#pragma unroll
+  for (int w = 0; w < kMaskWords; w++) amask[w] = 0;
 #pragma unroll
   for (int m = 0; m < M; m++) {
     const int64_t j = sl + (int64_t)m * G;
-    rho[m] = (j < d) ? gather_rho<K, T, AND>(inc_ids, b + j, tau_in) : -1;
+    if (kKeep) {
+      uint32_t a = 0;
+      rho[m] = (j < d) ? gather_rho_arg<K, T>(inc_ids, b + j, tau_in, &a) : -1;
+#pragma unroll
+      for (int x = 0; x < K; x++) {
+        const int bit = m * K + x;
+        amask[bit >> 5] |= ((a >> x) & 1u) << (bit & 31);
+      }
+    } else {
+      rho[m] = (j < d) ? gather_rho<K, T, AND>(inc_ids, b + j, tau_in) : -1;
+    }
   }
   const int cnt = count_ge<G, M>(rho, c);
   const int32_t h = cnt >= c ? c : hindex_search<G, M>(rho, c);
@@ -270,8 +373,15 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
       act_next[R] = next;
       if (sum_next) sum_next[R >> kGroupShift] = next;
     }
-    notify<K, T, AND>(inc_ids, b, d, sl, G, told, h, tau_in, act_next, next,
-                      sum_next);
+    if (kKept)
+      notify_kept<K, G, M>(inc_ids, b, d, sl, rho, amask, told, h, act_next,
+                           next, sum_next);
+    else if (!AND)
+      notify_slots<K, G, M, T>(inc_ids, b, d, sl, rho, told, h, tau_in,
+                               act_next, next, sum_next);
+    else
+      notify<K, T, AND>(inc_ids, b, d, sl, G, told, h, tau_in, act_next, next,
+                        sum_next);
   }
   *evald = lead && eval;
   return lead && ch;
