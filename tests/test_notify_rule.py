@@ -8,8 +8,10 @@ R' that a changed R marks through an s-clique S with
 (h = tau_{t+1}(R)); in-place sweeps use the looser test h < tau(R') and
 h <= tau(Q).  For the iterates to be exact, every r-clique whose value
 changes at sweep t+1 has to be among those recomputed.  This checks that on
-the oracle's iterates and incidence lists, for every kind, and that the rules
-do skip work (the frontier is not vacuous).
+the oracle's iterates and incidence lists, for every kind, that the rules do
+skip work (the frontier is not vacuous), and that the SND rule marks exactly
+the members holding their s-clique's minimum rho when h < rho <= tau_t(R),
+the form the device evaluates from the values it gathered.
 """
 
 import numpy as np
@@ -60,6 +62,19 @@ def marked(R, O, prev, cur, loose):
     return flags
 
 
+def marked_by_minimum(R, O, prev, cur):
+    """The SND rule as the device evaluates it from its own gathers: the
+    members holding the minimum rho of the s-clique, when h < rho <= told."""
+    flags = np.zeros(prev.size, bool)
+    ch = cur[R] != prev[R]
+    vals = prev[O]
+    rho = vals.min(axis=1)
+    ok = ch & (cur[R] < rho) & (rho <= prev[R])
+    for x in range(O.shape[1]):
+        flags[O[ok & (vals[:, x] == rho), x]] = True
+    return flags
+
+
 @pytest.mark.parametrize("name,raw", list(graphs()), ids=lambda x: x if
                          isinstance(x, str) else "")
 @pytest.mark.parametrize("r,s", KINDS)
@@ -74,6 +89,8 @@ def test_frontier_rules_cover_every_change(name, raw, r, s):
         prev, cur, nxt = seq[t - 1], seq[t], seq[t + 1]
         changed = cur != prev
         need = nxt != cur
+        assert np.array_equal(marked(R, O, prev, cur, False),
+                              marked_by_minimum(R, O, prev, cur))
         for loose in (False, True):
             act = marked(R, O, prev, cur, loose) | changed
             assert not np.any(need & ~act), (name, r, s, t, loose)
