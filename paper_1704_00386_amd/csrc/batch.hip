@@ -49,8 +49,11 @@ __host__ __device__ constexpr int rclq_per_pass(int type) {
 
 // Largest incidence count of one pass, in units of 1024: passes of the
 // G-bins cover at most 1024 incidences (R per pass x largest d_s of the
-// bin); a pass of the wave bin (4 R of d_s < 2048) up to 8x that.
-constexpr int pass_units(int type) { return type == kBinWave ? 8 : 1; }
+// bin); a pass of the wave bins (4 R of d_s < 2048, 1025, 513) up to 8x,
+// 4x and 2x that.
+constexpr int pass_units(int type) {
+  return type == kBinWave ? 8 : type == kBinWave16 ? 4 : type == kBinWave8 ? 2 : 1;
+}
 
 __device__ __forceinline__ bool graph_live(const BGraph &G, int64_t e,
                                            int64_t *local) {
@@ -130,6 +133,16 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
                                          tile.hi, wv, nw, act, act_next, stamp,
                                          &n_ch, &n_ev);
           break;
+        case kBinWave8:
+          sweep_sparse<K, 64, 8, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                         tile.hi, wv, nw, act, act_next, stamp,
+                                         &n_ch, &n_ev);
+          break;
+        case kBinWave16:
+          sweep_sparse<K, 64, 16, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                          tile.hi, wv, nw, act, act_next, stamp,
+                                          &n_ch, &n_ev);
+          break;
         default:  // kBinWave
           sweep_sparse<K, 64, 32, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                           tile.hi, wv, nw, act, act_next, stamp,
@@ -165,6 +178,18 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
           const int64_t R = base + threadIdx.x / 64;
           ch = update_regs<K, 64, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
                                              R, R < tile.hi, act, act_next, stamp, &ev);
+          break;
+        }
+        case kBinWave8: {
+          const int64_t R = base + threadIdx.x / 64;
+          ch = update_regs<K, 64, 8, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                             R, R < tile.hi, act, act_next, stamp, &ev);
+          break;
+        }
+        case kBinWave16: {
+          const int64_t R = base + threadIdx.x / 64;
+          ch = update_regs<K, 64, 16, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                              R, R < tile.hi, act, act_next, stamp, &ev);
           break;
         }
         default: {  // kBinWave

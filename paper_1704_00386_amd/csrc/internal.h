@@ -127,7 +127,9 @@ namespace nd {
 // order, with their d_s ranges:
 enum SweepBin : int {
   kBinBlock = 0,  // d_s >= 2048:  one workgroup per r-clique, LDS histogram
-  kBinWave,       // 257..2047:    one wave, 32 values per lane in registers
+  kBinWave,       // 1025..2047:   one wave, 32 values per lane in registers
+  kBinWave16,     // 513..1024:    one wave, 16 values per lane
+  kBinWave8,      // 257..512:     one wave, 8 values per lane
   kBinG64,        // 65..256:      one wave, 4 values per lane
   kBinG16,        // 17..64:       16 lanes
   kBinG4,         // 5..16:        4 lanes

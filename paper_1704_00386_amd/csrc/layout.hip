@@ -29,7 +29,9 @@ int bits_for(int64_t x) {
 
 __device__ __forceinline__ int bin_of(int64_t d) {
   return d >= 2048 ? kBinBlock
-       : d >= 257 ? kBinWave
+       : d >= 1025 ? kBinWave
+       : d >= 513 ? kBinWave16
+       : d >= 257 ? kBinWave8
        : d >= 65  ? kBinG64
        : d >= 17  ? kBinG16
        : d >= 5   ? kBinG4
@@ -171,8 +173,8 @@ void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
     DArr<uint64_t> keys(al, nr), tmp(al, nr);
     k_layout_keys<<<grid_for(nr, 256), 256, 0, s>>>(cnt, nr, rb, keys.p);
     ND_LAUNCHED();
-    static_assert(kNumBins <= 8, "bin index must fit 3 key bits");
-    uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, nr, 0, rb + 3, s, al);
+    static_assert(kNumBins <= 16, "bin index must fit 4 key bits");
+    uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, nr, 0, rb + 4, s, al);
     k_layout_perm<<<grid_for(nr, 256), 256, 0, s>>>(sorted, nr, rb, cnt,
                                                      ks.perm.p, ks.inv.p,
                                                      ks.ds.p);

@@ -24,7 +24,9 @@
 //
 // Mappings by S-degree bin:
 //   d_s <= 256     G = 1/4/16/64 lanes per r-clique, 4 rho values per lane
-//   257..2047      one wave per r-clique, 32 rho values per lane
+//   257..2047      one wave per r-clique, 8 / 16 / 32 rho values per lane
+//                  (257..512 / 513..1024 / 1025..2047: fewer registers, more
+//                  waves in flight for the shorter lists)
 //   >= 2048        one 256-thread workgroup per r-clique; LDS histogram of
 //                  min(rho, c) in up to 16384 bins; for larger c the values
 //                  are binned coarsely and the coarse bin holding H is refined
@@ -165,6 +167,12 @@ void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
         break;
       case kBinWave:
         k_sweep_regs<K, 64, 32, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
+        break;
+      case kBinWave16:
+        k_sweep_regs<K, 64, 16, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
+        break;
+      case kBinWave8:
+        k_sweep_regs<K, 64, 8, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
         break;
       default: {
         const unsigned grid = (unsigned)(n < 65536 ? n : 65536);
