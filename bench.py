@@ -109,7 +109,7 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_sweep")
 
 
-FULL_SWEEP_SUFFIX = ", false, false>"  # k_sweep_regs<..., AND, frontier>
+FULL_SWEEP_SUFFIX = ", false, false>"  # k_sweep_*<..., AND, frontier>
 
 
 def _short_kernel(name: str) -> str:
@@ -144,18 +144,20 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
              "full-sweep roofline leg (SND, every r-clique recomputed each sweep), two more steps from a",
              "pinned host edge list (host_io leg) and the AND leg (frontier), after a 1 GiB device copy.",
              "Each SND decompose enqueues sweeps in doubling chunks, so its last chunk also launches a few",
-             "sweeps past convergence that return at once (62 launches per bin for 47 sweeps).",
-             "Template arguments of `k_sweep_regs<k, lanes, values/lane, tau type, AND, frontier>`.", "",
+             "sweeps past convergence that return at once (62 launches per kernel for 47 sweeps).",
+             "Template arguments of `k_sweep_regs<k, lanes, values/lane, tau type, AND, frontier>`;",
+             "`k_sweep_small<k, tau type, AND, frontier>` sweeps the bins of at most 16 values per lane",
+             "(d_s 1..1024) in one launch.", "",
              "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
     full_avg = 0.0
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:32]:
         name = _short_kernel(r["Name"])
         avg = float(r["AverageNs"]) / 1e3
-        if name.startswith("k_sweep_regs") and name.endswith(FULL_SWEEP_SUFFIX):
+        if name.startswith("k_sweep_") and name.endswith(FULL_SWEEP_SUFFIX):
             full_avg += avg
         lines.append(f"| {100 * float(r['TotalDurationNs']) / tot:.1f} | {r['Calls']} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {avg:.1f} | `{name}` |")
-    lines += ["", f"Full sweep = the `k_sweep_regs<..., false, false>` launches (one per sweep bin): "
+    lines += ["", f"Full sweep = the `k_sweep_*<..., false, false>` launches of a sweep: "
               f"{full_avg:.0f} us per sweep (sum of their averages)."]
     open(os.path.join(out_dir, "kernel_trace_cl20_truss.md"), "w").write("\n".join(lines) + "\n")
 
@@ -176,7 +178,7 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
     write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
     gib_kib = float(1 << 20)  # the copy moves 1 GiB each way
     fscale, wscale = gib_kib / fcopy, gib_kib / wcopy
-    full = sorted(k for k in fetch if k.startswith("k_sweep_regs") and k.endswith(FULL_SWEEP_SUFFIX))
+    full = sorted(k for k in fetch if k.startswith("k_sweep_") and k.endswith(FULL_SWEEP_SUFFIX))
     f_kib = sum(statistics.mean(fetch[k]) for k in full)
     w_kib = sum(statistics.mean(write.get(k, [0.0])) for k in full)
     rec = {

@@ -137,6 +137,9 @@ enum SweepBin : int {
   kBinZero,       // 0:            tau stays 0
   kNumBins
 };
+// kBinWave16 .. kBinG1: the bins swept by one launch (k_sweep_small)
+constexpr int kFirstSmall = kBinWave16;
+constexpr int kNumSmall = kBinZero - kFirstSmall;
 
 // Per-kind state of a graph: internal numbering, incidence lists, schedule.
 struct KindState {

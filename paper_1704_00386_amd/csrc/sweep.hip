@@ -78,17 +78,19 @@ __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
   if (notify && blockIdx.x == 0 && threadIdx.x == 0) a.stats->notified = 1;
 }
 
+// One bin [lo, hi) of G lanes per r-clique with M values per lane, swept by
+// the workgroups block .. of nblocks (a launch of its own, or a block range
+// of k_sweep_small).
 template <int K, int G, int M, typename T, bool AND, bool FR>
-__global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
-                                                    int64_t hi) {
-  const unsigned long long pc = prev_changed(a);
-  if (pc == 0) return;  // converged: a sweep queued past the end
-  const uint8_t *act = nullptr, *act_sum = nullptr;
-  uint8_t *act_next = nullptr, *sum_next = nullptr;
-  if (FR) frontier_mode(a, pc, &act, &act_next, &act_sum, &sum_next);
+__device__ __forceinline__ void sweep_bin(const SweepArgs &a, int64_t lo,
+                                          int64_t hi, int64_t block,
+                                          int64_t nblocks, const uint8_t *act,
+                                          uint8_t *act_next,
+                                          const uint8_t *act_sum,
+                                          uint8_t *sum_next) {
   constexpr int kPerWave = kWave / G;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t wave = (block * blockDim.x + threadIdx.x) / kWave;
+  const int64_t waves = nblocks * (blockDim.x / kWave);
   const int sub = lane_id() / G;
   const T *tin = (const T *)a.tau_in;
   T *tout = (T *)a.tau_out;
@@ -112,6 +114,67 @@ __global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
     }
   }
   stat_add_counts(a.stats, n_ch, n_ev);
+}
+
+template <int K, int G, int M, typename T, bool AND, bool FR>
+__global__ __launch_bounds__(256) void k_sweep_regs(SweepArgs a, int64_t lo,
+                                                    int64_t hi) {
+  const unsigned long long pc = prev_changed(a);
+  if (pc == 0) return;  // converged: a sweep queued past the end
+  const uint8_t *act = nullptr, *act_sum = nullptr;
+  uint8_t *act_next = nullptr, *sum_next = nullptr;
+  if (FR) frontier_mode(a, pc, &act, &act_next, &act_sum, &sum_next);
+  sweep_bin<K, G, M, T, AND, FR>(a, lo, hi, blockIdx.x, gridDim.x, act,
+                                 act_next, act_sum, sum_next);
+}
+
+// The bins whose lanes hold at most 16 values (513..1024 down to 1..4) in
+// one launch: their registers are alike enough that one occupancy suits
+// all, a sparse sweep pays one launch for them instead of six, and the bins
+// run side by side instead of each draining the chip before the next starts.
+// Bin i (kFirstSmall + i) gets the workgroups [first[i], first[i+1]).
+struct SmallBins {
+  int64_t lo[kNumSmall], hi[kNumSmall];
+  unsigned first[kNumSmall + 1];
+};
+
+template <int K, typename T, bool AND, bool FR>
+__global__ __launch_bounds__(256) void k_sweep_small(SweepArgs a, SmallBins sb) {
+  const unsigned long long pc = prev_changed(a);
+  if (pc == 0) return;
+  const uint8_t *act = nullptr, *act_sum = nullptr;
+  uint8_t *act_next = nullptr, *sum_next = nullptr;
+  if (FR) frontier_mode(a, pc, &act, &act_next, &act_sum, &sum_next);
+  int i = 0;
+  while (i + 1 < kNumSmall && blockIdx.x >= sb.first[i + 1]) i++;
+  const int64_t block = blockIdx.x - sb.first[i];
+  const int64_t nblocks = sb.first[i + 1] - sb.first[i];
+  switch (kFirstSmall + i) {
+    case kBinWave16:
+      sweep_bin<K, 64, 16, T, AND, FR>(a, sb.lo[i], sb.hi[i], block, nblocks,
+                                       act, act_next, act_sum, sum_next);
+      break;
+    case kBinWave8:
+      sweep_bin<K, 64, 8, T, AND, FR>(a, sb.lo[i], sb.hi[i], block, nblocks,
+                                      act, act_next, act_sum, sum_next);
+      break;
+    case kBinG64:
+      sweep_bin<K, 64, 4, T, AND, FR>(a, sb.lo[i], sb.hi[i], block, nblocks,
+                                      act, act_next, act_sum, sum_next);
+      break;
+    case kBinG16:
+      sweep_bin<K, 16, 4, T, AND, FR>(a, sb.lo[i], sb.hi[i], block, nblocks,
+                                      act, act_next, act_sum, sum_next);
+      break;
+    case kBinG4:
+      sweep_bin<K, 4, 4, T, AND, FR>(a, sb.lo[i], sb.hi[i], block, nblocks,
+                                     act, act_next, act_sum, sum_next);
+      break;
+    default:  // kBinG1
+      sweep_bin<K, 1, 4, T, AND, FR>(a, sb.lo[i], sb.hi[i], block, nblocks,
+                                     act, act_next, act_sum, sum_next);
+      break;
+  }
 }
 
 template <int K, typename T, bool AND, bool FR>
@@ -149,30 +212,12 @@ inline unsigned regs_grid(const SweepArgs &a, int64_t n, int G) {
 
 template <int K, typename T, bool AND, bool FR>
 void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
-  for (int bin = kBinBlock; bin < kBinZero; bin++) {
+  for (int bin = kBinBlock; bin < kFirstSmall; bin++) {
     const int64_t lo = ks.bin_lo[bin], hi = ks.bin_hi[bin], n = hi - lo;
     if (n == 0) continue;
     switch (bin) {
-      case kBinG1:
-        k_sweep_regs<K, 1, 4, T, AND, FR><<<regs_grid(a, n, 1), 256, 0, s>>>(a, lo, hi);
-        break;
-      case kBinG4:
-        k_sweep_regs<K, 4, 4, T, AND, FR><<<regs_grid(a, n, 4), 256, 0, s>>>(a, lo, hi);
-        break;
-      case kBinG16:
-        k_sweep_regs<K, 16, 4, T, AND, FR><<<regs_grid(a, n, 16), 256, 0, s>>>(a, lo, hi);
-        break;
-      case kBinG64:
-        k_sweep_regs<K, 64, 4, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
-        break;
       case kBinWave:
         k_sweep_regs<K, 64, 32, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
-        break;
-      case kBinWave16:
-        k_sweep_regs<K, 64, 16, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
-        break;
-      case kBinWave8:
-        k_sweep_regs<K, 64, 8, T, AND, FR><<<regs_grid(a, n, 64), 256, 0, s>>>(a, lo, hi);
         break;
       default: {
         const unsigned grid = (unsigned)(n < 65536 ? n : 65536);
@@ -180,6 +225,21 @@ void launch_bins(const KindState &ks, const SweepArgs &a, hipStream_t s) {
         break;
       }
     }
+    ND_LAUNCHED();
+  }
+  constexpr int kLanes[kNumSmall] = {64, 64, 64, 16, 4, 1};  // G of each small bin
+  SmallBins sb{};
+  int64_t total = 0;
+  for (int i = 0; i < kNumSmall; i++) {
+    const int bin = kFirstSmall + i;
+    sb.lo[i] = ks.bin_lo[bin];
+    sb.hi[i] = ks.bin_hi[bin];
+    sb.first[i] = (unsigned)total;
+    if (sb.hi[i] > sb.lo[i]) total += regs_grid(a, sb.hi[i] - sb.lo[i], kLanes[i]);
+  }
+  sb.first[kNumSmall] = (unsigned)total;
+  if (total > 0) {
+    k_sweep_small<K, T, AND, FR><<<(unsigned)total, 256, 0, s>>>(a, sb);
     ND_LAUNCHED();
   }
 }
