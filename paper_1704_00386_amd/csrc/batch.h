@@ -45,8 +45,9 @@ struct BState {
   int32_t ntiles;
   int32_t nhubs;
   int32_t ng;
-  int32_t pad;
-  unsigned int counters[kCounterRing];
+  int32_t nwide;  // tiles [0, nwide): 16 or 32 values per lane (k_batch_sweep<WIDE>)
+  unsigned int counters[kCounterRing];         // tile counters, wide kernel
+  unsigned int counters_narrow[kCounterRing];  // the other tiles' kernel
 };
 
 struct BatchConfig {
@@ -129,7 +130,7 @@ class Batch {
   DArr<BState> state_;
   DArr<unsigned long long> poll_buf_;
   int64_t gs_cap_ = 0, tiles_cap_ = 0, hubs_cap_ = 0, poll_cap_ = 0;
-  int ntiles_ = 0, nhubs_ = 0, ng_ = 0;
+  int ntiles_ = 0, nhubs_ = 0, ng_ = 0, nwide_ = 0;
   int64_t work_ = 0;
   int64_t epoch_ = 0;
   int64_t dead_tiles_ = 0;  // tiles of finished members still in the table

@@ -84,20 +84,26 @@ __device__ __forceinline__ void graph_frontier(const BGraph &G, int64_t local,
   if (notify && threadIdx.x == 0) sst->notified = 1;
 }
 
-template <int K, typename T, bool AND, bool FR>
+// One epoch's tiles, pulled from a counter.  Two instances share the work:
+// WIDE takes the tiles of the bins of 16 and 32 values per lane (tiles
+// [0, nwide)), the other one every other bin, so that the registers of the
+// wide lanes do not set the occupancy of the rest.
+template <int K, typename T, bool AND, bool FR, bool WIDE>
 __global__ __launch_bounds__(256) void k_batch_sweep(
     const BGraph *__restrict__ gs, const BTile *__restrict__ tiles,
     BState *__restrict__ st) {
   __shared__ int s_tile;
   const int64_t e = st->epoch;
-  const int ntiles = st->ntiles;
-  unsigned int *counter = &st->counters[e % kCounterRing];
+  const int t_lo = WIDE ? 0 : st->nwide;
+  const int t_hi = WIDE ? st->nwide : st->ntiles;
+  unsigned int *counter = WIDE ? &st->counters[e % kCounterRing]
+                               : &st->counters_narrow[e % kCounterRing];
   for (;;) {
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) s_tile = t_lo + (int)atomicAdd(counter, 1u);
     __syncthreads();
     const int ti = s_tile;
     __syncthreads();
-    if (ti >= ntiles) break;
+    if (ti >= t_hi) break;
     const BTile tile = tiles[ti];
     const BGraph &G = gs[tile.g];
     int64_t local;
@@ -112,42 +118,43 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
       // sparse sweep of the tile: flags tested a chunk at a time per wave
       unsigned long long n_ch = 0, n_ev = 0;
       const int64_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-      switch (tile.type) {
-        case kBinG1:
-          sweep_sparse<K, 1, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
-                                        tile.hi, wv, nw, act, act_next, stamp,
-                                        &n_ch, &n_ev);
-          break;
-        case kBinG4:
-          sweep_sparse<K, 4, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
-                                        tile.hi, wv, nw, act, act_next, stamp,
-                                        &n_ch, &n_ev);
-          break;
-        case kBinG16:
-          sweep_sparse<K, 16, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
-                                         tile.hi, wv, nw, act, act_next, stamp,
-                                         &n_ch, &n_ev);
-          break;
-        case kBinG64:
-          sweep_sparse<K, 64, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
-                                         tile.hi, wv, nw, act, act_next, stamp,
-                                         &n_ch, &n_ev);
-          break;
-        case kBinWave8:
-          sweep_sparse<K, 64, 8, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
-                                         tile.hi, wv, nw, act, act_next, stamp,
-                                         &n_ch, &n_ev);
-          break;
-        case kBinWave16:
-          sweep_sparse<K, 64, 16, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
-                                          tile.hi, wv, nw, act, act_next, stamp,
-                                          &n_ch, &n_ev);
-          break;
-        default:  // kBinWave
+      if constexpr (WIDE) {
+        if (tile.type == kBinWave)
           sweep_sparse<K, 64, 32, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                           tile.hi, wv, nw, act, act_next, stamp,
                                           &n_ch, &n_ev);
-          break;
+        else
+          sweep_sparse<K, 64, 16, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                          tile.hi, wv, nw, act, act_next, stamp,
+                                          &n_ch, &n_ev);
+      } else {
+        switch (tile.type) {
+          case kBinG1:
+            sweep_sparse<K, 1, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                          tile.hi, wv, nw, act, act_next, stamp,
+                                          &n_ch, &n_ev);
+            break;
+          case kBinG4:
+            sweep_sparse<K, 4, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                          tile.hi, wv, nw, act, act_next, stamp,
+                                          &n_ch, &n_ev);
+            break;
+          case kBinG16:
+            sweep_sparse<K, 16, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                           tile.hi, wv, nw, act, act_next, stamp,
+                                           &n_ch, &n_ev);
+            break;
+          case kBinG64:
+            sweep_sparse<K, 64, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                           tile.hi, wv, nw, act, act_next, stamp,
+                                           &n_ch, &n_ev);
+            break;
+          default:  // kBinWave8
+            sweep_sparse<K, 64, 8, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
+                                           tile.hi, wv, nw, act, act_next, stamp,
+                                           &n_ch, &n_ev);
+            break;
+        }
       }
       stat_add_counts(sst, n_ch, n_ev);
       continue;
@@ -155,48 +162,46 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
     const int per = rclq_per_pass(tile.type);
     for (int64_t base = tile.lo; base < tile.hi; base += per) {
       bool ch = false, ev = false;
-      switch (tile.type) {
-        case kBinG1: {
-          const int64_t R = base + threadIdx.x;
-          ch = update_regs<K, 1, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                            R < tile.hi, act, act_next, stamp, &ev);
-          break;
-        }
-        case kBinG4: {
-          const int64_t R = base + threadIdx.x / 4;
-          ch = update_regs<K, 4, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                            R < tile.hi, act, act_next, stamp, &ev);
-          break;
-        }
-        case kBinG16: {
-          const int64_t R = base + threadIdx.x / 16;
-          ch = update_regs<K, 16, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                             R, R < tile.hi, act, act_next, stamp, &ev);
-          break;
-        }
-        case kBinG64: {
-          const int64_t R = base + threadIdx.x / 64;
-          ch = update_regs<K, 64, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                             R, R < tile.hi, act, act_next, stamp, &ev);
-          break;
-        }
-        case kBinWave8: {
-          const int64_t R = base + threadIdx.x / 64;
-          ch = update_regs<K, 64, 8, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                             R, R < tile.hi, act, act_next, stamp, &ev);
-          break;
-        }
-        case kBinWave16: {
-          const int64_t R = base + threadIdx.x / 64;
-          ch = update_regs<K, 64, 16, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                              R, R < tile.hi, act, act_next, stamp, &ev);
-          break;
-        }
-        default: {  // kBinWave
-          const int64_t R = base + threadIdx.x / 64;
+      if constexpr (WIDE) {
+        const int64_t R = base + threadIdx.x / 64;
+        if (tile.type == kBinWave)
           ch = update_regs<K, 64, 32, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
                                               R, R < tile.hi, act, act_next, stamp, &ev);
-          break;
+        else
+          ch = update_regs<K, 64, 16, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                              R, R < tile.hi, act, act_next, stamp, &ev);
+      } else {
+        switch (tile.type) {
+          case kBinG1: {
+            const int64_t R = base + threadIdx.x;
+            ch = update_regs<K, 1, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                              R < tile.hi, act, act_next, stamp, &ev);
+            break;
+          }
+          case kBinG4: {
+            const int64_t R = base + threadIdx.x / 4;
+            ch = update_regs<K, 4, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
+                                              R < tile.hi, act, act_next, stamp, &ev);
+            break;
+          }
+          case kBinG16: {
+            const int64_t R = base + threadIdx.x / 16;
+            ch = update_regs<K, 16, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                               R, R < tile.hi, act, act_next, stamp, &ev);
+            break;
+          }
+          case kBinG64: {
+            const int64_t R = base + threadIdx.x / 64;
+            ch = update_regs<K, 64, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                               R, R < tile.hi, act, act_next, stamp, &ev);
+            break;
+          }
+          default: {  // kBinWave8
+            const int64_t R = base + threadIdx.x / 64;
+            ch = update_regs<K, 64, 8, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
+                                               R, R < tile.hi, act, act_next, stamp, &ev);
+            break;
+          }
         }
       }
       stat_add(sst, ch, ev);
@@ -237,7 +242,10 @@ __global__ void k_epoch_begin(const BGraph *__restrict__ gs,
   const int64_t e = st->epoch;
   const int ng = st->ng;
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 == 0) st->counters[e % kCounterRing] = 0;
+  if (i0 == 0) {
+    st->counters[e % kCounterRing] = 0;
+    st->counters_narrow[e % kCounterRing] = 0;
+  }
   for (int i = i0; i < ng; i += gridDim.x * blockDim.x) {
     const int64_t local = e - gs[i].t0;
     if (local >= 0 && local < gs[i].max_local) {
@@ -458,6 +466,7 @@ void Batch::rebuild() {
   for (int b = kBinWave; b < kBinZero; b++)
     all.insert(all.end(), ht[b].begin(), ht[b].end());
   ntiles_ = (int)all.size();
+  nwide_ = (int)(ht[kBinWave].size() + ht[kBinWave16].size());  // first in `all`
   nhubs_ = (int)hh.size();
   ng_ = (int)hg.size();
   work_ = work;
@@ -485,7 +494,7 @@ void Batch::rebuild() {
   if (!hh.empty())
     ND_HIP(hipMemcpyAsync(hubs_.p, hh.data(), sizeof(BHub) * hh.size(),
                           hipMemcpyHostToDevice, s_));
-  int32_t counts[3] = {ntiles_, nhubs_, ng_};
+  int32_t counts[4] = {ntiles_, nhubs_, ng_, nwide_};
   ND_HIP(hipMemcpyAsync(&state_.p->ntiles, counts, sizeof counts,
                         hipMemcpyHostToDevice, s_));
   ND_HIP(hipStreamSynchronize(s_));  // the host vectors go out of scope
@@ -496,8 +505,11 @@ template <int K, typename T, bool AND, bool FR>
 void Batch::launch_epoch_t() {
   k_epoch_begin<<<kBeginGrid, 256, 0, s_>>>(gs_.p, state_.p);
   ND_LAUNCHED();
-  k_batch_sweep<K, T, AND, FR><<<cfg_.grid, 256, 0, s_>>>(gs_.p, tiles_.p,
-                                                           state_.p);
+  k_batch_sweep<K, T, AND, FR, true><<<cfg_.grid, 256, 0, s_>>>(
+      gs_.p, tiles_.p, state_.p);
+  ND_LAUNCHED();
+  k_batch_sweep<K, T, AND, FR, false><<<cfg_.grid, 256, 0, s_>>>(
+      gs_.p, tiles_.p, state_.p);
   ND_LAUNCHED();
   k_batch_hubs<K, T, AND, FR><<<kHubGrid, kBlockThreads, 0, s_>>>(
       gs_.p, hubs_.p, state_.p);
@@ -649,6 +661,7 @@ int Batch::autotune() {
         z.ntiles = ntiles_;
         z.nhubs = nhubs_;
         z.ng = ng_;
+        z.nwide = nwide_;
         ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
         const float ms = time_epoch();
         if (ms < best) {
@@ -664,6 +677,7 @@ int Batch::autotune() {
     z.ntiles = ntiles_;
     z.nhubs = nhubs_;
     z.ng = ng_;
+    z.nwide = nwide_;
     ND_HIP(hipMemcpyAsync(state_.p, &z, sizeof z, hipMemcpyHostToDevice, s_));
     ND_HIP(hipStreamSynchronize(s_));
   }
