@@ -9,6 +9,7 @@ oracle and the HIP library), which never share code.
 
 from .graphs import (  # noqa: F401
     RawGraph,
+    books,
     erdos_renyi,
     chung_lu,
     chung_lu_weights,

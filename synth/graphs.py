@@ -80,6 +80,37 @@ def erdos_renyi(n: int, p: float, seed: int = 1) -> RawGraph:
     return RawGraph(n, src, dst, f"er(n={n},p={p},seed={seed})")
 
 
+def books(pages=(400, 800, 1600), page_degree: float = 8.0,
+          seed: int = 1) -> RawGraph:
+    """Disjoint "books": a spine edge (a, b) and p page vertices, each joined
+    to both a and b, with a G(p, page_degree / p) graph among the pages.
+
+    The spine edge lies in exactly p triangles and its endpoints have p + 1
+    neighbours, so the pages counts choose the S-degree of single r-cliques
+    (for example one per range of a sweep's lane mapping), while the random
+    page graph keeps the iterates non-trivial.
+    """
+    rng = _rng(seed)
+    src_parts, dst_parts = [], []
+    base = 0
+    for p in pages:
+        a, b = base, base + 1
+        x = np.arange(base + 2, base + 2 + p, dtype=np.int64)
+        src_parts += [np.array([a]), np.full(p, a), np.full(p, b)]
+        dst_parts += [np.array([b]), x, x]
+        q = page_degree / max(p, 1)
+        for i in range(p - 1):
+            hit = np.nonzero(rng.random(p - 1 - i) < q)[0]
+            if hit.size:
+                src_parts.append(np.full(hit.size, x[i]))
+                dst_parts.append(x[i + 1 + hit])
+        base += 2 + p
+    src = np.concatenate(src_parts).astype(np.int32)
+    dst = np.concatenate(dst_parts).astype(np.int32)
+    return RawGraph(base, src, dst,
+                    f"books(pages={tuple(pages)},deg={page_degree},seed={seed})")
+
+
 def _searchsorted_threads(cdf: np.ndarray, keys: np.ndarray) -> np.ndarray:
     """np.searchsorted(cdf, keys, side="right"), over chunks of keys on a
     thread pool (numpy releases the GIL inside the search)."""

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from synth import chung_lu, erdos_renyi, sbm
+from synth import books, chung_lu, erdos_renyi, sbm
 
 pytestmark = pytest.mark.gpu
 
@@ -28,6 +28,7 @@ def mixed_graphs():
         chung_lu(800, 2.4, 8.0, seed=33),
         sbm(n_comm=20, size_lo=10, size_hi=30, p_in=0.35, p_out=0.004, seed=34),
         chung_lu(20000, 2.2, 16.0, seed=35),
+        books(pages=(400, 800, 1600), page_degree=8.0, seed=36),
     ]
     # a graph with an edge in 3000 triangles and a triangle in 3000 4-cliques
     pairs = [(0, 1), (0, 2), (1, 2)] + [(x, 3 + i) for i in range(3000)

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle
-from synth import chung_lu, erdos_renyi, sbm
+from synth import books, chung_lu, erdos_renyi, sbm
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +58,9 @@ SMALL = [
     ("cl4k", lambda: chung_lu(4096, 2.1, 16.0, seed=7)),
     ("sbm40", lambda: sbm(n_comm=40, size_lo=10, size_hi=40, p_in=0.3,
                           p_out=0.002, seed=9)),
+    # spine edges (and vertices) with S-degree 400 / 800 / 1600: one r-clique
+    # in each of the 8-, 16- and 32-values-per-lane bins of the sweep
+    ("books", lambda: books(pages=(400, 800, 1600), page_degree=8.0, seed=5)),
 ]
 
 
