@@ -25,6 +25,9 @@ constexpr int kStatsRing = 1024;  // device counters kept per decomposition
 constexpr int kMaxChunk = 16;     // sweeps enqueued per host round trip
 constexpr int kGridPerCu = 64;    // sweep workgroups per CU (they stride;
                                   // measured best of 8..64 and uncapped)
+constexpr int kGridPerCuFrontier = 40;  // with the frontier: mostly sparse
+                                        // sweeps, where fewer workgroups
+                                        // scan the flags sooner (24..64)
 
 // Zero the counters of sweeps first .. first+count-1 (a kernel, not a
 // memset, so that the sequence stays capturable).
@@ -169,7 +172,7 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
       a.stats = ring.p + (t % kStatsRing);
       a.prev = t > 0 ? ring.p + ((t - 1) % kStatsRing) : nullptr;
       a.cap_by_tau = 1;
-      a.grid_cap = g->ctx->num_cu * kGridPerCu;
+      a.grid_cap = g->ctx->num_cu * (frontier ? kGridPerCuFrontier : kGridPerCu);
       if (frontier) {
         a.act = act[t & 1].p;
         a.act_next = act[(t + 1) & 1].p;
