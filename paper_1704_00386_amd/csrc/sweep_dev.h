@@ -338,8 +338,9 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
     }
   }
   // SND with the frontier keeps which members hold each minimum, so that
-  // notifying needs no second gather (notify_kept).  Not with 32 values per
-  // lane: keeping them past the search costs that kernel occupancy.
+  // notifying needs no second gather (notify_kept).  Lanes with more than 4
+  // values re-read only the qualifying s-cliques instead (notify_slots):
+  // keeping masks past the search would cost those kernels occupancy.
   constexpr bool kKept = FR && !AND && M <= 4;
   constexpr bool kKeep = kKept && K > 1;
   constexpr int kMaskWords = kKeep ? (K * M + 31) / 32 : 1;
