@@ -12,6 +12,9 @@ Pinar, "Local Algorithms for Hierarchical Dense Subgraph Discovery"):
 * ``snd``         the synchronous iteration tau_{t+1} = U tau_t from
                   tau_0 = d_s (Section 4.1, Alg. SND), every iterate kept;
 * ``and_sweep``   one in-place asynchronous sweep (Section 4.2, Alg. AND);
+* ``and_notify``  Alg. AND with its notification lines (Section 4.3), with
+                  the per-iteration counts of computations and of active
+                  r-cliques (the indicator of Section 5.1.4);
 * ``levels``      degree levels (Section 3.1);
 * ``hindex``      H of a multiset (Section 2.2).
 
@@ -249,7 +252,7 @@ class Graph:
 
     def ego_set(self, r: int, s: int, q: int) -> np.ndarray:
         """The ego network of r-clique q used for its PartialAND estimate
-        (Section 6 application): q and every r-clique sharing an s-clique
+        (the application of Section 5.3): q and every r-clique sharing an s-clique
         with q (its neighbours for r = 1, the edges of its triangles for
         r = 2, ...), sorted."""
         m = self.members(r, s, q).reshape(-1)
@@ -289,6 +292,63 @@ class Graph:
             if ch == 0:
                 break
         return tau, sweeps, seq
+
+    def and_notify(self, r: int, s: int, order=None,
+                   self_activate: bool = False, max_iters: int = 1 << 30):
+        """Alg. AND with the notification mechanism (Section 4.3), sequential
+        and in place, visiting r-cliques in `order` (default: id order, the
+        natural order).  Every r-clique starts active.  An iteration visits
+        the r-cliques that are active when it begins, marking each idle as
+        it is visited; when R's value changes to h, every R' sharing an
+        s-clique with R whose current value is at least h is marked active.
+        The loop ends after the first iteration that changes nothing.
+
+        Two readings are forced by the worked example of Section 4.3 (order
+        a..f: only `a` active after the first iteration, `a` alone processed
+        in the second, `b` and `e` in the third; 9 computations in 3
+        iterations):
+          * the work of an iteration is the active set at its start -- the
+            parallel loop's view: `b` and `e`, notified by `a` in the second
+            iteration, are recomputed in the third, though they come after
+            `a` in the order; a notification that reaches an r-clique before
+            its visit in the same iteration is cleared by that visit (`f` in
+            the first);
+          * no self-activation: the listing marks R itself active when it
+            changes, which would keep `b` and `e` active after the first
+            iteration (`self_activate` turns it on).
+        Small graphs only (pure Python).
+
+        Returns (tau, iterations, computations per iteration, active
+        r-cliques after each iteration)."""
+        nr = self.num_rcliques(r)
+        tau = self.sdeg(r, s).astype(np.int64)
+        mem = [self.members(r, s, R) for R in range(nr)]
+        nbr = [np.unique(m.reshape(-1)) for m in mem]
+        visit = range(nr) if order is None else [int(x) for x in order]
+        active = np.ones(nr, bool)
+        comps, act_after = [], []
+        iters, changed_any = 0, True
+        while changed_any and iters < max_iters:
+            changed_any = False
+            iters += 1
+            n = 0
+            for R in [R for R in visit if active[R]]:
+                active[R] = False
+                n += 1
+                m = mem[R]
+                rho = tau[m].min(axis=1) if m.size else np.zeros(0, np.int64)
+                h = hindex(rho)
+                if tau[R] != h:
+                    changed_any = True
+                    if self_activate:
+                        active[R] = True
+                    for Rp in nbr[R]:
+                        if h <= tau[Rp]:
+                            active[Rp] = True
+                tau[R] = h
+            comps.append(n)
+            act_after.append(int(active.sum()))
+        return tau.astype(np.int32), iters, comps, act_after
 
     def levels(self, r: int, s: int):
         """(level per r-clique, number of levels)."""

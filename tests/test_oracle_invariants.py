@@ -97,3 +97,30 @@ def test_update_range_and_threads_agree():
     part = g.update(2, 3, tau, lo=100, hi=400)
     assert np.array_equal(part[100:400], full1[100:400])
     assert np.array_equal(part[:100], tau[:100])
+
+
+@pytest.mark.parametrize("name,raw", list(graphs()), ids=lambda x: x if
+                         isinstance(x, str) else "")
+@pytest.mark.parametrize("r,s", KINDS)
+def test_and_with_notifications(name, raw, r, s):
+    """Alg. AND with notifications (Section 4.3) reaches kappa, with no more
+    computations than the same sweeps would take without notifications, and
+    every computation after the first iteration is of an r-clique a
+    neighbour's change made active; in id order its iterations bound the
+    plain in-place sweeps'."""
+    g = oracle.Graph.from_raw(raw)
+    nr = g.num_rcliques(r)
+    if nr == 0:
+        pytest.skip("no r-cliques")
+    kappa = g.peel(r, s)
+    tau, iters, comps, active = g.and_notify(r, s)
+    assert np.array_equal(tau, kappa)
+    assert comps[0] == nr and all(c <= nr for c in comps)
+    # the work of iteration i+1 is exactly what was active after iteration i
+    assert comps[1:] == active[:-1]
+    assert active[-1] == 0 or iters == len(comps)
+    _, sweeps, _ = g.and_run(r, s)
+    assert sum(comps) <= sweeps * nr
+    # a reversed visiting order reaches the same kappa
+    tau_rev, _, _, _ = g.and_notify(r, s, order=np.arange(nr)[::-1])
+    assert np.array_equal(tau_rev, kappa)

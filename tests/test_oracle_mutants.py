@@ -46,20 +46,36 @@ MUTANTS = {
         ";"),
 }
 
+# Mistakes planted in oracle/__init__.py (the parts written in Python).
+PY_MUTANTS = {
+    # notifications reach neighbours whose value is >= the new one, not >
+    "notify_strict": ("if h <= tau[Rp]:", "if h < tau[Rp]:"),
+    # the listing's self-activation, which the worked example rules out
+    "notify_self": ("self_activate: bool = False,", "self_activate: bool = True,"),
+    # an iteration's work is the active set at its start
+    "notify_live_set": ("for R in [R for R in visit if active[R]]:\n"
+                        "                active[R] = False",
+                        "for R in visit:\n"
+                        "                if not active[R]:\n"
+                        "                    continue\n"
+                        "                active[R] = False"),
+}
+
 PIN_FILES = ["tests/test_oracle_pins.py", "tests/test_oracle_invariants.py",
              "tests/test_oracle_partial.py"]
 
 
-@pytest.mark.parametrize("name", sorted(MUTANTS))
+@pytest.mark.parametrize("name", sorted(MUTANTS) + sorted(PY_MUTANTS))
 def test_pins_catch_mutant(name, tmp_path):
-    before, after = MUTANTS[name]
-    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    fname = "oracle.c" if name in MUTANTS else "__init__.py"
+    before, after = (MUTANTS if name in MUTANTS else PY_MUTANTS)[name]
+    src = open(os.path.join(ROOT, "oracle", fname)).read()
     assert src.count(before) == 1, "mutation site moved"
     work = tmp_path / "repo"
     for d in ("oracle", "synth", "tests"):
         shutil.copytree(os.path.join(ROOT, d), work / d,
                         ignore=shutil.ignore_patterns("*.so", "__pycache__"))
-    (work / "oracle" / "oracle.c").write_text(src.replace(before, after))
+    (work / "oracle" / fname).write_text(src.replace(before, after))
     env = dict(os.environ, PYTHONPATH=str(work))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p",
                         "no:cacheprovider", *PIN_FILES], cwd=work, env=env,

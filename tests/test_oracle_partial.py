@@ -1,4 +1,4 @@
-"""PartialAND (Section 4.3, end) and its ego-network estimates (Section 6
+"""PartialAND (Section 4.3, end) and its ego-network estimates (Section 5.3
 application) in the oracle, pinned against what the definitions fix.  CPU
 only.
 

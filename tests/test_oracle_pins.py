@@ -102,6 +102,25 @@ def test_core_example_and_orders(which):
         assert upd == pr["and_natural_only_update_in_iteration_2"]
 
 
+def test_core_example_notifications():
+    """Section 4.3's example: Alg. AND with notifications in the order
+    a..f takes 9 tau computations in 3 iterations, only `a` being active
+    after the first; the result is kappa."""
+    spec = GOLD["core_example"]
+    pr = spec["printed"]
+    names, ix, g, _, _ = named_graph(spec)
+    order = [ix[v] for v in pr["and_natural_order"]]
+    tau, iters, comps, active = g.and_notify(1, 2, order=order)
+    assert sum(comps) == pr["notification_tau_computations"]
+    assert iters == pr["notification_iterations"]
+    assert comps == [6, 1, 2] and active[0] == 1
+    assert np.array_equal(tau, g.peel(1, 2))
+    # with the listing's self-activation the printed counts do not hold
+    _, iters_sa, comps_sa, _ = g.and_notify(1, 2, order=order,
+                                           self_activate=True)
+    assert sum(comps_sa) != pr["notification_tau_computations"]
+
+
 # ------------------------------------------------ k-truss worked example
 
 
