@@ -201,9 +201,13 @@ struct TriIsectArgs {
   const int64_t *toff;   // ne+1
   const int32_t *tri_w;
   const int32_t *tri_e;
-  int32_t *count;        // count pass
+  int32_t *count;        // count pass: S-degree of each triangle
+  int32_t *loc;          // count pass: its local 4-cliques (see below)
   const int32_t *inv;    // fill pass: triangle id -> internal id
+  const int64_t *inc_off;  // fill pass: list of internal triangle i
+  uint32_t *rcur;        // fill pass: next remote slot of internal triangle i
   int32_t *out;          // fill pass: 3 ids per 4-clique
+  int32_t *err;          // set to 1 on an inconsistency (nothing written)
 };
 
 // Id of the triangle whose lowest edge (lexicographically) is e and whose
@@ -240,9 +244,11 @@ __device__ __forceinline__ bool n34_stage(const int32_t *__restrict__ col,
 // step; from LDS instead of the L2 they are several times shorter.
 constexpr int n34_cap(int G) { return G == 16 ? 128 : G == 64 ? 512 : 0; }
 
-// (3,4) count pass: the 4-cliques containing triangle (u,v,w), i.e. the x
-// in N(u) & N(v) & N(w); G lanes stride over the shortest of the three
-// lists and binary-search the other two (held in LDS when they fit).
+// (3,4) count pass, one subgroup per triangle (the triangles whose lowest
+// vertex is too big for the per-vertex builder below): the 4-cliques
+// containing triangle (u,v,w), i.e. the x in N(u) & N(v) & N(w), and how
+// many of them are local (x > u); G lanes stride over the shortest of the
+// three lists and binary-search the other two (held in LDS when they fit).
 template <int G>
 __global__ __launch_bounds__(256) void k_n34_count(TriIsectArgs a) {
   constexpr int CAP = n34_cap(G);
@@ -263,14 +269,16 @@ __global__ __launch_bounds__(256) void k_n34_count(TriIsectArgs a) {
     if (en[2] - b[2] < en[sh] - b[sh]) sh = 2;
     const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
     const int64_t n1 = en[o1] - b[o1], n2 = en[o2] - b[o2];
-    int found = 0;
+    int found = 0, local = 0;
     if (n34_stage<G, CAP>(a.col, b[o1], n1, b[o2], n2, l1, l2, sl)) {
       for (int64_t j = b[sh] + sl; j < en[sh]; j += G) {
         const int32_t x = a.col[j];
         const int64_t q1 = lower_bound<int32_t>(l1, 0, n1, x);
         if (q1 >= n1 || l1[q1] != x) continue;
         const int64_t q2 = lower_bound<int32_t>(l2, 0, n2, x);
-        found += q2 < n2 && l2[q2] == x;
+        const bool f = q2 < n2 && l2[q2] == x;
+        found += f;
+        local += f && x > u;
       }
     } else {
       for (int64_t j = b[sh] + sl; j < en[sh]; j += G) {
@@ -278,12 +286,20 @@ __global__ __launch_bounds__(256) void k_n34_count(TriIsectArgs a) {
         const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
         if (q1 >= en[o1] || a.col[q1] != x) continue;
         const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
-        found += q2 < en[o2] && a.col[q2] == x;
+        const bool f = q2 < en[o2] && a.col[q2] == x;
+        found += f;
+        local += f && x > u;
       }
     }
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) found += __shfl_xor(found, off, G);
-    if (sl == 0) a.count[t] = found;
+    for (int off = G / 2; off > 0; off >>= 1) {
+      found += __shfl_xor(found, off, G);
+      local += __shfl_xor(local, off, G);
+    }
+    if (sl == 0) {
+      a.count[t] = found;
+      a.loc[t] = local;
+    }
   }
 }
 
@@ -752,38 +768,69 @@ void run_edge_isect(EdgeIsectArgs a, const int32_t *items,
   }
 }
 
-void run_n34_count(TriIsectArgs a, const int32_t *items, const int64_t *bin_off,
-                   hipStream_t s) {
-  for (int b = 0; b < kIsectBins; b++) {
-    a.items = items + bin_off[b];
-    a.nitems = bin_off[b + 1] - bin_off[b];
-    if (a.nitems == 0) continue;
-    switch (b) {
-      case 0: k_n34_count<1><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a); break;
-      case 1: k_n34_count<4><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a); break;
-      case 2: k_n34_count<16><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a); break;
-      default: k_n34_count<64><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a); break;
-    }
-    ND_LAUNCHED();
+// Where a triangle's 4-cliques go in its list.  A 4-clique {p<q<r<s} is
+// written by the builder of its lowest vertex p.  In the list of a triangle
+// T, the "local" entries come first: the 4-cliques T + y with y above T's
+// lowest vertex (their lowest vertex is T's, so T's own builder writes them,
+// each at its rank, without atomics); then the "remote" ones (y below: T is
+// the 4-clique's triangle without p, written by p's builder at a slot taken
+// from T's cursor, which starts at T's local count) -- one atomic per
+// 4-clique.
+
+// Write the 3 ids of one entry at place `slot` of internal triangle x's list,
+// if it lies inside the list (else flag an inconsistency).
+__device__ __forceinline__ void n34_put(const TriIsectArgs &a, int32_t x,
+                                        int64_t slot, int32_t i0, int32_t i1,
+                                        int32_t i2) {
+  const int64_t p = a.inc_off[x] + slot;
+  if (slot < 0 || p >= a.inc_off[x + 1]) {
+    *a.err = 1;
+    return;
   }
+  int32_t *o = a.out + 3 * p;
+  o[0] = i0;
+  o[1] = i1;
+  o[2] = i2;
 }
 
-// (3,4) fill pass, each 4-clique once: from its lowest triangle (u,v,w),
-// with x > w in all three lists (as k_k4_list), the four triangles
-// {u,v,w}, {u,v,x}, {u,w,x}, {v,w,x} -- whose lowest edges are (u,v), (u,v),
-// (u,w), (v,w) -- each receive the other three at a slot taken from their
-// list's cursor.  A quarter of the intersections and searches of filling
-// every triangle's list from its own intersection; list order varies.
+// Id of triangle p < q < r (-1 if it is not one): the edge (p,q) from p's
+// adjacency, then r among that edge's third vertices.
+__device__ __forceinline__ int32_t n34_tri_id(const TriIsectArgs &a, int32_t p,
+                                              int32_t q, int32_t r) {
+  const int64_t e0 = a.row_off[p], e1 = a.row_off[p + 1];
+  const int64_t pos = lower_bound<int32_t>(a.col, e0, e1, q);
+  if (pos >= e1 || a.col[pos] != q) return -1;
+  const int32_t e = a.eid[pos];
+  const int64_t t0 = a.toff[e], t1 = a.toff[e + 1];
+  const int64_t t = lower_bound<int32_t>(a.tri_w, t0, t1, r);
+  return (t < t1 && a.tri_w[t] == r) ? (int32_t)t : -1;
+}
+
+__device__ __forceinline__ int32_t n34_sorted_id(const TriIsectArgs &a,
+                                                 int32_t x, int32_t y,
+                                                 int32_t z) {
+  // sort three distinct vertices
+  const int32_t lo = min(x, min(y, z)), hi = max(x, max(y, z));
+  const int32_t mid = x + y + z - lo - hi;
+  return n34_tri_id(a, lo, mid, hi);
+}
+
+// (3,4) fill pass, one subgroup per triangle (u,v,w) whose lowest vertex u is
+// too big for the per-vertex builder: its local entries (x > u in
+// N(u) & N(v) & N(w)) at their rank, each with the three other triangles
+// found by search, and, for the 4-cliques where it is the lowest triangle
+// (x > w), the remote entry of the triangle {v,w,x}.
 template <int G>
-__global__ __launch_bounds__(256) void k_n34_fill(TriIsectArgs a,
-                                                  unsigned long long *cursor) {
+__global__ __launch_bounds__(256) void k_n34_fill_owner(TriIsectArgs a) {
   constexpr int CAP = n34_cap(G);
   __shared__ int32_t lds[256 / G][2][CAP > 0 ? CAP : 1];
   const int sl = lane_id() % G;
+  const int sub = lane_id() / G;
+  const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
   int32_t *l1 = lds[threadIdx.x / G][0], *l2 = lds[threadIdx.x / G][1];
   const int64_t nsub = (int64_t)gridDim.x * blockDim.x / G;
   for (int64_t gsub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-       gsub < a.nitems; gsub += nsub) {
+       gsub < a.nitems; gsub += nsub) {  // uniform within the subgroup
     const int32_t t = a.items[gsub];
     const int32_t e = a.tri_e[t];
     const int32_t u = a.ev[2 * (int64_t)e], v = a.ev[2 * (int64_t)e + 1];
@@ -794,52 +841,392 @@ __global__ __launch_bounds__(256) void k_n34_fill(TriIsectArgs a,
     if (en[1] - b[1] < en[sh] - b[sh]) sh = 1;
     if (en[2] - b[2] < en[sh] - b[sh]) sh = 2;
     const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
-    const int64_t start = lower_bound<int32_t>(a.col, b[sh], en[sh], w + 1);
-    if (start >= en[sh]) continue;  // uniform within the subgroup
-    const int32_t euw = a.eid[lower_bound<int32_t>(a.col, b[0], en[0], w)];
-    const int32_t evw = a.eid[lower_bound<int32_t>(a.col, b[1], en[1], w)];
-    const int32_t it = a.inv[t];
     const int64_t n1 = en[o1] - b[o1], n2 = en[o2] - b[o2];
     const bool staged = n34_stage<G, CAP>(a.col, b[o1], n1, b[o2], n2, l1, l2, sl);
-    for (int64_t j = start + sl; j < en[sh]; j += G) {
-      const int32_t x = a.col[j];
-      if (staged) {
-        const int64_t q1 = lower_bound<int32_t>(l1, 0, n1, x);
-        if (q1 >= n1 || l1[q1] != x) continue;
-        const int64_t q2 = lower_bound<int32_t>(l2, 0, n2, x);
-        if (q2 >= n2 || l2[q2] != x) continue;
-      } else {
-        const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
-        if (q1 >= en[o1] || a.col[q1] != x) continue;
-        const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
-        if (q2 >= en[o2] || a.col[q2] != x) continue;
+    const int32_t it = a.inv[t];
+    int64_t nloc = 0;  // local entries written so far (uniform)
+    for (int64_t j0 = b[sh]; j0 < en[sh]; j0 += G) {  // uniform rounds
+      const int64_t j = j0 + sl;
+      bool hit = false;
+      int32_t x = -1;
+      if (j < en[sh]) {
+        x = a.col[j];
+        if (x > u) {
+          if (staged) {
+            const int64_t q1 = lower_bound<int32_t>(l1, 0, n1, x);
+            const int64_t q2 = lower_bound<int32_t>(l2, 0, n2, x);
+            hit = q1 < n1 && l1[q1] == x && q2 < n2 && l2[q2] == x;
+          } else {
+            const int64_t q1 = lower_bound<int32_t>(a.col, b[o1], en[o1], x);
+            const int64_t q2 = lower_bound<int32_t>(a.col, b[o2], en[o2], x);
+            hit = q1 < en[o1] && a.col[q1] == x && q2 < en[o2] && a.col[q2] == x;
+          }
+        }
       }
-      const int32_t id[4] = {it, a.inv[tri_in(a, e, x)], a.inv[tri_in(a, euw, x)],
-                             a.inv[tri_in(a, evw, x)]};
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int64_t p = (int64_t)atomicAdd(&cursor[id[i]], 1ull);
-        int32_t *o = a.out + 3 * p;
-        int c = 0;
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-          if (q != i) o[c++] = id[q];
+      const uint64_t m = (ballot(hit) >> (sub * G)) & gmask;
+      if (hit) {
+        const int rank = __popcll(m & ((1ull << sl) - 1));
+        const int32_t tuv = n34_sorted_id(a, u, v, x);
+        const int32_t tuw = n34_sorted_id(a, u, w, x);
+        const int32_t tvw = n34_sorted_id(a, v, w, x);
+        if (tuv < 0 || tuw < 0 || tvw < 0) {
+          *a.err = 1;
+        } else {
+          const int32_t iuv = a.inv[tuv], iuw = a.inv[tuw], ivw = a.inv[tvw];
+          n34_put(a, it, nloc + rank, iuv, iuw, ivw);
+          if (x > w) {  // {u,v,w,x} seen from its lowest triangle: once
+            const uint32_t p = atomicAdd(&a.rcur[ivw], 1u);
+            n34_put(a, ivw, (int64_t)p, it, iuv, iuw);
+          }
+        }
       }
+      nloc += __popcll(m);
     }
   }
 }
 
-void run_n34_fill(TriIsectArgs a, unsigned long long *cursor,
-                  const int32_t *items, const int64_t *bin_off, hipStream_t s) {
+void run_n34_tri(TriIsectArgs a, bool fill, const int32_t *items,
+                 const int64_t *bin_off, hipStream_t s) {
   for (int b = 0; b < kIsectBins; b++) {
     a.items = items + bin_off[b];
     a.nitems = bin_off[b + 1] - bin_off[b];
     if (a.nitems == 0) continue;
-    switch (b) {
-      case 0: k_n34_fill<1><<<grid_stride(a.nitems, 1), 256, 0, s>>>(a, cursor); break;
-      case 1: k_n34_fill<4><<<grid_stride(a.nitems, 4), 256, 0, s>>>(a, cursor); break;
-      case 2: k_n34_fill<16><<<grid_stride(a.nitems, 16), 256, 0, s>>>(a, cursor); break;
-      default: k_n34_fill<64><<<grid_stride(a.nitems, 64), 256, 0, s>>>(a, cursor); break;
+    const int G = b == 0 ? 1 : b == 1 ? 4 : b == 2 ? 16 : 64;
+    const unsigned grid = grid_stride(a.nitems, G);
+    switch (b * 2 + (fill ? 1 : 0)) {
+      case 0: k_n34_count<1><<<grid, 256, 0, s>>>(a); break;
+      case 1: k_n34_fill_owner<1><<<grid, 256, 0, s>>>(a); break;
+      case 2: k_n34_count<4><<<grid, 256, 0, s>>>(a); break;
+      case 3: k_n34_fill_owner<4><<<grid, 256, 0, s>>>(a); break;
+      case 4: k_n34_count<16><<<grid, 256, 0, s>>>(a); break;
+      case 5: k_n34_fill_owner<16><<<grid, 256, 0, s>>>(a); break;
+      case 6: k_n34_count<64><<<grid, 256, 0, s>>>(a); break;
+      default: k_n34_fill_owner<64><<<grid, 256, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+  }
+}
+
+// ------------------------------------------- (3,4) per lowest vertex
+//
+// For a vertex p of degree d <= D, one wave holds N(p) = nb[0..d) in LDS
+// (ascending) with its induced adjacency as bit rows: bit q of A[i] is set
+// when nb[q] is adjacent to nb[i].  With nl = the number of neighbours below
+// p (nb[i] > p iff i >= nl) and i >= nl:
+//   * triangle (p, nb[i], nb[j]), i < j, exists iff bit j of A[i]; triangles
+//     are numbered by lowest edge, then third vertex, so its id is
+//     toff[edge (p, nb[i])] + #(bits of A[i] strictly between i and j);
+//   * its 4-cliques are the bits of A[i] & A[j]: its S-degree is their
+//     count, its local count (4th vertex above p) the count at bits >= nl;
+//   * the 4-cliques with lowest vertex p are the triples i < j < k (all
+//     >= nl) pairwise adjacent.  Three of their triangles contain p (ids and
+//     local ranks from the bit rows); the fourth, (nb[i], nb[j], nb[k]), is
+//     found by search and receives its remote entry.
+
+constexpr int kN34VMax = 256;  // largest degree of the per-vertex builder
+
+template <int D>
+struct N34VLds {
+  int32_t nb[D];
+  int32_t len[D];      // |N(nb[i])|
+  int64_t ro[D];       // row_off[nb[i]]
+  int32_t pre[D + 1];  // exclusive prefix: bit-row work, then triangles
+  uint32_t A[D][D / 32];
+  int64_t tb[D];       // toff of edge (p, nb[i]), i >= nl
+  // fill pass: one chunk of up to 64 triangles
+  int16_t ci[kWave], cj[kWave];
+  int32_t ct[kWave];
+  int32_t coff[kWave + 1];
+};
+
+// Exclusive prefix sums of v[0..n) in place, v[n] = total (one wave).
+__device__ void wave_scan_lds(int32_t *v, int n) {
+  const int lane = lane_id();
+  const int per = (n + kWave - 1) / kWave;
+  const int lo = min(n, lane * per), hi = min(n, lo + per);
+  int sum = 0;
+  for (int i = lo; i < hi; i++) sum += v[i];
+  int x = sum;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  const int total = __shfl(x, kWave - 1, kWave);
+  int run = x - sum;
+  for (int i = lo; i < hi; i++) {
+    const int t = v[i];
+    v[i] = run;
+    run += t;
+  }
+  if (lane == 0) v[n] = total;
+  wave_lds_sync();
+}
+
+// The row i of an exclusive prefix pre[0..n] (pre[n] > t) with
+// pre[i] <= t < pre[i+1].
+__device__ __forceinline__ int row_of(const int32_t *pre, int n, int32_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Bits [lo, hi) of the 32-bit word number w.
+__device__ __forceinline__ uint32_t word_range(int w, int lo, int hi) {
+  const int a = min(max(lo - 32 * w, 0), 32), b = min(max(hi - 32 * w, 0), 32);
+  const uint32_t upto_b = b >= 32 ? 0xffffffffu : ((1u << b) - 1);
+  const uint32_t from_a = a >= 32 ? 0u : ~((1u << a) - 1);
+  return upto_b & from_a;
+}
+
+// Set bits of x & y in [lo, hi) (y may be x).
+template <int W>
+__device__ __forceinline__ int popc_and(const uint32_t *x, const uint32_t *y,
+                                        int lo, int hi) {
+  int c = 0;
+#pragma unroll
+  for (int w = 0; w < W; w++) c += __popc(x[w] & y[w] & word_range(w, lo, hi));
+  return c;
+}
+
+// Position of the r-th (from 0) set bit of x & y at or above lo; -1 if none.
+template <int W>
+__device__ __forceinline__ int nth_and(const uint32_t *x, const uint32_t *y,
+                                       int lo, int r) {
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    uint32_t m = x[w] & y[w] & word_range(w, lo, 32 * W);
+    const int pc = __popc(m);
+    if (r < pc) {
+      for (; r > 0; r--) m &= m - 1;
+      return 32 * w + __ffs(m) - 1;
+    }
+    r -= pc;
+  }
+  return -1;
+}
+
+struct N34VArgs {
+  const int32_t *items;  // vertices of this degree class
+  int64_t nitems;
+  const int64_t *row_off;
+  const int32_t *col;
+  const int32_t *eid;
+  const int32_t *nlow;
+  const int64_t *eoff;
+  TriIsectArgs t;        // triangle tables, outputs and error flag
+};
+
+// One wave per vertex p of degree <= D: the S-degrees and local counts of
+// the triangles whose lowest vertex is p (FILL = false), or the entries of
+// the 4-cliques whose lowest vertex is p (FILL = true).
+template <int D, bool FILL>
+__global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
+  constexpr int W = D / 32;
+  __shared__ N34VLds<D> L;
+  const int lane = lane_id();
+  const TriIsectArgs &T = a.t;
+  for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+    const int32_t p = a.items[it];
+    const int64_t base = a.row_off[p];
+    const int d = (int)(a.row_off[p + 1] - base);
+    const int nl = a.nlow[p];
+    const int64_t e_lo = a.eoff[p];
+    wave_lds_sync();  // the previous vertex's reads are done
+    for (int x = lane; x < d * W; x += kWave) L.A[x / W][x % W] = 0;
+    for (int i = lane; i < d; i += kWave) {
+      const int32_t v = a.col[base + i];
+      L.nb[i] = v;
+      L.ro[i] = a.row_off[v];
+      L.len[i] = (int32_t)(a.row_off[v + 1] - L.ro[i]);
+    }
+    wave_lds_sync();
+    // bit rows: a short row walks N(nb[i]) and finds each entry in nb; a
+    // long one (a hub's) looks each nb[q] up in N(nb[i]) instead
+    for (int i = lane; i < d; i += kWave)
+      L.pre[i] = L.len[i] <= 4 * d ? L.len[i] : d;
+    wave_lds_sync();
+    wave_scan_lds(L.pre, d);
+    const int32_t work = L.pre[d];
+    for (int32_t t = lane; t < work; t += kWave) {
+      const int i = row_of(L.pre, d, t);
+      const int r = t - L.pre[i];
+      if (L.len[i] <= 4 * d) {
+        const int32_t z = T.col[L.ro[i] + r];
+        const int q = (int)lower_bound<int32_t>(L.nb, 0, d, z);
+        if (q < d && L.nb[q] == z) atomicOr(&L.A[i][q >> 5], 1u << (q & 31));
+      } else {
+        const int32_t z = L.nb[r];
+        const int64_t e1 = L.ro[i] + L.len[i];
+        const int64_t q = lower_bound<int32_t>(T.col, L.ro[i], e1, z);
+        if (q < e1 && T.col[q] == z) atomicOr(&L.A[i][r >> 5], 1u << (r & 31));
+      }
+    }
+    wave_lds_sync();
+    // triangles (p, nb[i], nb[j]), i >= nl, i < j: row i holds those of
+    // edge (p, nb[i]), numbered from tb[i]; every row must count exactly
+    // the edge's triangles, so that every id below lies in the edge's range
+    bool bad = false;
+    for (int i = lane; i < d; i += kWave) {
+      int c = 0;
+      if (i >= nl) {
+        const int64_t e = e_lo + (i - nl);
+        c = popc_and<W>(L.A[i], L.A[i], i + 1, d);
+        L.tb[i] = T.toff[e];
+        bad |= (int64_t)c != T.toff[e + 1] - L.tb[i];
+      }
+      L.pre[i] = c;
+    }
+    if (ballot(bad)) {  // the triangle list disagrees: write nothing
+      if (lane == 0) *T.err = 1;
+      continue;
+    }
+    wave_lds_sync();
+    wave_scan_lds(L.pre, d);
+    const int32_t nt = L.pre[d];
+    if (!FILL) {
+      for (int32_t t = lane; t < nt; t += kWave) {
+        const int i = row_of(L.pre, d, t);
+        const int r = t - L.pre[i];
+        const int j = nth_and<W>(L.A[i], L.A[i], i + 1, r);
+        const int64_t id = L.tb[i] + r;
+        T.count[id] = popc_and<W>(L.A[i], L.A[j], 0, d);
+        T.loc[id] = popc_and<W>(L.A[i], L.A[j], nl, d);
+      }
+      continue;
+    }
+    // fill: 64 triangles (i, j) at a time, then their 4-cliques (k > j)
+    for (int32_t t0 = 0; t0 < nt; t0 += kWave) {
+      const int32_t t = t0 + lane;
+      int i = 0, j = 0, kc = 0;
+      int64_t id = 0;
+      if (t < nt) {
+        i = row_of(L.pre, d, t);
+        const int r = t - L.pre[i];
+        j = nth_and<W>(L.A[i], L.A[i], i + 1, r);
+        id = L.tb[i] + r;
+        kc = popc_and<W>(L.A[i], L.A[j], j + 1, d);
+      }
+      int x = kc;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+      }
+      const int nq = __shfl(x, kWave - 1, kWave);
+      L.ci[lane] = (int16_t)i;
+      L.cj[lane] = (int16_t)j;
+      L.ct[lane] = (int32_t)id;
+      L.coff[lane] = x - kc;
+      if (lane == 0) L.coff[kWave] = nq;
+      wave_lds_sync();
+      for (int q = lane; q < nq; q += kWave) {
+        const int c = row_of(L.coff, kWave, q);
+        const int ii = L.ci[c], jj = L.cj[c];
+        const int k = nth_and<W>(L.A[ii], L.A[jj], jj + 1, q - L.coff[c]);
+        const int32_t tij = L.ct[c];
+        const int32_t tik = (int32_t)(L.tb[ii] + popc_and<W>(L.A[ii], L.A[ii], ii + 1, k));
+        const int32_t tjk = (int32_t)(L.tb[jj] + popc_and<W>(L.A[jj], L.A[jj], jj + 1, k));
+        // the triangle without p: lowest edge (nb[ii], nb[jj])
+        const int64_t e1 = L.ro[ii] + L.len[ii];
+        const int64_t pos = lower_bound<int32_t>(T.col, L.ro[ii], e1, L.nb[jj]);
+        int32_t top = -1;
+        if (pos < e1 && T.col[pos] == L.nb[jj]) {
+          const int32_t e = a.eid[pos];
+          const int64_t s0 = T.toff[e], s1 = T.toff[e + 1];
+          const int64_t s = lower_bound<int32_t>(T.tri_w, s0, s1, L.nb[k]);
+          if (s < s1 && T.tri_w[s] == L.nb[k]) top = (int32_t)s;
+        }
+        if (top < 0) {
+          *T.err = 1;
+          continue;
+        }
+        const int32_t iij = T.inv[tij], iik = T.inv[tik], ijk = T.inv[tjk];
+        const int32_t itop = T.inv[top];
+        n34_put(T, iij, popc_and<W>(L.A[ii], L.A[jj], nl, k), iik, ijk, itop);
+        n34_put(T, iik, popc_and<W>(L.A[ii], L.A[k], nl, jj), iij, ijk, itop);
+        n34_put(T, ijk, popc_and<W>(L.A[jj], L.A[k], nl, ii), iij, iik, itop);
+        const uint32_t slot = atomicAdd(&T.rcur[itop], 1u);
+        n34_put(T, itop, (int64_t)slot, iij, iik, ijk);
+      }
+      wave_lds_sync();  // before the next chunk overwrites ci .. coff
+    }
+  }
+}
+
+// Degree class of vertex p for the per-vertex builder: 0/1/2 for degree
+// <= 64/128/256 with at least one triangle whose lowest vertex is p, 3 for
+// a larger degree (its triangles go per triangle), 4 for none.
+__global__ void k_n34_vertex_bins(const int64_t *__restrict__ row_off,
+                                  const int64_t *__restrict__ eoff,
+                                  const int64_t *__restrict__ toff, int32_t n,
+                                  uint8_t *__restrict__ bin) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t d = row_off[p + 1] - row_off[p];
+  const bool any = toff[eoff[p + 1]] > toff[eoff[p]];
+  bin[p] = !any ? 4 : d <= 64 ? 0 : d <= 128 ? 1 : d <= kN34VMax ? 2 : 3;
+}
+
+// Intersection bin of the triangles whose lowest vertex is too big for the
+// per-vertex builder; kIsectBins (skipped) for the others.
+__global__ void k_n34_tri_bins(const int32_t *__restrict__ ev,
+                               const int32_t *__restrict__ tri_e,
+                               const int32_t *__restrict__ tri_w,
+                               const int64_t *__restrict__ row_off, int64_t nt,
+                               uint8_t *__restrict__ bin) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int32_t e = tri_e[t];
+  const int32_t u = ev[2 * (int64_t)e], v = ev[2 * (int64_t)e + 1], w = tri_w[t];
+  const int64_t du = row_off[u + 1] - row_off[u];
+  if (du <= kN34VMax) {
+    bin[t] = kIsectBins;
+    return;
+  }
+  int64_t m = min(du, row_off[v + 1] - row_off[v]);
+  m = min(m, row_off[w + 1] - row_off[w]);
+  bin[t] = isect_bin(m);
+}
+
+__global__ void k_n34_cursor(const int32_t *__restrict__ perm,
+                             const int32_t *__restrict__ loc, int64_t nt,
+                             uint32_t *__restrict__ rcur) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nt) rcur[i] = (uint32_t)loc[perm[i]];
+}
+
+// Every list full: each cursor ended at its list's length.
+__global__ void k_n34_check_full(const uint32_t *__restrict__ rcur,
+                                 const int64_t *__restrict__ off, int64_t nt,
+                                 int32_t *__restrict__ err) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= (int64_t)rcur[i] != off[i + 1] - off[i];
+  if (ballot(bad) && lane_id() == 0) atomicOr(err, 1);
+}
+
+void run_n34_vertex(N34VArgs a, bool fill, const int32_t *items,
+                    const int64_t *bin_off, hipStream_t s) {
+  for (int b = 0; b < 3; b++) {
+    a.items = items + bin_off[b];
+    a.nitems = bin_off[b + 1] - bin_off[b];
+    if (a.nitems == 0) continue;
+    const unsigned grid = (unsigned)std::min<int64_t>(a.nitems, 1 << 20);
+    switch (b * 2 + (fill ? 1 : 0)) {
+      case 0: k_n34_vertex<64, false><<<grid, kWave, 0, s>>>(a); break;
+      case 1: k_n34_vertex<64, true><<<grid, kWave, 0, s>>>(a); break;
+      case 2: k_n34_vertex<128, false><<<grid, kWave, 0, s>>>(a); break;
+      case 3: k_n34_vertex<128, true><<<grid, kWave, 0, s>>>(a); break;
+      case 4: k_n34_vertex<256, false><<<grid, kWave, 0, s>>>(a); break;
+      default: k_n34_vertex<256, true><<<grid, kWave, 0, s>>>(a); break;
     }
     ND_LAUNCHED();
   }
@@ -1038,22 +1425,40 @@ void build_triangles(nd_graph *g, hipStream_t s) {
   g->tris_ready = true;
 }
 
+// (3,4) incidence: each 4-clique is written once, by the builder of its
+// lowest vertex (per vertex for degrees up to kN34VMax, else per triangle),
+// into the lists of its four triangles: the three that contain that vertex
+// at ranks known from the count pass, the fourth at a cursor.
 void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   build_triangles(g, s);
   Allocator &al = g->ctx->alloc;
   const int64_t nt = g->nt;
-  DArr<uint8_t> bin(al, nt);
-  DArr<int32_t> items(al, nt);
-  if (nt > 0) {
-    k_tri_bins<<<grid_for(nt, 256), 256, 0, s>>>(g->ev.p, g->tri_e.p,
-                                                  g->tri_w.p, g->row_off.p, nt,
-                                                  bin.p);
+  const int32_t n = g->n;
+  // vertices by degree class; triangles of the big ones by intersection bin
+  DArr<uint8_t> vbin(al, std::max<int32_t>(n, 1));
+  DArr<int32_t> vitems(al, std::max<int32_t>(n, 1));
+  if (n > 0) {
+    k_n34_vertex_bins<<<grid_for(n, 256), 256, 0, s>>>(g->row_off.p, g->eoff.p,
+                                                        g->toff.p, n, vbin.p);
     ND_LAUNCHED();
   }
-  int64_t bin_off[kIsectBins + 1];
-  partition_by_bin(bin.p, nt, kIsectBins, items.p, bin_off, s, al);
+  int64_t voff[6];
+  partition_by_bin(vbin.p, n, 5, vitems.p, voff, s, al);
+  vbin.free();
+  DArr<uint8_t> bin(al, std::max<int64_t>(nt, 1));
+  DArr<int32_t> items(al, std::max<int64_t>(nt, 1));
+  int64_t bin_off[kIsectBins + 2] = {0};
+  if (voff[4] > voff[3]) {  // vertices too big for the per-vertex builder
+    k_n34_tri_bins<<<grid_for(nt, 256), 256, 0, s>>>(g->ev.p, g->tri_e.p,
+                                                      g->tri_w.p, g->row_off.p,
+                                                      nt, bin.p);
+    ND_LAUNCHED();
+    partition_by_bin(bin.p, nt, kIsectBins + 1, items.p, bin_off, s, al);
+  }
   bin.free();
-  DArr<int32_t> cnt(al, nt);
+  DArr<int32_t> cnt(al, std::max<int64_t>(nt, 1)), loc(al, std::max<int64_t>(nt, 1));
+  DArr<int32_t> err(al, 1);
+  fill_i32(err.p, 0, 1, s);
   TriIsectArgs a{};
   a.ev = g->ev.p;
   a.row_off = g->row_off.p;
@@ -1063,20 +1468,46 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   a.tri_w = g->tri_w.p;
   a.tri_e = g->tri_e.p;
   a.count = cnt.p;
-  run_n34_count(a, items.p, bin_off, s);
+  a.loc = loc.p;
+  a.err = err.p;
+  N34VArgs va{};
+  va.row_off = g->row_off.p;
+  va.col = g->col.p;
+  va.eid = g->eid.p;
+  va.nlow = g->nlow.p;
+  va.eoff = g->eoff.p;
+  va.t = a;
+  run_n34_vertex(va, false, vitems.p, voff, s);
+  run_n34_tri(a, false, items.p, bin_off, s);
   ks.nr = nt;
   build_layout(g, ks, cnt.p, s);
   cnt.free();
   ks.inc_ids.reset(al, 3 * ks.P);
-  a.inv = ks.inv.p;
-  a.out = ks.inc_ids.p;
-  DArr<unsigned long long> cursor(al, nt);
+  DArr<uint32_t> rcur(al, std::max<int64_t>(nt, 1));
   if (nt > 0) {
-    k_cursor_init<<<grid_for(nt, 256), 256, 0, s>>>(ks.inc_off.p, ks.perm.p,
-                                                     nullptr, nullptr, nt, cursor.p);
+    k_n34_cursor<<<grid_for(nt, 256), 256, 0, s>>>(ks.perm.p, loc.p, nt, rcur.p);
     ND_LAUNCHED();
   }
-  run_n34_fill(a, cursor.p, items.p, bin_off, s);
+  loc.free();
+  a.count = nullptr;
+  a.loc = nullptr;
+  a.inv = ks.inv.p;
+  a.inc_off = ks.inc_off.p;
+  a.rcur = rcur.p;
+  a.out = ks.inc_ids.p;
+  va.t = a;
+  run_n34_vertex(va, true, vitems.p, voff, s);
+  run_n34_tri(a, true, items.p, bin_off, s);
+  if (nt > 0) {
+    const unsigned grid = (unsigned)std::min<int64_t>(grid_for(nt, 256), 65536);
+    k_n34_check_full<<<grid, 256, 0, s>>>(rcur.p, ks.inc_off.p, nt, err.p);
+    ND_LAUNCHED();
+  }
+  int32_t h = 0;
+  ND_HIP(hipMemcpyAsync(&h, err.p, sizeof h, hipMemcpyDeviceToHost, s));
+  ND_HIP(hipStreamSynchronize(s));
+  ND_REQUIRE(h == 0, ND_ERR_DEVICE,
+             "internal error: the (3,4) incidence lists are inconsistent");
 }
 
 // ------------------------------------------------------- (1,3) and (2,4)
