@@ -343,8 +343,8 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
                                       use_frontier=True))
         lats = []
         for t, want in zip(tickets, solo):
-            kappa, r, lat = srv.wait(t)
-            lats.append(lat)
+            kappa, r, info = srv.wait(t)
+            lats.append(info["latency_ms"])
             same &= bool(torch.equal(kappa, want.cpu()))
         t_srv = time.perf_counter() - t0
         srv.close()
@@ -420,7 +420,7 @@ def ego_leg(g, kappa, count, seed=13):
     """PartialAND estimates on the ego networks of `count` random r-cliques
     of the prepared graph, all in one call: throughput, and accuracy against
     the exact kappa (share exact, mean relative error) -- the comparison of
-    the Section 6 application."""
+    the application of Section 5.3."""
     import numpy as np
     import torch
 

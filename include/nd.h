@@ -104,7 +104,11 @@ typedef struct {
   int32_t iter;           /* sweep number t >= 1; tau_dev holds tau_t */
   int64_t evaluated;      /* r-cliques whose h-index was computed */
   int64_t changed;        /* r-cliques whose value changed in this sweep */
-  int64_t active_next;    /* r-cliques scheduled for the next sweep */
+  int64_t active_next;    /* active r-cliques (Section 4.3): those the
+                             notifications flag for recomputation in the
+                             next sweep (with use_frontier exactly the
+                             next sweep's `evaluated`); -1 unless counted
+                             (count_active or stop_active_ratio) */
   const int32_t *tau_dev; /* device pointer, valid only during the callback */
   double ms;              /* device time of the sweep */
 } nd_iter_info;
@@ -120,14 +124,24 @@ typedef struct {
   int32_t use_frontier;     /* 1: recompute only r-cliques notified by a
                                changed neighbour (Section 4.3); results are
                                identical */
-  double stop_active_ratio; /* > 0: stop once the fraction of r-cliques that
-                               changed in a sweep falls below this ratio
-                               (Section 5.1.4); result is then tau_t */
+  double stop_active_ratio; /* > 0: stop after the first sweep t whose
+                               active_next / |R| falls below this ratio
+                               (the indicator of Section 5.1.4); the
+                               result is then tau_t, an upper bound on
+                               kappa_s.  Implies count_active */
+  int32_t snapshot_every;   /* on_iter sees every this-many-th sweep (and
+                               the last one); <= 1: every sweep */
+  int32_t count_active;     /* 1: count active_next after every sweep.
+                               Notifications then run from the first sweep
+                               (written and counted but not used to skip
+                               work when use_frontier is 0); one extra pass
+                               over |R| flag bytes per sweep */
   nd_iter_cb on_iter;       /* optional per-sweep callback (snapshots) */
   void *user;
 } nd_opts;
 
-/* Defaults: ND_SND, max_iters -1, no frontier, exact, no callback. */
+/* Defaults: ND_SND, max_iters -1, no frontier, exact, snapshot_every 1, no
+ * active counting, no callback. */
 void nd_opts_init(nd_opts *opts);
 
 typedef struct {
@@ -236,14 +250,14 @@ nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
  * update operator restricted to the set -- the same for any sweep order --
  * and an upper bound on kappa_s there.  ids and out: device pointers if
  * on_device, else host.  opts->mode and use_frontier are ignored (AND, no
- * notifications).  ND_ERR_INVALID for an id outside [0, |R|);
+ * notifications); stop_active_ratio must be 0 (ND_ERR_UNSUPPORTED).  ND_ERR_INVALID for an id outside [0, |R|);
  * ND_ERR_NOT_CONVERGED (out then holds the current values) when max_iters
  * stopped it.  res (may be NULL): sweeps, and updates = members x sweeps. */
 nd_status nd_partial_and(nd_graph *g, nd_kind kind, const int32_t *ids,
                          int64_t count, const nd_opts *opts, int32_t *out,
                          int on_device, void *stream, nd_result *res);
 
-/* Ego-network estimates (the Section 6 application of PartialAND): for
+/* Ego-network estimates (the application of PartialAND in Section 5.3): for
  * every query r-clique q = queries[i] (original ids), PartialAND on
  * P(q) = {q} and every r-clique sharing an s-clique with q -- for k-core q
  * and its neighbours, for k-truss q and the other edges of its triangles --
@@ -283,32 +297,62 @@ nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
 
 /* ------------------------------------------------------------ serving */
 
-/* A server owns a worker thread and its own stream.  Requests are graphs
- * submitted for decomposition; a request is admitted when a slot is free and
- * its device memory fits the context budget; admitted requests are swept
- * together (continuous batching), each retiring when it converges, which
- * frees its slot and memory for waiting requests. */
+/* A server serves decomposition requests with continuous batching (the
+ * batching of nd_batch_decompose, kept running).  It owns two host threads,
+ * each with its own stream: a preparation thread builds each admitted
+ * request's r-cliques and incidence lists (nd_prepare's work) while a slot
+ * (max_slots) is free and its device memory fits the context budget -- the
+ * lists are allocated at their exact size from the count pass; a request
+ * that does not fit releases what it built and waits for a running request
+ * to retire, or fails with ND_ERR_OOM if nothing else holds memory -- and a
+ * worker thread adds prepared requests to the running batch of their kind
+ * and options and keeps sweeping, so requests that arrive while others are
+ * on the GPU join them without stopping the sweeps.  A request retires when
+ * it converges, hits max_iters or is cancelled, freeing its slot and its
+ * device memory.  max_queue bounds the requests waiting for a slot. */
 nd_status nd_server_create(nd_ctx *ctx, int32_t max_slots, int32_t max_queue,
                            nd_server **out);
 
-/* Submit: the server takes ownership of g (destroyed when the request ends)
- * and writes the result to host buffer kappa[|R|] (caller keeps it alive
- * until nd_server_wait returns for this ticket).  ND_ERR_BUSY when
- * max_queue requests are waiting.  opts as for nd_batch_decompose. */
+/* Submit g for decomposition of `kind`: the server takes ownership of g
+ * (destroyed when the request ends) and does nothing with it on the calling
+ * thread.  opts: mode, max_iters and use_frontier (NULL: defaults); the
+ * other options give ND_ERR_UNSUPPORTED.  ND_ERR_BUSY when max_queue
+ * requests are waiting. */
 nd_status nd_server_submit(nd_server *srv, nd_graph *g, nd_kind kind,
-                           const nd_opts *opts, int32_t *kappa,
-                           uint64_t *ticket);
+                           const nd_opts *opts, uint64_t *ticket);
 
-/* Wait up to timeout_us (< 0: forever) for a request; returns its final
- * status (ND_ERR_TIMEOUT if still running).  res receives statistics and
- * latency_ms (submission to completion) when non-NULL. */
+/* How a served request went (nd_server_wait). */
+typedef struct {
+  double latency_ms;          /* submission to completion (host clock) */
+  double prep_ms;             /* host time spent preparing it */
+  int64_t epochs_during_prep; /* sweep epochs the server ran, over all
+                                 batches, while it was being prepared */
+  int64_t epoch_joined;       /* its batch's epoch count when it joined */
+  int64_t epoch_done;         /* the same after its last sweep */
+  int32_t joined_running;     /* 1: its batch was already sweeping another
+                                 request when it joined */
+  int32_t peak_members;       /* most requests of its batch swept together
+                                 in one epoch chunk while it ran */
+} nd_serve_info;
+
+/* Wait up to timeout_us (< 0: forever) for a request and return its final
+ * status (ND_ERR_TIMEOUT if still running: call again).  res and info
+ * (either may be NULL) receive its statistics.  After ND_OK or
+ * ND_ERR_NOT_CONVERGED the result (res->n_rcliques values) is kept until
+ * nd_server_result collects it; after any other status the request is gone. */
 nd_status nd_server_wait(nd_server *srv, uint64_t ticket, int64_t timeout_us,
-                         nd_result *res, double *latency_ms);
+                         nd_result *res, nd_serve_info *info);
+
+/* Copy a finished request's kappa into host buffer kappa[capacity] (in
+ * r-clique id order; ND_ERR_INVALID if capacity < n_rcliques) and release
+ * the request.  kappa = NULL only releases it. */
+nd_status nd_server_result(nd_server *srv, uint64_t ticket, int32_t *kappa,
+                           int64_t capacity);
 
 /* Cancel a waiting or running request; its wait returns ND_ERR_CANCELLED. */
 nd_status nd_server_cancel(nd_server *srv, uint64_t ticket);
 
-/* Stop the worker, cancel what is left, free everything. */
+/* Stop both threads, cancel what is left, free everything. */
 void nd_server_destroy(nd_server *srv);
 
 /* --------------------------------------------------------------- errors */

@@ -67,6 +67,8 @@ class nd_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("max_iters", ctypes.c_int32),
                 ("use_frontier", ctypes.c_int32),
                 ("stop_active_ratio", ctypes.c_double),
+                ("snapshot_every", ctypes.c_int32),
+                ("count_active", ctypes.c_int32),
                 ("on_iter", ITER_CB), ("user", ctypes.c_void_p)]
 
 
@@ -76,6 +78,17 @@ class nd_result(ctypes.Structure):
                 ("n_incidence", ctypes.c_int64), ("updates", ctypes.c_int64),
                 ("ms_prep", ctypes.c_double), ("ms_iterate", ctypes.c_double),
                 ("max_sdegree", ctypes.c_int32), ("tau_bytes", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class nd_serve_info(ctypes.Structure):
+    _fields_ = [("latency_ms", ctypes.c_double), ("prep_ms", ctypes.c_double),
+                ("epochs_during_prep", ctypes.c_int64),
+                ("epoch_joined", ctypes.c_int64), ("epoch_done", ctypes.c_int64),
+                ("joined_running", ctypes.c_int32),
+                ("peak_members", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -128,9 +141,10 @@ _sig("nd_batch_decompose", ctypes.c_int, _P, _I32, ctypes.POINTER(_P),
      _P, ctypes.POINTER(nd_result))
 _sig("nd_server_create", ctypes.c_int, _P, _I32, _I32, ctypes.POINTER(_P))
 _sig("nd_server_submit", ctypes.c_int, _P, _P, ctypes.c_int,
-     ctypes.POINTER(nd_opts), _P, ctypes.POINTER(ctypes.c_uint64))
+     ctypes.POINTER(nd_opts), ctypes.POINTER(ctypes.c_uint64))
 _sig("nd_server_wait", ctypes.c_int, _P, ctypes.c_uint64, _I64,
-     ctypes.POINTER(nd_result), ctypes.POINTER(ctypes.c_double))
+     ctypes.POINTER(nd_result), ctypes.POINTER(nd_serve_info))
+_sig("nd_server_result", ctypes.c_int, _P, ctypes.c_uint64, _P, _I64)
 _sig("nd_server_cancel", ctypes.c_int, _P, ctypes.c_uint64)
 _sig("nd_server_destroy", None, _P)
 
@@ -153,13 +167,16 @@ def _dev_i32(t: torch.Tensor, device) -> torch.Tensor:
 
 
 def _make_opts(mode="snd", max_iters=-1, use_frontier=False,
-               stop_active_ratio=0.0, on_iter=None):
+               stop_active_ratio=0.0, on_iter=None, count_active=False,
+               snapshot_every=1):
     o = nd_opts()
     _lib.nd_opts_init(ctypes.byref(o))
     o.mode = MODE[mode]
     o.max_iters = int(max_iters)
     o.use_frontier = int(bool(use_frontier))
     o.stop_active_ratio = float(stop_active_ratio)
+    o.count_active = int(bool(count_active))
+    o.snapshot_every = int(snapshot_every)
     keep = None
     if on_iter is not None:
         def _cb(_user, info_p):
@@ -356,15 +373,29 @@ class Graph:
                   on_iter: Optional[Callable] = None, out=None, stream=None,
                   allow_not_converged: bool = False,
                   keep_iterates: Optional[list] = None,
-                  keep_index: Optional[torch.Tensor] = None):
+                  keep_index: Optional[torch.Tensor] = None,
+                  count_active: bool = False, snapshot_every: int = 1,
+                  keep_stats: Optional[list] = None):
         """kappa for every r-clique (int32 tensor on the device) and the
         nd_result statistics as a dict.  With keep_iterates=[] the list
         receives (changed, tau_t) for every sweep t = 1, 2, ...; with
         keep_index (r-clique ids, a device tensor) only tau_t[keep_index]
-        is kept, so that big graphs can keep many sweeps."""
+        is kept, so that big graphs can keep many sweeps.  keep_stats=[]
+        receives a dict of nd_iter_info's counts for every sweep the callback
+        sees."""
         nr, _, _ = self.sizes(kind)
         kappa = out if out is not None else torch.empty(
             max(nr, 1), dtype=torch.int32, device=self.ctx.device)
+        if keep_stats is not None:
+            stats_cb = on_iter
+
+            def on_iter(info):
+                keep_stats.append({"iter": int(info.iter),
+                                   "evaluated": int(info.evaluated),
+                                   "changed": int(info.changed),
+                                   "active_next": int(info.active_next),
+                                   "ms": float(info.ms)})
+                return stats_cb(info) if stats_cb else 0
         if keep_iterates is not None:
             user_cb = on_iter
             dev = self.ctx.device
@@ -386,7 +417,7 @@ class Graph:
                 keep_iterates.append((int(info.changed), kept))
                 return user_cb(info) if user_cb else 0
         o, keep = _make_opts(mode, max_iters, use_frontier, stop_active_ratio,
-                             on_iter)
+                             on_iter, count_active, snapshot_every)
         res = nd_result()
         st = _lib.nd_decompose(self._h, KIND[kind], ctypes.byref(o),
                                _P(kappa.data_ptr()), 1, _stream(stream),
@@ -422,7 +453,7 @@ def batch_decompose(ctx: Context, graphs: Sequence[Graph], kind: str,
 
 class Server:
     """Continuous-batching request loop (nd_server).  Submitted graphs are
-    owned by the server; results land in pinned host tensors."""
+    owned by the server; results come back in host memory."""
 
     def __init__(self, ctx: Context, max_slots: int = 64,
                  max_queue: int = 1 << 16):
@@ -431,34 +462,39 @@ class Server:
                                      ctypes.byref(h)), "nd_server_create")
         self._h = h
         self.ctx = ctx
-        self._bufs = {}
 
     def submit(self, graph: Graph, kind: str, mode: str = "snd",
                max_iters: int = -1, use_frontier: bool = False) -> int:
         o, keep = _make_opts(mode, max_iters, use_frontier)
-        n_r = _server_rcount(graph, kind)
-        buf = torch.empty(max(n_r, 1), dtype=torch.int32, pin_memory=True)
         t = ctypes.c_uint64()
         _check(_lib.nd_server_submit(self._h, graph._h, KIND[kind],
-                                     ctypes.byref(o), _P(buf.data_ptr()),
-                                     ctypes.byref(t)), "nd_server_submit")
+                                     ctypes.byref(o), ctypes.byref(t)),
+               "nd_server_submit")
         graph.detach()
-        self._bufs[int(t.value)] = buf[:n_r]
         return int(t.value)
 
-    def wait(self, ticket: int, timeout_us: int = -1):
-        """(kappa, result dict, latency ms), or None on timeout.  Raises
-        NdError for a failed or cancelled request."""
+    def wait(self, ticket: int, timeout_us: int = -1,
+             allow_not_converged: bool = False):
+        """(kappa as a host int32 tensor, result dict, serve-info dict), or
+        None on timeout.  Raises NdError for a failed or cancelled request
+        (and for one that stopped at max_iters unless allow_not_converged)."""
         res = nd_result()
-        lat = ctypes.c_double()
+        info = nd_serve_info()
         st = _lib.nd_server_wait(self._h, ctypes.c_uint64(ticket),
                                  int(timeout_us), ctypes.byref(res),
-                                 ctypes.byref(lat))
+                                 ctypes.byref(info))
         if st == 8:
             return None
-        buf = self._bufs.pop(ticket, None)
+        if st in (0, 5):
+            n = int(res.n_rcliques)
+            buf = torch.empty(max(n, 1), dtype=torch.int32)
+            _check(_lib.nd_server_result(self._h, ctypes.c_uint64(ticket),
+                                         _P(buf.data_ptr()), n),
+                   "nd_server_result")
+            if st == 5 and not allow_not_converged:
+                _check(st, "nd_server_wait")
+            return buf[:n], res.as_dict(), info.as_dict()
         _check(st, "nd_server_wait")
-        return buf, res.as_dict(), float(lat.value)
 
     def cancel(self, ticket: int):
         _check(_lib.nd_server_cancel(self._h, ctypes.c_uint64(ticket)),
@@ -474,14 +510,3 @@ class Server:
             self.close()
         except Exception:
             pass
-
-
-def _server_rcount(graph: Graph, kind: str) -> int:
-    """|R| of a graph before it is prepared: n, |E| or the triangle count."""
-    n, nnz = graph.dims()
-    if kind == "core":
-        return n
-    if kind == "truss":
-        return nnz // 2
-    nr, _, _ = graph.sizes(kind)
-    return nr

@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <memory>
+#include <mutex>
 #include <new>
 
 #include "api_util.h"
@@ -77,23 +79,45 @@ void *Allocator::alloc(size_t bytes) {
   bytes = round_bytes(bytes);
   const hipStream_t s = current_stream();
   std::lock_guard<std::mutex> lk(mu_);
-  // Best fit among cached blocks no more than twice the request: same stream
-  // first, then any stream after synchronising it.
+  // Best fit among cached blocks no more than twice the request.  A block is
+  // taken at once when no pending work can touch it: idle, last used on this
+  // stream (stream order protects it), or on a stream that has drained.
+  // Waiting for another stream is the last resort, after a fresh block
+  // within the budget: a server's sweep loop must not wait for a
+  // preparation running on another thread's stream.
+  auto take = [&](std::multimap<size_t, Cached>::iterator it) {
+    void *p = it->second.p;
+    const size_t sz = it->first;
+    cache_.erase(it);
+    cache_total_ -= sz;
+    live_[p] = sz;
+    live_total_ += sz;
+    return p;
+  };
   for (int pass = 0; pass < 2; pass++) {
     auto it = cache_.lower_bound(bytes);
     for (; it != cache_.end() && it->first <= 2 * bytes; ++it) {
-      const bool free_now = it->second.idle || it->second.s == s;
-      if (pass == 0 && !free_now) continue;
-      if (pass == 1 && !free_now) {
-        ND_HIP(hipStreamSynchronize(it->second.s));
-      }
-      void *p = it->second.p;
-      const size_t sz = it->first;
-      cache_.erase(it);
-      cache_total_ -= sz;
-      live_[p] = sz;
-      live_total_ += sz;
+      const bool free_now =
+          it->second.idle || it->second.s == s ||
+          (pass == 1 && hipStreamQuery(it->second.s) == hipSuccess);
+      if (free_now) return take(it);
+    }
+  }
+  (void)hipGetLastError();  // a query of a busy stream is not an error
+  if (!budget_ || live_total_ + cache_total_ + bytes <= budget_) {
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) == hipSuccess) {
+      live_[p] = bytes;
+      live_total_ += bytes;
       return p;
+    }
+    (void)hipGetLastError();
+  }
+  {
+    auto it = cache_.lower_bound(bytes);
+    if (it != cache_.end() && it->first <= 2 * bytes) {
+      ND_HIP(hipStreamSynchronize(it->second.s));
+      return take(it);
     }
   }
   if (budget_ && live_total_ + cache_total_ + bytes > budget_) trim_locked();
@@ -334,12 +358,16 @@ nd_status nd_ctx_create(int device, size_t hbm_budget_bytes, nd_ctx **out) {
     ND_REQUIRE(device >= 0 && device < count, ND_ERR_INVALID,
                "device %d not present (%d devices)", device, count);
     ND_HIP(hipSetDevice(device));
-    nd_ctx *c = new nd_ctx(device, hbm_budget_bytes);
+    std::unique_ptr<nd_ctx> c(new nd_ctx(device, hbm_budget_bytes));
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount,
                               device) == hipSuccess && cu > 0)
       c->num_cu = cu;
-    *out = c;
+    // what a decomposition needs besides its device buffers, made once
+    ND_HIP(hipHostMalloc(&c->host_stats, sizeof(SweepStats) * kHostStatsRing,
+                         hipHostMallocDefault));
+    for (hipEvent_t &e : c->ev) ND_HIP(hipEventCreate(&e));
+    *out = c.release();
   });
 }
 
@@ -422,6 +450,29 @@ nd_status nd_graph_from_csr(nd_ctx *ctx, int32_t n, int64_t nnz,
   }
   return st;
 }
+
+}  // extern "C"
+
+namespace nd {
+
+// Free a graph whose last device work was ordered on stream s (the server's
+// retirement): waits for s only, not for the whole device, and returns the
+// graph's memory to the allocator tagged with s.
+void destroy_graph(nd_graph *g, hipStream_t s) {
+  if (!g) return;
+  nd_ctx *ctx = g->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(s);
+  {
+    StreamScope scope(s);
+    delete g;
+  }
+  ctx->release();
+}
+
+}  // namespace nd
+
+extern "C" {
 
 void nd_graph_destroy(nd_graph *g) {
   if (!g) return;

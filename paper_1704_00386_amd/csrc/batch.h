@@ -101,6 +101,15 @@ class Batch {
   nd_mode mode() const { return mode_; }
   hipStream_t stream() const { return s_; }
   size_t size() const { return members_.size(); }
+  // Epochs run so far (the next epoch's number).
+  int64_t epoch() const { return epoch_; }
+  // Members still being swept (not finished).
+  std::vector<Member *> live() const {
+    std::vector<Member *> v;
+    for (auto &m : members_)
+      if (!m->finished) v.push_back(m.get());
+    return v;
+  }
   bool use_graph = true;
   float tuned_ms = 0;
   BatchConfig config() const { return cfg_; }

@@ -104,11 +104,17 @@ struct nd_ctx {
   int device = 0;
   nd::Allocator alloc;
   int num_cu = 256;
-  void *host_stats = nullptr;  // pinned read-back ring for sweep counters
+  // Made once at creation, so that the sweep loop creates nothing on the
+  // host: the pinned read-back ring of the sweep counters (kHostStatsRing
+  // entries) and the timing events of the sweep loop (whole loop, one sweep).
+  void *host_stats = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::atomic<int> refs{1};    // the owner's reference + one per graph
   nd_ctx(int dev, size_t budget) : device(dev), alloc(dev, budget) {}
   ~nd_ctx() {
     if (host_stats) (void)hipHostFree(host_stats);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
   void retain() { refs.fetch_add(1); }
   void release() {
@@ -190,6 +196,10 @@ struct nd_graph {
 
 namespace nd {
 
+// Free a graph whose last device work was ordered on stream s (waits for s
+// only; nd_graph_destroy waits for the device).
+void destroy_graph(nd_graph *g, hipStream_t s);
+
 // ------------------------------------------------------- primitives
 
 // out[i] = sum_{j<i} in[j] for i <= n (out has n+1 entries).
@@ -258,7 +268,9 @@ struct alignas(128) StatPart {
 struct SweepStats {
   StatPart part[kStatParts];
   unsigned long long notified;  // 1: this sweep set the next sweep's flags
-  unsigned long long pad[15];
+  unsigned long long active;    // r-cliques flagged for the next sweep
+                                // (counted after the sweep when asked for)
+  unsigned long long pad[14];
   __host__ __device__ unsigned long long changed_total() const {
     unsigned long long s = 0;
     for (int i = 0; i < kStatParts; i++) s += part[i].changed;
@@ -293,6 +305,12 @@ struct SweepArgs {
   // the gathers it would save); from then on every sweep notifies and the
   // next one recomputes only flagged r-cliques.
   unsigned long long notify_below;
+  // 1: the first sweep notifies too (notify_below only applies from the
+  // second sweep on otherwise).
+  int notify_first;
+  // 1: flags are written and counted but never used to skip r-cliques (the
+  // active-ratio indicator without the frontier).
+  int flags_unused;
   // PartialAND (Section 4.3, end): act marks a fixed set (stamp 1) that is
   // the only thing recomputed, every sweep, and nothing notifies.
   int fixed_set;
@@ -300,6 +318,9 @@ struct SweepArgs {
   // over the rest of the bin); 0: one pass, no cap.
   int grid_cap;
 };
+
+// Entries of the pinned host ring that receives the sweep counters.
+constexpr int kHostStatsRing = 1024;
 
 // Launch one sweep over every bin of ks (internal numbering, tau of
 // ks.tau16 ? uint16 : int32).  `and_mode` selects in-place reads.

@@ -1,5 +1,5 @@
 // partial.hip -- ego-network estimates by PartialAND (the set-restricted AND
-// of Section 4.3, end, applied as in the Section 6 application): for a
+// of Section 4.3, end, applied as in Section 5.3): for a
 // query r-clique q, AND recomputes only the r-cliques of
 //   P(q) = {q} + every r-clique sharing an s-clique with q
 // (for k-core: q and its neighbours; for k-truss: q and the other edges of

@@ -1,18 +1,28 @@
 // server.hip -- a request loop with continuous batching.
 //
-// Callers submit graphs; a worker thread admits them while a slot is free and
-// their preparation (incidence lists, tau buffers) fits the context's
-// device-memory budget, adds them to the running batch of their kind, mode
-// and tau width (batch.hip), and keeps sweeping every batch one chunk of
-// epochs at a time.  A request that converges (or hits its sweep cap, or is
-// cancelled) is retired at the next poll: its result is copied to the
-// caller's buffer, its device memory released and its slot given to the next
-// waiting request.  Waiting requests therefore join while others are on the
-// GPU, and their sweeps share launches.  Results equal those of a lone
-// nd_decompose (SND iterates do not depend on what else is in a launch; AND
-// converges to the same unique fixed point).
+// Callers submit graphs.  Two host threads serve them, each with its own
+// stream:
+//   * the preparation thread takes waiting requests while a slot is free and
+//     builds what their kind needs (r-cliques, incidence lists, d_s) on its
+//     stream.  Admission is by device memory: the builders' allocations are
+//     charged to the context's budget, the incidence lists at their exact
+//     size from the count pass; a request that does not fit releases what it
+//     built and waits for a running request to retire (or fails when nothing
+//     else holds memory).  Preparing here keeps the sweep loop running while
+//     a newcomer is built;
+//   * the worker thread adds prepared requests to the running batch of their
+//     kind, mode, tau width and frontier setting (batch.hip) and keeps
+//     sweeping every batch a chunk of epochs at a time.  A request that
+//     converges (or hits its sweep cap, or is cancelled) is retired at the
+//     next poll: its result is copied into host memory the server owns, its
+//     device memory released and its slot given to the next waiting request.
+// Waiting requests therefore join while others are on the GPU and their
+// sweeps share launches.  Results equal those of a lone nd_decompose (SND
+// iterates do not depend on what else is in a launch; AND converges to the
+// same unique fixed point).
 #include <string.h>
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -31,13 +41,15 @@ struct Request {
   nd_graph *g = nullptr;
   nd_kind kind = ND_KCORE;
   nd_opts opts{};
-  int32_t *kappa = nullptr;  // caller's host buffer
   Clock::time_point t_submit, t_done;
-  bool admitted = false, done = false, cancelled = false;
+  bool admitted = false;  // holds a slot (preparing, ready or running)
+  bool done = false, cancelled = false;
   nd_status status = ND_OK;
   nd_result res{};
+  nd_serve_info info{};
   Member *member = nullptr;
   Batch *batch = nullptr;
+  std::vector<int32_t> kappa;  // the result, host memory owned here
   std::string error;
 };
 
@@ -47,14 +59,21 @@ struct nd_server {
   nd_ctx *ctx = nullptr;
   int32_t max_slots = 1, max_queue = 1;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<nd::Request *> queue;
+  std::condition_variable cv_work, cv_prep, cv_done;
+  std::deque<nd::Request *> queue;  // submitted, not yet being prepared
+  std::deque<nd::Request *> ready;  // prepared, not yet in a batch
   std::map<uint64_t, std::unique_ptr<nd::Request>> reqs;
-  std::thread worker;
+  std::thread worker, prep;
   bool stop = false;
-  int active = 0;
+  int admitted = 0;         // requests holding a slot
+  int running = 0;          // requests in a batch
+  uint64_t retired = 0;     // retirements so far (memory may have freed)
   uint64_t next_ticket = 1;
-  hipStream_t stream = nullptr;
+  std::atomic<int64_t> epochs{0};  // epochs run over all batches
+  hipStream_t stream = nullptr;       // the worker's
+  hipStream_t prep_stream = nullptr;  // the preparation thread's
+  void *stage = nullptr;              // pinned staging of results (worker)
+  size_t stage_bytes = 0;
   // one batch per (kind, mode, tau width, frontier)
   std::unique_ptr<nd::Batch> batches[nd::kNumKinds][2][2][2];
 };
@@ -63,24 +82,37 @@ namespace nd {
 
 namespace {
 
-void finish(nd_server *srv, Request *r, nd_status st) {
-  std::lock_guard<std::mutex> lk(srv->mu);
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// Mark r finished with status st (lock held by the caller).
+void finish_locked(nd_server *srv, Request *r, nd_status st) {
   r->status = st;
   r->t_done = Clock::now();
   r->done = true;
-  if (r->admitted) srv->active--;
+  r->info.latency_ms = ms_between(r->t_submit, r->t_done);
+  if (r->admitted) {
+    srv->admitted--;
+    r->admitted = false;
+  }
   srv->cv_done.notify_all();
+  srv->cv_prep.notify_all();
   srv->cv_work.notify_all();
 }
 
-void release_graph(Request *r) {
+// Free r's graph; its last device work was ordered on s (the server's
+// threads never wait for the whole device, which would stall the sweeps
+// behind a preparation or the other way round).
+void release_graph(Request *r, hipStream_t s) {
   if (r->g) {
-    nd_graph_destroy(r->g);
+    destroy_graph(r->g, s);
     r->g = nullptr;
   }
 }
 
-// Retire a finished member: copy its result out and free its memory.
+// Copy a retired member's result to host memory and free its device memory
+// (worker thread).
 void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
   Request *r = (Request *)m->user;
   nd_status st = ND_OK;
@@ -88,11 +120,22 @@ void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
   try {
     StreamScope scope(b.stream());
     if (ks.nr > 0 && !r->cancelled) {
+      const size_t bytes = sizeof(int32_t) * (size_t)ks.nr;
+      if (bytes > srv->stage_bytes) {
+        const size_t cap = std::max(bytes, 2 * srv->stage_bytes);
+        if (srv->stage) ND_HIP(hipHostFree(srv->stage));
+        srv->stage = nullptr;
+        srv->stage_bytes = 0;
+        ND_HIP(hipHostMalloc(&srv->stage, cap, hipHostMallocDefault));
+        srv->stage_bytes = cap;
+      }
       DArr<int32_t> tmp(srv->ctx->alloc, ks.nr);
       to_original(ks, b.result_tau(*m), b.tau16(), tmp.p, b.stream());
-      ND_HIP(hipMemcpyAsync(r->kappa, tmp.p, sizeof(int32_t) * ks.nr,
-                            hipMemcpyDeviceToHost, b.stream()));
+      ND_HIP(hipMemcpyAsync(srv->stage, tmp.p, bytes, hipMemcpyDeviceToHost,
+                            b.stream()));
       ND_HIP(hipStreamSynchronize(b.stream()));
+      r->kappa.assign((const int32_t *)srv->stage,
+                      (const int32_t *)srv->stage + ks.nr);
     }
     nd_result &res = r->res;
     memset(&res, 0, sizeof res);
@@ -104,6 +147,7 @@ void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
     res.ms_prep = ks.ms_prep;
     res.max_sdegree = ks.max_ds;
     res.tau_bytes = b.tau16() ? 2 : 4;
+    r->info.epoch_done = b.epoch();
     st = r->cancelled ? ND_ERR_CANCELLED
                       : (m->converged ? ND_OK : ND_ERR_NOT_CONVERGED);
   } catch (const Err &e) {
@@ -114,15 +158,88 @@ void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
     StreamScope scope(b.stream());
     m.reset();  // tau buffers and counters back to the allocator
   }
-  release_graph(r);
-  finish(srv, r, st);
+  release_graph(r, b.stream());
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->running--;
+  srv->retired++;
+  finish_locked(srv, r, st);
 }
 
-// Prepare and add one waiting request; false when it must wait for memory.
-bool admit(nd_server *srv, Request *r) {
+// The preparation thread: build waiting requests while slots are free.
+void prep_main(nd_server *srv) {
+  (void)hipSetDevice(srv->ctx->device);
+  for (;;) {
+    Request *r = nullptr;
+    uint64_t retired0 = 0;
+    int64_t epochs0 = 0;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      srv->cv_prep.wait(lk, [&] {
+        return srv->stop ||
+               (!srv->queue.empty() && srv->admitted < srv->max_slots);
+      });
+      if (srv->stop) return;
+      r = srv->queue.front();
+      srv->queue.pop_front();
+      if (r->cancelled) {
+        lk.unlock();
+        release_graph(r, srv->prep_stream);
+        lk.lock();
+        finish_locked(srv, r, ND_ERR_CANCELLED);
+        continue;
+      }
+      r->admitted = true;
+      srv->admitted++;
+      retired0 = srv->retired;
+      epochs0 = srv->epochs.load();
+    }
+    const Clock::time_point t0 = Clock::now();
+    nd_status code = ND_OK;
+    try {
+      StreamScope scope(srv->prep_stream);
+      prepare(r->g, r->kind, srv->prep_stream);
+    } catch (const Err &e) {
+      code = e.code;
+      r->error = nd_last_error();
+      // give back what the failed build holds
+      StreamScope scope(srv->prep_stream);
+      (void)hipStreamSynchronize(srv->prep_stream);
+      r->g->ks[r->kind] = KindState{};
+    }
+    std::unique_lock<std::mutex> lk(srv->mu);
+    r->info.prep_ms += ms_between(t0, Clock::now());
+    r->info.epochs_during_prep += srv->epochs.load() - epochs0;
+    if (code == ND_OK) {
+      srv->ready.push_back(r);
+      srv->cv_work.notify_all();
+      continue;
+    }
+    if (code == ND_ERR_OOM) {
+      // others hold memory: wait for one of them to retire, then retry
+      srv->cv_prep.wait(lk, [&] {
+        return srv->stop || srv->retired != retired0 ||
+               (srv->running == 0 && srv->ready.empty());
+      });
+      if (srv->retired != retired0 && !srv->stop) {
+        r->admitted = false;
+        srv->admitted--;
+        r->error.clear();
+        srv->queue.push_front(r);
+        continue;
+      }
+    }
+    lk.unlock();
+    release_graph(r, srv->prep_stream);
+    lk.lock();
+    finish_locked(srv, r, code);
+  }
+}
+
+// Add prepared requests to their batches (worker thread).  Returns false
+// when a request had to wait for memory.
+bool add_ready(nd_server *srv, Request *r) {
   try {
     StreamScope scope(srv->stream);
-    prepare(r->g, r->kind, srv->stream);
     const KindState &ks = r->g->ks[r->kind];
     const int mi = r->opts.mode == ND_AND ? 1 : 0;
     const int wi = ks.tau16 ? 1 : 0;
@@ -131,18 +248,24 @@ bool admit(nd_server *srv, Request *r) {
     if (!slot)
       slot = std::make_unique<Batch>(srv->ctx, r->kind, r->opts.mode, ks.tau16,
                                      fi != 0, srv->stream);
+    int running_before = 0;
+    for (Member *m : slot->live()) running_before += m->sweeps > 0 ? 1 : 0;
+    r->info.epoch_joined = slot->epoch();
+    r->info.joined_running = running_before > 0 ? 1 : 0;
     r->member = slot->add(r->g, r->opts.max_iters, r);
     r->batch = slot.get();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->running++;
     return true;
   } catch (const Err &e) {
-    if (e.code == ND_ERR_OOM) {
-      // others hold memory (this request already counts as active): wait
+    {
       std::lock_guard<std::mutex> lk(srv->mu);
-      if (srv->active > 1) return false;
+      if (e.code == ND_ERR_OOM && srv->running > 0) return false;
     }
     r->error = nd_last_error();
-    release_graph(r);
-    finish(srv, r, e.code);
+    release_graph(r, srv->stream);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    finish_locked(srv, r, e.code);
     return true;
   }
 }
@@ -151,70 +274,67 @@ void worker_main(nd_server *srv) {
   (void)hipSetDevice(srv->ctx->device);
   int chunk = 1;
   for (;;) {
-    // ------------------------------------------------ admission
-    for (;;) {
-      Request *r = nullptr;
-      {
-        std::unique_lock<std::mutex> lk(srv->mu);
-        srv->cv_work.wait(lk, [&] {
-          return srv->stop || srv->active > 0 || !srv->queue.empty();
-        });
-        if (srv->stop) return;
-        if (srv->queue.empty() || srv->active >= srv->max_slots) break;
-        r = srv->queue.front();
-        srv->queue.pop_front();
-        if (r->cancelled) {
-          lk.unlock();
-          release_graph(r);
-          finish(srv, r, ND_ERR_CANCELLED);
-          continue;
-        }
-        r->admitted = true;
-        srv->active++;
-      }
-      if (!admit(srv, r)) {
+    std::deque<Request *> newcomers;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      srv->cv_work.wait(lk, [&] {
+        return srv->stop || srv->running > 0 || !srv->ready.empty();
+      });
+      if (srv->stop) return;
+      newcomers.swap(srv->ready);
+    }
+    while (!newcomers.empty()) {
+      Request *r = newcomers.front();
+      if (r->cancelled) {
+        newcomers.pop_front();
+        release_graph(r, srv->stream);
         std::lock_guard<std::mutex> lk(srv->mu);
-        r->admitted = false;
-        srv->active--;
-        srv->queue.push_front(r);
-        break;
+        finish_locked(srv, r, ND_ERR_CANCELLED);
+        continue;
       }
+      if (!add_ready(srv, r)) break;  // wait for a retirement
+      newcomers.pop_front();
       chunk = 1;  // newcomers: poll soon
     }
-    // ------------------------------------------------ sweep
+    if (!newcomers.empty()) {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->ready.insert(srv->ready.begin(), newcomers.begin(), newcomers.end());
+    }
     bool any = false;
     for (auto &bk : srv->batches)
       for (auto &bm : bk)
         for (auto &bw : bm)
           for (auto &b : bw) {
-          if (!b || b->size() == 0) continue;
-          any = true;
-          try {
-            // cancelled running requests stop at this poll
-            {
-              std::lock_guard<std::mutex> lk(srv->mu);
-              for (auto &kv : srv->reqs) {
-                Request *r = kv.second.get();
-                if (r->admitted && !r->done && r->cancelled && r->batch == b.get() &&
-                    r->member)
-                  r->member->finished = true;
+            if (!b || b->size() == 0) continue;
+            any = true;
+            try {
+              // cancelled running requests stop at this poll
+              {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                for (Member *m : b->live())
+                  if (((Request *)m->user)->cancelled) m->finished = true;
               }
+              StreamScope scope(b->stream());
+              const std::vector<Member *> live = b->live();
+              b->run_epochs(chunk);
+              srv->epochs += chunk;
+              b->poll(chunk);
+              for (Member *m : live) {
+                Request *r = (Request *)m->user;
+                r->info.peak_members =
+                    std::max<int32_t>(r->info.peak_members, (int32_t)live.size());
+              }
+              for (auto &m : b->take_finished()) retire(srv, *b, std::move(m));
+            } catch (const Err &e) {
+              // a device failure ends every request of this batch
+              for (Member *m : b->live()) {
+                m->finished = true;
+                ((Request *)m->user)->error = nd_last_error();
+              }
+              for (auto &m : b->take_finished()) retire(srv, *b, std::move(m));
+              (void)e;
             }
-            StreamScope scope(b->stream());
-            b->run_epochs(chunk);
-            b->poll(chunk);
-            for (auto &m : b->take_finished()) retire(srv, *b, std::move(m));
-          } catch (const Err &e) {
-            // a device failure ends every request of this batch
-            for (auto &m : b->take_finished()) retire(srv, *b, std::move(m));
-            std::lock_guard<std::mutex> lk(srv->mu);
-            for (auto &kv : srv->reqs) {
-              Request *r = kv.second.get();
-              if (r->batch == b.get() && !r->done) r->member->finished = true;
-            }
-            (void)e;
           }
-        }
     if (any) chunk = std::min(chunk * 2, Batch::kGraphEpochs);
   }
 }
@@ -236,37 +356,42 @@ nd_status nd_server_create(nd_ctx *ctx, int32_t max_slots, int32_t max_queue,
     ND_HIP(hipSetDevice(ctx->device));
     auto srv = std::make_unique<nd_server>();
     srv->ctx = ctx;
-    ctx->retain();
     srv->max_slots = max_slots;
     srv->max_queue = max_queue;
     ND_HIP(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
+    hipError_t e = hipStreamCreateWithFlags(&srv->prep_stream,
+                                            hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(srv->stream);
+      ND_HIP(e);
+    }
+    ctx->retain();
     nd_server *raw = srv.release();
     raw->worker = std::thread(worker_main, raw);
+    raw->prep = std::thread(prep_main, raw);
     *out = raw;
   });
 }
 
 nd_status nd_server_submit(nd_server *srv, nd_graph *g, nd_kind kind,
-                           const nd_opts *opts, int32_t *kappa,
-                           uint64_t *ticket) {
+                           const nd_opts *opts, uint64_t *ticket) {
   return guarded([&] {
     ND_REQUIRE(srv && g && ticket, ND_ERR_INVALID, "NULL argument");
     ND_REQUIRE(g->ctx == srv->ctx, ND_ERR_INVALID,
                "graph belongs to another context");
-    ND_REQUIRE(kind_valid(kind),
-               ND_ERR_UNSUPPORTED, "unknown kind");
+    ND_REQUIRE(kind_valid(kind), ND_ERR_UNSUPPORTED, "unknown kind");
     nd_opts o;
     nd_opts_init(&o);
     if (opts) o = *opts;
     ND_REQUIRE(o.mode == ND_SND || o.mode == ND_AND, ND_ERR_INVALID,
                "unknown mode");
-    ND_REQUIRE(!o.on_iter && o.stop_active_ratio == 0, ND_ERR_UNSUPPORTED,
+    ND_REQUIRE(!o.on_iter && o.stop_active_ratio == 0 && !o.count_active,
+               ND_ERR_UNSUPPORTED,
                "served requests support mode, max_iters and use_frontier");
     auto r = std::make_unique<Request>();
     r->g = g;
     r->kind = kind;
     r->opts = o;
-    r->kappa = kappa;
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(srv->mu);
     ND_REQUIRE((int32_t)srv->queue.size() < srv->max_queue, ND_ERR_BUSY,
@@ -275,12 +400,12 @@ nd_status nd_server_submit(nd_server *srv, nd_graph *g, nd_kind kind,
     *ticket = r->ticket;
     srv->queue.push_back(r.get());
     srv->reqs[r->ticket] = std::move(r);
-    srv->cv_work.notify_all();
+    srv->cv_prep.notify_all();
   });
 }
 
 nd_status nd_server_wait(nd_server *srv, uint64_t ticket, int64_t timeout_us,
-                         nd_result *res, double *latency_ms) {
+                         nd_result *res, nd_serve_info *info) {
   if (!srv) {
     set_error("server is NULL");
     return ND_ERR_INVALID;
@@ -301,13 +426,35 @@ nd_status nd_server_wait(nd_server *srv, uint64_t ticket, int64_t timeout_us,
     return ND_ERR_TIMEOUT;
   }
   if (res) *res = r->res;
-  if (latency_ms)
-    *latency_ms =
-        std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  if (info) *info = r->info;
   const nd_status st = r->status;
-  if (st != ND_OK) set_error("%s", r->error.empty() ? nd_status_str(st) : r->error.c_str());
-  srv->reqs.erase(it);
+  if (st != ND_OK)
+    set_error("%s", r->error.empty() ? nd_status_str(st) : r->error.c_str());
+  // a result stays until nd_server_result collects it
+  if (st != ND_OK && st != ND_ERR_NOT_CONVERGED) srv->reqs.erase(it);
   return st;
+}
+
+nd_status nd_server_result(nd_server *srv, uint64_t ticket, int32_t *kappa,
+                           int64_t capacity) {
+  return guarded([&] {
+    ND_REQUIRE(srv, ND_ERR_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    ND_REQUIRE(it != srv->reqs.end(), ND_ERR_INVALID, "unknown ticket %llu",
+               (unsigned long long)ticket);
+    Request *r = it->second.get();
+    ND_REQUIRE(r->done, ND_ERR_INVALID, "request %llu has not finished",
+               (unsigned long long)ticket);
+    const int64_t n = (int64_t)r->kappa.size();
+    if (kappa) {
+      ND_REQUIRE(capacity >= n, ND_ERR_INVALID,
+                 "kappa holds %lld entries, the result %lld",
+                 (long long)capacity, (long long)n);
+      if (n) memcpy(kappa, r->kappa.data(), sizeof(int32_t) * (size_t)n);
+    }
+    srv->reqs.erase(it);
+  });
 }
 
 nd_status nd_server_cancel(nd_server *srv, uint64_t ticket) {
@@ -323,6 +470,7 @@ nd_status nd_server_cancel(nd_server *srv, uint64_t ticket) {
   }
   it->second->cancelled = true;
   srv->cv_work.notify_all();
+  srv->cv_prep.notify_all();
   return ND_OK;
 }
 
@@ -332,17 +480,23 @@ void nd_server_destroy(nd_server *srv) {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->stop = true;
     srv->cv_work.notify_all();
+    srv->cv_prep.notify_all();
   }
+  if (srv->prep.joinable()) srv->prep.join();
   if (srv->worker.joinable()) srv->worker.join();
   (void)hipSetDevice(srv->ctx->device);
   for (auto &bk : srv->batches)
     for (auto &bm : bk)
       for (auto &bw : bm)
         for (auto &b : bw) b.reset();
-  for (auto &kv : srv->reqs) release_graph(kv.second.get());
+  (void)hipDeviceSynchronize();
+  for (auto &kv : srv->reqs) release_graph(kv.second.get(), srv->stream);
   srv->reqs.clear();
   srv->ctx->alloc.forget_stream(srv->stream);
+  srv->ctx->alloc.forget_stream(srv->prep_stream);
   (void)hipStreamDestroy(srv->stream);
+  (void)hipStreamDestroy(srv->prep_stream);
+  if (srv->stage) (void)hipHostFree(srv->stage);
   nd_ctx *ctx = srv->ctx;
   delete srv;
   ctx->release();

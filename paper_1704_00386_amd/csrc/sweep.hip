@@ -52,8 +52,9 @@ __device__ __forceinline__ unsigned long long prev_changed(const SweepArgs &a) {
 }
 
 // Frontier state of this sweep (uniform over the launch): flags are read
-// only if the previous sweep wrote them; this sweep notifies once the
-// previous one changed few enough r-cliques, and keeps notifying after.
+// only if the previous sweep wrote them (and a.flags_unused is clear); this
+// sweep notifies once the previous one changed few enough r-cliques, and
+// keeps notifying after; the first sweep notifies only with a.notify_first.
 __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
                                               unsigned long long prev_changed,
                                               const uint8_t **act,
@@ -67,10 +68,12 @@ __device__ __forceinline__ void frontier_mode(const SweepArgs &a,
     *act_next = nullptr;
     return;
   }
-  const bool flags_valid = a.prev != nullptr && a.prev->notified;
+  const bool flags_valid =
+      !a.flags_unused && a.prev != nullptr && a.prev->notified;
   const bool notify =
-      a.prev != nullptr &&
-      (a.prev->notified || prev_changed <= a.notify_below);
+      a.prev != nullptr
+          ? (a.prev->notified || prev_changed <= a.notify_below)
+          : a.notify_first != 0;
   *act = flags_valid ? a.act : nullptr;
   *act_next = notify ? a.act_next : nullptr;
   *act_sum = flags_valid ? a.act_sum : nullptr;

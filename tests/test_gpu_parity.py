@@ -199,19 +199,71 @@ def test_max_iters_returns_iterate(nd, ctx):
     assert e.value.name == "not_converged"
 
 
-def test_stop_active_ratio(nd, ctx):
+def expected_active(og, r, s, seq):
+    """Active r-cliques after each SND sweep t = 1, 2, ... (Section 4.3):
+    those the library's notifications flag for sweep t+1 -- every r-clique
+    that changed at sweep t, and every member R' of an s-clique of a changed
+    R with h < tau_{t-1}(R') <= tau_{t-1}(R) and tau_{t-1}(Q) >= tau_{t-1}(R')
+    for the other members Q (the rule checked against the oracle's iterates
+    in test_notify_rule)."""
+    from test_notify_rule import marked, pairs
+    R, O = pairs(og, r, s)
+    s64 = [x.astype(np.int64) for x in seq]
+    return [int((marked(R, O, s64[t - 1], s64[t], False)
+                 | (s64[t] != s64[t - 1])).sum()) for t in range(1, len(s64))]
+
+
+@pytest.mark.parametrize("kind", ["core", "truss", "nucleus34"])
+def test_active_counts_and_stop_ratio(nd, ctx, kind):
+    """The active-ratio indicator (Section 5.1.4): each sweep's count of
+    active r-cliques equals the notification rule's on the oracle's
+    iterates, with and without the frontier (with it, exactly the next
+    sweep's evaluated count); stop_active_ratio stops after the first sweep
+    whose active / |R| falls below the ratio, returning that iterate."""
     raw = chung_lu(4096, 2.1, 16.0, seed=7)
+    r, s = KINDS[kind]
     g = gpu_graph(nd, ctx, raw)
     og = oracle.Graph.from_raw(raw)
-    seq = og.snd(2, 3)
+    seq = og.snd(r, s)
     nr = seq[0].size
-    ratio = 0.01
-    tau, res = g.decompose("truss", "snd", stop_active_ratio=ratio)
-    t = res["sweeps"]
-    changed = [(seq[i] != seq[i - 1]).sum() for i in range(1, len(seq))]
-    want_t = next(i + 1 for i, c in enumerate(changed) if c < ratio * nr)
-    assert t == want_t
-    assert np.array_equal(tau.cpu().numpy(), seq[t])
+    active = expected_active(og, r, s, seq)
+    assert active[-1] == 0
+    for fr in (False, True):
+        st = []
+        kappa, res = g.decompose(kind, "snd", use_frontier=fr, count_active=True,
+                                 keep_stats=st)
+        assert np.array_equal(kappa.cpu().numpy(), seq[-1])
+        assert [x["active_next"] for x in st] == active, fr
+        assert [x["changed"] for x in st] == \
+            [int((seq[t] != seq[t - 1]).sum()) for t in range(1, len(seq))]
+        if fr:
+            assert [x["evaluated"] for x in st[1:]] == active[:-1]
+    st = []
+    g.decompose(kind, "snd", keep_stats=st)  # not counted unless asked
+    assert all(x["active_next"] == -1 for x in st)
+    for ratio in (0.4, 0.1, 0.01):
+        want_t = next(i + 1 for i, a in enumerate(active) if a < ratio * nr)
+        for fr in (False, True):
+            tau, res = g.decompose(kind, "snd", stop_active_ratio=ratio,
+                                   use_frontier=fr)
+            assert res["sweeps"] == want_t, (ratio, fr)
+            assert np.array_equal(tau.cpu().numpy(), seq[want_t])
+
+
+@pytest.mark.parametrize("kind", ["core", "truss", "nucleus34"])
+def test_and_active_counts(nd, ctx, kind):
+    """AND with the frontier: the active count after a sweep is exactly what
+    the next sweep recomputes, and the result is kappa."""
+    raw = chung_lu(4096, 2.1, 16.0, seed=8)
+    r, s = KINDS[kind]
+    g = gpu_graph(nd, ctx, raw)
+    kref = oracle.Graph.from_raw(raw).peel(r, s)
+    st = []
+    kappa, res = g.decompose(kind, "and", use_frontier=True, count_active=True,
+                             keep_stats=st)
+    assert np.array_equal(kappa.cpu().numpy(), kref)
+    assert [x["evaluated"] for x in st[1:]] == [x["active_next"] for x in st[:-1]]
+    assert st[-1]["active_next"] == 0
 
 
 # ----------------------------------------------------------- edge cases
@@ -234,6 +286,8 @@ EDGE_CASES = {
     "k40": (40, [(a, b) for a in range(40) for b in range(a + 1, 40)]),
     # hub of degree 20000 > 16384 bins: coarse-then-fine histogram path
     "star20000": (20001, [(0, i) for i in range(1, 20001)]),
+    # hub of degree 40000 >= 32768: k-core tau stored in 32 bits
+    "star40000": (40001, [(0, i) for i in range(1, 40001)]),
     # K_{40,20000} plus a 60-clique joined to vertex 0, whose degree
     # 20060 takes the coarse path with a large H
     "bipartite_hub": (20100, [(a, 100 + b) for a in range(40) for b in range(20000)]
