@@ -1,7 +1,9 @@
 """Build ``libnd.so`` (the HIP library behind include/nd.h) for gfx950.
 
-Every source in ``csrc/`` is compiled with hipcc for gfx950 only, then linked
-into one shared library next to this file.  Usage:
+Every library source in ``csrc/`` is compiled with hipcc for gfx950 only,
+then linked into one shared library next to this file.  ``csrc/ceiling.hip``
+(the benchmark's ceiling measurements, not part of the library) becomes
+``libndceil.so`` beside it.  Usage:
 ``python paper_1704_00386_amd/build.py [--jobs N]`` (run as a script: importing
 the package itself needs the library).
 """
@@ -18,6 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libnd.so")
+CEIL_LIB = os.path.join(HERE, "libndceil.so")
+CEIL_SRC = "ceiling.hip"
 
 SOURCES = ["api.hip", "prim.hip", "graph.hip", "cliques.hip", "layout.hip",
            "sweep.hip", "driver.hip", "partial.hip", "levels.hip", "batch.hip", "server.hip"]
@@ -42,18 +46,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    os.makedirs(OBJ, exist_ok=True)
-    jobs = jobs or min(8, os.cpu_count() or 1)
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib: str) -> None:
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs,
            "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs: int | None = None) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, SOURCES + [CEIL_SRC]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], CEIL_LIB)
     return LIB
 
 

@@ -1,0 +1,144 @@
+// ceiling.hip -- measurement kernels for the ceilings the benchmark reports
+// beside the sweep's fraction of HBM peak.  Not part of the method and not
+// linked into libnd.so: built as libndceil.so and loaded by the benchmark
+// only.
+//
+//   ndc_read      streams n bytes (16-byte loads, summed): the achievable
+//                 read bandwidth;
+//   ndc_copy      copies n bytes (16-byte loads and stores);
+//   ndc_gather    for every s-clique j: min over its k listed ids of tau[id]
+//                 (tau 16- or 32-bit), summed -- the id stream and the random
+//                 tau gathers of one sweep without the h-index: the ceiling of
+//                 the gather pattern itself.
+// Each enqueues one kernel on `stream` between two events of its own and
+// returns the kernel's device time in milliseconds (negative on error).
+// The sums go to *sink so that no load is optimised away.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void sink_add(unsigned long long *sink,
+                                         unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (__lane_id() == 0 && v) atomicAdd(sink, v);
+}
+
+__global__ __launch_bounds__(kThreads) void k_read(const uint4 *__restrict__ p,
+                                                   int64_t n16,
+                                                   unsigned long long *sink) {
+  unsigned long long s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n16;
+       i += (int64_t)gridDim.x * kThreads) {
+    const uint4 v = p[i];
+    s += v.x ^ v.y ^ v.z ^ v.w;
+  }
+  sink_add(sink, s);
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy(const uint4 *__restrict__ a,
+                                                   uint4 *__restrict__ b,
+                                                   int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n16;
+       i += (int64_t)gridDim.x * kThreads)
+    b[i] = a[i];
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(kThreads) void k_gather(
+    const int32_t *__restrict__ ids, int64_t nsets, const T *__restrict__ tau,
+    unsigned long long *sink) {
+  unsigned long long s = 0;
+  for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < nsets;
+       j += (int64_t)gridDim.x * kThreads) {
+    const int32_t *q = ids + K * j;
+    uint32_t m = 0xffffffffu;
+#pragma unroll
+    for (int x = 0; x < K; x++) m = min(m, (uint32_t)tau[q[x]]);
+    s += m;
+  }
+  sink_add(sink, s);
+}
+
+template <class F>
+float timed(hipStream_t s, F &&launch) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return -1;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return -1;
+  }
+  float ms = -1;
+  if (hipEventRecord(a, s) == hipSuccess) {
+    launch();
+    if (hipGetLastError() == hipSuccess && hipEventRecord(b, s) == hipSuccess &&
+        hipEventSynchronize(b) == hipSuccess)
+      (void)hipEventElapsedTime(&ms, a, b);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms;
+}
+
+unsigned grid_of(int64_t items, int cus) {
+  const int64_t g = (items + kThreads - 1) / kThreads;
+  const int64_t cap = (int64_t)cus * 32;
+  return (unsigned)(g < 1 ? 1 : g > cap ? cap : g);
+}
+
+int num_cus() {
+  int dev = 0, cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+  return cu > 0 ? cu : 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+// bytes must be a multiple of 16 and p 16-byte aligned.
+float ndc_read(const void *p, int64_t bytes, unsigned long long *sink,
+               void *stream) {
+  if (!p || bytes < 16 || bytes % 16 || !sink) return -1;
+  const int64_t n16 = bytes / 16;
+  hipStream_t s = (hipStream_t)stream;
+  return timed(s, [&] {
+    k_read<<<grid_of(n16, num_cus()), kThreads, 0, s>>>((const uint4 *)p, n16,
+                                                        sink);
+  });
+}
+
+float ndc_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+  if (!src || !dst || bytes < 16 || bytes % 16) return -1;
+  const int64_t n16 = bytes / 16;
+  hipStream_t s = (hipStream_t)stream;
+  return timed(s, [&] {
+    k_copy<<<grid_of(n16, num_cus()), kThreads, 0, s>>>((const uint4 *)src,
+                                                        (uint4 *)dst, n16);
+  });
+}
+
+// ids[k * nsets] (every id a valid index of tau), tau 16-bit (tau32 = 0) or
+// 32-bit; k in {1, 2, 3}.
+float ndc_gather(const int32_t *ids, int64_t nsets, int k, const void *tau,
+                 int tau32, unsigned long long *sink, void *stream) {
+  if (!ids || !tau || !sink || nsets < 1 || k < 1 || k > 3) return -1;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned grid = grid_of(nsets, num_cus());
+  return timed(s, [&] {
+    switch (k * 2 + (tau32 ? 1 : 0)) {
+      case 2: k_gather<1, uint16_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const uint16_t *)tau, sink); break;
+      case 3: k_gather<1, int32_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const int32_t *)tau, sink); break;
+      case 4: k_gather<2, uint16_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const uint16_t *)tau, sink); break;
+      case 5: k_gather<2, int32_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const int32_t *)tau, sink); break;
+      case 6: k_gather<3, uint16_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const uint16_t *)tau, sink); break;
+      default: k_gather<3, int32_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const int32_t *)tau, sink); break;
+    }
+  });
+}
+
+}  // extern "C"
