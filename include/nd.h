@@ -236,6 +236,29 @@ nd_status nd_decompose(nd_graph *g, nd_kind kind, const nd_opts *opts,
                        int32_t *kappa, int on_device, void *stream,
                        nd_result *res);
 
+/* nd_decompose for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same contract and results as nd_decompose, except:
+ *   - the graph must already be prepared for `kind` (nd_prepare, or any
+ *     earlier call that prepared it); otherwise ND_ERR_INVALID;
+ *   - every buffer of the iteration (tau buffers, notification flags, sweep
+ *     counters, the snapshot handed to on_iter, and the staging of kappa
+ *     when it goes to host memory) lives in one static device workspace of
+ *     ND_NOALLOC_WORKSPACE_BYTES, reserved on a device when the first
+ *     context is created there and held until the process ends.  It needs
+ *     about (2b + 2)|R| bytes for SND with notifications (b = bytes per tau,
+ *     nd_result.tau_bytes; b|R| fewer for AND, 2|R| fewer without flags),
+ *     plus 4|R| with on_iter and 4|R| for a host kappa; a decomposition
+ *     that does not fit fails with ND_ERR_OOM before running anything;
+ *   - the call allocates no device or host memory.
+ * Every call on a device shares that device's workspace, whose contents
+ * persist between calls: calls that overlap in time on one device (other
+ * threads, other streams) race and give undefined results. */
+#define ND_NOALLOC_WORKSPACE_BYTES ((size_t)128 << 20)
+nd_status nd_decompose_noalloc(nd_graph *g, nd_kind kind, const nd_opts *opts,
+                               int32_t *kappa, int on_device, void *stream,
+                               nd_result *res);
+
 /* Apply the update operator once: tau_out = U tau_in (Section 3, Defn. of U),
  * for an arbitrary tau_in[|R|] with 0 <= tau_in <= d_s (values above d_s are
  * rejected).  Both arrays device or both host per on_device. */

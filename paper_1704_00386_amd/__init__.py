@@ -129,6 +129,8 @@ _sig("nd_incidence", ctypes.c_int, _P, ctypes.c_int, _P, _P, ctypes.c_int, _P)
 _sig("nd_sdegree", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int, _P)
 _sig("nd_decompose", ctypes.c_int, _P, ctypes.c_int, ctypes.POINTER(nd_opts),
      _P, ctypes.c_int, _P, ctypes.POINTER(nd_result))
+_sig("nd_decompose_noalloc", ctypes.c_int, _P, ctypes.c_int,
+     ctypes.POINTER(nd_opts), _P, ctypes.c_int, _P, ctypes.POINTER(nd_result))
 _sig("nd_update", ctypes.c_int, _P, ctypes.c_int, _P, _P, ctypes.c_int, _P)
 _sig("nd_levels", ctypes.c_int, _P, ctypes.c_int, _P,
      ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _P)
@@ -375,17 +377,26 @@ class Graph:
                   keep_iterates: Optional[list] = None,
                   keep_index: Optional[torch.Tensor] = None,
                   count_active: bool = False, snapshot_every: int = 1,
-                  keep_stats: Optional[list] = None):
+                  keep_stats: Optional[list] = None, noalloc: bool = False):
         """kappa for every r-clique (int32 tensor on the device) and the
         nd_result statistics as a dict.  With keep_iterates=[] the list
         receives (changed, tau_t) for every sweep t = 1, 2, ...; with
         keep_index (r-clique ids, a device tensor) only tau_t[keep_index]
         is kept, so that big graphs can keep many sweeps.  keep_stats=[]
         receives a dict of nd_iter_info's counts for every sweep the callback
-        sees."""
-        nr, _, _ = self.sizes(kind)
-        kappa = out if out is not None else torch.empty(
-            max(nr, 1), dtype=torch.int32, device=self.ctx.device)
+        sees.  noalloc=True calls nd_decompose_noalloc: the graph must be
+        prepared and `out` (int32, device, at least |R| long) receives kappa;
+        nothing is prepared or allocated here."""
+        if noalloc:
+            if out is None:
+                raise ValueError("noalloc needs the caller's kappa buffer `out`")
+            if keep_iterates is not None:
+                raise ValueError("keep_iterates allocates; not with noalloc")
+            kappa, nr = out, None
+        else:
+            nr, _, _ = self.sizes(kind)
+            kappa = out if out is not None else torch.empty(
+                max(nr, 1), dtype=torch.int32, device=self.ctx.device)
         if keep_stats is not None:
             stats_cb = on_iter
 
@@ -419,12 +430,14 @@ class Graph:
         o, keep = _make_opts(mode, max_iters, use_frontier, stop_active_ratio,
                              on_iter, count_active, snapshot_every)
         res = nd_result()
-        st = _lib.nd_decompose(self._h, KIND[kind], ctypes.byref(o),
-                               _P(kappa.data_ptr()), 1, _stream(stream),
-                               ctypes.byref(res))
+        fn = _lib.nd_decompose_noalloc if noalloc else _lib.nd_decompose
+        st = fn(self._h, KIND[kind], ctypes.byref(o), _P(kappa.data_ptr()), 1,
+                _stream(stream), ctypes.byref(res))
         del keep
         if not (st == 0 or (st == 5 and allow_not_converged)):
-            _check(st, "nd_decompose")
+            _check(st, "nd_decompose_noalloc" if noalloc else "nd_decompose")
+        if nr is None:
+            nr = int(res.n_rcliques)
         return kappa[:nr], res.as_dict()
 
 

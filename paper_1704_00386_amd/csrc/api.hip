@@ -26,6 +26,38 @@ void set_error(const char *fmt, ...) {
   va_end(ap);
 }
 
+// ------------------------------------------------- static workspace
+
+// The workspace of nd_decompose_noalloc.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address on each device
+// is looked up once (hipGetSymbolAddress, with that device current) and only
+// that address is ever handed to kernels or copies.  Every device keeps its
+// own copy of the array, held until the process ends.
+static __device__ __align__(256) uint8_t scratch[kNoallocWorkspaceBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// With `device` current: look up its workspace address (once per device).
+static void noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  ND_REQUIRE(device >= 0 && device < kMaxDevices, ND_ERR_UNSUPPORTED,
+             "device %d: at most %d devices are supported", device, kMaxDevices);
+  if (g_scratch_ptr[device]) return;
+  void *p = nullptr;
+  ND_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  ND_REQUIRE(p != nullptr, ND_ERR_DEVICE,
+             "no device address for the static workspace on device %d", device);
+  g_scratch_ptr[device] = p;
+}
+
+void *noalloc_workspace(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 // ------------------------------------------------------------ streams
 
 static thread_local hipStream_t g_stream = nullptr;
@@ -367,6 +399,7 @@ nd_status nd_ctx_create(int device, size_t hbm_budget_bytes, nd_ctx **out) {
     ND_HIP(hipHostMalloc(&c->host_stats, sizeof(SweepStats) * kHostStatsRing,
                          hipHostMallocDefault));
     for (hipEvent_t &e : c->ev) ND_HIP(hipEventCreate(&e));
+    noalloc_setup(device);
     *out = c.release();
   });
 }

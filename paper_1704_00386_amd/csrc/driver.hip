@@ -22,8 +22,10 @@ namespace nd {
 namespace {
 
 constexpr int kStatsRing = 1024;  // device counters kept per decomposition
+constexpr int kStaticRing = 64;   // the same, in the static workspace
 constexpr int kMaxChunk = 16;     // sweeps enqueued per host round trip
-static_assert(kMaxChunk < kStatsRing && kStatsRing <= kHostStatsRing,
+static_assert(kMaxChunk < kStaticRing && kStaticRing <= kHostStatsRing &&
+                  kStatsRing <= kHostStatsRing,
               "a chunk and its predecessor must fit every counter ring");
 constexpr int kGridPerCu = 64;    // sweep workgroups per CU (they stride;
                                   // measured best of 8..64 and uncapped)
@@ -369,6 +371,54 @@ nd_status decompose_impl(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
   return sweep_loop(g, ks, opts, kappa, on_device, s, res, r, fixed_set, b);
 }
 
+// The same decomposition in the static workspace (nd_decompose_noalloc): no
+// device or host memory is allocated.
+nd_status decompose_noalloc(nd_graph *g, nd_kind kind, const nd_opts *opts_in,
+                            int32_t *kappa, int on_device, hipStream_t s,
+                            nd_result *res) {
+  const nd_opts opts = effective_opts(opts_in, false);
+  ND_REQUIRE(kind_valid(kind), ND_ERR_UNSUPPORTED, "unknown kind %d",
+             (int)kind);
+  const KindState &ks = g->ks[kind];
+  ND_REQUIRE(ks.ready, ND_ERR_INVALID,
+             "the graph is not prepared for this kind (call nd_prepare first)");
+  const nd_result r = result_head(ks, true);
+  ND_REQUIRE(kappa || ks.nr == 0, ND_ERR_INVALID, "kappa is NULL");
+  if (ks.nr == 0) {
+    nd_result z = r;
+    z.converged = 1;
+    if (res) *res = z;
+    return ND_OK;
+  }
+  const bool flags = opts.use_frontier != 0 || wants_indicator(opts, false);
+  const LoopLayout L = loop_layout(ks, opts, flags, on_device != 0, kStaticRing);
+  ND_REQUIRE(L.total() <= (int64_t)kNoallocWorkspaceBytes, ND_ERR_OOM,
+             "the decomposition needs %lld bytes of workspace; the static "
+             "workspace holds %lld",
+             (long long)L.total(), (long long)kNoallocWorkspaceBytes);
+  uint8_t *w = (uint8_t *)noalloc_workspace(g->ctx->device);
+  ND_REQUIRE(w != nullptr, ND_ERR_DEVICE,
+             "no static workspace on device %d", g->ctx->device);
+  auto take = [&](int64_t bytes) {
+    uint8_t *p = w;
+    w += bytes;
+    return p;
+  };
+  LoopBufs b;
+  b.tau[0] = b.tau[1] = take(L.tau);
+  if (opts.mode != ND_AND) b.tau[1] = take(L.tau);
+  if (flags)
+    for (int i = 0; i < 2; i++) {
+      b.act[i] = take(L.flags);
+      b.act_sum[i] = take(L.sums);
+    }
+  b.ring = (SweepStats *)take(L.ring);
+  b.ring_len = kStaticRing;
+  if (L.snap) b.snap = (int32_t *)take(L.snap);
+  if (L.stage) b.stage = (int32_t *)take(L.stage);
+  return sweep_loop(g, ks, opts, kappa, on_device, s, res, r, nullptr, b);
+}
+
 nd_status decompose(nd_graph *g, nd_kind kind, const nd_opts *opts,
                     int32_t *kappa, int on_device, hipStream_t s,
                     nd_result *res) {
@@ -463,6 +513,21 @@ extern "C" nd_status nd_partial_and(nd_graph *g, nd_kind kind,
                         (hipStream_t)stream, res);
   });
   return st != ND_OK ? st : outst;
+}
+
+extern "C" nd_status nd_decompose_noalloc(nd_graph *g, nd_kind kind,
+                                          const nd_opts *opts, int32_t *kappa,
+                                          int on_device, void *stream,
+                                          nd_result *res) {
+  nd_status out = ND_OK;
+  nd_status st = guarded([&] {
+    ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_HIP(hipSetDevice(g->ctx->device));
+    StreamScope scope((hipStream_t)stream);
+    out = decompose_noalloc(g, kind, opts, kappa, on_device,
+                            (hipStream_t)stream, res);
+  });
+  return st != ND_OK ? st : out;
 }
 
 extern "C" nd_status nd_decompose(nd_graph *g, nd_kind kind,

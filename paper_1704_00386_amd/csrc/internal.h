@@ -105,8 +105,9 @@ struct nd_ctx {
   nd::Allocator alloc;
   int num_cu = 256;
   // Made once at creation, so that the sweep loop creates nothing on the
-  // host: the pinned read-back ring of the sweep counters (kHostStatsRing
-  // entries) and the timing events of the sweep loop (whole loop, one sweep).
+  // host (nd_decompose_noalloc relies on it): the pinned read-back ring of
+  // the sweep counters (kHostStatsRing entries) and the timing events of the
+  // sweep loop (whole loop, one sweep).
   void *host_stats = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::atomic<int> refs{1};    // the owner's reference + one per graph
@@ -318,6 +319,12 @@ struct SweepArgs {
   // over the rest of the bin); 0: one pass, no cap.
   int grid_cap;
 };
+
+// The static device workspace of nd_decompose_noalloc: one array per device
+// (api.hip), its address looked up when the first context on the device is
+// created; NULL before that.
+constexpr size_t kNoallocWorkspaceBytes = ND_NOALLOC_WORKSPACE_BYTES;
+void *noalloc_workspace(int device);
 
 // Entries of the pinned host ring that receives the sweep counters.
 constexpr int kHostStatsRing = 1024;
