@@ -49,7 +49,8 @@ def _compile(src: str) -> str:
 def _link(objs, lib: str) -> None:
     tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs,
-           "-o", tmp, "-lpthread"]
+           "-o", tmp, "-lpthread", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+           "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -257,6 +257,10 @@ __global__ void k_check_tau(const int32_t *__restrict__ tau,
 static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
   KindState &ks = g->ks[kind];
   if (ks.ready) return;
+  static const char *const kPhase[kNumKinds] = {
+      "nd.prepare.core", "nd.prepare.truss", "nd.prepare.nucleus34",
+      "nd.prepare.nucleus13", "nd.prepare.nucleus24"};
+  Phase phase(kPhase[kind]);
   hipEvent_t e0, e1;
   ND_HIP(hipEventCreate(&e0));
   ND_HIP(hipEventCreate(&e1));
@@ -423,6 +427,7 @@ nd_status nd_graph_from_edges(nd_ctx *ctx, int32_t n, int64_t m,
     ND_REQUIRE(ctx && out, ND_ERR_INVALID, "ctx/out is NULL");
     ND_REQUIRE(n >= 0 && m >= 0, ND_ERR_INVALID, "negative size");
     ND_REQUIRE(m == 0 || (src && dst), ND_ERR_INVALID, "src/dst is NULL");
+    Phase phase("nd.graph_from_edges");
     ND_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     StreamScope scope(s);
@@ -459,6 +464,7 @@ nd_status nd_graph_from_csr(nd_ctx *ctx, int32_t n, int64_t nnz,
     ND_REQUIRE(ctx && out && row_off, ND_ERR_INVALID, "NULL argument");
     ND_REQUIRE(n >= 0 && nnz >= 0, ND_ERR_INVALID, "negative size");
     ND_REQUIRE(nnz == 0 || col, ND_ERR_INVALID, "col is NULL");
+    Phase phase("nd.graph_from_csr");
     ND_HIP(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)stream;
     StreamScope scope(s);

@@ -781,7 +781,10 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
                "graph %d is NULL or from another context", i);
     was[i] = graphs[i]->ks[kind].ready;
   }
-  prepare_all(ctx, count, graphs, kind, s);
+  {
+    Phase phase("nd.batch.prepare");
+    prepare_all(ctx, count, graphs, kind, s);
+  }
   for (int i = 0; i < count; i++) {
     prep[i] = was[i] ? 0.0 : graphs[i]->ks[kind].ms_prep;
     all16 &= graphs[i]->ks[kind].tau16;
@@ -795,6 +798,7 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
   ND_HIP(hipEventCreate(&a));
   ND_HIP(hipEventCreate(&b));
   ND_HIP(hipEventRecord(a, bs));
+  Phase sweep_phase("nd.batch.sweeps");
   batch.poll(batch.autotune());
   int chunk = 2;
   for (;;) {

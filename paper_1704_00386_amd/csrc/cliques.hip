@@ -1373,7 +1373,10 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
     fill_i32(hcount.p, 0, ne, s);
     a.hcount = hcount.p;
   }
-  run_orient<false>(a, items.p, bin_off, hs, s);
+  {
+    Phase phase("nd.incidence.count");
+    run_orient<false>(a, items.p, bin_off, hs, s);
+  }
   if (hcount.p) {
     k_add_i32<<<grid_for(ne, 256), 256, 0, s>>>(cnt.p, hcount.p, ne);
     ND_LAUNCHED();
@@ -1393,6 +1396,7 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
   a.cursor = cursor.p;
   a.ids = ks.inc_ids.p;
   a.base_off = ks.inc_off.p;
+  Phase fill_phase("nd.incidence.fill");
   if (tri_buf.p)
     run_scatter(a, items.p, bin_off, hs, s);
   else
@@ -1402,6 +1406,7 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
 void build_triangles(nd_graph *g, hipStream_t s) {
   if (g->tris_ready) return;
   build_edges(g, s);
+  Phase phase("nd.triangles");
   Allocator &al = g->ctx->alloc;
   const int64_t ne = g->ne;
   DArr<int32_t> items;
@@ -1477,8 +1482,11 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   va.nlow = g->nlow.p;
   va.eoff = g->eoff.p;
   va.t = a;
-  run_n34_vertex(va, false, vitems.p, voff, s);
-  run_n34_tri(a, false, items.p, bin_off, s);
+  {
+    Phase phase("nd.incidence.count");
+    run_n34_vertex(va, false, vitems.p, voff, s);
+    run_n34_tri(a, false, items.p, bin_off, s);
+  }
   ks.nr = nt;
   build_layout(g, ks, cnt.p, s);
   cnt.free();
@@ -1496,6 +1504,7 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   a.rcur = rcur.p;
   a.out = ks.inc_ids.p;
   va.t = a;
+  Phase fill_phase("nd.incidence.fill");
   run_n34_vertex(va, true, vitems.p, voff, s);
   run_n34_tri(a, true, items.p, bin_off, s);
   if (nt > 0) {

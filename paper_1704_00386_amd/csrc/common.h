@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include <exception>
@@ -56,6 +57,16 @@ struct Err {
 #define ND_LAUNCHED() ND_HIP(hipGetLastError())
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// A named range around a phase of the path (graph build, enumeration,
+// incidence, layout, sweeps, output) for profilers that collect markers
+// (rocprofv3 --marker-trace); nothing happens when none listens.
+struct Phase {
+  explicit Phase(const char *name) { roctxRangePushA(name); }
+  ~Phase() { roctxRangePop(); }
+  Phase(const Phase &) = delete;
+  Phase &operator=(const Phase &) = delete;
+};
 
 // The (r,s) of every nd_kind and k = C(s,r) - 1, the number of other
 // r-cliques listed per s-clique.

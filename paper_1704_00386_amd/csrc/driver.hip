@@ -188,6 +188,7 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
   int64_t sweeps = 0, updates = 0;
   bool converged = false, stop_ratio = false, stop_cb = false;
   hipEvent_t *ev = ctx->ev;  // ev[0..1]: whole loop; ev[2..3]: one sweep
+  Phase sweeps_phase("nd.sweeps");
   ND_HIP(hipEventRecord(ev[0], s));
   // Lemma 2: the iteration is exact after at most (number of degree levels)
   // <= |R| sweeps, so |R| + 1 sweeps always observe convergence; the cap only
@@ -293,6 +294,7 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
   r.converged = converged ? 1 : 0;
   r.updates = updates;
   const void *result = b.tau[sweeps & 1];
+  Phase out_phase("nd.output");
   if (on_device) {
     to_original(ks, result, ks.tau16, kappa, s);
   } else {

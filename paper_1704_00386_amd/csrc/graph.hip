@@ -235,6 +235,7 @@ void build_rowid(nd_graph *g, hipStream_t s) {
 
 void build_edges(nd_graph *g, hipStream_t s) {
   if (g->edges_ready) return;
+  Phase phase("nd.edges");
   Allocator &al = g->ctx->alloc;
   const int32_t n = g->n;
   g->nlow.reset(al, n);

@@ -138,6 +138,7 @@ void init_tau(const KindState &ks, void *tau, hipStream_t s) {
 
 void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
                   hipStream_t s) {
+  Phase phase("nd.layout");
   Allocator &al = g->ctx->alloc;
   const int64_t nr = ks.nr;
   ND_REQUIRE(nr < ((int64_t)1 << 31), ND_ERR_INVALID,

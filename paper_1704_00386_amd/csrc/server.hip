@@ -196,6 +196,7 @@ void prep_main(nd_server *srv) {
     const Clock::time_point t0 = Clock::now();
     nd_status code = ND_OK;
     try {
+      Phase phase("nd.server.prepare");
       StreamScope scope(srv->prep_stream);
       prepare(r->g, r->kind, srv->prep_stream);
     } catch (const Err &e) {
@@ -315,6 +316,7 @@ void worker_main(nd_server *srv) {
                   if (((Request *)m->user)->cancelled) m->finished = true;
               }
               StreamScope scope(b->stream());
+              Phase phase("nd.server.epochs");
               const std::vector<Member *> live = b->live();
               b->run_epochs(chunk);
               srv->epochs += chunk;
