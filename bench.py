@@ -1,31 +1,36 @@
-"""Benchmark: k-truss (2,3) decomposition of a Chung-Lu power-law graph
-(2^20 vertices, degree exponent 2.1, mean degree 32) on one MI355X.
+"""Benchmark: (3,4)-nucleus decomposition of a stochastic block model
+(5000 communities of U{50..400} vertices, p_in 0.3, p_out 2e-6; 1.13M
+vertices, 4.2e8 triangles, 3.6e9 triangle-4-clique incidences) on one
+MI355X -- the largest single-GPU configuration of the workloads.
 
 One step is the whole path on a graph whose raw edge list is already in HBM:
-canonical CSR -> edge numbering -> triangle incidence lists -> d_s -> SND
-sweeps (notification frontier on) until a sweep changes nothing.  ``value`` is r-clique h-index updates
-(the r-cliques with d_s > 0, each sweep; the others are exact from the start)
-per second of step time; the step time itself is the time-to-exact-convergence
-including preparation.
+canonical CSR -> edge and triangle numbering -> 4-clique incidence lists ->
+d_s -> SND sweeps (notification frontier on) until a sweep changes nothing.
+``value`` is the r-clique h-index evaluations the step performs (the
+frontier skips r-cliques that cannot change; the iterates are those of
+plain SND) per second of step time; the step time itself is the
+time-to-exact-convergence including preparation.
 
 Also reported on the same line:
-  * ``roofline``: the sweep's algorithmic bytes (see sweep_bytes)
-    over its average device time per sweep (HIP events on the library's
-    stream), against the 8 TB/s HBM peak; ``traffic`` from rocprofv3 counters
-    when a summary for the current kernels is present (else null);
-  * ``full_sweeps``: the same graph by SND recomputing every r-clique each
-    sweep (the roofline is taken on these launches);
-  * ``and``: the same graph decomposed by AND (sweeps, time);
-  * ``stream``: batched and served decomposition of a sample of the
-    request-stream workload against one graph per launch;
-  * ``small_graphs``: the same comparison on small graphs only (n <= 5000),
-    where each graph alone is launch-bound;
-  * ``degree_levels``: the number of degree levels of the same graph (the
-    bound on SND sweeps) beside the SND and AND sweep counts;
-  * ``ego``: PartialAND estimates on the ego networks of random edges of the
-    same graph, one call for all queries, with their accuracy;
-  * ``cpu_baseline``: the CPU oracle's update operator timed on the host over
-    a bounded sample of the same graph's r-cliques.
+  * ``roofline``: the update kernel in full sweeps (every r-clique with
+    d_s > 0 recomputed) on the same prepared graph: algorithmic bytes (see
+    sweep_bytes) over its device time per sweep (HIP events on the
+    library's stream), against the 8 TB/s HBM peak; ``traffic`` from the
+    committed rocprofv3 counters when they were taken on the current sweep
+    kernels (else null);
+  * ``ceilings``: a streaming read, a streaming copy and the sweep's gather
+    pattern alone (its id stream and tau gathers, no h-index) measured on
+    this device, with the update kernel's fraction of each;
+  * ``and``: the same graph decomposed by AND;
+  * ``truss_cl20`` / ``core_cl23``: the k-truss (Chung-Lu 2^20) and k-core
+    (Chung-Lu 2^23) workloads: SND and AND time to exact with and without
+    preparation, full-sweep roofline; for k-core the fraction of exact
+    values and of active r-cliques after every sweep;
+  * ``stream`` / ``small_graphs``: batched and served k-truss against one
+    graph per launch on a sample of the request-stream workload;
+  * ``ego``: PartialAND estimates on ego networks of random cl20 edges;
+  * ``cpu_baseline``: the CPU oracle's update operator timed on the host
+    over a bounded sample of the block model's triangles.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -33,6 +38,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -42,8 +48,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "cl20"
-KIND = "truss"
+HEADLINE = "sbm"
+HEADLINE_KIND = "nucleus34"
+STREAM_BUDGET = 96 << 30  # device-memory budget of the served stream
+K_OF = {"core": 1, "truss": 2, "nucleus34": 3}
+
+
+def progress(msg: str) -> None:
+    """A line on stderr when a step or leg has finished (stdout carries only
+    the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def sweep_bytes(P: int, nr_eval: int, k: int, tb: int) -> int:
@@ -54,35 +68,49 @@ def sweep_bytes(P: int, nr_eval: int, k: int, tb: int) -> int:
     return (4 + tb) * k * P + (8 + 2 * tb) * nr_eval
 
 
-def cpu_baseline(raw, kind, budget_s=15.0):
-    """The oracle's update operator on a contiguous sample of r-cliques (ids
-    are a random relabelling, so a contiguous range is an unbiased sample)."""
+def cpu_baseline(budget_s=10.0, seed=4):
+    """The oracle's update operator on the triangles of whole communities of
+    the block model, taken as one graph: the disjoint union of the sampled
+    communities' induced subgraphs.  No 4-clique of this workload leaves a
+    community (the full-size digest checks it), so U on those triangles is
+    the same there as in the whole graph.  Communities are drawn at random;
+    their number is calibrated so that U takes about budget_s."""
     import numpy as np
 
     import oracle
-    r, s = oracle.KINDS[kind]
+    from synth import sbm
+
+    raw, labels = sbm(seed=seed, with_communities=True)
     threads = oracle.default_threads()
-    og = oracle.Graph.from_raw(raw)
-    nr = og.num_rcliques(r)
-    tau = og.sdeg(r, s, threads)
-    # calibrate on a small range, then size the sample to ~budget_s
-    n0 = min(nr, 20000)
-    t = time.perf_counter()
-    og.update(r, s, tau, lo=0, hi=n0, threads=threads)
-    rate0 = n0 / max(time.perf_counter() - t, 1e-9)
-    n = int(min(nr, max(n0, rate0 * budget_s)))
-    lo = n0
-    hi = min(nr, lo + n)
-    t = time.perf_counter()
-    og.update(r, s, tau, lo=lo, hi=hi, threads=threads)
-    dt = time.perf_counter() - t
-    del og
-    # count the r-cliques with d_s > 0, as the GPU figure does
-    upd = int(np.count_nonzero(tau[lo:hi]))
+    intra = labels[raw.src] == labels[raw.dst]
+    es, ed, el = raw.src[intra], raw.dst[intra], labels[raw.src[intra]]
+    ncomm = int(labels.max()) + 1
+    order = np.random.default_rng(seed + 1).permutation(ncomm)
+
+    def union_of(comms):
+        pick = np.isin(el, comms)
+        s, d = es[pick], ed[pick]
+        verts = np.unique(np.concatenate([s, d]))
+        return (verts.size, np.searchsorted(verts, s).astype(np.int32),
+                np.searchsorted(verts, d).astype(np.int32))
+
+    def time_u(comms):
+        n, s, d = union_of(comms)
+        og = oracle.Graph(n, s, d)
+        ds = og.sdeg(3, 4, threads)
+        t = time.perf_counter()
+        og.update(3, 4, ds, threads=threads)
+        dt = time.perf_counter() - t
+        return int(np.count_nonzero(ds)), dt, og.num_rcliques(3)
+
+    upd0, dt0, _ = time_u(order[:20])
+    want = int(min(ncomm, max(20, 20 * budget_s / max(dt0, 1e-6))))
+    upd, dt, nt = time_u(order[:want])
     return {"value": upd / dt, "unit": "r-clique h-index updates/s",
             "cores": threads, "kind": "oracle",
-            "sample": f"U applied to r-cliques {lo}..{hi} of {nr} "
-                      f"({upd} with d_s > 0, tau = d_s) in {dt:.1f} s"}
+            "sample": f"U applied to the {nt} triangles ({upd} with d_s > 0, "
+                      f"tau = d_s) of {want} of the {ncomm} communities "
+                      f"(random, seed {seed + 1}) in {dt:.1f} s"}
 
 
 def sweep_source_hash() -> str:
@@ -96,12 +124,15 @@ def sweep_source_hash() -> str:
     return h.hexdigest()
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_sbm_nucleus34.json")
+
+
 def measured_traffic():
-    """HBM bytes per full sweep from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on different sweep kernels."""
-    path = os.path.join(ROOT, "profiles", "traffic_sweep_cl20_truss.json")
+    """HBM bytes per full sweep of the headline workload from the committed
+    rocprofv3 counter record, or None when it is missing or was taken on
+    different sweep kernels."""
     try:
-        rec = json.load(open(path))
+        rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if rec.get("sweep_source_sha256") != sweep_source_hash():
@@ -110,6 +141,7 @@ def measured_traffic():
 
 
 FULL_SWEEP_SUFFIX = ", false, false>"  # k_sweep_*<..., AND, frontier>
+HEADLINE_FLAGS = "--only-headline --steps 2 --warmup 1 --calib-copy"
 
 
 def _short_kernel(name: str) -> str:
@@ -120,37 +152,32 @@ def _short_kernel(name: str) -> str:
 
 def _profile_command(args_extra: str, out: str) -> str:
     return (f"rocprofv3 {args_extra} --output-format csv -d $OUT/{out} -o {out} "
-            "-- python3 $R/bench.py --steps 1 --warmup 0 --no-cpu --stream-graphs 0 "
-            "--small-graphs 0 --ego-queries 0 --no-nucleus34 --calib-copy")
+            f"-- python3 $R/bench.py {HEADLINE_FLAGS}")
 
 
 def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
-    """Write the committed profile summaries from the CSV output of three
-    rocprofv3 runs of this script (see the commands recorded in them): the
-    kernel trace statistics of one bench run, and FETCH_SIZE / WRITE_SIZE per
-    dispatch, scaled by what the same counters read for the 1 GiB device copy
-    that --calib-copy makes first in the same run."""
+    """Write the committed profile summaries of the headline workload from
+    the CSV output of three rocprofv3 runs of `bench.py --only-headline`
+    (see the commands recorded in them): the kernel trace statistics, and
+    FETCH_SIZE / WRITE_SIZE per dispatch, scaled by what the same counters
+    read for the 1 GiB device copy that --calib-copy makes first."""
     import csv
     import statistics
 
     out_dir = os.path.join(ROOT, "profiles")
-    # kernel trace statistics
     rows = list(csv.DictReader(open(trace_csv)))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
-    lines = ["# Kernel trace: one bench step (k-truss SND on Chung-Lu 2^20, beta 2.1, mean 32)", "",
+    lines = ["# Kernel trace: the headline leg ((3,4) SND on the block model)", "",
              "Command (run from /tmp, `TMPDIR=/tmp`, repo at `$R`, output under `$OUT`):", "", "```",
              _profile_command("--kernel-trace --stats", "kt"), "```", "",
-             "The run holds one timed step (build + prep + SND with the notification frontier), the",
-             "full-sweep roofline leg (SND, every r-clique recomputed each sweep), two more steps from a",
-             "pinned host edge list (host_io leg) and the AND leg (frontier), after a 1 GiB device copy.",
-             "Each SND decompose enqueues sweeps in doubling chunks, so its last chunk also launches a few",
-             "sweeps past convergence that return at once (62 launches per kernel for 47 sweeps).",
-             "Template arguments of `k_sweep_regs<k, lanes, values/lane, tau type, AND, frontier>`;",
-             "`k_sweep_small<k, tau type, AND, frontier>` sweeps the bins of at most 16 values per lane",
-             "(d_s 1..1024) in one launch.", "",
+             "The run holds a 1 GiB device copy, one warm-up and two timed steps (build + prepare +",
+             "SND with the notification frontier until exact), the full-sweep roofline leg (4 SND",
+             "sweeps recomputing every r-clique), AND with the frontier, and the ceiling kernels.",
+             "`k_sweep_small<k, tau type, AND, frontier>` sweeps the bins of at most 16 values per",
+             "lane (d_s 1..1024) in one launch; `<3, unsigned short, false, false>` is the full sweep.", "",
              "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
     full_avg = 0.0
-    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:32]:
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:36]:
         name = _short_kernel(r["Name"])
         avg = float(r["AverageNs"]) / 1e3
         if name.startswith("k_sweep_") and name.endswith(FULL_SWEEP_SUFFIX):
@@ -159,9 +186,8 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {avg:.1f} | `{name}` |")
     lines += ["", f"Full sweep = the `k_sweep_*<..., false, false>` launches of a sweep: "
               f"{full_avg:.0f} us per sweep (sum of their averages)."]
-    open(os.path.join(out_dir, "kernel_trace_cl20_truss.md"), "w").write("\n".join(lines) + "\n")
+    open(os.path.join(out_dir, "kernel_trace_sbm_nucleus34.md"), "w").write("\n".join(lines) + "\n")
 
-    # calibrated HBM-side traffic of one full sweep
     def per_kernel(path, counter):
         vals, copy = {}, []
         for r in csv.DictReader(open(path)):
@@ -182,7 +208,8 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
     f_kib = sum(statistics.mean(fetch[k]) for k in full)
     w_kib = sum(statistics.mean(write.get(k, [0.0])) for k in full)
     rec = {
-        "workload": "k-truss SND, full sweeps, Chung-Lu n=2^20 beta 2.1 mean 32 seed 2",
+        "workload": "(3,4) SND, full sweeps, block model (5000 communities of U{50..400}, "
+                    "p_in 0.3, p_out 2e-6, seed 4)",
         "kernels": full,
         "fetch_bytes_per_sweep": f_kib * 1024 * fscale,
         "write_bytes_per_sweep": w_kib * 1024 * wscale,
@@ -193,8 +220,8 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
         "commands": [_profile_command("--pmc FETCH_SIZE", "pf"),
                      _profile_command("--pmc WRITE_SIZE", "pw")],
     }
-    json.dump(rec, open(os.path.join(out_dir, "traffic_sweep_cl20_truss.json"), "w"), indent=1)
-    md = ["# HBM-side traffic of one full sweep (k-truss SND, Chung-Lu 2^20)", "",
+    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    md = ["# HBM-side traffic of one full sweep ((3,4) SND, block model)", "",
           "Counters per dispatch (KiB), averaged over the full sweeps of the roofline leg and summed over",
           "the bin kernels of a sweep, then scaled by what the same counter reads for a 1 GiB",
           f"device-to-device copy in the same run (FETCH_SIZE reads {fcopy / 1024:.0f} MiB for it, "
@@ -209,9 +236,9 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
     md += ["", "Commands (run from /tmp, `TMPDIR=/tmp`, repo at `$R`, output under `$OUT`), then "
            "`python bench.py --summarize-profiles <trace stats csv> <fetch csv> <write csv>`:", "", "```",
            *rec["commands"], "```", "",
-           "These counters measure L2-to-fabric traffic, which includes Infinity Cache (MALL) hits; the",
-           "tau array (33 MB as uint16) fits in the MALL, so this is an upper bound on DRAM bytes."]
-    open(os.path.join(out_dir, "traffic_sweep_cl20_truss.md"), "w").write("\n".join(md) + "\n")
+           "These counters measure L2-to-fabric traffic, which includes Infinity Cache (MALL) hits,",
+           "so they bound DRAM bytes from above."]
+    open(os.path.join(out_dir, "traffic_sweep_sbm_nucleus34.md"), "w").write("\n".join(md) + "\n")
     print(f"full sweep {full_avg:.0f} us; HBM-side {rec['hbm_bytes_per_sweep'] / 1e9:.2f} GB per sweep")
 
 
@@ -223,23 +250,31 @@ def summarize_quality(json_path: str) -> None:
     L = [f"# Accuracy per sweep: {kind} on the `{name}` workload ({q['n_rcliques']} r-cliques)", "",
          f"Command (repo root): `python bench.py --quality {name}`", "",
          "`fraction_exact`: share of all r-cliques with tau_t = kappa.  `kendall_tau`: scipy's tau-b of",
-         f"tau_t against kappa on a uniform sample of {q['kendall_sample']} r-cliques.  `ms_cum`: summed device",
-         "time of sweeps 1..t (events around each sweep's launches; sweeps run one at a time here).", "",
+         f"tau_t against kappa on a uniform sample of {q['kendall_sample']} r-cliques.  `active`: share of",
+         "all r-cliques that the notifications flag for the next sweep (the indicator of Section",
+         "5.1.4).  `changed`: share that changed in the sweep.  `ms_cum`: summed device time of",
+         "sweeps 1..t (events around each sweep's launches; sweeps run one at a time and count the",
+         "active flags here).", "",
          f"Degree levels (Defn. 4; the bound on SND sweeps): {q['degree_levels']}.  "
          f"SND sweeps: {len(q['snd']['rows']) - 1}; AND sweeps: {len(q['and']['rows']) - 1}."]
     for mode in ("snd", "and"):
         m = q[mode]
         L += ["", f"## {mode.upper()}", "",
-              "Active-ratio stop (stop once fewer than this share of r-cliques changed):", "",
-              "| ratio | sweep | ms | fraction exact | Kendall-Tau |", "|---:|---:|---:|---:|---:|"]
-        for ratio, st in m["active_ratio_stops"].items():
-            L.append(f"| {ratio} | {st['sweep']} | {st['ms_cum']:.2f} | "
-                     f"{st['fraction_exact']:.4f} | {st['kendall_tau']:.4f} |")
-        L += ["", "| sweep | changed | ms (cum.) | fraction exact | Kendall-Tau |",
-              "|---:|---:|---:|---:|---:|"]
+              "Stops: after the first sweep whose active (paper's indicator) or changed share falls",
+              "below the ratio:", "",
+              "| ratio | by | sweep | ms | fraction exact | Kendall-Tau |",
+              "|---:|---|---:|---:|---:|---:|"]
+        for by in ("active", "changed"):
+            for ratio, st in m[f"{by}_ratio_stops"].items():
+                L.append(f"| {ratio} | {by} | {st['sweep']} | {st['ms_cum']:.2f} | "
+                         f"{st['fraction_exact']:.4f} | {st['kendall_tau']:.4f} |")
+        L += ["", "| sweep | active | changed | ms (cum.) | fraction exact | Kendall-Tau |",
+              "|---:|---:|---:|---:|---:|---:|"]
+        nr = q["n_rcliques"]
         for r in m["rows"]:
-            ch = "" if r["changed"] is None else r["changed"]
-            L.append(f"| {r['sweep']} | {ch} | {r['ms_cum']:.2f} | {r['fraction_exact']:.5f} | "
+            a = "" if r["active"] is None else f"{r['active'] / nr:.5f}"
+            c = "" if r["changed"] is None else f"{r['changed'] / nr:.5f}"
+            L.append(f"| {r['sweep']} | {a} | {c} | {r['ms_cum']:.2f} | {r['fraction_exact']:.5f} | "
                      f"{r['kendall_tau']:.5f} |")
     path = os.path.join(ROOT, "profiles", f"quality_{name}_{kind}.md")
     open(path, "w").write("\n".join(L) + "\n")
@@ -247,10 +282,8 @@ def summarize_quality(json_path: str) -> None:
 
 
 TRACE_RUNS = {
-    "sbm_nucleus34": ("(3,4)-nucleus on the stochastic block model (5000 communities of "
-                      "U{50..400} vertices, p_in 0.3, p_out 2e-6, seed 4): build + prepare, "
-                      "SND and AND with the frontier until exact, 4 full sweeps",
-                      "--only-nucleus34"),
+    "stream_truss": ("batched and served k-truss on a sample of the request-stream workload "
+                     "(the stream leg alone)", "--only-stream"),
 }
 
 
@@ -277,48 +310,259 @@ def summarize_trace(stats_csv: str, name: str) -> None:
     print(path)
 
 
+# ----------------------------------------------------------------- legs
+
+
+def device_edges(raw):
+    import torch
+    src = torch.from_numpy(raw.src).cuda()
+    dst = torch.from_numpy(raw.dst).cuda()
+    torch.cuda.synchronize()
+    return src, dst
+
+
+def timed_steps(nd, ctx, raw, src, dst, kind, steps, warmup, mode="snd"):
+    """Build + prepare + decompose (frontier on) from the edge list in HBM,
+    `warmup` untimed then `steps` timed; returns (last graph, kappa, results,
+    step times in ms)."""
+    import torch
+
+    def step():
+        g = nd.Graph.from_edges(ctx, raw.n, src, dst)
+        kappa, res = g.decompose(kind, mode, use_frontier=True)
+        return g, kappa, res
+
+    for _ in range(warmup):
+        g, _, _ = step()
+        g.close()
+    torch.cuda.synchronize()
+    times, results = [], []
+    g = kappa = None
+    for i in range(steps):
+        if g is not None:
+            g.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, kappa, res = step()
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+        results.append(res)
+        progress(f"{raw.name} {kind} {mode} step {i + 1}/{steps}: {times[-1]:.1f} ms")
+    return g, kappa, results, times
+
+
+def full_sweep_roofline(g, kind, res, sweeps=None):
+    """Full SND sweeps (every r-clique with d_s > 0 recomputed) on a prepared
+    graph, each timed with HIP events on the library's stream (nd_iter_info.ms);
+    algorithmic bytes per sweep over the mean sweep time."""
+    import numpy as np
+
+    nr_eval = int(np.count_nonzero(g.sdegree(kind).cpu().numpy()))
+    ms = []
+
+    def collect(info):
+        ms.append(info.ms)
+        return 0
+
+    kfull, rfull = g.decompose(kind, "snd", on_iter=collect,
+                               max_iters=-1 if sweeps is None else sweeps,
+                               allow_not_converged=True)
+    B = sweep_bytes(res["n_incidence"], nr_eval, K_OF[kind], res["tau_bytes"])
+    avg = sum(ms) / len(ms)
+    return {"nr_eval": nr_eval, "bytes_per_sweep": B, "avg_sweep_ms": avg,
+            "sweeps_timed": len(ms), "achieved_GBs": B / (avg * 1e-3) / 1e9,
+            "kappa": kfull, "res": rfull}
+
+
+def ceilings(nd, g, kind, tau_bytes):
+    """Streaming read, streaming copy and the sweep's gather pattern (its id
+    stream and tau gathers without the h-index) on this device, timed with
+    events on the current stream by libndceil.so."""
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1704_00386_amd", "libndceil.so"))
+    lib.ndc_read.restype = ctypes.c_float
+    lib.ndc_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                             ctypes.c_void_p]
+    lib.ndc_copy.restype = ctypes.c_float
+    lib.ndc_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                             ctypes.c_void_p]
+    lib.ndc_gather.restype = ctypes.c_float
+    lib.ndc_gather.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                               ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                               ctypes.c_void_p]
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nbytes = 8 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    reads = [lib.ndc_read(a.data_ptr(), nbytes, sink.data_ptr(), st) for _ in range(3)]
+    copies = [lib.ndc_copy(a.data_ptr(), b.data_ptr(), nbytes, st) for _ in range(3)]
+    del a, b
+    off, ids = g.incidence(kind)
+    k = ids.shape[1]
+    ds = g.sdegree(kind)
+    tau = ds.to(torch.int16) if tau_bytes == 2 else ds
+    del off
+    nsets = ids.shape[0]
+    gathers = [lib.ndc_gather(ids.data_ptr(), nsets, k, tau.data_ptr(),
+                              0 if tau_bytes == 2 else 1, sink.data_ptr(), st)
+               for _ in range(3)]
+    del ids, tau
+    torch.cuda.synchronize()
+    gb = (4 + tau_bytes) * k * nsets
+    return {"read_GBs": nbytes / (min(reads) * 1e-3) / 1e9,
+            "copy_GBs": 2 * nbytes / (min(copies) * 1e-3) / 1e9,
+            "gather_GBs": gb / (min(gathers) * 1e-3) / 1e9,
+            "gather_bytes": gb, "gather_ms": min(gathers),
+            "what": "8 GiB streamed with 16-byte loads (read) and loads+stores "
+                    "(copy); the incidence ids (r-clique-id order) with one "
+                    f"{tau_bytes}-byte tau gather per id, min per s-clique "
+                    "(gather); best of 3 each"}
+
+
+def headline_leg(nd, ctx, args):
+    """The headline: (3,4) SND with the frontier on the block model, then the
+    full-sweep roofline, AND and the ceilings on the prepared graph."""
+    import numpy as np
+    import torch
+
+    from synth import workload
+
+    raw = workload(HEADLINE)
+    src, dst = device_edges(raw)
+    g, kappa, results, times = timed_steps(nd, ctx, raw, src, dst, HEADLINE_KIND,
+                                           args.steps, args.warmup)
+    del src, dst
+    res = results[-1]
+    ms_step = sum(times) / len(times)
+    nr_eval = int(np.count_nonzero(g.sdegree(HEADLINE_KIND).cpu().numpy()))
+    roof = full_sweep_roofline(g, HEADLINE_KIND, res, sweeps=4)
+    kand, rand = g.decompose(HEADLINE_KIND, "and", use_frontier=True)
+    out = {"raw": raw, "g": g, "kappa": kappa, "res": res, "times": times,
+           "ms_step": ms_step, "nr_eval": nr_eval, "roof": roof,
+           "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
+                   "frontier": True,
+                   "kappa_equals_snd": bool(torch.equal(kand, kappa))}}
+    del kand
+    progress("headline roofline and AND legs done")
+    if not args.no_ceilings:
+        out["ceilings"] = ceilings(nd, g, HEADLINE_KIND, res["tau_bytes"])
+        progress("ceilings done")
+    return out
+
+
+def workload_leg(nd, ctx, name, kind, quality=False):
+    """One of the other single-GPU workloads: SND and AND (frontier) time to
+    exact with and without preparation (one warm step, then one timed), the
+    full-sweep roofline, and with `quality` the fraction of exact values and
+    of active r-cliques after every SND sweep."""
+    import numpy as np
+    import torch
+
+    from synth import workload
+
+    raw = workload(name)
+    src, dst = device_edges(raw)
+    out = {"workload": raw.name, "kind": kind}
+    g = kappa = None
+    for mode in ("snd", "and"):
+        if g is not None:
+            g.close()
+        g, k, results, times = timed_steps(nd, ctx, raw, src, dst, kind, 1, 1,
+                                           mode=mode)
+        r = results[-1]
+        out[mode] = {"time_to_exact_ms": times[-1], "ms_iterate": r["ms_iterate"],
+                     "ms_prep": times[-1] - r["ms_iterate"], "sweeps": r["sweeps"],
+                     "evaluated_updates": r["updates"],
+                     "evaluated_updates_per_s": r["updates"] / (times[-1] * 1e-3)}
+        if kappa is None:
+            kappa = k
+        else:
+            out["kappa_and_equals_snd"] = bool(torch.equal(k, kappa))
+    del src, dst
+    res = results[-1]
+    roof = full_sweep_roofline(g, kind, res)
+    out["n_rcliques"] = res["n_rcliques"]
+    out["incidence_P"] = res["n_incidence"]
+    out["tau_bytes"] = res["tau_bytes"]
+    nre = roof["nr_eval"]
+    out["snd"]["full_sweep_equivalent_updates_per_s"] = (
+        nre * out["snd"]["sweeps"] / (out["snd"]["time_to_exact_ms"] * 1e-3))
+    out["full_sweep"] = {"avg_ms": roof["avg_sweep_ms"],
+                         "bytes_per_sweep": roof["bytes_per_sweep"],
+                         "achieved_GBs": roof["achieved_GBs"],
+                         "frac_of_hbm_peak": roof["achieved_GBs"] / HBM_PEAK_GBS,
+                         "kappa_equals_frontier": bool(torch.equal(roof["kappa"], kappa))}
+    if quality:
+        nr = kappa.numel()
+        snap = torch.empty(max(nr, 1), dtype=torch.int32, device="cuda")
+        curve = []
+
+        def on_iter(info):
+            rc = nd._hip.hipMemcpy(snap.data_ptr(), info.tau_dev, 4 * nr, 3)
+            if rc != 0:
+                raise RuntimeError(f"hipMemcpy failed ({rc})")
+            curve.append({"sweep": int(info.iter),
+                          "fraction_exact": int((snap[:nr] == kappa).sum()) / nr,
+                          "active": int(info.active_next) / nr,
+                          "changed": int(info.changed) / nr})
+            return 0
+
+        g.decompose(kind, "snd", use_frontier=True, count_active=True,
+                    on_iter=on_iter)
+        out["snd_per_sweep"] = curve
+    progress(f"{name} leg done")
+    return out, g, kappa
+
+
 def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     """Batched and served k-truss against one graph per launch, on `count`
     graphs of the request-stream workload (Chung-Lu, n ~ U{n_lo..n_hi},
     mean degree ~ U[8,64], exponent ~ U[2.0,2.5]).  Edge lists are resident
     in HBM before timing; every path builds, prepares and decomposes its
-    graphs (frontier SND, the same iterates as plain SND)."""
+    graphs (frontier SND, the same iterates as plain SND).  The server runs
+    on a context with a device-memory budget of STREAM_BUDGET bytes and
+    admits requests by it."""
+    import concurrent.futures as cf
+
     import numpy as np
     import torch
 
     from synth import chung_lu, request_stream
 
     specs = request_stream(count=count, n_lo=n_lo, n_hi=n_hi, seed=seed)
-    raws = [chung_lu(sp["n"], sp["beta"], sp["mean"], sp["seed"]) for sp in specs]
+    progress(f"generating {count} stream graphs")
+    with cf.ThreadPoolExecutor(8) as ex:
+        raws = list(ex.map(lambda sp: chung_lu(sp["n"], sp["beta"], sp["mean"],
+                                               sp["seed"]), specs))
     dev = [(r.n, torch.from_numpy(r.src).cuda(), torch.from_numpy(r.dst).cuda())
            for r in raws]
+    del raws
+    kind = "truss"
     updates = 0
-
-    # warm the allocator and kernels once
-    for n, s, d in dev[:4]:
-        nd.Graph.from_edges(ctx, n, s, d).decompose(KIND, "snd", use_frontier=True)
+    for n, s, d in dev[:4]:  # warm the allocator and kernels once
+        nd.Graph.from_edges(ctx, n, s, d).decompose(kind, "snd", use_frontier=True)
     torch.cuda.synchronize()
-    # one graph per launch sequence: build, prepare, decompose, next
     t0 = time.perf_counter()
     solo = []
     for n, s, d in dev:
         g = nd.Graph.from_edges(ctx, n, s, d)
-        k, r = g.decompose(KIND, "snd", use_frontier=True)
+        k, r = g.decompose(kind, "snd", use_frontier=True)
         solo.append(k)
         updates += r["updates"]
         g.close()
     torch.cuda.synchronize()
     t_solo = time.perf_counter() - t0
-    # batched: build all, then one call that prepares them (several host
-    # threads and streams) and sweeps them together
     t0 = time.perf_counter()
     gs = [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev]
-    ks, rs = nd.batch_decompose(ctx, gs, KIND, "snd", use_frontier=True)
+    ks, rs = nd.batch_decompose(ctx, gs, kind, "snd", use_frontier=True)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     same = all(torch.equal(a, b) for a, b in zip(ks, solo))
     for g in gs:
         g.close()
+    del gs, ks
     out = {
         "graphs": count,
         "workload": f"request stream of Chung-Lu k-truss graphs, n ~ U{{{n_lo}.."
@@ -330,93 +574,42 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
     }
     if serve:
         # served: Poisson arrivals at 80% of the one-graph-per-launch rate
+        sctx = nd.Context(0, hbm_budget_bytes=STREAM_BUDGET)
         rate = 0.8 * count / t_solo
         gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
         arrive = np.cumsum(gaps) - gaps[0]
-        srv = nd.Server(ctx, max_slots=64)
+        srv = nd.Server(sctx, max_slots=64)
         tickets = []
         t0 = time.perf_counter()
         for i, (n, s, d) in enumerate(dev):
             while time.perf_counter() - t0 < arrive[i]:
                 time.sleep(0.0002)
-            tickets.append(srv.submit(nd.Graph.from_edges(ctx, n, s, d), KIND,
+            tickets.append(srv.submit(nd.Graph.from_edges(sctx, n, s, d), kind,
                                       use_frontier=True))
-        lats = []
+        lats, joined, peak, prep_overlap = [], 0, 0, 0
         for t, want in zip(tickets, solo):
             kappa, r, info = srv.wait(t)
             lats.append(info["latency_ms"])
+            joined += info["joined_running"]
+            peak = max(peak, info["peak_members"])
+            prep_overlap += info["epochs_during_prep"] > 0
             same &= bool(torch.equal(kappa, want.cpu()))
         t_srv = time.perf_counter() - t0
         srv.close()
+        del sctx
         out["served"] = {"arrival_rate_per_s": rate, "graphs_per_s": count / t_srv,
                          "p50_ms": float(np.percentile(lats, 50)),
-                         "p99_ms": float(np.percentile(lats, 99))}
+                         "p99_ms": float(np.percentile(lats, 99)),
+                         "hbm_budget_bytes": STREAM_BUDGET,
+                         "joined_running_batch": joined,
+                         "peak_requests_per_epoch": peak,
+                         "prepared_while_sweeping": prep_overlap}
     out["results_identical"] = bool(same)
+    progress(f"stream leg ({count} graphs) done")
     return out
 
 
-def nucleus34_leg(nd, ctx, full_sweeps=4):
-    """(3,4)-nucleus decomposition of the stochastic block model workload
-    (5000 communities of U{50..400} vertices, p_in 0.3, p_out 2e-6, seed 4;
-    triangles as r-cliques, 4-clique incidence lists): the edge list already
-    in HBM, build + prepare, then SND and AND with the notification frontier
-    until exact, and a few full sweeps (every r-clique with d_s > 0
-    recomputed) for the roofline of the k = 3 sweep kernels."""
-    import numpy as np
-    import torch
-
-    from synth import workload
-
-    raw = workload("sbm")
-    src = torch.from_numpy(raw.src).cuda()
-    dst = torch.from_numpy(raw.dst).cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g = nd.Graph.from_edges(ctx, raw.n, src, dst)
-    g.prepare("nucleus34")
-    torch.cuda.synchronize()
-    ms_prep = 1e3 * (time.perf_counter() - t0)
-    del src, dst
-    nr, P, dev_bytes = g.sizes("nucleus34")
-    out = {"workload": "(3,4)-nucleus on the stochastic block model: 5000 "
-                       "communities of U{50..400} vertices, p_in 0.3, "
-                       "p_out 2e-6, seed 4",
-           "n": raw.n, "raw_pairs": raw.m, "triangles": nr, "incidence_P": P,
-           "device_bytes": dev_bytes, "ms_build_prepare": ms_prep}
-    kappa = None
-    for mode in ("snd", "and"):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        k, r = g.decompose("nucleus34", mode, use_frontier=True)
-        torch.cuda.synchronize()
-        out[mode] = {"sweeps": r["sweeps"], "ms": 1e3 * (time.perf_counter() - t0),
-                     "ms_iterate": r["ms_iterate"], "updates": r["updates"]}
-        tau_bytes = r["tau_bytes"]
-        if kappa is None:
-            kappa = k
-        else:
-            out["kappa_and_equals_snd"] = bool(torch.equal(k, kappa))
-    nr_eval = int(np.count_nonzero(g.sdegree("nucleus34").cpu().numpy()))
-    sweep_ms = []
-
-    def collect(info):
-        sweep_ms.append(info.ms)
-        return 0
-
-    g.decompose("nucleus34", "snd", max_iters=full_sweeps, on_iter=collect,
-                allow_not_converged=True)
-    avg = sum(sweep_ms) / len(sweep_ms)
-    B = sweep_bytes(P, nr_eval, 3, tau_bytes)
-    out["full_sweep"] = {"sweeps_timed": len(sweep_ms), "avg_ms": avg,
-                         "bytes_per_sweep": B,
-                         "achieved_GBs": B / (avg * 1e-3) / 1e9,
-                         "frac_of_hbm_peak": B / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    out["kappa_max"] = int(kappa.max()) if kappa.numel() else 0
-    g.close()
-    return out
-
-
-def ego_leg(g, kappa, count, seed=13):
+def ego_leg(nd, g, kappa, kind, count, seed=13):
     """PartialAND estimates on the ego networks of `count` random r-cliques
     of the prepared graph, all in one call: throughput, and accuracy against
     the exact kappa (share exact, mean relative error) -- the comparison of
@@ -427,10 +620,10 @@ def ego_leg(g, kappa, count, seed=13):
     nr = kappa.numel()
     q = torch.from_numpy(np.random.default_rng(seed).integers(
         0, nr, size=count).astype(np.int32)).cuda()
-    g.ego_estimate(KIND, q[:64])  # warm
+    g.ego_estimate(kind, q[:64])  # warm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    est, sw = g.ego_estimate(KIND, q)
+    est, sw = g.ego_estimate(kind, q)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k = kappa[q.long()].to(torch.float64)
@@ -445,12 +638,14 @@ def ego_leg(g, kappa, count, seed=13):
 
 def quality_leg(nd, name, sample=1_000_000, seed=9):
     """Per-sweep accuracy of the iterates against the exact result (the
-    approximation trade-off of Sections 5.2-5.3): fraction of r-cliques whose
-    tau_t equals kappa (all of them) and the Kendall-Tau similarity of tau_t
-    and kappa (scipy's tau-b on a uniform sample of r-cliques), with each
-    sweep's device time, for SND and AND on one of the named workloads.
-    Also the stop points of the active-ratio control (stop once fewer than
-    40% / 10% / 1% of the r-cliques changed in a sweep)."""
+    approximation trade-off of Sections 5.1.4 and 5.2.3): fraction of
+    r-cliques whose tau_t equals kappa (all of them), the Kendall-Tau
+    similarity of tau_t and kappa (scipy's tau-b on a uniform sample of
+    r-cliques), the share of active r-cliques (flagged by the
+    notifications for the next sweep) and of changed ones, with each
+    sweep's device time, for SND and AND on one of the named workloads; and
+    the stop points of the active-ratio control at 40% / 10% / 1%, by active
+    share (the paper's indicator) and by changed share."""
     import numpy as np
     import scipy.stats
     import torch
@@ -472,31 +667,45 @@ def quality_leg(nd, name, sample=1_000_000, seed=9):
     out = {"workload": name, "kind": kind, "n_rcliques": int(nr),
            "kendall_sample": int(idx.size), "degree_levels": n_levels}
     for mode in ("snd", "and"):
-        its, ms = [], []
-
-        def on_iter(info):
-            ms.append(info.ms)
-            return 0
-
-        g.decompose(kind, mode, keep_iterates=its, on_iter=on_iter)
+        its, stats = [], []
+        g.decompose(kind, mode, keep_iterates=its, keep_stats=stats,
+                    count_active=True)
         tau0 = g.sdegree(kind).cpu().numpy()
         rows, t_cum = [], 0.0
-        seq = [(None, tau0)] + [(c, t.cpu().numpy()) for c, t in its]
-        for t, (changed, tau) in enumerate(seq):
-            if t > 0:
-                t_cum += ms[t - 1]
+        seq = [tau0] + [t.cpu().numpy() for _, t in its]
+        for t, tau in enumerate(seq):
+            st = stats[t - 1] if t > 0 else None
+            if st:
+                t_cum += st["ms"]
             exact = float(np.count_nonzero(tau == kap)) / max(nr, 1)
             kt = float(scipy.stats.kendalltau(tau[idx], kap[idx]).statistic)
-            rows.append({"sweep": t, "changed": changed, "ms_cum": t_cum,
-                         "fraction_exact": exact, "kendall_tau": kt})
-        stops = {}
-        for ratio in (0.4, 0.1, 0.01):
-            hit = next((r for r in rows[1:] if r["changed"] < ratio * nr), rows[-1])
-            stops[str(ratio)] = {k: hit[k] for k in ("sweep", "ms_cum",
-                                                     "fraction_exact", "kendall_tau")}
-        out[mode] = {"rows": rows, "active_ratio_stops": stops}
+            rows.append({"sweep": t, "changed": st["changed"] if st else None,
+                         "active": st["active_next"] if st else None,
+                         "ms_cum": t_cum, "fraction_exact": exact,
+                         "kendall_tau": kt})
+        res = {"rows": rows}
+        for by in ("active", "changed"):
+            stops = {}
+            for ratio in (0.4, 0.1, 0.01):
+                hit = next((r for r in rows[1:] if r[by] < ratio * nr), rows[-1])
+                stops[str(ratio)] = {k: hit[k] for k in ("sweep", "ms_cum",
+                                                         "fraction_exact",
+                                                         "kendall_tau")}
+            res[f"{by}_ratio_stops"] = stops
+        out[mode] = res
     g.close()
     return out
+
+
+def recorded_peeling(name: str):
+    """Seconds the oracle's peeling took on a workload when its full-size
+    digest was recorded, or None."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                          "full_size.json")))
+        return float(rec[name]["oracle_seconds"])
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def main():
@@ -505,26 +714,27 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a known-size "
                          "kernel for scaling hardware byte counters)")
-    ap.add_argument("--stream-graphs", type=int, default=96,
+    ap.add_argument("--no-ceilings", action="store_true")
+    ap.add_argument("--stream-graphs", type=int, default=256,
                     help="graphs in the batched/served comparison (0: skip)")
-    ap.add_argument("--levels", action="store_true",
-                    help="also count the degree levels of the graph")
-    ap.add_argument("--ego-queries", type=int, default=4096,
-                    help="random r-cliques for the ego-estimate leg (0: skip)")
-    ap.add_argument("--quality", default=None,
-                    help="only run the per-sweep accuracy leg on this "
-                         "workload (e.g. cl23) and print its JSON")
     ap.add_argument("--small-graphs", type=int, default=512,
                     help="graphs in the small-graph batched comparison "
                          "(0: skip)")
-    ap.add_argument("--no-nucleus34", action="store_true",
-                    help="skip the (3,4)-nucleus leg on the block model")
-    ap.add_argument("--only-nucleus34", action="store_true",
-                    help="run only the (3,4)-nucleus leg and print its JSON")
+    ap.add_argument("--ego-queries", type=int, default=4096,
+                    help="random edges for the ego-estimate leg (0: skip)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the k-truss (cl20) and k-core (cl23) legs")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="run only the headline leg (for the profiles)")
+    ap.add_argument("--only-stream", action="store_true",
+                    help="run only the stream leg and print its JSON")
+    ap.add_argument("--quality", default=None,
+                    help="only run the per-sweep accuracy leg on this "
+                         "workload (e.g. cl23) and print its JSON")
     ap.add_argument("--summarize-quality", default=None, metavar="JSON",
                     help="write profiles/quality_*.md from the output of "
                          "--quality and exit")
@@ -547,161 +757,86 @@ def main():
         summarize_quality(args.summarize_quality)
         return
     if args.gpus != 1:
-        print("bench.py: measures one GPU only; the multi-GPU "
-              "sharding is a design note, not a measured path", file=sys.stderr)
+        print("bench.py measures one GPU only: no part of this path runs on "
+              "several GPUs here (the sharding is a design note)",
+              file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1704_00386_amd as nd
-    from synth import workload
 
     if args.quality:
         print(json.dumps(quality_leg(nd, args.quality)), flush=True)
         return
-    if args.only_nucleus34:
-        print(json.dumps({"nucleus34": nucleus34_leg(nd, nd.Context(0))}),
+    ctx = nd.Context(0)
+    if args.only_stream:
+        print(json.dumps({"stream": stream_leg(nd, ctx, args.stream_graphs)}),
               flush=True)
         return
-
     if args.calib_copy:
         a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    raw = workload(WORKLOAD)
-    ctx = nd.Context(0)
-    src = torch.from_numpy(raw.src).cuda()
-    dst = torch.from_numpy(raw.dst).cuda()
-    torch.cuda.synchronize()
 
-    def step():
-        g = nd.Graph.from_edges(ctx, raw.n, src, dst)
-        kappa, res = g.decompose(KIND, "snd", use_frontier=True)
-        return g, kappa, res
-
-    for _ in range(args.warmup):
-        g, _, _ = step()
-        g.close()
-    torch.cuda.synchronize()
-
-    # timed steps: the whole path, SND with the notification frontier
-    times, results = [], []
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g, kappa, res = step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        results.append(res)
-        if i < args.steps - 1:
-            g.close()
-    ms_per_step = 1e3 * sum(times) / len(times)
-    res = results[-1]
-    nr, P = res["n_rcliques"], res["n_incidence"]
-    k = {"core": 1, "truss": 2, "nucleus34": 3}[KIND]
-    nr_eval = int(np.count_nonzero(g.sdegree(KIND).cpu().numpy()))
-    full_equiv = nr_eval * res["sweeps"]
-
-    # roofline leg: full sweeps (every r-clique with d_s > 0 recomputed each
-    # sweep) on the same prepared graph, per-sweep device time from events
-    # recorded around each sweep's launches on the library's stream
-    sweep_ms = []
-
-    def collect(info):
-        sweep_ms.append(info.ms)
-        return 0
-
-    kfull, rfull = g.decompose(KIND, "snd", on_iter=collect)
-    same_full = bool(torch.equal(kfull, kappa))
-    B = sweep_bytes(P, nr_eval, k, res["tau_bytes"])
-    avg_sweep_ms = sum(sweep_ms) / len(sweep_ms)
-    achieved = B / (avg_sweep_ms * 1e-3) / 1e9
-
-    # the same step from host memory: pinned host edge list in, kappa back
-    # to host memory (PCIe both ways; never the bench value)
-    hsrc = torch.from_numpy(raw.src).pin_memory()
-    hdst = torch.from_numpy(raw.dst).pin_memory()
-    host_ms = []
-    for _ in range(2):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        gh = nd.Graph.from_edges(ctx, raw.n, hsrc, hdst)
-        kh, _ = gh.decompose(KIND, "snd", use_frontier=True)
-        kh = kh.cpu()
-        host_ms.append(1e3 * (time.perf_counter() - t0))
-        gh.close()
-    same_host = bool(torch.equal(kh, kappa.cpu()))
-    del hsrc, hdst, kh
-
-    # AND on the prepared graph (same incidence lists), frontier on
-    kand, rand = g.decompose(KIND, "and", use_frontier=True)
-    same_and = bool(torch.equal(kand, kappa))
-
-    # ego-network estimates (PartialAND per query) for random edges
-    ego = ego_leg(g, kappa, args.ego_queries) if args.ego_queries > 0 else None
-
-    # degree levels: the bound on SND sweeps (the DL row of Table 3)
-    n_levels = levels_ms = None
-    if args.levels:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, n_levels = g.levels(KIND)
-        torch.cuda.synchronize()
-        levels_ms = 1e3 * (time.perf_counter() - t0)
-    g.close()
-
+    h = headline_leg(nd, ctx, args)
+    res, roof, raw = h["res"], h["roof"], h["raw"]
+    ms_step = h["ms_step"]
+    h["g"].close()
     traffic = measured_traffic()
-
     line = {
         "metric": "r-clique h-index updates/sec + time-to-exact-convergence "
                   "vs CPU peeling",
-        "value": full_equiv / (ms_per_step * 1e-3),
+        "value": res["updates"] / (ms_step * 1e-3),
         "unit": "r-clique h-index updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "k-truss (2,3) SND on Chung-Lu n=2^20, "
-                               "exponent 2.1, mean degree 32, seed 2",
-                   "n": raw.n, "raw_pairs": raw.m, "edges": nr,
-                   "incidence_P": P, "swept_per_sweep": nr_eval,
-                   "tau_bytes": res["tau_bytes"], "kind": KIND,
+        "config": {"workload": "(3,4)-nucleus SND on the stochastic block model: "
+                               "5000 communities of U{50..400} vertices, p_in 0.3, "
+                               "p_out 2e-6, seed 4; triangles as r-cliques",
+                   "n": raw.n, "raw_pairs": raw.m, "triangles": res["n_rcliques"],
+                   "incidence_P": res["n_incidence"],
+                   "swept_per_sweep": h["nr_eval"],
+                   "tau_bytes": res["tau_bytes"], "kind": HEADLINE_KIND,
                    "mode": "snd", "frontier": True},
-        "updates_counted": "r-cliques with d_s > 0 per sweep (full-sweep "
-                           "equivalent: the frontier recomputes only notified "
-                           "r-cliques and yields the same iterates)",
-        "time_to_exact_ms": ms_per_step,
-        "ms_prep": ms_per_step - res["ms_iterate"],
+        "updates_counted": "h-index evaluations the step performs (r-cliques "
+                           "the frontier recomputes, summed over sweeps)",
+        "time_to_exact_ms": ms_step,
+        "time_to_exact_no_prep_ms": res["ms_iterate"],
+        "ms_prep": ms_step - res["ms_iterate"],
         "ms_iterate": res["ms_iterate"],
+        "step_ms_all": h["times"],
         "sweeps": res["sweeps"],
         "t_star": res["sweeps"] - 1,  # first t with tau_t = kappa
         "evaluated_updates": res["updates"],
-        "full_sweeps": {"ms_iterate": rfull["ms_iterate"],
-                        "sweeps": rfull["sweeps"],
-                        "updates_per_s": rfull["updates"] /
-                        (rfull["ms_iterate"] * 1e-3),
-                        "kappa_equals_frontier": same_full},
-        "roofline": {"bound": "hbm", "achieved": achieved,
+        "evaluated_updates_per_s_of_sweep_time": res["updates"] / (res["ms_iterate"] * 1e-3),
+        "full_sweep_equivalent_updates_per_s": h["nr_eval"] * res["sweeps"] / (ms_step * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": roof["achieved_GBs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "full sweep (one application of U to every "
-                               "r-clique with d_s > 0)",
-                     "bytes_per_launch": B, "avg_launch_ms": avg_sweep_ms},
-        "and": {"sweeps": rand["sweeps"], "ms_iterate": rand["ms_iterate"],
-                "frontier": True, "kappa_equals_snd": same_and},
-        "host_io": {"ms_per_step": min(host_ms), "kappa_equals": same_host,
-                    "what": "the same step from a pinned host edge list to "
-                            "kappa in host memory (PCIe both ways)"},
+                     "frac": roof["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "full sweep: one application of U to every "
+                               "r-clique with d_s > 0 (k_sweep_small<3, u16>)",
+                     "bytes_per_launch": roof["bytes_per_sweep"],
+                     "avg_launch_ms": roof["avg_sweep_ms"],
+                     "sweeps_timed": roof["sweeps_timed"]},
+        "and": h["and"],
     }
-    # the paper's own figures, other hardware and real graphs: context only
+    if "ceilings" in h:
+        c = h["ceilings"]
+        c["update_kernel_frac_of_read"] = roof["achieved_GBs"] / c["read_GBs"]
+        c["update_kernel_frac_of_gather"] = roof["achieved_GBs"] / c["gather_GBs"]
+        line["ceilings"] = c
+    del h
     line["paper_context"] = {
         "hardware": "2 x 12-core Intel Ivy Bridge at 2.4 GHz, 24 threads, "
                     "C++/OpenMP (Section 5)",
@@ -712,45 +847,41 @@ def main():
                         "AND time on 24 threads (Table 4) for the facebook and "
                         "web-Google graphs (Table 2); order of magnitude only",
     }
-    if n_levels is not None:
-        line["degree_levels"] = {"levels": n_levels, "ms": levels_ms,
-                                 "snd_sweeps": res["sweeps"],
-                                 "and_sweeps": rand["sweeps"]}
-    if ego is not None:
-        line["ego"] = ego
-    if args.stream_graphs > 0:
-        line["stream"] = stream_leg(nd, ctx, args.stream_graphs)
-    if args.small_graphs > 0:
-        # the launch-bound end of the stream: n ~ U{1000..5000}
-        line["small_graphs"] = stream_leg(nd, ctx, args.small_graphs, seed=7,
-                                          n_lo=1000, n_hi=5000, serve=False)
-    if not args.no_nucleus34:
-        line["nucleus34"] = nucleus34_leg(nd, ctx)
+    if not args.only_headline:
+        if not args.no_workloads:
+            tr, g, kappa = workload_leg(nd, ctx, "cl20", "truss")
+            line["truss_cl20"] = tr
+            if args.ego_queries > 0:
+                line["ego"] = ego_leg(nd, g, kappa, "truss", args.ego_queries)
+            g.close()
+            del kappa
+            line["core_cl23"], g, _ = workload_leg(nd, ctx, "cl23", "core",
+                                                   quality=True)
+            g.close()
+        if args.stream_graphs > 0:
+            line["stream"] = stream_leg(nd, ctx, args.stream_graphs)
+        if args.small_graphs > 0:
+            line["small_graphs"] = stream_leg(nd, ctx, args.small_graphs, seed=7,
+                                              n_lo=1000, n_hi=5000, serve=False)
     if not args.no_cpu:
-        cb = cpu_baseline(raw, KIND, args.cpu_budget)
-        cb["time_to_exact_s_est"] = full_equiv / cb["value"]
+        progress("cpu baseline (oracle) starts")
+        cb = cpu_baseline(args.cpu_budget)
+        # the step's h-index evaluations at the oracle's update rate
+        cb["time_to_exact_s_est"] = res["updates"] / cb["value"]
+        cb["time_to_exact_s_est_is"] = ("the step's evaluated updates divided "
+                                        "by the oracle's rate")
         line["cpu_baseline"] = cb
-    peel = recorded_peeling("cl20")
+    peel = recorded_peeling(HEADLINE)
     if peel is not None:
         line["cpu_peeling_recorded"] = {
-            "s": peel, "step_speedup": peel / (ms_per_step * 1e-3),
-            "what": "the oracle's Alg. Peeling on this workload (parallel "
-                    "S-degree count, sequential peeling), timed when the "
-                    "full-size kappa digests in tests/golden/full_size.json "
-                    "were written, on that machine's cores (not this run's "
-                    "host): context, not the baseline"}
+            "s": peel, "step_speedup": peel / (ms_step * 1e-3),
+            "what": "the oracle's Alg. Peeling on this workload, split exactly "
+                    "by community over a pool of 8 processes (parallel S-degree "
+                    "count, sequential peeling per community), timed when the "
+                    "full-size kappa digests in tests/golden/full_size.json were "
+                    "written, on that machine's cores (not this run's host): "
+                    "context, not the baseline"}
     print(json.dumps(line), flush=True)
-
-
-def recorded_peeling(name: str):
-    """Seconds the oracle's peeling took on a workload when its full-size
-    digest was recorded, or None."""
-    try:
-        rec = json.load(open(os.path.join(ROOT, "tests", "golden",
-                                          "full_size.json")))
-        return float(rec[name]["oracle_seconds"])
-    except (OSError, ValueError, KeyError):
-        return None
 
 
 if __name__ == "__main__":
