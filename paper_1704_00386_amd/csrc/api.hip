@@ -300,9 +300,7 @@ static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
       k_check_incidence<<<grid, 256, 0, s>>>(ks.inc_ids.p, nids, ks.nr, err.p);
       ND_LAUNCHED();
     }
-    int32_t h = 0;
-    ND_HIP(hipMemcpyAsync(&h, err.p, sizeof h, hipMemcpyDeviceToHost, s));
-    ND_HIP(hipStreamSynchronize(s));
+    const int32_t h = *PinnedChunk().read(err.p, 1, s);
     ND_REQUIRE(h == 0, ND_ERR_DEVICE,
                "internal error: incidence list holds an invalid r-clique id");
   }
@@ -331,9 +329,7 @@ void check_tau_range(nd_graph *g, const KindState &ks, const int32_t *tau,
                                                       ks.nr, err.p);
     ND_LAUNCHED();
   }
-  int32_t h = 0;
-  ND_HIP(hipMemcpyAsync(&h, err.p, sizeof h, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
+  const int32_t h = *PinnedChunk().read(err.p, 1, s);
   ND_REQUIRE(h == 0, ND_ERR_INVALID, "tau must satisfy 0 <= tau <= d_s");
 }
 
@@ -495,13 +491,13 @@ nd_status nd_graph_from_csr(nd_ctx *ctx, int32_t n, int64_t nnz,
 namespace nd {
 
 // Free a graph whose last device work was ordered on stream s (the server's
-// retirement): waits for s only, not for the whole device, and returns the
-// graph's memory to the allocator tagged with s.
-void destroy_graph(nd_graph *g, hipStream_t s) {
+// retirement): waits for s only (or not at all), never for the whole device,
+// and returns the graph's memory to the allocator tagged with s.
+void destroy_graph(nd_graph *g, hipStream_t s, bool wait) {
   if (!g) return;
   nd_ctx *ctx = g->ctx;
   (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(s);
+  if (wait) (void)hipStreamSynchronize(s);
   {
     StreamScope scope(s);
     delete g;

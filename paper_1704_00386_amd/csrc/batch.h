@@ -22,6 +22,7 @@ struct BGraph {
   int64_t t0;          // epoch at which the graph joined
   int64_t max_local;   // sweeps allowed
   uint8_t *act[2];     // frontier stamps: sweep t reads act[t & 1]
+  uint8_t *act_sum[2]; // one stamp per 64 r-cliques, set with any of their flags
   unsigned long long notify_below;  // start notifying at <= this many changes
 };
 
@@ -69,6 +70,7 @@ struct Member {
   int64_t ntiles = 0;     // tiles it contributes
   DArr<uint8_t> tau0, tau1;
   DArr<uint8_t> act0, act1;  // frontier batches only
+  DArr<uint8_t> sum0, sum1;  // their group summaries (one per 64 r-cliques)
   DArr<SweepStats> ring;
 };
 
@@ -120,6 +122,7 @@ class Batch {
   void rebuild();
   void set_config(const BatchConfig &c);
   void launch_epoch();
+  void capture();
   template <int K, typename T, bool AND, bool FR>
   void launch_epoch_t();
   void drop_graph();

@@ -70,9 +70,13 @@ __device__ __forceinline__ void graph_frontier(const BGraph &G, int64_t local,
                                                SweepStats *sst,
                                                const uint8_t **act,
                                                uint8_t **act_next,
-                                               uint8_t *stamp) {
+                                               uint8_t *stamp,
+                                               const uint8_t **act_sum,
+                                               uint8_t **sum_next) {
   *act = nullptr;
   *act_next = nullptr;
+  *act_sum = nullptr;
+  *sum_next = nullptr;
   *stamp = 0;
   if (!FR || local == 0) return;
   const SweepStats *prev = &G.ring[(local - 1) % kBatchRing];
@@ -80,6 +84,8 @@ __device__ __forceinline__ void graph_frontier(const BGraph &G, int64_t local,
   const bool notify = valid || changed_sum(prev) <= G.notify_below;
   *act = valid ? G.act[local & 1] : nullptr;
   *act_next = notify ? G.act[(local + 1) & 1] : nullptr;
+  *act_sum = valid ? G.act_sum[local & 1] : nullptr;
+  *sum_next = notify ? G.act_sum[(local + 1) & 1] : nullptr;
   *stamp = sweep_stamp(local);
   if (notify && threadIdx.x == 0) sst->notified = 1;
 }
@@ -111,9 +117,10 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
     const T *in = (const T *)G.tau[local & 1];
     T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
     SweepStats *sst = &G.ring[local % kBatchRing];
-    const uint8_t *act;
-    uint8_t *act_next, stamp;
-    graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp);
+    const uint8_t *act, *act_sum;
+    uint8_t *act_next, *sum_next, stamp;
+    graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp, &act_sum,
+                       &sum_next);
     if (FR && act != nullptr) {
       // sparse sweep of the tile: flags tested a chunk at a time per wave
       unsigned long long n_ch = 0, n_ev = 0;
@@ -122,37 +129,37 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
         if (tile.type == kBinWave)
           sweep_sparse<K, 64, 32, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                           tile.hi, wv, nw, act, act_next, stamp,
-                                          &n_ch, &n_ev);
+                                          &n_ch, &n_ev, act_sum, sum_next);
         else
           sweep_sparse<K, 64, 16, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                           tile.hi, wv, nw, act, act_next, stamp,
-                                          &n_ch, &n_ev);
+                                          &n_ch, &n_ev, act_sum, sum_next);
       } else {
         switch (tile.type) {
           case kBinG1:
             sweep_sparse<K, 1, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                           tile.hi, wv, nw, act, act_next, stamp,
-                                          &n_ch, &n_ev);
+                                          &n_ch, &n_ev, act_sum, sum_next);
             break;
           case kBinG4:
             sweep_sparse<K, 4, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                           tile.hi, wv, nw, act, act_next, stamp,
-                                          &n_ch, &n_ev);
+                                          &n_ch, &n_ev, act_sum, sum_next);
             break;
           case kBinG16:
             sweep_sparse<K, 16, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                            tile.hi, wv, nw, act, act_next, stamp,
-                                           &n_ch, &n_ev);
+                                           &n_ch, &n_ev, act_sum, sum_next);
             break;
           case kBinG64:
             sweep_sparse<K, 64, 4, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                            tile.hi, wv, nw, act, act_next, stamp,
-                                           &n_ch, &n_ev);
+                                           &n_ch, &n_ev, act_sum, sum_next);
             break;
           default:  // kBinWave8
             sweep_sparse<K, 64, 8, T, AND>(G.inc_off, G.inc_ids, in, out, 1, tile.lo,
                                            tile.hi, wv, nw, act, act_next, stamp,
-                                           &n_ch, &n_ev);
+                                           &n_ch, &n_ev, act_sum, sum_next);
             break;
         }
       }
@@ -166,40 +173,40 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
         const int64_t R = base + threadIdx.x / 64;
         if (tile.type == kBinWave)
           ch = update_regs<K, 64, 32, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                              R, R < tile.hi, act, act_next, stamp, &ev);
+                                              R, R < tile.hi, act, act_next, stamp, &ev, sum_next);
         else
           ch = update_regs<K, 64, 16, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                              R, R < tile.hi, act, act_next, stamp, &ev);
+                                              R, R < tile.hi, act, act_next, stamp, &ev, sum_next);
       } else {
         switch (tile.type) {
           case kBinG1: {
             const int64_t R = base + threadIdx.x;
             ch = update_regs<K, 1, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                              R < tile.hi, act, act_next, stamp, &ev);
+                                              R < tile.hi, act, act_next, stamp, &ev, sum_next);
             break;
           }
           case kBinG4: {
             const int64_t R = base + threadIdx.x / 4;
             ch = update_regs<K, 4, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1, R,
-                                              R < tile.hi, act, act_next, stamp, &ev);
+                                              R < tile.hi, act, act_next, stamp, &ev, sum_next);
             break;
           }
           case kBinG16: {
             const int64_t R = base + threadIdx.x / 16;
             ch = update_regs<K, 16, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                               R, R < tile.hi, act, act_next, stamp, &ev);
+                                               R, R < tile.hi, act, act_next, stamp, &ev, sum_next);
             break;
           }
           case kBinG64: {
             const int64_t R = base + threadIdx.x / 64;
             ch = update_regs<K, 64, 4, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                               R, R < tile.hi, act, act_next, stamp, &ev);
+                                               R, R < tile.hi, act, act_next, stamp, &ev, sum_next);
             break;
           }
           default: {  // kBinWave8
             const int64_t R = base + threadIdx.x / 64;
             ch = update_regs<K, 64, 8, T, AND, FR>(G.inc_off, G.inc_ids, in, out, 1,
-                                               R, R < tile.hi, act, act_next, stamp, &ev);
+                                               R, R < tile.hi, act, act_next, stamp, &ev, sum_next);
             break;
           }
         }
@@ -225,13 +232,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch_hubs(
     const T *in = (const T *)G.tau[local & 1];
     T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
     SweepStats *sst = &G.ring[local % kBatchRing];
-    const uint8_t *act;
-    uint8_t *act_next, stamp;
-    graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp);
+    const uint8_t *act, *act_sum;
+    uint8_t *act_next, *sum_next, stamp;
+    graph_frontier<FR>(G, local, sst, &act, &act_next, &stamp, &act_sum,
+                       &sum_next);
     bool ev;
     const bool ch = update_block<K, T, AND, FR>(G.inc_off, G.inc_ids, in, out,
                                                 1, hb.R, hist, act, act_next,
-                                                stamp, &ev);
+                                                stamp, &ev, sum_next);
     stat_add(sst, ch, ev);
   }
 }
@@ -367,6 +375,9 @@ Member *Batch::add(nd_graph *g, int32_t max_iters, void *user) {
   if (frontier_) {
     m->act0.reset(ctx_->alloc, std::max<int64_t>(ks.nr, 1));
     m->act1.reset(ctx_->alloc, std::max<int64_t>(ks.nr, 1));
+    const int64_t ng = std::max<int64_t>((ks.nr + (1 << kGroupShift) - 1) >> kGroupShift, 1);
+    m->sum0.reset(ctx_->alloc, ng);
+    m->sum1.reset(ctx_->alloc, ng);
   }
   init_member_tau(*m);
   if (ks.nr == 0 || m->max_local == 0) {
@@ -393,6 +404,9 @@ void Batch::init_member_tau(Member &m) {
   if (frontier_) {  // no stamps yet
     fill_u8(m.act0.p, 0, ks.nr, s_);
     fill_u8(m.act1.p, 0, ks.nr, s_);
+    const int64_t ng = (ks.nr + (1 << kGroupShift) - 1) >> kGroupShift;
+    fill_u8(m.sum0.p, 0, ng, s_);
+    fill_u8(m.sum1.p, 0, ng, s_);
   }
 }
 
@@ -444,6 +458,8 @@ void Batch::rebuild() {
     if (frontier_) {
       G.act[0] = m.act0.p;
       G.act[1] = m.act1.p;
+      G.act_sum[0] = m.sum0.p;
+      G.act_sum[1] = m.sum1.p;
       G.notify_below = notify_div_ <= 0
                            ? ~0ull
                            : (unsigned long long)(ks.bin_lo[kBinZero] / notify_div_);
@@ -541,18 +557,42 @@ void Batch::launch_epoch() {
 #undef ND_EPOCH_CASES
 }
 
+// Capture kGraphEpochs epochs into graph_exec_.  Relaxed mode: the capture
+// itself makes no call that a capture forbids, and other threads of the
+// process (a server's preparation thread allocating memory) must stay free
+// to.  If the capture fails anyway, it is ended (so the stream leaves
+// capture mode) and this batch launches its epochs directly from then on.
+void Batch::capture() {
+  hipGraph_t gr = nullptr;
+  if (hipStreamBeginCapture(s_, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    use_graph = false;
+    return;
+  }
+  bool ok = true;
+  try {
+    for (int i = 0; i < kGraphEpochs; i++) launch_epoch();
+  } catch (const Err &) {
+    ok = false;
+  }
+  if (hipStreamEndCapture(s_, &gr) != hipSuccess) ok = false;
+  if (ok && hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0) != hipSuccess) {
+    graph_exec_ = nullptr;
+    ok = false;
+  }
+  if (gr) (void)hipGraphDestroy(gr);
+  if (!ok) {
+    (void)hipGetLastError();
+    graph_exec_ = nullptr;
+    use_graph = false;
+  }
+}
+
 void Batch::run_epochs(int count) {
   if (dirty_) rebuild();
   if (ng_ == 0) return;
-  if (use_graph && count == kGraphEpochs) {
-    if (!graph_exec_) {
-      hipGraph_t gr;
-      ND_HIP(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
-      for (int i = 0; i < kGraphEpochs; i++) launch_epoch();
-      ND_HIP(hipStreamEndCapture(s_, &gr));
-      ND_HIP(hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0));
-      (void)hipGraphDestroy(gr);
-    }
+  if (use_graph && count == kGraphEpochs && !graph_exec_) capture();
+  if (use_graph && count == kGraphEpochs && graph_exec_) {
     ND_HIP(hipGraphLaunch(graph_exec_, s_));
   } else {
     for (int i = 0; i < count; i++) launch_epoch();

@@ -1340,9 +1340,7 @@ void build_incidence_truss(nd_graph *g, KindState &ks, hipStream_t s) {
     k_max_outdeg<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(
         out_off.p, n, mx.p);
     ND_LAUNCHED();
-    int32_t hmax = 0;
-    ND_HIP(hipMemcpyAsync(&hmax, mx.p, sizeof hmax, hipMemcpyDeviceToHost, s));
-    ND_HIP(hipStreamSynchronize(s));
+    const int32_t hmax = *PinnedChunk().read(mx.p, 1, s);
     constexpr int kMaxLdsEntries = 5120;  // 60 KiB: three int32 arrays
     const char *no_lds = getenv("ND_TRUSS_NO_LDS");
     if (hmax <= kMaxLdsEntries && !(no_lds && no_lds[0] == '1')) {
@@ -1512,9 +1510,7 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
     k_n34_check_full<<<grid, 256, 0, s>>>(rcur.p, ks.inc_off.p, nt, err.p);
     ND_LAUNCHED();
   }
-  int32_t h = 0;
-  ND_HIP(hipMemcpyAsync(&h, err.p, sizeof h, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
+  const int32_t h = *PinnedChunk().read(err.p, 1, s);
   ND_REQUIRE(h == 0, ND_ERR_DEVICE,
              "internal error: the (3,4) incidence lists are inconsistent");
 }

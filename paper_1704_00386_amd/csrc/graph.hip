@@ -169,9 +169,7 @@ void build_from_edges(nd_graph *g, int64_t m, const int32_t *src,
                                                   keys.p, err.p);
     ND_LAUNCHED();
   }
-  int32_t herr = 0;
-  ND_HIP(hipMemcpyAsync(&herr, err.p, sizeof herr, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
+  const int32_t herr = *PinnedChunk().read(err.p, 1, s);
   ND_REQUIRE(herr == 0, ND_ERR_INVALID,
              "edge list has an endpoint outside [0, %d)", n);
   uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, nk, 0, total_bits, s, al);
@@ -205,9 +203,7 @@ void validate_csr(nd_graph *g, hipStream_t s) {
   k_check_rows<<<grid_for((int64_t)g->n + 1, 256), 256, 0, s>>>(
       g->row_off.p, g->n, g->nnz, err.p);
   ND_LAUNCHED();
-  int32_t herr = 0;
-  ND_HIP(hipMemcpyAsync(&herr, err.p, sizeof herr, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
+  int32_t herr = *PinnedChunk().read(err.p, 1, s);
   ND_REQUIRE(herr == 0, ND_ERR_INVALID,
              "CSR row offsets malformed (flags 0x%x: 1 first != 0, 2 last != "
              "nnz, 4 decreasing)", herr);
@@ -217,8 +213,7 @@ void validate_csr(nd_graph *g, hipStream_t s) {
         g->row_off.p, g->col.p, g->rowid.p, g->n, g->nnz, err.p);
     ND_LAUNCHED();
   }
-  ND_HIP(hipMemcpyAsync(&herr, err.p, sizeof herr, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
+  herr = *PinnedChunk().read(err.p, 1, s);
   ND_REQUIRE(herr == 0, ND_ERR_INVALID,
              "CSR is not a canonical simple graph (flags 0x%x: 8 id out of "
              "range, 16 self-loop, 32 row not strictly ascending, 64 not "

@@ -197,9 +197,12 @@ struct nd_graph {
 
 namespace nd {
 
-// Free a graph whose last device work was ordered on stream s (waits for s
-// only; nd_graph_destroy waits for the device).
-void destroy_graph(nd_graph *g, hipStream_t s);
+// Free a graph whose last device work was ordered on stream s, returning
+// its memory to the allocator tagged with s (waits for s first when `wait`;
+// nd_graph_destroy waits for the device).  Without waiting this is still
+// safe for the graph's own arrays: the allocator hands a block tagged with s
+// to another stream only once s has drained.
+void destroy_graph(nd_graph *g, hipStream_t s, bool wait = true);
 
 // ------------------------------------------------------- primitives
 
@@ -221,6 +224,32 @@ void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);  // p[i] = i
 int64_t read_i64(const int64_t *dev, hipStream_t s);  // synchronous
+
+// A 4 KiB pinned host chunk taken from a pool for the life of the object,
+// for reading a few words back from the device: a copy into pageable memory
+// goes through the runtime's staging path instead of straight to its
+// destination.  Chunks return to the pool, never to the runtime.
+class PinnedChunk {
+ public:
+  static constexpr size_t kBytes = 4096;
+  PinnedChunk();
+  ~PinnedChunk();
+  PinnedChunk(const PinnedChunk &) = delete;
+  PinnedChunk &operator=(const PinnedChunk &) = delete;
+  template <class T>
+  T *as() const { return static_cast<T *>(p_); }
+  // Copy n words of T from the device (ordered on s, waits for it).
+  template <class T>
+  const T *read(const T *dev, size_t n, hipStream_t s) {
+    ND_REQUIRE(n * sizeof(T) <= kBytes, ND_ERR_INVALID, "read-back too large");
+    ND_HIP(hipMemcpyAsync(p_, dev, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    ND_HIP(hipStreamSynchronize(s));
+    return as<T>();
+  }
+
+ private:
+  void *p_ = nullptr;
+};
 
 // ------------------------------------------------------------ graph prep
 

@@ -152,11 +152,14 @@ void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
                                                           bins.p);
     ND_LAUNCHED();
   }
-  int32_t hmax = 0;
-  unsigned long long hb[kNumBins];
-  ND_HIP(hipMemcpyAsync(&hmax, maxd.p, sizeof hmax, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipMemcpyAsync(hb, bins.p, sizeof hb, hipMemcpyDeviceToHost, s));
+  PinnedChunk pc;
+  unsigned long long *hb = pc.as<unsigned long long>();
+  int32_t *hmaxp = reinterpret_cast<int32_t *>(hb + kNumBins);
+  ND_HIP(hipMemcpyAsync(hmaxp, maxd.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  ND_HIP(hipMemcpyAsync(hb, bins.p, sizeof(unsigned long long) * kNumBins,
+                        hipMemcpyDeviceToHost, s));
   ND_HIP(hipStreamSynchronize(s));
+  const int32_t hmax = *hmaxp;
   ks.max_ds = hmax;
   ks.tau16 = hmax < 32768;
   int64_t at = 0;

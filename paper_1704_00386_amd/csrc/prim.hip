@@ -1,6 +1,9 @@
 // prim.hip -- device primitives used by graph preparation: exclusive scan,
 // stable LSD radix sort of 64-bit keys, stable partition by a small key, and
 // fills.  All integer, all deterministic.
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 namespace nd {
@@ -280,10 +283,8 @@ void partition_by_bin(const uint8_t *bin, int64_t n, int nbins, int32_t *items,
   uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, n, 32, 40, s, al);
   k_low32<<<grid_for(n, 256), 256, 0, s>>>(sorted, n, items);
   ND_LAUNCHED();
-  std::vector<unsigned long long> h(nbins);
-  ND_HIP(hipMemcpyAsync(h.data(), counts.p, sizeof(unsigned long long) * nbins,
-                        hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
+  PinnedChunk pc;
+  const unsigned long long *h = pc.read(counts.p, (size_t)nbins, s);
   for (int b = 0; b < nbins; b++) offsets[b + 1] = offsets[b] + (int64_t)h[b];
 }
 
@@ -318,11 +319,31 @@ void fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
   ND_LAUNCHED();
 }
 
+namespace {
+std::mutex g_pinned_mu;
+std::vector<void *> g_pinned_free;
+}  // namespace
+
+PinnedChunk::PinnedChunk() {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      p_ = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return;
+    }
+  }
+  ND_HIP(hipHostMalloc(&p_, kBytes, hipHostMallocDefault));
+}
+
+PinnedChunk::~PinnedChunk() {
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  g_pinned_free.push_back(p_);
+}
+
 int64_t read_i64(const int64_t *dev, hipStream_t s) {
-  int64_t v = 0;
-  ND_HIP(hipMemcpyAsync(&v, dev, sizeof v, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
-  return v;
+  PinnedChunk h;
+  return *h.read(dev, 1, s);
 }
 
 }  // namespace nd

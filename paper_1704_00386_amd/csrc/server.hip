@@ -49,7 +49,12 @@ struct Request {
   nd_serve_info info{};
   Member *member = nullptr;
   Batch *batch = nullptr;
-  std::vector<int32_t> kappa;  // the result, host memory owned here
+  // the result: kappa in pinned host memory owned by the server (a pooled
+  // buffer of host_cap bytes), complete once `copied` has fired
+  void *host = nullptr;
+  size_t host_cap = 0;
+  int64_t n_result = 0;
+  hipEvent_t copied = nullptr;
   std::string error;
 };
 
@@ -72,8 +77,8 @@ struct nd_server {
   std::atomic<int64_t> epochs{0};  // epochs run over all batches
   hipStream_t stream = nullptr;       // the worker's
   hipStream_t prep_stream = nullptr;  // the preparation thread's
-  void *stage = nullptr;              // pinned staging of results (worker)
-  size_t stage_bytes = 0;
+  // pinned result buffers not in use, by capacity (guarded by mu)
+  std::multimap<size_t, void *> pinned_free;
   // one batch per (kind, mode, tau width, frontier)
   std::unique_ptr<nd::Batch> batches[nd::kNumKinds][2][2][2];
 };
@@ -104,15 +109,50 @@ void finish_locked(nd_server *srv, Request *r, nd_status st) {
 // Free r's graph; its last device work was ordered on s (the server's
 // threads never wait for the whole device, which would stall the sweeps
 // behind a preparation or the other way round).
-void release_graph(Request *r, hipStream_t s) {
+void release_graph(Request *r, hipStream_t s, bool wait = true) {
   if (r->g) {
-    destroy_graph(r->g, s);
+    destroy_graph(r->g, s, wait);
     r->g = nullptr;
   }
 }
 
-// Copy a retired member's result to host memory and free its device memory
-// (worker thread).
+// A pinned buffer of at least `bytes` from the pool (or a new one, in power
+// of two sizes from 64 KiB), and its return.
+void *take_pinned(nd_server *srv, size_t bytes, size_t *cap) {
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->pinned_free.lower_bound(bytes);
+    if (it != srv->pinned_free.end()) {
+      void *p = it->second;
+      *cap = it->first;
+      srv->pinned_free.erase(it);
+      return p;
+    }
+  }
+  size_t c = (size_t)64 << 10;
+  while (c < bytes) c <<= 1;
+  void *p = nullptr;
+  ND_HIP(hipHostMalloc(&p, c, hipHostMallocDefault));
+  *cap = c;
+  return p;
+}
+
+// Give r's result buffer and event back (lock held).
+void drop_result_locked(nd_server *srv, Request *r) {
+  if (r->copied) {
+    (void)hipEventSynchronize(r->copied);
+    (void)hipEventDestroy(r->copied);
+    r->copied = nullptr;
+  }
+  if (r->host) {
+    srv->pinned_free.emplace(r->host_cap, r->host);
+    r->host = nullptr;
+  }
+}
+
+// Retire a finished member (worker thread): queue the copy of its result
+// into a pinned buffer (the caller's nd_server_result waits for it) and free
+// its device memory, all without waiting for the device.
 void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
   Request *r = (Request *)m->user;
   nd_status st = ND_OK;
@@ -121,21 +161,14 @@ void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
     StreamScope scope(b.stream());
     if (ks.nr > 0 && !r->cancelled) {
       const size_t bytes = sizeof(int32_t) * (size_t)ks.nr;
-      if (bytes > srv->stage_bytes) {
-        const size_t cap = std::max(bytes, 2 * srv->stage_bytes);
-        if (srv->stage) ND_HIP(hipHostFree(srv->stage));
-        srv->stage = nullptr;
-        srv->stage_bytes = 0;
-        ND_HIP(hipHostMalloc(&srv->stage, cap, hipHostMallocDefault));
-        srv->stage_bytes = cap;
-      }
+      r->host = take_pinned(srv, bytes, &r->host_cap);
+      r->n_result = ks.nr;
       DArr<int32_t> tmp(srv->ctx->alloc, ks.nr);
       to_original(ks, b.result_tau(*m), b.tau16(), tmp.p, b.stream());
-      ND_HIP(hipMemcpyAsync(srv->stage, tmp.p, bytes, hipMemcpyDeviceToHost,
+      ND_HIP(hipMemcpyAsync(r->host, tmp.p, bytes, hipMemcpyDeviceToHost,
                             b.stream()));
-      ND_HIP(hipStreamSynchronize(b.stream()));
-      r->kappa.assign((const int32_t *)srv->stage,
-                      (const int32_t *)srv->stage + ks.nr);
+      ND_HIP(hipEventCreateWithFlags(&r->copied, hipEventDisableTiming));
+      ND_HIP(hipEventRecord(r->copied, b.stream()));
     }
     nd_result &res = r->res;
     memset(&res, 0, sizeof res);
@@ -158,7 +191,7 @@ void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
     StreamScope scope(b.stream());
     m.reset();  // tau buffers and counters back to the allocator
   }
-  release_graph(r, b.stream());
+  release_graph(r, b.stream(), /*wait=*/false);
   std::lock_guard<std::mutex> lk(srv->mu);
   srv->running--;
   srv->retired++;
@@ -433,7 +466,10 @@ nd_status nd_server_wait(nd_server *srv, uint64_t ticket, int64_t timeout_us,
   if (st != ND_OK)
     set_error("%s", r->error.empty() ? nd_status_str(st) : r->error.c_str());
   // a result stays until nd_server_result collects it
-  if (st != ND_OK && st != ND_ERR_NOT_CONVERGED) srv->reqs.erase(it);
+  if (st != ND_OK && st != ND_ERR_NOT_CONVERGED) {
+    drop_result_locked(srv, r);
+    srv->reqs.erase(it);
+  }
   return st;
 }
 
@@ -441,21 +477,26 @@ nd_status nd_server_result(nd_server *srv, uint64_t ticket, int32_t *kappa,
                            int64_t capacity) {
   return guarded([&] {
     ND_REQUIRE(srv, ND_ERR_INVALID, "server is NULL");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->reqs.find(ticket);
-    ND_REQUIRE(it != srv->reqs.end(), ND_ERR_INVALID, "unknown ticket %llu",
-               (unsigned long long)ticket);
-    Request *r = it->second.get();
-    ND_REQUIRE(r->done, ND_ERR_INVALID, "request %llu has not finished",
-               (unsigned long long)ticket);
-    const int64_t n = (int64_t)r->kappa.size();
-    if (kappa) {
-      ND_REQUIRE(capacity >= n, ND_ERR_INVALID,
+    std::unique_ptr<Request> r;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      auto it = srv->reqs.find(ticket);
+      ND_REQUIRE(it != srv->reqs.end(), ND_ERR_INVALID, "unknown ticket %llu",
+                 (unsigned long long)ticket);
+      ND_REQUIRE(it->second->done, ND_ERR_INVALID,
+                 "request %llu has not finished", (unsigned long long)ticket);
+      ND_REQUIRE(!kappa || capacity >= it->second->n_result, ND_ERR_INVALID,
                  "kappa holds %lld entries, the result %lld",
-                 (long long)capacity, (long long)n);
-      if (n) memcpy(kappa, r->kappa.data(), sizeof(int32_t) * (size_t)n);
+                 (long long)capacity, (long long)it->second->n_result);
+      r = std::move(it->second);
+      srv->reqs.erase(it);
     }
-    srv->reqs.erase(it);
+    // the copy was queued at retirement; wait for it outside the lock
+    if (r->copied) ND_HIP(hipEventSynchronize(r->copied));
+    if (kappa && r->n_result)
+      memcpy(kappa, r->host, sizeof(int32_t) * (size_t)r->n_result);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    drop_result_locked(srv, r.get());
   });
 }
 
@@ -492,13 +533,17 @@ void nd_server_destroy(nd_server *srv) {
       for (auto &bw : bm)
         for (auto &b : bw) b.reset();
   (void)hipDeviceSynchronize();
-  for (auto &kv : srv->reqs) release_graph(kv.second.get(), srv->stream);
+  for (auto &kv : srv->reqs) {
+    release_graph(kv.second.get(), srv->stream);
+    drop_result_locked(srv, kv.second.get());
+  }
   srv->reqs.clear();
+  for (auto &kv : srv->pinned_free) (void)hipHostFree(kv.second);
+  srv->pinned_free.clear();
   srv->ctx->alloc.forget_stream(srv->stream);
   srv->ctx->alloc.forget_stream(srv->prep_stream);
   (void)hipStreamDestroy(srv->stream);
   (void)hipStreamDestroy(srv->prep_stream);
-  if (srv->stage) (void)hipHostFree(srv->stage);
   nd_ctx *ctx = srv->ctx;
   delete srv;
   ctx->release();
