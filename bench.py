@@ -545,17 +545,20 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
         nd.Graph.from_edges(ctx, n, s, d).decompose(kind, "snd", use_frontier=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solo = []
+    solo, solo_ms = [], []
     for n, s, d in dev:
+        t1 = time.perf_counter()
         g = nd.Graph.from_edges(ctx, n, s, d)
         k, r = g.decompose(kind, "snd", use_frontier=True)
         solo.append(k)
         updates += r["updates"]
         g.close()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        solo_ms.append(1e3 * (time.perf_counter() - t1))
     t_solo = time.perf_counter() - t0
     t0 = time.perf_counter()
     gs = [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev]
+    t_built = time.perf_counter() - t0
     ks, rs = nd.batch_decompose(ctx, gs, kind, "snd", use_frontier=True)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
@@ -570,6 +573,8 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
         "one_per_launch_graphs_per_s": count / t_solo,
         "batched_graphs_per_s": count / t_batch,
         "batched_speedup": t_solo / t_batch,
+        "batched_split_s": {"graph_from_edges": t_built,
+                            "batch_decompose": t_batch - t_built},
         "updates": updates,
     }
     if serve:
@@ -578,28 +583,49 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
         rate = 0.8 * count / t_solo
         gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
         arrive = np.cumsum(gaps) - gaps[0]
+        import queue
+        import threading
         srv = nd.Server(sctx, max_slots=64)
-        tickets = []
+        lag, got, pending = [], [], queue.Queue()
+
+        def collect():  # the results, in submission order, as they finish
+            for _ in range(count):
+                got.append(srv.wait(pending.get()))
+
+        consumer = threading.Thread(target=collect)
         t0 = time.perf_counter()
+        consumer.start()
         for i, (n, s, d) in enumerate(dev):
             while time.perf_counter() - t0 < arrive[i]:
                 time.sleep(0.0002)
-            tickets.append(srv.submit(nd.Graph.from_edges(sctx, n, s, d), kind,
-                                      use_frontier=True))
-        lats, joined, peak, prep_overlap = [], 0, 0, 0
-        for t, want in zip(tickets, solo):
-            kappa, r, info = srv.wait(t)
+            pending.put(srv.submit(nd.Graph.from_edges(sctx, n, s, d), kind,
+                                   use_frontier=True))
+            lag.append(1e3 * (time.perf_counter() - t0 - arrive[i]))
+        consumer.join()
+        t_srv = time.perf_counter() - t0
+        lats, slow, joined, peak, prep_overlap = [], [], 0, 0, 0
+        for (kappa, r, info), want, ms in zip(got, solo, solo_ms):
             lats.append(info["latency_ms"])
+            slow.append(info["latency_ms"] / ms)
             joined += info["joined_running"]
             peak = max(peak, info["peak_members"])
             prep_overlap += info["epochs_during_prep"] > 0
             same &= bool(torch.equal(kappa, want.cpu()))
-        t_srv = time.perf_counter() - t0
+        del got
         srv.close()
         del sctx
         out["served"] = {"arrival_rate_per_s": rate, "graphs_per_s": count / t_srv,
                          "p50_ms": float(np.percentile(lats, 50)),
                          "p99_ms": float(np.percentile(lats, 99)),
+                         # latency over the same graph's one-per-launch time
+                         # (the request sizes differ 200-fold, so raw
+                         # latency percentiles mostly reflect the sizes)
+                         "slowdown_p50": float(np.percentile(slow, 50)),
+                         "slowdown_p99": float(np.percentile(slow, 99)),
+                         # how far the caller's submissions (graph build
+                         # included) fell behind the arrival times
+                         "submit_lag_ms_p50": float(np.percentile(lag, 50)),
+                         "submit_lag_ms_max": float(np.max(lag)),
                          "hbm_budget_bytes": STREAM_BUDGET,
                          "joined_running_batch": joined,
                          "peak_requests_per_epoch": peak,
@@ -771,8 +797,13 @@ def main():
         return
     ctx = nd.Context(0)
     if args.only_stream:
-        print(json.dumps({"stream": stream_leg(nd, ctx, args.stream_graphs)}),
-              flush=True)
+        out = {}
+        if args.stream_graphs > 0:
+            out["stream"] = stream_leg(nd, ctx, args.stream_graphs)
+        if args.small_graphs > 0:
+            out["small_graphs"] = stream_leg(nd, ctx, args.small_graphs, seed=7,
+                                             n_lo=1000, n_hi=5000, serve=False)
+        print(json.dumps(out), flush=True)
         return
     if args.calib_copy:
         a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")

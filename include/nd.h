@@ -43,14 +43,17 @@
  *     of triangles must be below 2^31); offsets and incidence counts are
  *     int64.
  *   - Objects are not thread-safe: calls on one nd_ctx (and its graphs) must
- *     not overlap, except the nd_server_* calls, which are.
+ *     not overlap, except the nd_server_* calls, which are, and graph
+ *     creation and destruction, which may run beside a server's threads.
+ *     The library captures no stream: the caller may use any stream,
+ *     the legacy default one included, while a server is sweeping.
  *
  * Environment (tuning only; results never depend on them).
  *   ND_FRONTIER_SWITCH=d  with use_frontier, notifications start once a sweep
  *                         changes at most 1/d of the swept r-cliques
  *                         (default 16; 0: from the second sweep on).
  *   ND_BATCH_NO_GRAPH=1   batched epochs are launched one by one instead of
- *                         through captured HIP graphs.
+ *                         through HIP graphs of eight epochs.
  *   ND_TRUSS_NO_LDS=1     the k-truss builder intersects the 64-lane bin
  *                         without the per-source LDS copy (the path taken
  *                         when an out-list exceeds 5120 entries).
@@ -205,8 +208,19 @@ nd_status nd_graph_csr(nd_graph *g, int64_t *row_off, int32_t *col,
  * library stores them once.  Called implicitly by nd_decompose. */
 nd_status nd_prepare(nd_graph *g, nd_kind kind, void *stream);
 
-/* Sizes for `kind` (prepares it if needed): |R|, P = sum_R d_s(R), and the
- * device bytes the graph holds after preparing it. */
+/* Prepare `count` graphs of one context for `kind`, like nd_prepare on each,
+ * on up to four host threads with a stream each (ordered after `stream`,
+ * which waits for all of them on return), largest graphs first, so that
+ * their short, launch-bound build phases overlap.  Graphs already prepared
+ * are skipped.  The first failure is returned; graphs prepared before it
+ * stay prepared. */
+nd_status nd_prepare_many(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
+                          nd_kind kind, void *stream);
+
+/* Sizes for `kind`: |R|, P = sum_R d_s(R), and the device bytes the graph
+ * holds after preparing it.  Prepares the graph if needed, except when only
+ * |R| is asked for (n_incidence and dev_bytes NULL) and it follows from the
+ * graph itself: the vertex count for r = 1, the edge count for r = 2. */
 nd_status nd_sizes(nd_graph *g, nd_kind kind, int64_t *n_rcliques,
                    int64_t *n_incidence, size_t *dev_bytes);
 
@@ -308,10 +322,14 @@ nd_status nd_levels(nd_graph *g, nd_kind kind, int32_t *level,
 
 /* Decompose `count` graphs together: their r-cliques form one combined work
  * list swept by each launch; a graph stops being swept once one of its sweeps
- * changes nothing.  kappas[i] receives graph i's result (device pointers if
- * on_device), res[i] its statistics (res may be NULL).  Results equal those
- * of nd_decompose on each graph alone.  opts: mode, max_iters and
- * use_frontier apply to every graph; on_iter and stop_active_ratio give
+ * changes nothing.  Graphs not yet prepared are prepared as by
+ * nd_prepare_many while those already prepared are being swept, each joining
+ * the sweeps as soon as it is ready (graphs needing 32-bit tau are swept in
+ * a second combined list).  kappas[i] receives graph i's result (device
+ * pointers if on_device), res[i] its statistics (res may be NULL; its
+ * ms_iterate is the time of the whole call).  Results equal those of
+ * nd_decompose on each graph alone.  opts: mode, max_iters and use_frontier
+ * apply to every graph; on_iter and stop_active_ratio give
  * ND_ERR_UNSUPPORTED. */
 nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
                              nd_graph *const *graphs, nd_kind kind,
@@ -321,18 +339,23 @@ nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
 /* ------------------------------------------------------------ serving */
 
 /* A server serves decomposition requests with continuous batching (the
- * batching of nd_batch_decompose, kept running).  It owns two host threads,
- * each with its own stream: a preparation thread builds each admitted
- * request's r-cliques and incidence lists (nd_prepare's work) while a slot
- * (max_slots) is free and its device memory fits the context budget -- the
- * lists are allocated at their exact size from the count pass; a request
- * that does not fit releases what it built and waits for a running request
- * to retire, or fails with ND_ERR_OOM if nothing else holds memory -- and a
- * worker thread adds prepared requests to the running batch of their kind
- * and options and keeps sweeping, so requests that arrive while others are
- * on the GPU join them without stopping the sweeps.  A request retires when
- * it converges, hits max_iters or is cancelled, freeing its slot and its
- * device memory.  max_queue bounds the requests waiting for a slot. */
+ * batching of nd_batch_decompose, kept running).  It owns six host threads,
+ * each with its own stream.  Four preparation threads build admitted
+ * requests' r-cliques and incidence lists (nd_prepare's work) while a slot
+ * (max_slots) is free and the device memory fits the context budget -- the
+ * lists are allocated at their exact size from the count pass.  A build
+ * starts beside others only while the free budget holds twice the largest
+ * graph built so far for each of them.  A request that does not fit
+ * releases what it built and is retried with no other build running, then
+ * waits for a running request to retire, and fails with ND_ERR_OOM if
+ * nothing else holds memory.  Two worker threads, one for small requests
+ * (fewer than 2^20 incidence entries) and one for the rest, add prepared
+ * requests to the running batch of their class, kind and options and keep
+ * sweeping, so requests that arrive while others are on the GPU join them
+ * without stopping the sweeps, and small ones do not wait at every sweep for
+ * the long sweeps of large ones.  A request retires when it converges, hits
+ * max_iters or is cancelled, freeing its slot and its device memory.
+ * max_queue bounds the requests waiting for a slot. */
 nd_status nd_server_create(nd_ctx *ctx, int32_t max_slots, int32_t max_queue,
                            nd_server **out);
 

@@ -138,6 +138,8 @@ _sig("nd_partial_and", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int64,
      ctypes.POINTER(nd_opts), _P, ctypes.c_int, _P, ctypes.POINTER(nd_result))
 _sig("nd_ego_estimate", ctypes.c_int, _P, ctypes.c_int, _P, ctypes.c_int64,
      _I32, _P, _P, ctypes.c_int, _P)
+_sig("nd_prepare_many", ctypes.c_int, _P, _I32, ctypes.POINTER(_P),
+     ctypes.c_int, _P)
 _sig("nd_batch_decompose", ctypes.c_int, _P, _I32, ctypes.POINTER(_P),
      ctypes.c_int, ctypes.POINTER(nd_opts), ctypes.POINTER(_P), ctypes.c_int,
      _P, ctypes.POINTER(nd_result))
@@ -287,6 +289,13 @@ class Graph:
         _check(_lib.nd_sizes(self._h, KIND[kind], ctypes.byref(nr),
                              ctypes.byref(P), ctypes.byref(b)), "nd_sizes")
         return int(nr.value), int(P.value), int(b.value)
+
+    def rclique_count(self, kind: str) -> int:
+        """|R| for `kind`; for r <= 2 read off the graph without preparing."""
+        nr = _I64()
+        _check(_lib.nd_sizes(self._h, KIND[kind], ctypes.byref(nr), None, None),
+               "nd_sizes")
+        return int(nr.value)
 
     def rcliques(self, kind: str, stream=None) -> torch.Tensor:
         nr, _, _ = self.sizes(kind)
@@ -441,6 +450,16 @@ class Graph:
         return kappa[:nr], res.as_dict()
 
 
+def prepare_many(ctx: Context, graphs: Sequence[Graph], kind: str,
+                 stream=None):
+    """nd_prepare_many: prepare several graphs with overlapping builds."""
+    hs = (_P * max(len(graphs), 1))()
+    for i, g in enumerate(graphs):
+        hs[i] = g._h
+    _check(_lib.nd_prepare_many(ctx._h, len(graphs), hs, KIND[kind],
+                                _stream(stream)), "nd_prepare_many")
+
+
 def batch_decompose(ctx: Context, graphs: Sequence[Graph], kind: str,
                     mode: str = "snd", max_iters: int = -1,
                     use_frontier: bool = False, stream=None):
@@ -450,11 +469,15 @@ def batch_decompose(ctx: Context, graphs: Sequence[Graph], kind: str,
     outs, ptrs = [], (_P * max(count, 1))()
     hs = (_P * max(count, 1))()
     for i, g in enumerate(graphs):
-        nr, _, _ = g.sizes(kind)
+        hs[i] = g._h
+    if RS[kind][0] > 2:  # |R| is known only once the graphs are prepared
+        _check(_lib.nd_prepare_many(ctx._h, count, hs, KIND[kind],
+                                    _stream(stream)), "nd_prepare_many")
+    for i, g in enumerate(graphs):
+        nr = g.rclique_count(kind)
         k = torch.empty(max(nr, 1), dtype=torch.int32, device=ctx.device)
         outs.append(k[:nr])
         ptrs[i] = k.data_ptr()
-        hs[i] = g._h
     o, keep = _make_opts(mode, max_iters, use_frontier)
     res = (nd_result * max(count, 1))()
     _check(_lib.nd_batch_decompose(ctx._h, count, hs, KIND[kind],

@@ -557,6 +557,15 @@ nd_status nd_sizes(nd_graph *g, nd_kind kind, int64_t *n_rcliques,
                    int64_t *n_incidence, size_t *dev_bytes) {
   return guarded([&] {
     ND_REQUIRE(g, ND_ERR_INVALID, "graph is NULL");
+    ND_REQUIRE(kind_valid(kind), ND_ERR_UNSUPPORTED, "unknown kind %d",
+               (int)kind);
+    const int r = kind_rs(kind).r;
+    if (!n_incidence && !dev_bytes && !g->ks[kind].ready && r <= 2) {
+      // |R| without building anything: vertices, or edges (the CSR is
+      // symmetric and simple, so every edge is stored twice)
+      if (n_rcliques) *n_rcliques = r == 1 ? (int64_t)g->n : g->nnz / 2;
+      return;
+    }
     ND_HIP(hipSetDevice(g->ctx->device));
     StreamScope scope(nullptr);
     prepare(g, kind, nullptr);

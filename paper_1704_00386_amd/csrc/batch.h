@@ -10,7 +10,6 @@
 namespace nd {
 
 constexpr int kBatchRing = 32;    // per-graph sweep counters kept
-constexpr int kCounterRing = 64;  // tile counters, one per epoch slot
 constexpr int kPollMax = 16;      // epochs between host polls, at most
 
 // Device descriptor of one graph in a batch.
@@ -40,21 +39,20 @@ struct BHub {  // one r-clique with d_s >= 2048
 };
 
 // Device-resident launch state: every kernel of an epoch reads it, so a
-// captured chunk of epochs stays valid when the tables change.
+// chunk of epochs built as a HIP graph stays valid when the tables change.
 struct BState {
   int64_t epoch;
   int32_t ntiles;
   int32_t nhubs;
   int32_t ng;
   int32_t nwide;  // tiles [0, nwide): 16 or 32 values per lane (k_batch_sweep<WIDE>)
-  unsigned int counters[kCounterRing];         // tile counters, wide kernel
-  unsigned int counters_narrow[kCounterRing];  // the other tiles' kernel
 };
 
+// Tile length: an epoch is cut into about grid * tiles_per_group tiles of
+// about equal work (one workgroup each).
 struct BatchConfig {
-  int grid = 2048;          // workgroups of the persistent sweep kernel
-  int tiles_per_group = 8;  // target tiles per workgroup and epoch; sets the
-                            // tile length (block passes per tile)
+  int grid = 2048;
+  int tiles_per_group = 8;
 };
 
 // One graph taking part in a batch.
@@ -76,7 +74,7 @@ struct Member {
 
 class Batch {
  public:
-  static constexpr int kGraphEpochs = 8;  // epochs per captured HIP graph
+  static constexpr int kGraphEpochs = 8;  // epochs per HIP graph
 
   // Work is issued on a private stream ordered after `caller`.
   Batch(nd_ctx *ctx, nd_kind kind, nd_mode mode, bool tau16, bool frontier,
@@ -122,9 +120,7 @@ class Batch {
   void rebuild();
   void set_config(const BatchConfig &c);
   void launch_epoch();
-  void capture();
-  template <int K, typename T, bool AND, bool FR>
-  void launch_epoch_t();
+  void build_graph();
   void drop_graph();
 
   nd_ctx *ctx_;
@@ -142,6 +138,7 @@ class Batch {
   DArr<BState> state_;
   DArr<unsigned long long> poll_buf_;
   int64_t gs_cap_ = 0, tiles_cap_ = 0, hubs_cap_ = 0, poll_cap_ = 0;
+  int64_t wide_grid_ = 0, narrow_grid_ = 0;  // grids of the two tile kernels
   int ntiles_ = 0, nhubs_ = 0, ng_ = 0, nwide_ = 0;
   int64_t work_ = 0;
   int64_t epoch_ = 0;

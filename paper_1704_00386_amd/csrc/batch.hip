@@ -3,17 +3,17 @@
 // Every graph of a batch keeps its own internal numbering, incidence lists,
 // tau buffers and per-sweep counters.  Their r-cliques are cut into tiles
 // (graph, bin, id range) that form one combined work list; one epoch is one
-// sweep of every graph still running, done by a persistent kernel whose
-// workgroups pull tiles from an atomic counter until the list is exhausted
-// (heaviest tiles first, so the tail of an epoch is short).  A graph whose
+// sweep of every graph still running, one workgroup per tile, heaviest
+// tiles first (dispatched first, so the tail of an epoch is short).  A
+// graph whose
 // previous sweep changed nothing is skipped tile by tile and dropped from the
 // table at the next poll; graphs may join at any epoch (the server uses
 // this), each counting its own sweeps from the epoch it joined.  All launch
 // arguments are fixed device pointers and grid sizes -- the epoch number and
-// table sizes live in device memory -- so a chunk of epochs is captured once
+// table sizes live in device memory -- so a chunk of epochs is built once
 // in a HIP graph and replayed until the table outgrows its buffers.
 //
-// Tile and grid sizes come from a small autotuner, cached by (kind, mode,
+// Tile sizes come from a small autotuner, cached by (kind, mode,
 // tau width, frontier, work bucket): a batch whose first sweep is short
 // (launch-bound) times one trial sweep per candidate on scratch state and
 // keeps the fastest; a longer one keeps the default, since there the
@@ -23,7 +23,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -90,30 +93,28 @@ __device__ __forceinline__ void graph_frontier(const BGraph &G, int64_t local,
   if (notify && threadIdx.x == 0) sst->notified = 1;
 }
 
-// One epoch's tiles, pulled from a counter.  Two instances share the work:
-// WIDE takes the tiles of the bins of 16 and 32 values per lane (tiles
-// [0, nwide)), the other one every other bin, so that the registers of the
-// wide lanes do not set the occupancy of the rest.
+// One epoch's tiles, one workgroup per tile (tile i of the kernel's range
+// on workgroup i; the grid is the table's capacity, surplus workgroups
+// exit at once).  Workgroups are short-lived, so the work of other streams
+// (a server's preparations) is dispatched between them rather than waiting
+// for the epoch to end.  Two instances share the work: WIDE takes the tiles
+// of the bins of 16 and 32 values per lane (tiles [0, nwide)), the other
+// one every other bin, so that the registers of the wide lanes do not set
+// the occupancy of the rest.
 template <int K, typename T, bool AND, bool FR, bool WIDE>
 __global__ __launch_bounds__(256) void k_batch_sweep(
     const BGraph *__restrict__ gs, const BTile *__restrict__ tiles,
-    BState *__restrict__ st) {
-  __shared__ int s_tile;
+    const BState *__restrict__ st) {
   const int64_t e = st->epoch;
   const int t_lo = WIDE ? 0 : st->nwide;
   const int t_hi = WIDE ? st->nwide : st->ntiles;
-  unsigned int *counter = WIDE ? &st->counters[e % kCounterRing]
-                               : &st->counters_narrow[e % kCounterRing];
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = t_lo + (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int ti = s_tile;
-    __syncthreads();
-    if (ti >= t_hi) break;
+  const int ti = t_lo + (int)blockIdx.x;
+  if (ti >= t_hi) return;
+  {
     const BTile tile = tiles[ti];
     const BGraph &G = gs[tile.g];
     int64_t local;
-    if (!graph_live(G, e, &local)) continue;
+    if (!graph_live(G, e, &local)) return;
     const T *in = (const T *)G.tau[local & 1];
     T *out = (T *)G.tau[AND ? (local & 1) : ((local + 1) & 1)];
     SweepStats *sst = &G.ring[local % kBatchRing];
@@ -164,9 +165,10 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
         }
       }
       stat_add_counts(sst, n_ch, n_ev);
-      continue;
+      return;
     }
     const int per = rclq_per_pass(tile.type);
+    unsigned long long n_ch = 0, n_ev = 0;  // this wave's, over the passes
     for (int64_t base = tile.lo; base < tile.hi; base += per) {
       bool ch = false, ev = false;
       if constexpr (WIDE) {
@@ -211,8 +213,10 @@ __global__ __launch_bounds__(256) void k_batch_sweep(
           }
         }
       }
-      stat_add(sst, ch, ev);
+      n_ch += __popcll(ballot(ch));
+      n_ev += __popcll(ballot(ev));
     }
+    stat_add_counts(sst, n_ch, n_ev);
   }
 }
 
@@ -244,16 +248,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_batch_hubs(
   }
 }
 
-// Before an epoch: clear its tile counter and each live graph's counters.
+// Before an epoch: clear each live graph's counters.
 __global__ void k_epoch_begin(const BGraph *__restrict__ gs,
-                              BState *__restrict__ st) {
+                              const BState *__restrict__ st) {
   const int64_t e = st->epoch;
   const int ng = st->ng;
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 == 0) {
-    st->counters[e % kCounterRing] = 0;
-    st->counters_narrow[e % kCounterRing] = 0;
-  }
   for (int i = i0; i < ng; i += gridDim.x * blockDim.x) {
     const int64_t local = e - gs[i].t0;
     if (local >= 0 && local < gs[i].max_local) {
@@ -427,8 +427,8 @@ void Batch::rebuild() {
   std::vector<BHub> hh;
   int64_t work = 0;
   // Tile length: tiles hold about equal work bounds (pass_units) and an
-  // epoch has about grid * tiles_per_group of them -- each costs one atomic
-  // on the shared tile counter -- but never less than one block pass.
+  // epoch has about grid * tiles_per_group of them -- each a workgroup of
+  // its own -- but never less than one block pass.
   int64_t units_total = 0;
   for (auto &mp : members_) {
     if (mp->finished) continue;
@@ -488,7 +488,7 @@ void Batch::rebuild() {
   work_ = work;
   dead_tiles_ = 0;
   // Grow device tables (capacity doubles); a new buffer invalidates the
-  // captured graph, whose kernels hold the table pointers.
+  // epoch graph, whose kernel nodes hold the table pointers.
   auto ensure = [&](auto &arr, int64_t need, int64_t &cap) {
     need = std::max<int64_t>(need, 1);
     if (need > cap) {
@@ -510,6 +510,16 @@ void Batch::rebuild() {
   if (!hh.empty())
     ND_HIP(hipMemcpyAsync(hubs_.p, hh.data(), sizeof(BHub) * hh.size(),
                           hipMemcpyHostToDevice, s_));
+  // grids of the two tile kernels: the capacity of their tile ranges
+  auto ensure_grid = [&](int64_t need, int64_t &cap) {
+    need = std::max<int64_t>(need, 1);
+    if (need > cap) {
+      cap = std::max<int64_t>(need, 2 * cap);
+      drop_graph();
+    }
+  };
+  ensure_grid(nwide_, wide_grid_);
+  ensure_grid((int64_t)ntiles_ - nwide_, narrow_grid_);
   int32_t counts[4] = {ntiles_, nhubs_, ng_, nwide_};
   ND_HIP(hipMemcpyAsync(&state_.p->ntiles, counts, sizeof counts,
                         hipMemcpyHostToDevice, s_));
@@ -517,32 +527,26 @@ void Batch::rebuild() {
   dirty_ = false;
 }
 
+// The kernels of one epoch, in launch order, for the batch's instance.
+struct EpochKernels {
+  const void *fn[5];  // begin, wide tiles, other tiles, hubs, end
+};
+
 template <int K, typename T, bool AND, bool FR>
-void Batch::launch_epoch_t() {
-  k_epoch_begin<<<kBeginGrid, 256, 0, s_>>>(gs_.p, state_.p);
-  ND_LAUNCHED();
-  k_batch_sweep<K, T, AND, FR, true><<<cfg_.grid, 256, 0, s_>>>(
-      gs_.p, tiles_.p, state_.p);
-  ND_LAUNCHED();
-  k_batch_sweep<K, T, AND, FR, false><<<cfg_.grid, 256, 0, s_>>>(
-      gs_.p, tiles_.p, state_.p);
-  ND_LAUNCHED();
-  k_batch_hubs<K, T, AND, FR><<<kHubGrid, kBlockThreads, 0, s_>>>(
-      gs_.p, hubs_.p, state_.p);
-  ND_LAUNCHED();
-  k_epoch_end<<<1, 1, 0, s_>>>(state_.p);
-  ND_LAUNCHED();
+EpochKernels epoch_kernels_t() {
+  return {{(const void *)k_epoch_begin,
+           (const void *)k_batch_sweep<K, T, AND, FR, true>,
+           (const void *)k_batch_sweep<K, T, AND, FR, false>,
+           (const void *)k_batch_hubs<K, T, AND, FR>, (const void *)k_epoch_end}};
 }
 
-void Batch::launch_epoch() {
-  const int k = kind_rs(kind_).k;
-  const int key = (k * 2 + (tau16_ ? 1 : 0)) * 4 + (mode_ == ND_AND ? 2 : 0) +
-                  (frontier_ ? 1 : 0);
-#define ND_EPOCH_CASES(KK, T, BASE)                                   \
-  case BASE + 0: launch_epoch_t<KK, T, false, false>(); break;       \
-  case BASE + 1: launch_epoch_t<KK, T, false, true>(); break;        \
-  case BASE + 2: launch_epoch_t<KK, T, true, false>(); break;        \
-  case BASE + 3: launch_epoch_t<KK, T, true, true>(); break;
+static EpochKernels epoch_kernels(int k, bool tau16, bool and_mode, bool fr) {
+  const int key = (k * 2 + (tau16 ? 1 : 0)) * 4 + (and_mode ? 2 : 0) + (fr ? 1 : 0);
+#define ND_EPOCH_CASES(KK, T, BASE)                                 \
+  case BASE + 0: return epoch_kernels_t<KK, T, false, false>();    \
+  case BASE + 1: return epoch_kernels_t<KK, T, false, true>();     \
+  case BASE + 2: return epoch_kernels_t<KK, T, true, false>();     \
+  case BASE + 3: return epoch_kernels_t<KK, T, true, true>();
   switch (key) {
     ND_EPOCH_CASES(1, int32_t, 8)
     ND_EPOCH_CASES(1, uint16_t, 12)
@@ -552,30 +556,81 @@ void Batch::launch_epoch() {
     ND_EPOCH_CASES(3, uint16_t, 28)
     ND_EPOCH_CASES(5, int32_t, 40)
     ND_EPOCH_CASES(5, uint16_t, 44)
-    default: ND_REQUIRE(false, ND_ERR_INVALID, "bad batch key %d", key);
+    default: break;
   }
 #undef ND_EPOCH_CASES
+  ND_REQUIRE(false, ND_ERR_INVALID, "bad batch key %d", key);
+  return {};
 }
 
-// Capture kGraphEpochs epochs into graph_exec_.  Relaxed mode: the capture
-// itself makes no call that a capture forbids, and other threads of the
-// process (a server's preparation thread allocating memory) must stay free
-// to.  If the capture fails anyway, it is ended (so the stream leaves
-// capture mode) and this batch launches its epochs directly from then on.
-void Batch::capture() {
+// Grid, block and arguments of kernel i of an epoch.  The argument values
+// live in *this (table pointers), so `args` stays valid while they do.
+struct EpochLaunch {
+  const BGraph *gs;
+  const BTile *tiles;
+  const BHub *hubs;
+  BState *st;
+  void *a_begin[2], *a_tiles[3], *a_hubs[3], *a_end[1];
+  dim3 grid[5], block[5];
+  void **args[5];
+  EpochLaunch(const BGraph *g, const BTile *t, const BHub *h, BState *s,
+              int64_t wide_grid, int64_t narrow_grid)
+      : gs(g), tiles(t), hubs(h), st(s) {
+    a_begin[0] = &gs;
+    a_begin[1] = &st;
+    a_tiles[0] = &gs;
+    a_tiles[1] = &tiles;
+    a_tiles[2] = &st;
+    a_hubs[0] = &gs;
+    a_hubs[1] = &hubs;
+    a_hubs[2] = &st;
+    a_end[0] = &st;
+    void **a[5] = {a_begin, a_tiles, a_tiles, a_hubs, a_end};
+    const int64_t gr[5] = {kBeginGrid, wide_grid, narrow_grid, kHubGrid, 1};
+    const int bl[5] = {256, 256, 256, kBlockThreads, 1};
+    for (int i = 0; i < 5; i++) {
+      args[i] = a[i];
+      grid[i] = dim3((unsigned)gr[i]);
+      block[i] = dim3(bl[i]);
+    }
+  }
+  EpochLaunch(const EpochLaunch &) = delete;
+};
+
+void Batch::launch_epoch() {
+  const EpochKernels ek =
+      epoch_kernels(kind_rs(kind_).k, tau16_, mode_ == ND_AND, frontier_);
+  EpochLaunch el(gs_.p, tiles_.p, hubs_.p, state_.p, wide_grid_, narrow_grid_);
+  for (int i = 0; i < 5; i++) {
+    ND_HIP(hipLaunchKernel(ek.fn[i], el.grid[i], el.block[i], el.args[i], 0, s_));
+  }
+}
+
+// Build kGraphEpochs epochs as a HIP graph, node by node (no stream
+// capture, so other threads stay free to use any stream, the legacy one
+// included, while it is built); on failure this batch launches its epochs
+// directly from then on.
+void Batch::build_graph() {
+  const EpochKernels ek =
+      epoch_kernels(kind_rs(kind_).k, tau16_, mode_ == ND_AND, frontier_);
+  EpochLaunch el(gs_.p, tiles_.p, hubs_.p, state_.p, wide_grid_, narrow_grid_);
   hipGraph_t gr = nullptr;
-  if (hipStreamBeginCapture(s_, hipStreamCaptureModeRelaxed) != hipSuccess) {
-    (void)hipGetLastError();
-    use_graph = false;
-    return;
-  }
-  bool ok = true;
-  try {
-    for (int i = 0; i < kGraphEpochs; i++) launch_epoch();
-  } catch (const Err &) {
-    ok = false;
-  }
-  if (hipStreamEndCapture(s_, &gr) != hipSuccess) ok = false;
+  bool ok = hipGraphCreate(&gr, 0) == hipSuccess;
+  hipGraphNode_t prev = nullptr;
+  for (int e = 0; ok && e < kGraphEpochs; e++)
+    for (int i = 0; ok && i < 5; i++) {
+      hipKernelNodeParams np{};
+      np.func = const_cast<void *>(ek.fn[i]);
+      np.gridDim = el.grid[i];
+      np.blockDim = el.block[i];
+      np.sharedMemBytes = 0;
+      np.kernelParams = el.args[i];
+      np.extra = nullptr;
+      hipGraphNode_t node = nullptr;
+      ok = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0,
+                                 &np) == hipSuccess;
+      prev = node;
+    }
   if (ok && hipGraphInstantiate(&graph_exec_, gr, nullptr, nullptr, 0) != hipSuccess) {
     graph_exec_ = nullptr;
     ok = false;
@@ -591,7 +646,7 @@ void Batch::capture() {
 void Batch::run_epochs(int count) {
   if (dirty_) rebuild();
   if (ng_ == 0) return;
-  if (use_graph && count == kGraphEpochs && !graph_exec_) capture();
+  if (use_graph && count == kGraphEpochs && !graph_exec_) build_graph();
   if (use_graph && count == kGraphEpochs && graph_exec_) {
     ND_HIP(hipGraphLaunch(graph_exec_, s_));
   } else {
@@ -733,74 +788,200 @@ int Batch::autotune() {
 
 namespace {
 
-constexpr int kPrepThreads = 4;
+constexpr int kPrepThreads = 2;
 
-// Prepare the graphs that are not yet prepared for `kind`, on up to
-// kPrepThreads host threads with a stream each (ordered after s), so that
-// the short, launch-bound build phases of different graphs overlap; s then
-// waits for every prep stream.  The first failure is rethrown.
-void prepare_all(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
-                 nd_kind kind, hipStream_t s) {
-  std::vector<nd_graph *> todo;
-  for (int i = 0; i < count; i++)
-    if (!graphs[i]->ks[kind].ready &&
-        std::find(todo.begin(), todo.end(), graphs[i]) == todo.end())
-      todo.push_back(graphs[i]);
-  if (todo.size() <= 1) {
-    for (nd_graph *g : todo) prepare(g, kind, s);
-    return;
-  }
-  const int nt = (int)std::min<size_t>(kPrepThreads, todo.size());
-  hipEvent_t start;
-  ND_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-  ND_HIP(hipEventRecord(start, s));
-  std::vector<hipStream_t> streams(nt, nullptr);
-  for (int t = 0; t < nt; t++) {
-    ND_HIP(hipStreamCreateWithFlags(&streams[t], hipStreamNonBlocking));
-    ND_HIP(hipStreamWaitEvent(streams[t], start, 0));
-  }
-  (void)hipEventDestroy(start);
-  std::atomic<size_t> next{0};
-  std::atomic<bool> failed{false};
-  std::vector<nd_status> codes(nt, ND_OK);
-  std::vector<std::string> msgs(nt);
-  std::vector<std::thread> threads;
-  for (int t = 0; t < nt; t++)
-    threads.emplace_back([&, t] {
-      try {
-        ND_HIP(hipSetDevice(ctx->device));
-        StreamScope scope(streams[t]);
-        for (size_t i; !failed && (i = next++) < todo.size();)
-          prepare(todo[i], kind, streams[t]);
-      } catch (const Err &e) {
-        codes[t] = e.code;
-        msgs[t] = nd_last_error();
-        failed = true;
-      } catch (const std::exception &e) {
-        codes[t] = ND_ERR_DEVICE;
-        msgs[t] = e.what();
-        failed = true;
-      }
-    });
-  for (auto &th : threads) th.join();
-  for (int t = 0; t < nt; t++) {
-    hipEvent_t done;
-    ND_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-    ND_HIP(hipEventRecord(done, streams[t]));
-    ND_HIP(hipStreamWaitEvent(s, done, 0));
-    (void)hipEventDestroy(done);
-    ctx->alloc.forget_stream(streams[t]);
-    (void)hipStreamDestroy(streams[t]);
-  }
-  for (int t = 0; t < nt; t++)
-    if (codes[t] != ND_OK) {
-      set_error("%s", msgs[t].c_str());
-      throw Err(codes[t]);
-    }
+int prep_threads() {
+  static const int n = [] {
+    const char *v = getenv("ND_PREP_THREADS");
+    const int x = v ? atoi(v) : kPrepThreads;
+    return x < 1 ? 1 : x > 16 ? 16 : x;
+  }();
+  return n;
 }
+
+// Prepares graphs for one kind on up to prep_threads() host threads, each
+// with a stream of its own ordered after the caller's, largest graphs first
+// (their sweeps are the longest, so they should start first).  Each
+// prepared graph is handed to the consumer with an event recorded after its
+// work, so the consumer's stream can wait for exactly that graph; the
+// short, launch-bound build phases of different graphs overlap each other
+// and the consumer's sweeps.
+class PrepPool {
+ public:
+  PrepPool(nd_ctx *ctx, int32_t count, nd_graph *const *graphs, nd_kind kind,
+           hipStream_t after)
+      : ctx_(ctx), kind_(kind) {
+    for (int i = 0; i < count; i++)
+      if (!graphs[i]->ks[kind].ready &&
+          std::find(todo_.begin(), todo_.end(), graphs[i]) == todo_.end())
+        todo_.push_back(graphs[i]);
+    std::stable_sort(todo_.begin(), todo_.end(),
+                     [](const nd_graph *a, const nd_graph *b) { return a->nnz > b->nnz; });
+    if (todo_.empty()) return;
+    const int nt = (int)std::min<size_t>(prep_threads(), todo_.size());
+    hipEvent_t start;
+    ND_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    ND_HIP(hipEventRecord(start, after));
+    for (int t = 0; t < nt; t++) {
+      hipStream_t st = nullptr;
+      const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(start);
+        ND_HIP(e);
+      }
+      streams_.push_back(st);
+      ND_HIP(hipStreamWaitEvent(st, start, 0));
+    }
+    (void)hipEventDestroy(start);
+    for (int t = 0; t < nt; t++) threads_.emplace_back([this, t] { run(t); });
+  }
+
+  ~PrepPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      failed_ = true;  // stop taking graphs
+    }
+    join();
+    for (auto &d : done_) (void)hipEventDestroy(d.second);
+    for (hipStream_t st : streams_) {
+      ctx_->alloc.forget_stream(st);
+      (void)hipStreamDestroy(st);
+    }
+  }
+
+  int pending() const { return (int)todo_.size(); }
+
+  // The next prepared graph and its event (owned by the caller).  Waits for
+  // one when `block`; returns false when none is ready (not blocking), when
+  // every graph has been handed out, or after a failure (see rethrow).
+  bool next(bool block, nd_graph **g, hipEvent_t *ev) {
+    std::unique_lock<std::mutex> lk(mu_);
+    if (block)
+      cv_.wait(lk, [&] { return !done_.empty() || failed_ || handed_ == todo_.size(); });
+    if (done_.empty()) return false;
+    *g = done_.front().first;
+    *ev = done_.front().second;
+    done_.pop_front();
+    handed_++;
+    return true;
+  }
+
+  // Every graph handed out.
+  bool finished() {
+    std::lock_guard<std::mutex> lk(mu_);
+    return handed_ == todo_.size();
+  }
+
+  // A preparation failed (finish() throws it).
+  bool failed() {
+    std::lock_guard<std::mutex> lk(mu_);
+    return code_ != ND_OK;
+  }
+
+  // Join the threads; make `s` wait for every preparation stream; throw the
+  // first failure.
+  void finish(hipStream_t s) {
+    join();
+    for (hipStream_t st : streams_) {
+      hipEvent_t d;
+      ND_HIP(hipEventCreateWithFlags(&d, hipEventDisableTiming));
+      ND_HIP(hipEventRecord(d, st));
+      ND_HIP(hipStreamWaitEvent(s, d, 0));
+      (void)hipEventDestroy(d);
+    }
+    rethrow();
+  }
+
+  void rethrow() {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (code_ != ND_OK) {
+      set_error("%s", msg_.c_str());
+      throw Err(code_);
+    }
+  }
+
+ private:
+  void join() {
+    for (auto &th : threads_)
+      if (th.joinable()) th.join();
+  }
+
+  void run(int t) {
+    try {
+      ND_HIP(hipSetDevice(ctx_->device));
+      StreamScope scope(streams_[t]);
+      for (;;) {
+        nd_graph *g;
+        {
+          std::lock_guard<std::mutex> lk(mu_);
+          if (failed_ || next_ == todo_.size()) return;
+          g = todo_[next_++];
+        }
+        prepare(g, kind_, streams_[t]);
+        hipEvent_t ev;
+        ND_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        const hipError_t e = hipEventRecord(ev, streams_[t]);
+        if (e != hipSuccess) {
+          (void)hipEventDestroy(ev);
+          ND_HIP(e);
+        }
+        std::lock_guard<std::mutex> lk(mu_);
+        done_.emplace_back(g, ev);
+        cv_.notify_all();
+      }
+    } catch (const Err &e) {
+      fail(e.code, nd_last_error());
+    } catch (const std::exception &e) {
+      fail(ND_ERR_DEVICE, e.what());
+    }
+  }
+
+  void fail(nd_status code, const std::string &msg) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (code_ == ND_OK) {
+      code_ = code;
+      msg_ = msg;
+    }
+    failed_ = true;
+    cv_.notify_all();
+  }
+
+  nd_ctx *ctx_;
+  nd_kind kind_;
+  std::vector<nd_graph *> todo_;
+  std::vector<hipStream_t> streams_;
+  std::vector<std::thread> threads_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::pair<nd_graph *, hipEvent_t>> done_;
+  size_t next_ = 0, handed_ = 0;
+  bool failed_ = false;
+  nd_status code_ = ND_OK;
+  std::string msg_;
+};
 
 }  // namespace
 
+void prepare_many(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
+                  nd_kind kind, hipStream_t s) {
+  PrepPool pool(ctx, count, graphs, kind, s);
+  nd_graph *g;
+  hipEvent_t ev;
+  while (pool.next(true, &g, &ev)) (void)hipEventDestroy(ev);
+  pool.finish(s);
+}
+
+// Incidence entries the live graphs must hold before sweeps run while
+// other graphs are still being prepared.  Shorter epochs would mostly add
+// launches and polls beside the preparation threads' own (whose build
+// phases are launch-bound), slowing them more than the overlap gains.
+constexpr int64_t kOverlapWork = (int64_t)1 << 24;
+
+// The batched decomposition.  Graphs not yet prepared are prepared by a
+// PrepPool while the graphs already prepared are being swept (once their
+// sweeps are long enough, kOverlapWork): each joins the batch of its tau
+// width (16 or 32 bits; two batches, on streams of their own, when the
+// graphs need both) as soon as it is ready.
 nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
                           nd_kind kind, const nd_opts *opts_in,
                           int32_t *const *kappas, int on_device, hipStream_t s,
@@ -813,60 +994,108 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
   ND_REQUIRE(opts.on_iter == nullptr && opts.stop_active_ratio == 0,
              ND_ERR_UNSUPPORTED,
              "batched decomposition supports mode, max_iters and use_frontier");
-  bool all16 = true;
-  std::vector<double> prep(count, 0.0);
   std::vector<bool> was(count);
   for (int i = 0; i < count; i++) {
     ND_REQUIRE(graphs[i] && graphs[i]->ctx == ctx, ND_ERR_INVALID,
                "graph %d is NULL or from another context", i);
     was[i] = graphs[i]->ks[kind].ready;
   }
-  {
-    Phase phase("nd.batch.prepare");
-    prepare_all(ctx, count, graphs, kind, s);
-  }
-  for (int i = 0; i < count; i++) {
-    prep[i] = was[i] ? 0.0 : graphs[i]->ks[kind].ms_prep;
-    all16 &= graphs[i]->ks[kind].tau16;
-  }
-  Batch batch(ctx, kind, opts.mode, all16, opts.use_frontier != 0, s);
-  hipStream_t bs = batch.stream();
-  std::vector<Member *> ms;
-  for (int i = 0; i < count; i++)
-    ms.push_back(batch.add(graphs[i], opts.max_iters, nullptr));
+  for (int i = 0; i < count; i++)  // outputs of graphs already prepared
+    ND_REQUIRE(!was[i] || graphs[i]->ks[kind].nr == 0 || (kappas && kappas[i]),
+               ND_ERR_INVALID, "kappas[%d] is NULL", i);
+  std::unique_ptr<Batch> batches[2];  // 16-bit, 32-bit tau
+  bool tuned[2] = {false, false};
+  std::map<nd_graph *, Member *> member;
   hipEvent_t a, b;
   ND_HIP(hipEventCreate(&a));
   ND_HIP(hipEventCreate(&b));
-  ND_HIP(hipEventRecord(a, bs));
-  Phase sweep_phase("nd.batch.sweeps");
-  batch.poll(batch.autotune());
-  int chunk = 2;
-  for (;;) {
-    bool any = false;
-    for (Member *m : ms) any |= !m->finished;
-    if (!any) break;
-    batch.run_epochs(chunk);
-    batch.poll(chunk);
-    chunk = std::min(chunk * 2, Batch::kGraphEpochs);
+  ND_HIP(hipEventRecord(a, s));
+  auto join = [&](nd_graph *g, hipEvent_t ready) {
+    const int w = g->ks[kind].tau16 ? 0 : 1;
+    if (!batches[w])
+      batches[w] = std::make_unique<Batch>(ctx, kind, opts.mode, w == 0,
+                                           opts.use_frontier != 0, s);
+    if (ready) ND_HIP(hipStreamWaitEvent(batches[w]->stream(), ready, 0));
+    member[g] = batches[w]->add(g, opts.max_iters, nullptr);
+  };
+  {
+    PrepPool pool(ctx, count, graphs, kind, s);
+    Phase sweep_phase("nd.batch.sweeps");
+    for (int i = 0; i < count; i++)
+      if (was[i] && !member.count(graphs[i])) join(graphs[i], nullptr);
+    int chunk = 2;
+    while (!pool.failed()) {
+      auto live_work = [&] {
+        int64_t w = 0;
+        for (auto &bt : batches)
+          if (bt)
+            for (Member *m : bt->live()) w += std::max<int64_t>(m->g->ks[kind].P, 1);
+        return w;
+      };
+      int64_t work = live_work();
+      // newcomers; wait for one while the sweeps would be too short to
+      // overlap the preparations usefully
+      nd_graph *g;
+      hipEvent_t ev;
+      while (pool.next(work < kOverlapWork && !pool.finished(), &g, &ev)) {
+        try {
+          join(g, ev);
+        } catch (...) {
+          (void)hipEventDestroy(ev);
+          throw;
+        }
+        (void)hipEventDestroy(ev);
+        work = live_work();
+      }
+      if (work == 0) {
+        if (pool.finished()) break;
+        continue;
+      }
+      int ran[2] = {0, 0};
+      for (int w = 0; w < 2; w++) {
+        if (!batches[w] || batches[w]->live().empty()) continue;
+        if (!tuned[w]) {  // its first epoch, or trial epochs on scratch state
+          ran[w] = batches[w]->autotune();
+          tuned[w] = true;
+        } else {
+          batches[w]->run_epochs(chunk);
+          ran[w] = chunk;
+        }
+      }
+      for (int w = 0; w < 2; w++)
+        if (ran[w]) batches[w]->poll(ran[w]);
+      chunk = std::min(chunk * 2, Batch::kGraphEpochs);
+    }
+    pool.finish(s);
   }
-  ND_HIP(hipEventRecord(b, bs));
+  for (auto &bt : batches)
+    if (bt) {
+      hipEvent_t d;
+      ND_HIP(hipEventCreateWithFlags(&d, hipEventDisableTiming));
+      ND_HIP(hipEventRecord(d, bt->stream()));
+      ND_HIP(hipStreamWaitEvent(s, d, 0));
+      (void)hipEventDestroy(d);
+    }
+  ND_HIP(hipEventRecord(b, s));
   ND_HIP(hipEventSynchronize(b));
   float ms_total = 0;
   ND_HIP(hipEventElapsedTime(&ms_total, a, b));
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   nd_status out = ND_OK;
-  StreamScope scope(bs);
   for (int i = 0; i < count; i++) {
-    Member &m = *ms[i];
+    const Member &m = *member.at(graphs[i]);
     const KindState &ks = graphs[i]->ks[kind];
+    const Batch &bt = *batches[ks.tau16 ? 0 : 1];
+    hipStream_t bs = bt.stream();
+    StreamScope scope(bs);
     if (ks.nr > 0) {
       ND_REQUIRE(kappas && kappas[i], ND_ERR_INVALID, "kappas[%d] is NULL", i);
       if (on_device) {
-        to_original(ks, batch.result_tau(m), batch.tau16(), kappas[i], bs);
+        to_original(ks, bt.result_tau(m), bt.tau16(), kappas[i], bs);
       } else {
         DArr<int32_t> tmp(ctx->alloc, ks.nr);
-        to_original(ks, batch.result_tau(m), batch.tau16(), tmp.p, bs);
+        to_original(ks, bt.result_tau(m), bt.tau16(), tmp.p, bs);
         ND_HIP(hipMemcpyAsync(kappas[i], tmp.p, sizeof(int32_t) * ks.nr,
                               hipMemcpyDeviceToHost, bs));
         ND_HIP(hipStreamSynchronize(bs));
@@ -880,14 +1109,22 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
       r.n_rcliques = ks.nr;
       r.n_incidence = ks.P;
       r.updates = ks.bin_lo[kBinZero] * m.sweeps;
-      r.ms_prep = prep[i];
+      r.ms_prep = was[i] ? 0.0 : ks.ms_prep;
       r.ms_iterate = ms_total;  // shared by the whole batch
       r.max_sdegree = ks.max_ds;
-      r.tau_bytes = batch.tau16() ? 2 : 4;
+      r.tau_bytes = bt.tau16() ? 2 : 4;
     }
     if (!m.converged) out = ND_ERR_NOT_CONVERGED;
   }
-  ND_HIP(hipStreamSynchronize(bs));
+  for (auto &bt : batches)
+    if (bt) {
+      ND_HIP(hipStreamSynchronize(bt->stream()));
+      hipEvent_t d;  // the caller's later work follows the output kernels
+      ND_HIP(hipEventCreateWithFlags(&d, hipEventDisableTiming));
+      ND_HIP(hipEventRecord(d, bt->stream()));
+      ND_HIP(hipStreamWaitEvent(s, d, 0));
+      (void)hipEventDestroy(d);
+    }
   if (out != ND_OK) set_error("a graph of the batch stopped without converging");
   return out;
 }
@@ -915,4 +1152,21 @@ extern "C" nd_status nd_batch_decompose(nd_ctx *ctx, int32_t count,
                           (hipStream_t)stream, res);
   });
   return st != ND_OK ? st : out;
+}
+
+extern "C" nd_status nd_prepare_many(nd_ctx *ctx, int32_t count,
+                                     nd_graph *const *graphs, nd_kind kind,
+                                     void *stream) {
+  return guarded([&] {
+    ND_REQUIRE(ctx, ND_ERR_INVALID, "ctx is NULL");
+    ND_REQUIRE(count >= 0 && (count == 0 || graphs), ND_ERR_INVALID,
+               "bad graph list");
+    ND_REQUIRE(kind_valid(kind), ND_ERR_UNSUPPORTED, "unknown kind");
+    for (int i = 0; i < count; i++)
+      ND_REQUIRE(graphs[i] && graphs[i]->ctx == ctx, ND_ERR_INVALID,
+                 "graph %d is NULL or from another context", i);
+    ND_HIP(hipSetDevice(ctx->device));
+    StreamScope scope((hipStream_t)stream);
+    prepare_many(ctx, count, graphs, kind, (hipStream_t)stream);
+  });
 }

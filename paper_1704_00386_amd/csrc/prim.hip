@@ -1,6 +1,7 @@
 // prim.hip -- device primitives used by graph preparation: exclusive scan,
 // stable LSD radix sort of 64-bit keys, stable partition by a small key, and
 // fills.  All integer, all deterministic.
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -89,18 +90,44 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + total;
 }
 
+// Up to this many tiles, one workgroup scans them in turn, carrying the
+// running total: one launch instead of three (the scans of graph
+// preparation are mostly this short, and launches dominate them).
+constexpr int64_t kScanLoopTiles = 64;
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_loop(
+    const T *__restrict__ in, int64_t n, int64_t *__restrict__ out) {
+  int64_t carry = 0;
+  for (int64_t base0 = 0; base0 < n; base0 += kScanTile) {
+    const int64_t base = base0 + threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+      const int64_t i = base + j;
+      v[j] = i < n ? (int64_t)in[i] : 0;
+      sum += v[j];
+    }
+    int64_t total;
+    int64_t run = carry + block_exclusive_scan(sum, &total);
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+      const int64_t i = base + j;
+      if (i < n) out[i] = run;
+      run += v[j];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
 template <typename T>
 void exclusive_scan_impl(const T *in, int64_t *out, int64_t n, hipStream_t s,
                          Allocator &al) {
-  if (n <= 0) {
-    int64_t zero = 0;
-    ND_HIP(hipMemcpyAsync(out, &zero, sizeof zero, hipMemcpyHostToDevice, s));
-    ND_HIP(hipStreamSynchronize(s));  // `zero` lives on this stack frame
-    return;
-  }
-  const int64_t nb = ceil_div(n, kScanTile);
-  if (nb == 1) {
-    k_scan_tile<T><<<1, kScanThreads, 0, s>>>(in, n, nullptr, out);
+  const int64_t nb = ceil_div(std::max<int64_t>(n, 0), kScanTile);
+  if (nb <= kScanLoopTiles) {  // n == 0 too: writes out[0] = 0
+    k_scan_loop<T><<<1, kScanThreads, 0, s>>>(in, std::max<int64_t>(n, 0), out);
     ND_LAUNCHED();
     return;
   }

@@ -1,18 +1,25 @@
 // server.hip -- a request loop with continuous batching.
 //
-// Callers submit graphs.  Two host threads serve them, each with its own
+// Callers submit graphs.  Host threads serve them, each with its own
 // stream:
-//   * the preparation thread takes waiting requests while a slot is free and
-//     builds what their kind needs (r-cliques, incidence lists, d_s) on its
-//     stream.  Admission is by device memory: the builders' allocations are
-//     charged to the context's budget, the incidence lists at their exact
-//     size from the count pass; a request that does not fit releases what it
-//     built and waits for a running request to retire (or fails when nothing
-//     else holds memory).  Preparing here keeps the sweep loop running while
-//     a newcomer is built;
-//   * the worker thread adds prepared requests to the running batch of their
-//     kind, mode, tau width and frontier setting (batch.hip) and keeps
-//     sweeping every batch a chunk of epochs at a time.  A request that
+//   * kPrepThreads preparation threads take waiting requests while a slot is
+//     free and build what their kind needs (r-cliques, incidence lists, d_s)
+//     on their streams, so that the short, launch-bound build phases of
+//     several newcomers overlap.  Admission is by device memory: the
+//     builders' allocations are charged to the context's budget, the
+//     incidence lists at their exact size from the count pass.  A request
+//     that does not fit releases what it built and is retried on its own
+//     (no other build running); if it still does not fit it waits for a
+//     running request to retire, and fails when nothing else holds memory.
+//     Preparing here keeps the sweep loop running while newcomers are built;
+//   * two worker threads add prepared requests to the running batch of their
+//     size class, kind, mode, tau width and frontier setting (batch.hip) and
+//     keep sweeping every batch of their class a chunk of epochs at a time.
+//     Small requests (fewer than kSmallWork incidence entries) have a worker
+//     and batches of their own: in a batch every member advances one sweep
+//     per epoch, and an epoch lasts as long as its largest member's sweep,
+//     so a small request batched with large ones would wait for them at
+//     every sweep.  A request that
 //     converges (or hits its sweep cap, or is cancelled) is retired at the
 //     next poll: its result is copied into host memory the server owns, its
 //     device memory released and its slot given to the next waiting request.
@@ -20,8 +27,10 @@
 // sweeps share launches.  Results equal those of a lone nd_decompose (SND
 // iterates do not depend on what else is in a launch; AND converges to the
 // same unique fixed point).
+#include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -43,6 +52,8 @@ struct Request {
   nd_opts opts{};
   Clock::time_point t_submit, t_done;
   bool admitted = false;  // holds a slot (preparing, ready or running)
+  bool retry_alone = false;  // did not fit beside other builds
+  int cls = 0;               // size class, set once prepared
   bool done = false, cancelled = false;
   nd_status status = ND_OK;
   nd_result res{};
@@ -68,19 +79,24 @@ struct nd_server {
   std::deque<nd::Request *> queue;  // submitted, not yet being prepared
   std::deque<nd::Request *> ready;  // prepared, not yet in a batch
   std::map<uint64_t, std::unique_ptr<nd::Request>> reqs;
-  std::thread worker, prep;
+  std::thread workers[2];  // size classes: small, large
+  std::vector<std::thread> preps;
   bool stop = false;
   int admitted = 0;         // requests holding a slot
+  int preparing = 0;        // builds in progress
+  bool alone = false;       // a retried build runs with no other build
+  size_t build_bytes = 0;   // largest graph a build has produced so far
   int running = 0;          // requests in a batch
+  int running_cls[2] = {0, 0};  // of them, per size class
   uint64_t retired = 0;     // retirements so far (memory may have freed)
   uint64_t next_ticket = 1;
   std::atomic<int64_t> epochs{0};  // epochs run over all batches
-  hipStream_t stream = nullptr;       // the worker's
-  hipStream_t prep_stream = nullptr;  // the preparation thread's
+  hipStream_t streams[2] = {nullptr, nullptr};  // the workers
+  std::vector<hipStream_t> prep_streams;  // one per preparation thread
   // pinned result buffers not in use, by capacity (guarded by mu)
   std::multimap<size_t, void *> pinned_free;
-  // one batch per (kind, mode, tau width, frontier)
-  std::unique_ptr<nd::Batch> batches[nd::kNumKinds][2][2][2];
+  // one batch per (size class, kind, mode, tau width, frontier)
+  std::unique_ptr<nd::Batch> batches[2][nd::kNumKinds][2][2][2];
 };
 
 namespace nd {
@@ -194,35 +210,64 @@ void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
   release_graph(r, b.stream(), /*wait=*/false);
   std::lock_guard<std::mutex> lk(srv->mu);
   srv->running--;
+  srv->running_cls[r->cls]--;
   srv->retired++;
   finish_locked(srv, r, st);
 }
 
-// The preparation thread: build waiting requests while slots are free.
-void prep_main(nd_server *srv) {
+constexpr int kPrepThreads = 4;
+constexpr int64_t kSmallWork = (int64_t)1 << 20;  // incidence entries
+
+int server_prep_threads() {
+  const char *v = getenv("ND_PREP_THREADS");
+  const int x = v ? atoi(v) : kPrepThreads;
+  return x < 1 ? 1 : x > 16 ? 16 : x;
+}
+
+// May a build start now (lock held)?  One build always may (the budget
+// admits or rejects it as it allocates).  Another starts beside running
+// builds only while the free budget holds twice the largest graph built so
+// far for each of them and the newcomer, so that concurrent builds do not
+// take the memory the callers' own graphs need.  A request marked
+// retry_alone starts only when no other build runs, and none starts beside it.
+bool may_start_build(nd_server *srv) {
+  if (srv->queue.empty() || srv->admitted >= srv->max_slots || srv->alone)
+    return false;
+  if (srv->preparing == 0) return true;
+  if (srv->queue.front()->retry_alone || srv->build_bytes == 0) return false;
+  const Allocator &al = srv->ctx->alloc;
+  const size_t live = al.live_bytes();
+  const size_t free_b = al.budget() > live ? al.budget() - live : 0;
+  return free_b / 2 / (size_t)(srv->preparing + 1) >= srv->build_bytes;
+}
+
+// A preparation thread: build waiting requests while slots are free.
+void prep_main(nd_server *srv, int t) {
   (void)hipSetDevice(srv->ctx->device);
+  hipStream_t ps = srv->prep_streams[t];
   for (;;) {
     Request *r = nullptr;
     uint64_t retired0 = 0;
     int64_t epochs0 = 0;
+    bool alone = false;
     {
       std::unique_lock<std::mutex> lk(srv->mu);
-      srv->cv_prep.wait(lk, [&] {
-        return srv->stop ||
-               (!srv->queue.empty() && srv->admitted < srv->max_slots);
-      });
+      srv->cv_prep.wait(lk, [&] { return srv->stop || may_start_build(srv); });
       if (srv->stop) return;
       r = srv->queue.front();
       srv->queue.pop_front();
       if (r->cancelled) {
         lk.unlock();
-        release_graph(r, srv->prep_stream);
+        release_graph(r, ps);
         lk.lock();
         finish_locked(srv, r, ND_ERR_CANCELLED);
         continue;
       }
       r->admitted = true;
       srv->admitted++;
+      srv->preparing++;
+      alone = r->retry_alone;
+      srv->alone = alone;
       retired0 = srv->retired;
       epochs0 = srv->epochs.load();
     }
@@ -230,58 +275,73 @@ void prep_main(nd_server *srv) {
     nd_status code = ND_OK;
     try {
       Phase phase("nd.server.prepare");
-      StreamScope scope(srv->prep_stream);
-      prepare(r->g, r->kind, srv->prep_stream);
+      StreamScope scope(ps);
+      prepare(r->g, r->kind, ps);
     } catch (const Err &e) {
       code = e.code;
       r->error = nd_last_error();
       // give back what the failed build holds
-      StreamScope scope(srv->prep_stream);
-      (void)hipStreamSynchronize(srv->prep_stream);
+      StreamScope scope(ps);
+      (void)hipStreamSynchronize(ps);
       r->g->ks[r->kind] = KindState{};
     }
     std::unique_lock<std::mutex> lk(srv->mu);
+    srv->preparing--;
+    if (alone) srv->alone = false;
+    srv->cv_prep.notify_all();
     r->info.prep_ms += ms_between(t0, Clock::now());
     r->info.epochs_during_prep += srv->epochs.load() - epochs0;
     if (code == ND_OK) {
+      srv->build_bytes = std::max(srv->build_bytes, r->g->bytes());
+      r->cls = r->g->ks[r->kind].P < kSmallWork ? 0 : 1;
       srv->ready.push_back(r);
       srv->cv_work.notify_all();
       continue;
     }
     if (code == ND_ERR_OOM) {
-      // others hold memory: wait for one of them to retire, then retry
-      srv->cv_prep.wait(lk, [&] {
-        return srv->stop || srv->retired != retired0 ||
-               (srv->running == 0 && srv->ready.empty());
-      });
-      if (srv->retired != retired0 && !srv->stop) {
+      bool retry = false;
+      if (!alone) {
+        retry = true;  // other builds held memory too: retry on its own
+      } else if (srv->running > 0 || !srv->ready.empty()) {
+        // others hold memory: wait for one of them to retire (or for all
+        // of them to be gone), then retry
+        srv->cv_prep.wait(lk, [&] {
+          return srv->stop || srv->retired != retired0 ||
+                 (srv->running == 0 && srv->ready.empty());
+        });
+        retry = !srv->stop;
+      }
+      if (retry) {
         r->admitted = false;
         srv->admitted--;
+        r->retry_alone = true;
         r->error.clear();
         srv->queue.push_front(r);
+        srv->cv_prep.notify_all();
         continue;
       }
     }
     lk.unlock();
-    release_graph(r, srv->prep_stream);
+    release_graph(r, ps);
     lk.lock();
     finish_locked(srv, r, code);
   }
 }
 
-// Add prepared requests to their batches (worker thread).  Returns false
-// when a request had to wait for memory.
+// Add a prepared request to its batch (worker thread of its class).
+// Returns false when it has to wait for memory.
 bool add_ready(nd_server *srv, Request *r) {
+  hipStream_t ws = srv->streams[r->cls];
   try {
-    StreamScope scope(srv->stream);
+    StreamScope scope(ws);
     const KindState &ks = r->g->ks[r->kind];
     const int mi = r->opts.mode == ND_AND ? 1 : 0;
     const int wi = ks.tau16 ? 1 : 0;
     const int fi = r->opts.use_frontier ? 1 : 0;
-    auto &slot = srv->batches[r->kind][mi][wi][fi];
+    auto &slot = srv->batches[r->cls][r->kind][mi][wi][fi];
     if (!slot)
       slot = std::make_unique<Batch>(srv->ctx, r->kind, r->opts.mode, ks.tau16,
-                                     fi != 0, srv->stream);
+                                     fi != 0, ws);
     int running_before = 0;
     for (Member *m : slot->live()) running_before += m->sweeps > 0 ? 1 : 0;
     r->info.epoch_joined = slot->epoch();
@@ -290,6 +350,7 @@ bool add_ready(nd_server *srv, Request *r) {
     r->batch = slot.get();
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->running++;
+    srv->running_cls[r->cls]++;
     return true;
   } catch (const Err &e) {
     {
@@ -297,31 +358,44 @@ bool add_ready(nd_server *srv, Request *r) {
       if (e.code == ND_ERR_OOM && srv->running > 0) return false;
     }
     r->error = nd_last_error();
-    release_graph(r, srv->stream);
+    release_graph(r, ws);
     std::lock_guard<std::mutex> lk(srv->mu);
     finish_locked(srv, r, e.code);
     return true;
   }
 }
 
-void worker_main(nd_server *srv) {
+// The worker of size class c.
+void worker_main(nd_server *srv, int c) {
   (void)hipSetDevice(srv->ctx->device);
   int chunk = 1;
   for (;;) {
     std::deque<Request *> newcomers;
     {
       std::unique_lock<std::mutex> lk(srv->mu);
+      auto mine = [&] {
+        for (Request *r : srv->ready)
+          if (r->cls == c) return true;
+        return false;
+      };
       srv->cv_work.wait(lk, [&] {
-        return srv->stop || srv->running > 0 || !srv->ready.empty();
+        return srv->stop || srv->running_cls[c] > 0 || mine();
       });
       if (srv->stop) return;
-      newcomers.swap(srv->ready);
+      for (auto it = srv->ready.begin(); it != srv->ready.end();) {
+        if ((*it)->cls == c) {
+          newcomers.push_back(*it);
+          it = srv->ready.erase(it);
+        } else {
+          ++it;
+        }
+      }
     }
     while (!newcomers.empty()) {
       Request *r = newcomers.front();
       if (r->cancelled) {
         newcomers.pop_front();
-        release_graph(r, srv->stream);
+        release_graph(r, srv->streams[c]);
         std::lock_guard<std::mutex> lk(srv->mu);
         finish_locked(srv, r, ND_ERR_CANCELLED);
         continue;
@@ -335,7 +409,7 @@ void worker_main(nd_server *srv) {
       srv->ready.insert(srv->ready.begin(), newcomers.begin(), newcomers.end());
     }
     bool any = false;
-    for (auto &bk : srv->batches)
+    for (auto &bk : srv->batches[c])
       for (auto &bm : bk)
         for (auto &bw : bm)
           for (auto &b : bw) {
@@ -393,17 +467,34 @@ nd_status nd_server_create(nd_ctx *ctx, int32_t max_slots, int32_t max_queue,
     srv->ctx = ctx;
     srv->max_slots = max_slots;
     srv->max_queue = max_queue;
-    ND_HIP(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
-    hipError_t e = hipStreamCreateWithFlags(&srv->prep_stream,
-                                            hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      (void)hipStreamDestroy(srv->stream);
-      ND_HIP(e);
+    auto drop_streams = [&] {
+      for (hipStream_t q : srv->prep_streams) (void)hipStreamDestroy(q);
+      for (hipStream_t q : srv->streams)
+        if (q) (void)hipStreamDestroy(q);
+    };
+    for (hipStream_t &ws : srv->streams) {
+      const hipError_t e = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        ws = nullptr;
+        drop_streams();
+        ND_HIP(e);
+      }
+    }
+    const int npt = server_prep_threads();
+    for (int t = 0; t < npt; t++) {
+      hipStream_t ps = nullptr;
+      const hipError_t e = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        drop_streams();
+        ND_HIP(e);
+      }
+      srv->prep_streams.push_back(ps);
     }
     ctx->retain();
     nd_server *raw = srv.release();
-    raw->worker = std::thread(worker_main, raw);
-    raw->prep = std::thread(prep_main, raw);
+    for (int c = 0; c < 2; c++) raw->workers[c] = std::thread(worker_main, raw, c);
+    for (int t = 0; t < npt; t++)
+      raw->preps.emplace_back(prep_main, raw, t);
     *out = raw;
   });
 }
@@ -525,25 +616,28 @@ void nd_server_destroy(nd_server *srv) {
     srv->cv_work.notify_all();
     srv->cv_prep.notify_all();
   }
-  if (srv->prep.joinable()) srv->prep.join();
-  if (srv->worker.joinable()) srv->worker.join();
+  for (auto &th : srv->preps)
+    if (th.joinable()) th.join();
+  for (auto &w : srv->workers)
+    if (w.joinable()) w.join();
   (void)hipSetDevice(srv->ctx->device);
-  for (auto &bk : srv->batches)
-    for (auto &bm : bk)
-      for (auto &bw : bm)
-        for (auto &b : bw) b.reset();
+  for (auto &bc : srv->batches)
+    for (auto &bk : bc)
+      for (auto &bm : bk)
+        for (auto &bw : bm)
+          for (auto &b : bw) b.reset();
   (void)hipDeviceSynchronize();
   for (auto &kv : srv->reqs) {
-    release_graph(kv.second.get(), srv->stream);
+    release_graph(kv.second.get(), srv->streams[0]);
     drop_result_locked(srv, kv.second.get());
   }
   srv->reqs.clear();
   for (auto &kv : srv->pinned_free) (void)hipHostFree(kv.second);
   srv->pinned_free.clear();
-  srv->ctx->alloc.forget_stream(srv->stream);
-  srv->ctx->alloc.forget_stream(srv->prep_stream);
-  (void)hipStreamDestroy(srv->stream);
-  (void)hipStreamDestroy(srv->prep_stream);
+  for (hipStream_t ws : srv->streams) srv->ctx->alloc.forget_stream(ws);
+  for (hipStream_t ps : srv->prep_streams) srv->ctx->alloc.forget_stream(ps);
+  for (hipStream_t ws : srv->streams) (void)hipStreamDestroy(ws);
+  for (hipStream_t ps : srv->prep_streams) (void)hipStreamDestroy(ps);
   nd_ctx *ctx = srv->ctx;
   delete srv;
   ctx->release();

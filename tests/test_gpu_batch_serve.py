@@ -65,6 +65,45 @@ def test_batch_equals_solo_and_oracle(nd, ctx, kind, mode, frontier):
         assert np.array_equal(kb.cpu().numpy(), want), raw.name
 
 
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_batch_prepares_while_sweeping(nd, ctx, kind):
+    """Graphs handed to the batch unprepared are prepared on the library's
+    threads while the prepared ones are swept, each joining when ready; the
+    results equal the oracle's, whichever graphs were prepared beforehand."""
+    raws = mixed_graphs() + [chung_lu(int(n), 2.2, 12.0, seed=600 + i)
+                             for i, n in enumerate((900, 7000, 2500, 15000))]
+    r, s = KINDS[kind]
+    gs = [make(nd, ctx, raw) for raw in raws]
+    if r <= 2:  # |R| is read off the graph, nothing is built
+        for g, raw in zip(gs, raws):
+            og = oracle.Graph.from_raw(raw)
+            assert g.rclique_count(kind) == og.num_rcliques(r)
+    for g in gs[::3]:
+        g.prepare(kind)
+    kappas, results = nd.batch_decompose(ctx, gs + gs[:2], kind, "snd",
+                                         use_frontier=True)
+    for i, (k, rb) in enumerate(zip(kappas, results)):
+        raw = raws[i % len(raws)]
+        assert rb["converged"] == 1
+        want = oracle.Graph.from_raw(raw).peel(r, s)
+        assert np.array_equal(k.cpu().numpy(), want), (raw.name, i)
+        assert rb["sweeps"] == len(oracle.Graph.from_raw(raw).snd(r, s)) - 1 \
+            or want.size == 0, raw.name
+
+
+def test_prepare_many(nd, ctx):
+    raws = mixed_graphs()
+    gs = [make(nd, ctx, raw) for raw in raws]
+    gs[1].prepare("nucleus34")
+    nd.prepare_many(ctx, gs + [gs[0]], "nucleus34")
+    for g, raw in zip(gs, raws):
+        og = oracle.Graph.from_raw(raw)
+        nr, P, _ = g.sizes("nucleus34")
+        assert nr == og.num_rcliques(3)
+        assert np.array_equal(g.decompose("nucleus34")[0].cpu().numpy(),
+                              og.peel(3, 4))
+
+
 def test_batch_replays_with_eager_work_between(nd, ctx):
     """Repeated batches (the epoch loop replays a captured HIP graph) with
     eager decompositions and synchronisations in between: every replay
@@ -166,7 +205,7 @@ def test_server_requests_overlap_on_the_device(nd, ctx):
     join its batch (their epochs overlap, the batch sweeps them together),
     and the sweeps go on while a large newcomer is being prepared."""
     from synth import RawGraph
-    n = 20000  # a path: k-core SND takes about n/2 sweeps
+    n = 100000  # a path: k-core SND takes about n/2 sweeps
     path = RawGraph(n, np.arange(n - 1, dtype=np.int32),
                     np.arange(1, n, dtype=np.int32), "path")
     others = [chung_lu(3000 + 1000 * i, 2.2, 10.0, seed=500 + i) for i in range(4)]
@@ -200,6 +239,31 @@ def test_server_requests_overlap_on_the_device(nd, ctx):
     assert np.array_equal(kb.numpy(), oracle.Graph.from_raw(big).peel(2, 3))
     # the long request kept sweeping while the newcomer was being prepared
     assert ib["epochs_during_prep"] > 0 and ib["prep_ms"] > 0
+    srv.close()
+
+
+def test_server_beside_caller_work_on_the_legacy_stream(nd, ctx):
+    """While a long request keeps the worker replaying its epoch graphs, the
+    caller builds graphs and runs torch work on the legacy default stream;
+    every request's result equals the oracle's."""
+    from synth import RawGraph
+    n = 12000
+    path = RawGraph(n, np.arange(n - 1, dtype=np.int32),
+                    np.arange(1, n, dtype=np.int32), "path")
+    srv = nd.Server(ctx, max_slots=32)
+    t_long = srv.submit(make(nd, ctx, path), "core", "snd")
+    raws = [chung_lu(1500 + 100 * i, 2.2, 10.0, seed=700 + i) for i in range(24)]
+    ts = []
+    for raw in raws:
+        x = torch.ones(1 << 16, device="cuda")
+        torch.cuda.default_stream().synchronize()
+        ts.append(srv.submit(make(nd, ctx, raw), "truss", "snd"))
+        assert float(x.sum()) == float(1 << 16)
+    for t, raw in zip(ts, raws):
+        kappa, res, info = srv.wait(t)
+        assert np.array_equal(kappa.numpy(), oracle.Graph.from_raw(raw).peel(2, 3))
+    k_long, r_long, _ = srv.wait(t_long)
+    assert r_long["sweeps"] == (n - 1) // 2 + 1 and int(k_long.max()) == 1
     srv.close()
 
 
