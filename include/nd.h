@@ -54,6 +54,9 @@
  *                         (default 16; 0: from the second sweep on).
  *   ND_BATCH_NO_GRAPH=1   batched epochs are launched one by one instead of
  *                         through HIP graphs of eight epochs.
+ *   ND_PREP_THREADS=t     host threads preparing graphs in nd_prepare_many and
+ *                         nd_batch_decompose (default 2) and in a server
+ *                         (default 4).
  *   ND_TRUSS_NO_LDS=1     the k-truss builder intersects the 64-lane bin
  *                         without the per-source LDS copy (the path taken
  *                         when an out-list exceeds 5120 entries).
@@ -209,7 +212,7 @@ nd_status nd_graph_csr(nd_graph *g, int64_t *row_off, int32_t *col,
 nd_status nd_prepare(nd_graph *g, nd_kind kind, void *stream);
 
 /* Prepare `count` graphs of one context for `kind`, like nd_prepare on each,
- * on up to four host threads with a stream each (ordered after `stream`,
+ * on host threads (two by default) with a stream each (ordered after `stream`,
  * which waits for all of them on return), largest graphs first, so that
  * their short, launch-bound build phases overlap.  Graphs already prepared
  * are skipped.  The first failure is returned; graphs prepared before it
