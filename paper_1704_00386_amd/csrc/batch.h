@@ -128,7 +128,7 @@ class Batch {
   nd_mode mode_;
   bool tau16_;
   bool frontier_;
-  int notify_div_ = 16;
+  int notify_div_ = 4;
   hipStream_t s_ = nullptr;
   BatchConfig cfg_;
   std::vector<std::unique_ptr<Member>> members_;

@@ -311,7 +311,7 @@ Batch::Batch(nd_ctx *ctx, nd_kind kind, nd_mode mode, bool tau16,
              bool frontier, hipStream_t caller)
     : ctx_(ctx), kind_(kind), mode_(mode), tau16_(tau16), frontier_(frontier) {
   cfg_ = default_config(ctx);
-  if (const char *v = getenv("ND_FRONTIER_SWITCH")) notify_div_ = atoi(v);
+  notify_div_ = frontier_switch(mode == ND_AND);
   if (const char *v = getenv("ND_BATCH_NO_GRAPH")) use_graph = v[0] != '1';
   ND_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
   hipEvent_t ev;

@@ -19,6 +19,12 @@
 
 namespace nd {
 
+int frontier_switch(bool and_mode) {
+  if (const char *v = getenv("ND_FRONTIER_SWITCH")) return atoi(v);
+  return and_mode ? 8 : 4;
+}
+
+
 namespace {
 
 constexpr int kStatsRing = 1024;  // device counters kept per decomposition
@@ -164,18 +170,16 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
   const int64_t ng = (nr + (1 << dev::kGroupShift) - 1) >> dev::kGroupShift;
   // frontier flags (Section 4.3): act[t & 1] selects the r-cliques of sweep
   // t; every r-clique takes part in the first sweep.  Notifications start
-  // once a sweep changes at most 1/16 of the swept r-cliques
-  // (ND_FRONTIER_SWITCH overrides the divisor; 0 = from the start); with the
-  // indicator they run from the first sweep, so that every sweep's active
-  // count is known.
+  // once a sweep changes at most 1/frontier_switch() of the swept r-cliques;
+  // with the indicator they run from the first sweep, so that every sweep's
+  // active count is known.
   unsigned long long notify_below = 0;
   if (flags) {
     for (int i = 0; i < 2; i++) {
       fill_u8(b.act[i], 0, nr, s);  // no stamps yet
       fill_u8(b.act_sum[i], 0, ng, s);
     }
-    int div = 16;
-    if (const char *v = getenv("ND_FRONTIER_SWITCH")) div = atoi(v);
+    const int div = frontier_switch(and_mode);
     notify_below = (indicator || div <= 0)
                        ? ~0ull
                        : (unsigned long long)(ks.bin_lo[kBinZero] / div);
