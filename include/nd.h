@@ -64,6 +64,8 @@
  *   ND_TRUSS_NO_TRIBUF=1  the k-truss builder intersects twice instead of
  *                         recording the triangles (the path taken when the
  *                         buffer does not fit the memory budget).
+ *   ND_LEVELS_BIG=c       nd_levels runs a level on the whole GPU when it has
+ *                         at least c candidate r-cliques (default 1024).
  */
 #ifndef ND_H
 #define ND_H
@@ -319,8 +321,9 @@ nd_status nd_ego_estimate(nd_graph *g, nd_kind kind, const int32_t *queries,
  * sweeps (the level-i r-cliques are exact after i sweeps; the DL row of
  * Table 3).  L_0 = r-cliques of minimum S-degree; removing an r-clique
  * removes every s-clique containing it; L_i = the minimum-degree r-cliques
- * of what remains.  One device step per level (three kernels and a 16-byte
- * read-back). */
+ * of what remains.  One workgroup runs the levels in turn; a level with
+ * many candidate r-cliques runs on the whole GPU instead (four kernels and
+ * a 64-byte read-back). */
 nd_status nd_levels(nd_graph *g, nd_kind kind, int32_t *level,
                     int32_t *num_levels, int on_device, void *stream);
 

@@ -25,9 +25,16 @@
 // everything not lowered in level i has degree above m.
 //
 // The loop over levels runs in one workgroup (barriers between the phases of
-// a level cost far less than kernel launches); every loop has a hard bound
-// and an inconsistency ends it with an error flag rather than a hang.
+// a level cost far less than kernel launches): most levels are small, and
+// their cost is the chain of dependent memory accesses of their phases.  A
+// level with many candidates (kBigLevel, ND_LEVELS_BIG) would keep one CU
+// busy for long while the others idle, so the workgroup stops before it,
+// leaving its state in a control block; that level runs as four grid-wide
+// kernels (collect, peel, re-bucket, finish), and the workgroup resumes.
+// Every loop has a hard bound and an inconsistency ends it with an error
+// flag rather than a hang.
 #include <limits.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <vector>
@@ -41,6 +48,10 @@ namespace {
 
 constexpr int kLvThreads = 1024;
 constexpr int kLvWaves = kLvThreads / kWave;
+// A level with this many candidates runs on the whole grid (measured on the
+// Chung-Lu k-core and k-truss workloads: 512 to 16384 all within 10% of each
+// other, every one 1.3-3x faster than the workgroup alone).
+constexpr int64_t kBigLevel = kLvThreads;
 
 struct LevelArgs {
   const int64_t *inc_off;  // internal numbering
@@ -62,6 +73,21 @@ struct LevelArgs {
   int32_t *F;             // frontier (this level), nr slots
   int32_t *MV;            // r-cliques lowered in this level, nr slots
   int32_t *out;           // [0] = number of levels, [1] = error code
+  struct LevelCtl *ctl;   // state between launches
+  int64_t big;            // candidates from which a level runs grid-wide
+};
+
+// The level loop's state between launches.
+struct LevelCtl {
+  int64_t alive;       // r-cliques not yet removed
+  int64_t ilo, ilen;   // candidates of the pending big level: I part
+  int64_t blo, blen;   //   and B part
+  int32_t m;           // current minimum degree
+  int32_t level;       // next level number
+  int32_t err;
+  int32_t big;         // 1: the level `level` (minimum m) is pending
+  int32_t nf, nmv, dmin;
+  int32_t pad;
 };
 
 template <int K>
@@ -70,10 +96,10 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(LevelArgs a) {
   __shared__ int64_t s_alive, s_ilo, s_ilen, s_blo, s_blen;
   const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
   if (t == 0) {
-    s_m = a.m0;
-    s_alive = a.nr;
-    s_err = 0;
-    s_level = 0;
+    s_m = a.ctl->m;
+    s_alive = a.ctl->alive;
+    s_err = a.ctl->err;
+    s_level = a.ctl->level;
   }
   __syncthreads();
   for (int64_t guard = 0; guard <= a.nr; guard++) {
@@ -91,6 +117,20 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(LevelArgs a) {
     }
     __syncthreads();
     const int64_t ilo = s_ilo, ilen = s_ilen, blo = s_blo, blen = s_blen;
+    if (ilen + blen >= a.big) {  // uniform: leave this level to the grid
+      if (t == 0) {
+        LevelCtl &c = *a.ctl;
+        c.ilo = ilo;
+        c.ilen = ilen;
+        c.blo = blo;
+        c.blen = blen;
+        c.nf = 0;
+        c.nmv = 0;
+        c.dmin = INT_MAX;
+        c.big = 1;
+      }
+      break;
+    }
     for (int64_t x = t; x < ilen + blen; x += kLvThreads) {
       const int32_t R = x < ilen ? a.I[ilo + x] : a.B[blo + (x - ilen)];
       if (a.deg[R] == m && atomicCAS(&a.lvl[R], -1, level) == -1)
@@ -179,8 +219,124 @@ __global__ __launch_bounds__(kLvThreads) void k_levels(LevelArgs a) {
     __syncthreads();
   }
   if (t == 0) {
+    LevelCtl &c = *a.ctl;
+    c.m = s_m;
+    c.alive = s_alive;
+    c.level = s_level;
+    c.err = s_err;
     a.out[0] = s_level;
-    a.out[1] = s_err ? s_err : (s_alive > 0 ? 3 : 0);
+    a.out[1] = s_err ? s_err : (s_alive > 0 && !c.big ? 3 : 0);
+  }
+}
+
+// ---- a big level on the whole grid (the same steps, counters in *ctl)
+
+__global__ void k_lv_collect(LevelArgs a) {
+  const LevelCtl &c = *a.ctl;
+  if (!c.big) return;
+  const int32_t m = c.m, level = c.level;
+  const int64_t n = c.ilen + c.blen;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t R = x < c.ilen ? a.I[c.ilo + x] : a.B[c.blo + (x - c.ilen)];
+    if (a.deg[R] == m && atomicCAS(&a.lvl[R], -1, level) == -1)
+      a.F[atomicAdd(&a.ctl->nf, 1)] = R;
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_lv_peel(LevelArgs a) {
+  LevelCtl &c = *a.ctl;
+  if (!c.big) return;
+  const int32_t m = c.m, level = c.level, nf = c.nf;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (nf == 0) c.err = 1;  // the minimum bucket must hold a present r-clique
+    a.Iused[m] = 1;
+    a.Bused[m] += c.blen;
+  }
+  const int lane = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  int32_t dmin = INT_MAX;
+  for (int64_t f = wave; f < nf; f += nwaves) {
+    const int32_t R = a.F[f];
+    const int64_t b = a.inc_off[R], d = a.inc_off[R + 1] - b;
+    for (int64_t j = lane; j < d; j += kWave) {
+      const int32_t *o = a.inc_ids + (int64_t)K * (b + j);
+      bool skip = false;
+#pragma unroll
+      for (int x = 0; x < K; x++) {
+        const int32_t l = a.lvl[o[x]];
+        skip |= (l >= 0 && l < level) || (l == level && o[x] < R);
+      }
+      if (skip) continue;
+#pragma unroll
+      for (int x = 0; x < K; x++) {
+        const int32_t q = o[x];
+        if (a.lvl[q] >= 0) continue;
+        const int32_t old = atomicSub(&a.deg[q], 1);
+        if (old < 1 || old > a.maxd) {
+          c.err = 4;
+          continue;
+        }
+        atomicSub(&a.hist[old], 1);
+        atomicAdd(&a.hist[old - 1], 1);
+        dmin = min(dmin, old - 1);
+        if (atomicExch(&a.moved_at[q], level) != level)
+          a.MV[atomicAdd(&c.nmv, 1)] = q;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dmin = min(dmin, __shfl_xor(dmin, off, kWave));
+  if (lane == 0 && dmin != INT_MAX) atomicMin(&c.dmin, dmin);
+}
+
+__global__ void k_lv_rebucket(LevelArgs a) {
+  LevelCtl &c = *a.ctl;
+  if (!c.big) return;
+  const int32_t nmv = c.nmv;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nmv;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t q = a.MV[x];
+    const int32_t dq = a.deg[q];
+    if (dq < 0 || dq > a.maxd) {
+      c.err = 5;
+      continue;
+    }
+    const int64_t p = (int64_t)atomicAdd((unsigned long long *)&a.Bcnt[dq], 1ull);
+    if (a.Boff[dq] + p < a.Boff[dq + 1])
+      a.B[a.Boff[dq] + p] = q;
+    else
+      c.err = 6;
+  }
+}
+
+// One wave: close the level and find the next minimum, the first
+// non-empty bucket from min(lowest degree produced, m + 1).
+__global__ void k_lv_finish(LevelArgs a) {
+  LevelCtl &c = *a.ctl;
+  if (!c.big) return;
+  const int lane = lane_id();
+  const int32_t m = c.m, nf = c.nf;
+  const int64_t alive = c.alive - nf;
+  if (lane == 0) a.hist[m] -= nf;
+  __syncthreads();
+  int32_t found = -1;
+  if (alive > 0) {
+    const int32_t lo = min(c.dmin, m + 1);
+    for (int32_t base = lo; base <= a.maxd && found < 0; base += kWave) {
+      const int32_t dd = base + lane;
+      const uint64_t bal = ballot(dd <= a.maxd && a.hist[dd] > 0);
+      if (bal) found = base + __ffsll((long long)bal) - 1;
+    }
+  }
+  if (lane == 0) {
+    if (alive > 0 && found < 0) c.err = 2;
+    if (found >= 0) c.m = found;
+    c.alive = alive;
+    c.level += 1;
+    c.big = 0;
   }
 }
 
@@ -275,7 +431,15 @@ nd_status levels(nd_graph *g, nd_kind kind, int32_t *level_out,
   int32_t m0 = 0;
   while (m0 <= maxd && hoff[m0 + 1] == hoff[m0]) m0++;
   ND_REQUIRE(m0 <= maxd, ND_ERR_DEVICE, "degree buckets are empty");
+  DArr<LevelCtl> ctl(al, 1);
+  LevelCtl c0{};
+  c0.alive = nr;
+  c0.m = m0;
+  ND_HIP(hipMemcpyAsync(ctl.p, &c0, sizeof c0, hipMemcpyHostToDevice, s));
   LevelArgs a{};
+  a.ctl = ctl.p;
+  a.big = kBigLevel;
+  if (const char *v = getenv("ND_LEVELS_BIG")) a.big = std::max<int64_t>(1, atoll(v));
   a.inc_off = ks.inc_off.p;
   a.inc_ids = ks.inc_ids.p;
   a.nr = nr;
@@ -295,20 +459,43 @@ nd_status levels(nd_graph *g, nd_kind kind, int32_t *level_out,
   a.F = F.p;
   a.MV = MV.p;
   a.out = out.p;
-  switch (ks.k) {
-    case 1: k_levels<1><<<1, kLvThreads, 0, s>>>(a); break;
-    case 2: k_levels<2><<<1, kLvThreads, 0, s>>>(a); break;
-    case 3: k_levels<3><<<1, kLvThreads, 0, s>>>(a); break;
-    case 5: k_levels<5><<<1, kLvThreads, 0, s>>>(a); break;
-    default: ND_REQUIRE(false, ND_ERR_UNSUPPORTED, "no level kernel for k=%d", ks.k);
+  ND_REQUIRE(ks.k == 1 || ks.k == 2 || ks.k == 3 || ks.k == 5, ND_ERR_UNSUPPORTED,
+             "no level kernel for k=%d", ks.k);
+  const unsigned grid = (unsigned)g->ctx->num_cu * 8;
+  PinnedChunk pc;
+  const LevelCtl *hc = nullptr;
+  // the workgroup runs levels until it finishes or meets a big one, which
+  // the grid then runs; each round removes at least one level
+  for (int64_t round = 0; round <= nr; round++) {
+    switch (ks.k) {
+      case 1: k_levels<1><<<1, kLvThreads, 0, s>>>(a); break;
+      case 2: k_levels<2><<<1, kLvThreads, 0, s>>>(a); break;
+      case 3: k_levels<3><<<1, kLvThreads, 0, s>>>(a); break;
+      default: k_levels<5><<<1, kLvThreads, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+    hc = pc.read(ctl.p, 1, s);
+    ND_REQUIRE(hc->err == 0, ND_ERR_DEVICE,
+               "degree levels: inconsistent buckets (code %d)", hc->err);
+    if (!hc->big) break;
+    k_lv_collect<<<grid, 256, 0, s>>>(a);
+    ND_LAUNCHED();
+    switch (ks.k) {
+      case 1: k_lv_peel<1><<<grid, 256, 0, s>>>(a); break;
+      case 2: k_lv_peel<2><<<grid, 256, 0, s>>>(a); break;
+      case 3: k_lv_peel<3><<<grid, 256, 0, s>>>(a); break;
+      default: k_lv_peel<5><<<grid, 256, 0, s>>>(a); break;
+    }
+    ND_LAUNCHED();
+    k_lv_rebucket<<<grid, 256, 0, s>>>(a);
+    ND_LAUNCHED();
+    k_lv_finish<<<1, kWave, 0, s>>>(a);
+    ND_LAUNCHED();
   }
-  ND_LAUNCHED();
-  int32_t res[2] = {0, 0};
-  ND_HIP(hipMemcpyAsync(res, out.p, sizeof res, hipMemcpyDeviceToHost, s));
-  ND_HIP(hipStreamSynchronize(s));
-  ND_REQUIRE(res[1] == 0, ND_ERR_DEVICE,
-             "degree levels: inconsistent buckets (code %d)", res[1]);
-  *num_levels = res[0];
+  ND_REQUIRE(hc && !hc->big && hc->alive == 0, ND_ERR_DEVICE,
+             "degree levels: %lld r-cliques left without a level",
+             hc ? (long long)hc->alive : (long long)nr);
+  *num_levels = hc->level;
   if (on_device) {
     to_original(ks, lvl.p, false, level_out, s);
   } else {

@@ -41,7 +41,13 @@ def graphs():
 
 
 @pytest.mark.parametrize("kind", list(KINDS))
-def test_levels_equal_oracle(nd, ctx, kind):
+@pytest.mark.parametrize("big", [None, "1", "40"])
+def test_levels_equal_oracle(nd, ctx, kind, big, monkeypatch):
+    """big: levels with at least this many candidates run as grid-wide
+    kernels (1: every level; 40: a mix; None: the default, mostly one
+    workgroup at these sizes)."""
+    if big is not None:
+        monkeypatch.setenv("ND_LEVELS_BIG", big)
     r, s = KINDS[kind]
     for raw in graphs():
         og = oracle.Graph.from_raw(raw)
