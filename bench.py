@@ -416,7 +416,8 @@ def ceilings(nd, g, kind, tau_bytes):
             "gather_GBs": gb / (min(gathers) * 1e-3) / 1e9,
             "gather_bytes": gb, "gather_ms": min(gathers),
             "what": "8 GiB streamed with 16-byte loads (read) and loads+stores "
-                    "(copy); the incidence ids (r-clique-id order) with one "
+                    "(copy); the incidence ids (r-clique-id order, each "
+                    "workgroup streaming contiguous runs of 32768 lists) with one "
                     f"{tau_bytes}-byte tau gather per id, min per s-clique "
                     "(gather); best of 3 each"}
 

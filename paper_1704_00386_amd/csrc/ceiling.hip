@@ -9,7 +9,12 @@
 //   ndc_gather    for every s-clique j: min over its k listed ids of tau[id]
 //                 (tau 16- or 32-bit), summed -- the id stream and the random
 //                 tau gathers of one sweep without the h-index: the ceiling of
-//                 the gather pattern itself.
+//                 the gather pattern itself.  Each workgroup takes contiguous
+//                 runs of the id stream (the mapping of the update kernel's
+//                 full sweeps, which lets a CU's cache serve the values that
+//                 neighbouring lists share); with the whole grid striding
+//                 over the stream instead, the same gathers take about 1.7x
+//                 longer on the block-model (3,4) workload.
 // Each enqueues one kernel on `stream` between two events of its own and
 // returns the kernel's device time in milliseconds (negative on error).
 // The sums go to *sink so that no load is optimised away.
@@ -47,18 +52,23 @@ __global__ __launch_bounds__(kThreads) void k_copy(const uint4 *__restrict__ a,
     b[i] = a[i];
 }
 
+constexpr int64_t kGatherRun = 32768;  // s-cliques per workgroup run
+
 template <int K, typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(
     const int32_t *__restrict__ ids, int64_t nsets, const T *__restrict__ tau,
     unsigned long long *sink) {
   unsigned long long s = 0;
-  for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < nsets;
-       j += (int64_t)gridDim.x * kThreads) {
-    const int32_t *q = ids + K * j;
-    uint32_t m = 0xffffffffu;
+  for (int64_t r = (int64_t)blockIdx.x * kGatherRun; r < nsets;
+       r += (int64_t)gridDim.x * kGatherRun) {
+    const int64_t end = r + kGatherRun < nsets ? r + kGatherRun : nsets;
+    for (int64_t j = r + threadIdx.x; j < end; j += kThreads) {
+      const int32_t *q = ids + K * j;
+      uint32_t m = 0xffffffffu;
 #pragma unroll
-    for (int x = 0; x < K; x++) m = min(m, (uint32_t)tau[q[x]]);
-    s += m;
+      for (int x = 0; x < K; x++) m = min(m, (uint32_t)tau[q[x]]);
+      s += m;
+    }
   }
   sink_add(sink, s);
 }
@@ -128,7 +138,9 @@ float ndc_gather(const int32_t *ids, int64_t nsets, int k, const void *tau,
                  int tau32, unsigned long long *sink, void *stream) {
   if (!ids || !tau || !sink || nsets < 1 || k < 1 || k > 3) return -1;
   hipStream_t s = (hipStream_t)stream;
-  const unsigned grid = grid_of(nsets, num_cus());
+  const int64_t runs = (nsets + kGatherRun - 1) / kGatherRun;
+  const int64_t cap = (int64_t)num_cus() * 8;
+  const unsigned grid = (unsigned)(runs < cap ? runs : cap);
   return timed(s, [&] {
     switch (k * 2 + (tau32 ? 1 : 0)) {
       case 2: k_gather<1, uint16_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const uint16_t *)tau, sink); break;
