@@ -51,8 +51,7 @@
  * Environment (tuning only; results never depend on them).
  *   ND_FRONTIER_SWITCH=d  with use_frontier, notifications start once a sweep
  *                         changes at most 1/d of the swept r-cliques
- *                         (default 4 for SND, 8 for AND; 0: from the
- *                         second sweep on).
+ *                         (default 8; 0: from the second sweep on).
  *   ND_BATCH_NO_GRAPH=1   batched epochs are launched one by one instead of
  *                         through HIP graphs of eight epochs.
  *   ND_PREP_THREADS=t     host threads preparing graphs in nd_prepare_many and

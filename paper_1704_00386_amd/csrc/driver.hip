@@ -21,7 +21,8 @@ namespace nd {
 
 int frontier_switch(bool and_mode) {
   if (const char *v = getenv("ND_FRONTIER_SWITCH")) return atoi(v);
-  return and_mode ? 8 : 4;
+  (void)and_mode;
+  return 8;
 }
 
 

@@ -364,9 +364,9 @@ void launch_sweep(const KindState &ks, const SweepArgs &a, bool and_mode,
                   hipStream_t s);
 
 // Frontier switch: notifications start once a sweep changes at most
-// 1/d of the swept r-cliques; d = 4 for SND and 8 for AND (measured on the
-// three benchmark workloads), ND_FRONTIER_SWITCH overrides both (0: from the
-// first sweep on).
+// 1/d of the swept r-cliques; d = 8 for SND and AND (measured on the three
+// benchmark workloads), ND_FRONTIER_SWITCH overrides it (0: from the first
+// sweep on).
 int frontier_switch(bool and_mode);
 
 }  // namespace nd

@@ -91,6 +91,8 @@ template <typename T>
 struct FlatLds {
   T rho[kFlatRun];
   int32_t off[kFlatRun / 4 + 1];
+  // sweep_flat_fr: per entry, the listed members holding the minimum
+  uint8_t mask[kFlatRun];
 };
 
 // A full sweep (no flags read, none written) of a bin of G lanes per
@@ -158,10 +160,107 @@ __device__ __forceinline__ void sweep_flat(const SweepArgs &a, int64_t lo,
   }
 }
 
+// The full SND sweep that notifies (Section 4.3: the first sweep after the
+// frontier switches on, or every sweep while active counts are taken), in
+// the same runs as sweep_flat: the flat gather also keeps which members hold
+// each minimum, and the subgroups write, self-activate on a change and
+// notify through the kept minima (notify_kept), as update_regs does.
+template <int K, int G, typename T>
+__device__ __forceinline__ void sweep_flat_fr(const SweepArgs &a, int64_t lo,
+                                              int64_t hi, int64_t block,
+                                              int64_t nblocks, uint8_t *act_next,
+                                              uint8_t *sum_next,
+                                              FlatLds<T> *lds,
+                                              unsigned long long *n_ch,
+                                              unsigned long long *n_ev) {
+  constexpr int M = 4;
+  constexpr int kRun = kFlatRun / (G * M);
+  constexpr int kPerPass = 256 / G;
+  constexpr int kMaskWords = (K * M + 31) / 32;
+  const T *tin = (const T *)a.tau_in;
+  T *tout = (T *)a.tau_out;
+  const uint8_t next = a.stamp == 255 ? 1 : a.stamp + 1;
+  const int t = threadIdx.x;
+  const int sl = lane_id() % G;
+  const int64_t nruns = (hi - lo + kRun - 1) / kRun;
+  const int64_t per = (nruns + nblocks - 1) / nblocks;
+  const int64_t q1 = std::min<int64_t>(nruns, (block + 1) * per);
+  for (int64_t q = block * per; q < q1; q++) {  // uniform over the workgroup
+    const int64_t r0 = lo + q * kRun;
+    const int n = (int)std::min<int64_t>(kRun, hi - r0);
+    const int64_t e0 = a.inc_off[r0];
+    for (int i = t; i <= n; i += blockDim.x)
+      lds->off[i] = (int32_t)(a.inc_off[r0 + i] - e0);
+    __syncthreads();
+    const int ne = lds->off[n];
+    for (int e = t; e < ne; e += blockDim.x) {
+      uint32_t arg = 1;
+      int32_t r;
+      if constexpr (K > 1)
+        r = gather_rho_arg<K, T>(a.inc_ids, e0 + e, tin, &arg);
+      else
+        r = gather_rho<K, T, false>(a.inc_ids, e0 + e, tin);
+      lds->rho[e] = (T)r;
+      lds->mask[e] = (uint8_t)arg;
+    }
+    __syncthreads();
+    for (int p = 0; p < n; p += kPerPass) {  // uniform over the workgroup
+      const int i = p + t / G;
+      const bool active = i < n;
+      int32_t told = 0, c = 0;
+      int b = 0, d = 0;
+      if (active) {
+        b = lds->off[i];
+        d = lds->off[i + 1] - b;
+        told = (int32_t)tin[r0 + i];
+        c = a.cap_by_tau ? told : d;
+      }
+      int32_t rho[M];
+      uint32_t amask[kMaskWords];
+#pragma unroll
+      for (int w = 0; w < kMaskWords; w++) amask[w] = 0;
+#pragma unroll
+      for (int m = 0; m < M; m++) {
+        const int j = sl + m * G;
+        const bool in = j < d;
+        rho[m] = in ? (int32_t)lds->rho[b + j] : -1;
+        if (K > 1 && in) {
+          const uint32_t am = lds->mask[b + j];
+#pragma unroll
+          for (int x = 0; x < K; x++) {
+            const int bit = m * K + x;
+            amask[bit >> 5] |= ((am >> x) & 1u) << (bit & 31);
+          }
+        }
+      }
+      const int cnt = count_ge<G, M>(rho, c);
+      const int32_t h = cnt >= c ? c : hindex_search<G, M>(rho, c);
+      const bool lead = sl == 0;
+      const bool ch = active && h != told;
+      const int64_t R = r0 + i;
+      if (active && lead) store_tau<T, false>(tout + R, h, ch);
+      if (ch) {
+        if (lead) {
+          act_next[R] = next;
+          if (sum_next) sum_next[R >> kGroupShift] = next;
+        }
+        notify_kept<K, G, M>(a.inc_ids, e0 + b, d, sl, rho, amask, told, h,
+                             act_next, next, sum_next);
+      }
+      *n_ch += __popcll(ballot(lead && ch));
+      *n_ev += __popcll(ballot(lead && active));
+    }
+    __syncthreads();  // the next run reuses the LDS
+  }
+}
+
 // One bin [lo, hi) of G lanes per r-clique with M values per lane, swept by
 // the workgroups block .. of nblocks (a launch of its own, or a block range
 // of k_sweep_small).  With `flat` LDS (small bins), a full sweep that
-// notifies nobody runs as sweep_flat.
+// notifies nobody runs as sweep_flat and a full SND sweep that notifies as
+// sweep_flat_fr.  Sweeps that read flags find their flagged r-cliques per
+// wave (sweep_sparse): run-based variants of those (marking, or compacting
+// the flagged r-cliques of each run in LDS) measured no faster.
 template <int K, int G, int M, typename T, bool AND, bool FR>
 __device__ __forceinline__ void sweep_bin(const SweepArgs &a, int64_t lo,
                                           int64_t hi, int64_t block,
@@ -177,7 +276,12 @@ __device__ __forceinline__ void sweep_bin(const SweepArgs &a, int64_t lo,
   const T *tin = (const T *)a.tau_in;
   T *tout = (T *)a.tau_out;
   unsigned long long n_ch = 0, n_ev = 0;  // wave totals, from ballots
-  if (FR && act != nullptr) {
+  constexpr bool kFlatFr = FR && !AND && M == 4;
+  if (kFlatFr && flat != nullptr && act == nullptr && act_next != nullptr) {
+    if constexpr (kFlatFr)
+      sweep_flat_fr<K, G, T>(a, lo, hi, block, nblocks, act_next, sum_next,
+                             flat, &n_ch, &n_ev);
+  } else if (FR && act != nullptr) {
     sweep_sparse<K, G, M, T, AND>(a.inc_off, a.inc_ids, tin, tout, a.cap_by_tau,
                                   lo, hi, wave, waves, act, act_next, a.stamp,
                                   &n_ch, &n_ev, act_sum, sum_next);
