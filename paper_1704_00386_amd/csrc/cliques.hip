@@ -933,10 +933,14 @@ struct N34VLds {
   int32_t pre[D + 1];  // exclusive prefix: bit-row work, then triangles
   uint32_t A[D][D / 32];
   int64_t tb[D];       // toff of edge (p, nb[i]), i >= nl
-  // fill pass: one chunk of up to 64 triangles
+  // fill pass: one chunk of up to 64 triangles, and for each the range of
+  // triangles of edge (nb[i], nb[j]) in which its 4-cliques' remote
+  // triangles lie (found once per triangle, not once per 4-clique)
   int16_t ci[kWave], cj[kWave];
   int32_t ct[kWave];
   int32_t coff[kWave + 1];
+  int64_t cs0[kWave];
+  int32_t cn[kWave];
 };
 
 // Exclusive prefix sums of v[0..n) in place, v[n] = total (one wave).
@@ -1105,13 +1109,26 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
     for (int32_t t0 = 0; t0 < nt; t0 += kWave) {
       const int32_t t = t0 + lane;
       int i = 0, j = 0, kc = 0;
-      int64_t id = 0;
+      int64_t id = 0, s0 = 0;
+      int32_t sn = 0;
       if (t < nt) {
         i = row_of(L.pre, d, t);
         const int r = t - L.pre[i];
         j = nth_and<W>(L.A[i], L.A[i], i + 1, r);
         id = L.tb[i] + r;
         kc = popc_and<W>(L.A[i], L.A[j], j + 1, d);
+        if (kc > 0) {  // the remote triangles' edge: (nb[i], nb[j])
+          const int64_t e1 = L.ro[i] + L.len[i];
+          const int64_t pos = lower_bound<int32_t>(T.col, L.ro[i], e1, L.nb[j]);
+          if (pos < e1 && T.col[pos] == L.nb[j]) {
+            const int32_t e = a.eid[pos];
+            s0 = T.toff[e];
+            sn = (int32_t)(T.toff[e + 1] - s0);
+          } else {
+            *T.err = 1;
+            kc = 0;
+          }
+        }
       }
       int x = kc;
 #pragma unroll
@@ -1123,6 +1140,8 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
       L.ci[lane] = (int16_t)i;
       L.cj[lane] = (int16_t)j;
       L.ct[lane] = (int32_t)id;
+      L.cs0[lane] = s0;
+      L.cn[lane] = sn;
       L.coff[lane] = x - kc;
       if (lane == 0) L.coff[kWave] = nq;
       wave_lds_sync();
@@ -1133,16 +1152,11 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
         const int32_t tij = L.ct[c];
         const int32_t tik = (int32_t)(L.tb[ii] + popc_and<W>(L.A[ii], L.A[ii], ii + 1, k));
         const int32_t tjk = (int32_t)(L.tb[jj] + popc_and<W>(L.A[jj], L.A[jj], jj + 1, k));
-        // the triangle without p: lowest edge (nb[ii], nb[jj])
-        const int64_t e1 = L.ro[ii] + L.len[ii];
-        const int64_t pos = lower_bound<int32_t>(T.col, L.ro[ii], e1, L.nb[jj]);
+        // the triangle without p: third vertex nb[k] on edge (nb[ii], nb[jj])
+        const int64_t s0 = L.cs0[c], s1 = s0 + L.cn[c];
+        const int64_t s = lower_bound<int32_t>(T.tri_w, s0, s1, L.nb[k]);
         int32_t top = -1;
-        if (pos < e1 && T.col[pos] == L.nb[jj]) {
-          const int32_t e = a.eid[pos];
-          const int64_t s0 = T.toff[e], s1 = T.toff[e + 1];
-          const int64_t s = lower_bound<int32_t>(T.tri_w, s0, s1, L.nb[k]);
-          if (s < s1 && T.tri_w[s] == L.nb[k]) top = (int32_t)s;
-        }
+        if (s < s1 && T.tri_w[s] == L.nb[k]) top = (int32_t)s;
         if (top < 0) {
           *T.err = 1;
           continue;
