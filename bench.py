@@ -517,14 +517,17 @@ def workload_leg(nd, ctx, name, kind, quality=False):
     return out, g, kappa
 
 
-def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
+def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
+               group=None):
     """Batched and served k-truss against one graph per launch, on `count`
     graphs of the request-stream workload (Chung-Lu, n ~ U{n_lo..n_hi},
     mean degree ~ U[8,64], exponent ~ U[2.0,2.5]).  Edge lists are resident
     in HBM before timing; every path builds, prepares and decomposes its
     graphs (frontier SND, the same iterates as plain SND).  The server runs
     on a context with a device-memory budget of STREAM_BUDGET bytes and
-    admits requests by it."""
+    admits requests by it.  The batched path takes the graphs `group` at a
+    time (default: all at once up to 512 graphs, else 256), since all of a
+    call's graphs are prepared and resident together."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -534,12 +537,17 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
 
     specs = request_stream(count=count, n_lo=n_lo, n_hi=n_hi, seed=seed)
     progress(f"generating {count} stream graphs")
+    dev = []
     with cf.ThreadPoolExecutor(8) as ex:
-        raws = list(ex.map(lambda sp: chung_lu(sp["n"], sp["beta"], sp["mean"],
-                                               sp["seed"]), specs))
-    dev = [(r.n, torch.from_numpy(r.src).cuda(), torch.from_numpy(r.dst).cuda())
-           for r in raws]
-    del raws
+        for a in range(0, count, 256):
+            for r in ex.map(lambda sp: chung_lu(sp["n"], sp["beta"], sp["mean"],
+                                                sp["seed"]), specs[a:a + 256]):
+                dev.append((r.n, torch.from_numpy(r.src).cuda(),
+                            torch.from_numpy(r.dst).cuda()))
+            if count > 256:
+                progress(f"generated {len(dev)} of {count}")
+    if group is None:
+        group = count if count <= 512 else 256
     kind = "truss"
     updates = 0
     for n, s, d in dev[:4]:  # warm the allocator and kernels once
@@ -557,16 +565,22 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
         torch.cuda.synchronize()
         solo_ms.append(1e3 * (time.perf_counter() - t1))
     t_solo = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    gs = [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev]
-    t_built = time.perf_counter() - t0
-    ks, rs = nd.batch_decompose(ctx, gs, kind, "snd", use_frontier=True)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    same = all(torch.equal(a, b) for a, b in zip(ks, solo))
-    for g in gs:
-        g.close()
-    del gs, ks
+    solo = [k.cpu() for k in solo]  # keep HBM for the other paths
+    t_built, t_batch, same = 0.0, 0.0, True
+    for a in range(0, count, group):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gs = [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev[a:a + group]]
+        t_built += time.perf_counter() - t0
+        ks, rs = nd.batch_decompose(ctx, gs, kind, "snd", use_frontier=True)
+        for g in gs:
+            g.close()
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t0
+        same &= all(torch.equal(x.cpu(), y) for x, y in zip(ks, solo[a:a + group]))
+        del gs, ks
+        if count > group:
+            progress(f"batched {min(a + group, count)} of {count}")
     out = {
         "graphs": count,
         "workload": f"request stream of Chung-Lu k-truss graphs, n ~ U{{{n_lo}.."
@@ -574,6 +588,7 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
         "one_per_launch_graphs_per_s": count / t_solo,
         "batched_graphs_per_s": count / t_batch,
         "batched_speedup": t_solo / t_batch,
+        "batch_group": group,
         "batched_split_s": {"graph_from_edges": t_built,
                             "batch_decompose": t_batch - t_built},
         "updates": updates,
@@ -611,7 +626,7 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True):
             joined += info["joined_running"]
             peak = max(peak, info["peak_members"])
             prep_overlap += info["epochs_during_prep"] > 0
-            same &= bool(torch.equal(kappa, want.cpu()))
+            same &= bool(torch.equal(kappa, want))
         del got
         srv.close()
         del sctx
@@ -748,6 +763,9 @@ def main():
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--stream-graphs", type=int, default=256,
                     help="graphs in the batched/served comparison (0: skip)")
+    ap.add_argument("--stream-group", type=int, default=None,
+                    help="graphs per batched call in the stream leg (default: "
+                         "all up to 512, else 256)")
     ap.add_argument("--small-graphs", type=int, default=512,
                     help="graphs in the small-graph batched comparison "
                          "(0: skip)")
@@ -800,7 +818,8 @@ def main():
     if args.only_stream:
         out = {}
         if args.stream_graphs > 0:
-            out["stream"] = stream_leg(nd, ctx, args.stream_graphs)
+            out["stream"] = stream_leg(nd, ctx, args.stream_graphs,
+                                       group=args.stream_group)
         if args.small_graphs > 0:
             out["small_graphs"] = stream_leg(nd, ctx, args.small_graphs, seed=7,
                                              n_lo=1000, n_hi=5000, serve=False)
@@ -891,7 +910,8 @@ def main():
                                                    quality=True)
             g.close()
         if args.stream_graphs > 0:
-            line["stream"] = stream_leg(nd, ctx, args.stream_graphs)
+            line["stream"] = stream_leg(nd, ctx, args.stream_graphs,
+                                        group=args.stream_group)
         if args.small_graphs > 0:
             line["small_graphs"] = stream_leg(nd, ctx, args.small_graphs, seed=7,
                                               n_lo=1000, n_hi=5000, serve=False)
