@@ -228,15 +228,23 @@ __global__ void k_tri_verts(const int32_t *__restrict__ ev,
 
 // Every listed id must name another r-clique: a cheap guard that turns a
 // builder fault into an error instead of an out-of-range gather.
+// Reads 16 bytes a lane (ids is 256-byte aligned), the tail one id a lane.
 __global__ void k_check_incidence(const int32_t *__restrict__ ids,
                                   int64_t nids, int64_t nr,
                                   int32_t *__restrict__ err) {
   bool bad = false;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nids;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t x = ids[j];
-    bad |= x < 0 || x >= nr;
+  const uint32_t lim = (uint32_t)nr;  // ids below 0 wrap above it
+  const int64_t n4 = nids / 4;
+  const int4 *v = reinterpret_cast<const int4 *>(ids);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t j = t0; j < n4; j += stride) {
+    const int4 x = v[j];
+    bad |= (uint32_t)x.x >= lim || (uint32_t)x.y >= lim ||
+           (uint32_t)x.z >= lim || (uint32_t)x.w >= lim;
   }
+  for (int64_t j = 4 * n4 + t0; j < nids; j += stride)
+    bad |= (uint32_t)ids[j] >= lim;
   if (ballot(bad) && lane_id() == 0) atomicOr(err, 1);
 }
 
@@ -296,7 +304,7 @@ static void prepare_kind(nd_graph *g, nd_kind kind, hipStream_t s) {
     fill_i32(err.p, 0, 1, s);
     const int64_t nids = ks.P * ks.k;
     if (nids > 0) {
-      const unsigned grid = (unsigned)std::min<int64_t>(grid_for(nids, 256), 65536);
+      const unsigned grid = (unsigned)std::min<int64_t>(grid_for((nids + 3) / 4, 256), 65536);
       k_check_incidence<<<grid, 256, 0, s>>>(ks.inc_ids.p, nids, ks.nr, err.p);
       ND_LAUNCHED();
     }

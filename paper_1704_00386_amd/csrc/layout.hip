@@ -39,7 +39,9 @@ __device__ __forceinline__ int bin_of(int64_t d) {
                   : kBinZero;
 }
 
-// Maximum degree and bin sizes (LDS histogram, one atomic per block and bin).
+// Maximum degree and bin sizes: counts per thread in registers, then per
+// block in LDS, then one global atomic per block and bin (a handful of bins
+// would otherwise serialise every thread on the same LDS words).
 __global__ __launch_bounds__(256) void k_layout_stats(
     const int32_t *__restrict__ cnt, int64_t nr, int32_t *__restrict__ maxd,
     unsigned long long *__restrict__ bins) {
@@ -47,14 +49,26 @@ __global__ __launch_bounds__(256) void k_layout_stats(
   if (threadIdx.x < kNumBins) h[threadIdx.x] = 0;
   __syncthreads();
   int32_t m = 0;
+  unsigned int c[kNumBins];
+#pragma unroll
+  for (int b = 0; b < kNumBins; b++) c[b] = 0;
   const int64_t base = (int64_t)blockIdx.x * 256 * 8;
   for (int j = 0; j < 8; j++) {
     const int64_t i = base + j * 256 + threadIdx.x;
     if (i < nr) {
       const int32_t d = cnt[i];
       m = max(m, d);
-      atomicAdd(&h[bin_of(d)], 1u);
+      const int bd = bin_of(d);
+#pragma unroll
+      for (int b = 0; b < kNumBins; b++) c[b] += bd == b;
     }
+  }
+#pragma unroll
+  for (int b = 0; b < kNumBins; b++) {
+    unsigned int v = c[b];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (lane_id() == 0 && v) atomicAdd(&h[b], v);
   }
   for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
   if (lane_id() == 0) atomicMax(maxd, m);
@@ -178,7 +192,9 @@ void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
     k_layout_keys<<<grid_for(nr, 256), 256, 0, s>>>(cnt, nr, rb, keys.p);
     ND_LAUNCHED();
     static_assert(kNumBins <= 16, "bin index must fit 4 key bits");
-    uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, nr, 0, rb + 4, s, al);
+    // the keys are in id order already and the sort is stable, so sorting
+    // by the bin bits alone (one pass) orders them by (bin, id)
+    uint64_t *sorted = radix_sort_u64(keys.p, tmp.p, nr, rb, rb + 4, s, al);
     k_layout_perm<<<grid_for(nr, 256), 256, 0, s>>>(sorted, nr, rb, cnt,
                                                      ks.perm.p, ks.inv.p,
                                                      ks.ds.p);
