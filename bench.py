@@ -570,7 +570,7 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
     for a in range(0, count, group):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        gs = [nd.Graph.from_edges(ctx, n, s, d) for n, s, d in dev[a:a + group]]
+        gs = nd.graphs_from_edges(ctx, dev[a:a + group])
         t_built += time.perf_counter() - t0
         ks, rs = nd.batch_decompose(ctx, gs, kind, "snd", use_frontier=True)
         for g in gs:
@@ -619,6 +619,7 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
             lag.append(1e3 * (time.perf_counter() - t0 - arrive[i]))
         consumer.join()
         t_srv = time.perf_counter() - t0
+        sizes = np.array([int(s.numel()) for _, s, _ in dev])
         lats, slow, joined, peak, prep_overlap = [], [], 0, 0, 0
         for (kappa, r, info), want, ms in zip(got, solo, solo_ms):
             lats.append(info["latency_ms"])
@@ -640,6 +641,13 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
                          "slowdown_p99": float(np.percentile(slow, 99)),
                          # how far the caller's submissions (graph build
                          # included) fell behind the arrival times
+                         # within each half of the requests by edge count
+                         "by_size": {
+                             h: {"p50_ms": float(np.percentile(np.array(lats)[sel], 50)),
+                                 "p99_ms": float(np.percentile(np.array(lats)[sel], 99))}
+                             for h, sel in (("smaller_half", sizes <= np.median(sizes)),
+                                            ("larger_half", sizes > np.median(sizes)))
+                             if sel.any()},
                          "submit_lag_ms_p50": float(np.percentile(lag, 50)),
                          "submit_lag_ms_max": float(np.max(lag)),
                          "hbm_budget_bytes": STREAM_BUDGET,

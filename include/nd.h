@@ -54,7 +54,8 @@
  *                         (default 8; 0: from the second sweep on).
  *   ND_BATCH_NO_GRAPH=1   batched epochs are launched one by one instead of
  *                         through HIP graphs of eight epochs.
- *   ND_PREP_THREADS=t     host threads preparing graphs in nd_prepare_many and
+ *   ND_PREP_THREADS=t     host threads building or preparing graphs in
+ *                         nd_graphs_from_edges, nd_prepare_many and
  *                         nd_batch_decompose (default 2) and in a server
  *                         (default 4).
  *   ND_TRUSS_NO_LDS=1     the k-truss builder intersects the 64-lane bin
@@ -188,6 +189,17 @@ size_t nd_ctx_bytes_in_use(const nd_ctx *ctx);
 nd_status nd_graph_from_edges(nd_ctx *ctx, int32_t n, int64_t m,
                               const int32_t *src, const int32_t *dst,
                               int on_device, void *stream, nd_graph **out);
+
+/* count graphs at once, graph i as nd_graph_from_edges(ctx, n[i], m[i],
+ * src[i], dst[i], on_device, ...) would build it, on host threads (two by
+ * default) with a stream each, ordered after `stream`; their short,
+ * launch-bound build phases overlap.  out[i] receives graph i.  On any
+ * failure (the first is returned) no graph is kept and every out[i] is
+ * NULL. */
+nd_status nd_graphs_from_edges(nd_ctx *ctx, int32_t count, const int32_t *n,
+                               const int64_t *m, const int32_t *const *src,
+                               const int32_t *const *dst, int on_device,
+                               void *stream, nd_graph **out);
 
 /* Graph from a canonical CSR: row_off[n+1] (row_off[0] = 0, non-decreasing,
  * row_off[n] = nnz) and col[nnz], each list strictly ascending, no self-loop,

@@ -115,6 +115,9 @@ _sig("nd_ctx_destroy", None, _P)
 _sig("nd_ctx_bytes_in_use", ctypes.c_size_t, _P)
 _sig("nd_graph_from_edges", ctypes.c_int, _P, _I32, _I64, _P, _P, ctypes.c_int,
      _P, ctypes.POINTER(_P))
+_sig("nd_graphs_from_edges", ctypes.c_int, _P, _I32, ctypes.POINTER(_I32),
+     ctypes.POINTER(_I64), ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_int,
+     _P, ctypes.POINTER(_P))
 _sig("nd_graph_from_csr", ctypes.c_int, _P, _I32, _I64, _P, _P, ctypes.c_int,
      _P, ctypes.POINTER(_P))
 _sig("nd_graph_destroy", None, _P)
@@ -448,6 +451,29 @@ class Graph:
         if nr is None:
             nr = int(res.n_rcliques)
         return kappa[:nr], res.as_dict()
+
+
+def graphs_from_edges(ctx: Context, edge_lists, stream=None):
+    """nd_graphs_from_edges: [Graph] from [(n, src, dst)], built together."""
+    count = len(edge_lists)
+    ns = (_I32 * max(count, 1))()
+    ms = (_I64 * max(count, 1))()
+    ss = (_P * max(count, 1))()
+    ds = (_P * max(count, 1))()
+    keep = []
+    for i, (n, src, dst) in enumerate(edge_lists):
+        s = _dev_i32(src, ctx.device)
+        d = _dev_i32(dst, ctx.device)
+        if s.numel() != d.numel():
+            raise ValueError(f"graph {i}: src and dst differ in length")
+        keep += [s, d]
+        ns[i], ms[i] = int(n), int(s.numel())
+        ss[i], ds[i] = s.data_ptr(), d.data_ptr()
+    out = (_P * max(count, 1))()
+    _check(_lib.nd_graphs_from_edges(ctx._h, count, ns, ms, ss, ds, 1,
+                                     _stream(stream), out), "nd_graphs_from_edges")
+    del keep
+    return [Graph(ctx, _P(out[i])) for i in range(count)]
 
 
 def prepare_many(ctx: Context, graphs: Sequence[Graph], kind: str,

@@ -6,9 +6,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "api_util.h"
 #include "internal.h"
@@ -456,6 +460,117 @@ nd_status nd_graph_from_edges(nd_ctx *ctx, int32_t n, int64_t m,
   if (st != ND_OK && g) {
     (void)hipStreamSynchronize((hipStream_t)stream);
     nd_graph_destroy(g);
+  }
+  return st;
+}
+
+nd_status nd_graphs_from_edges(nd_ctx *ctx, int32_t count, const int32_t *n,
+                               const int64_t *m, const int32_t *const *src,
+                               const int32_t *const *dst, int on_device,
+                               void *stream, nd_graph **out) {
+  std::vector<nd_graph *> built;
+  hipStream_t s = (hipStream_t)stream;
+  nd_status st = guarded([&] {
+    ND_REQUIRE(ctx && (count == 0 || (n && m && src && dst && out)),
+               ND_ERR_INVALID, "NULL argument");
+    ND_REQUIRE(count >= 0, ND_ERR_INVALID, "negative count");
+    for (int i = 0; i < count; i++) {
+      ND_REQUIRE(n[i] >= 0 && m[i] >= 0, ND_ERR_INVALID, "graph %d: negative size", i);
+      ND_REQUIRE(m[i] == 0 || (src[i] && dst[i]), ND_ERR_INVALID,
+                 "graph %d: src/dst is NULL", i);
+      out[i] = nullptr;
+    }
+    if (count == 0) return;
+    ND_HIP(hipSetDevice(ctx->device));
+    built.assign(count, nullptr);
+    // graph i built on stream bs (its own copies, validation and CSR)
+    auto build = [&](int i, hipStream_t bs) {
+      Phase phase("nd.graph_from_edges");
+      StreamScope scope(bs);
+      nd_graph *g = new nd_graph();
+      g->ctx = ctx;
+      ctx->retain();
+      g->n = n[i];
+      built[i] = g;
+      DArr<int32_t> hs, hd;
+      const int32_t *ds = src[i], *dd = dst[i];
+      if (!on_device && m[i] > 0) {
+        hs.reset(ctx->alloc, m[i]);
+        hd.reset(ctx->alloc, m[i]);
+        ND_HIP(hipMemcpyAsync(hs.p, src[i], sizeof(int32_t) * m[i],
+                              hipMemcpyHostToDevice, bs));
+        ND_HIP(hipMemcpyAsync(hd.p, dst[i], sizeof(int32_t) * m[i],
+                              hipMemcpyHostToDevice, bs));
+        ds = hs.p;
+        dd = hd.p;
+      }
+      build_from_edges(g, m[i], ds, dd, bs);
+      ND_HIP(hipStreamSynchronize(bs));
+    };
+    const int nt = std::min(prep_threads(), count);
+    if (nt <= 1) {
+      StreamScope scope(s);
+      for (int i = 0; i < count; i++) build(i, s);
+    } else {
+      hipEvent_t start;
+      ND_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+      ND_HIP(hipEventRecord(start, s));
+      std::vector<hipStream_t> streams;
+      for (int t = 0; t < nt; t++) {
+        hipStream_t bs = nullptr;
+        const hipError_t e = hipStreamCreateWithFlags(&bs, hipStreamNonBlocking);
+        if (e != hipSuccess) break;
+        streams.push_back(bs);
+        (void)hipStreamWaitEvent(bs, start, 0);
+      }
+      (void)hipEventDestroy(start);
+      std::atomic<int> next{0};
+      std::mutex mu;
+      nd_status code = ND_OK;
+      std::string msg;
+      std::vector<std::thread> threads;
+      for (size_t t = 0; t < streams.size(); t++)
+        threads.emplace_back([&, t] {
+          try {
+            ND_HIP(hipSetDevice(ctx->device));
+            for (int i; (i = next++) < count;) {
+              {
+                std::lock_guard<std::mutex> lk(mu);
+                if (code != ND_OK) return;
+              }
+              build(i, streams[t]);
+            }
+          } catch (const Err &e) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (code == ND_OK) {
+              code = e.code;
+              msg = nd_last_error();
+            }
+          } catch (const std::exception &e) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (code == ND_OK) {
+              code = ND_ERR_DEVICE;
+              msg = e.what();
+            }
+          }
+        });
+      for (auto &th : threads) th.join();
+      for (hipStream_t bs : streams) {
+        ctx->alloc.forget_stream(bs);  // waits for it
+        (void)hipStreamDestroy(bs);
+      }
+      ND_REQUIRE(!streams.empty(), ND_ERR_DEVICE, "no stream for the builders");
+      if (code != ND_OK) {
+        set_error("%s", msg.c_str());
+        throw Err(code);
+      }
+    }
+    for (int i = 0; i < count; i++) out[i] = built[i];
+  });
+  if (st != ND_OK) {
+    (void)hipStreamSynchronize(s);
+    for (nd_graph *g : built)
+      if (g) nd_graph_destroy(g);
   }
   return st;
 }

@@ -786,8 +786,6 @@ int Batch::autotune() {
 
 // ------------------------------------------------------- batch ABI
 
-namespace {
-
 constexpr int kPrepThreads = 2;
 
 int prep_threads() {
@@ -798,6 +796,8 @@ int prep_threads() {
   }();
   return n;
 }
+
+namespace {
 
 // Prepares graphs for one kind on up to prep_threads() host threads, each
 // with a stream of its own ordered after the caller's, largest graphs first

@@ -363,6 +363,10 @@ constexpr int kHostStatsRing = 1024;
 void launch_sweep(const KindState &ks, const SweepArgs &a, bool and_mode,
                   hipStream_t s);
 
+// Host threads (each with a stream) that build or prepare several graphs
+// at once: 2, or ND_PREP_THREADS.
+int prep_threads();
+
 // Frontier switch: notifications start once a sweep changes at most
 // 1/d of the swept r-cliques; d = 8 for SND and AND (measured on the three
 // benchmark workloads), ND_FRONTIER_SWITCH overrides it (0: from the first

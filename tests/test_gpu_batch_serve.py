@@ -91,6 +91,27 @@ def test_batch_prepares_while_sweeping(nd, ctx, kind):
             or want.size == 0, raw.name
 
 
+def test_graphs_from_edges(nd, ctx):
+    """Graphs built together equal graphs built one at a time (CSR and
+    decomposition); an invalid edge list fails the whole call."""
+    raws = mixed_graphs()
+    gs = nd.graphs_from_edges(ctx, [(r.n, torch.from_numpy(r.src), torch.from_numpy(r.dst))
+                                    for r in raws])
+    for g, raw in zip(gs, raws):
+        one = make(nd, ctx, raw)
+        ro1, c1 = one.csr()
+        ro2, c2 = g.csr()
+        assert torch.equal(ro1, ro2) and torch.equal(c1, c2), raw.name
+        assert np.array_equal(g.decompose("truss")[0].cpu().numpy(),
+                              oracle.Graph.from_raw(raw).peel(2, 3))
+    bad = [(raws[0].n, torch.from_numpy(raws[0].src), torch.from_numpy(raws[0].dst)),
+           (3, torch.tensor([0, 1], dtype=torch.int32), torch.tensor([1, 7], dtype=torch.int32))]
+    with pytest.raises(nd.NdError) as e:
+        nd.graphs_from_edges(ctx, bad)
+    assert e.value.name == "invalid"
+    assert nd.graphs_from_edges(ctx, []) == []
+
+
 def test_prepare_many(nd, ctx):
     raws = mixed_graphs()
     gs = [make(nd, ctx, raw) for raw in raws]
