@@ -550,6 +550,7 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
         group = count if count <= 512 else 256
     kind = "truss"
     updates = 0
+    alg_bytes = 0.0
     for n, s, d in dev[:4]:  # warm the allocator and kernels once
         nd.Graph.from_edges(ctx, n, s, d).decompose(kind, "snd", use_frontier=True)
     torch.cuda.synchronize()
@@ -561,6 +562,13 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
         k, r = g.decompose(kind, "snd", use_frontier=True)
         solo.append(k)
         updates += r["updates"]
+        # algorithmic bytes of the evaluations (ids, tau gathers, offsets and
+        # own tau per update, each evaluated r-clique taken at its graph's
+        # mean list length)
+        if r["n_rcliques"]:
+            tb = r["tau_bytes"]
+            alg_bytes += r["updates"] * ((4 + tb) * 2 * r["n_incidence"] / r["n_rcliques"]
+                                         + 8 + 2 * tb)
         g.close()
         torch.cuda.synchronize()
         solo_ms.append(1e3 * (time.perf_counter() - t1))
@@ -592,6 +600,13 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
         "batched_split_s": {"graph_from_edges": t_built,
                             "batch_decompose": t_batch - t_built},
         "updates": updates,
+        "aggregate_algorithmic_GBs": {
+            "one_per_launch": alg_bytes / t_solo / 1e9,
+            "batched": alg_bytes / t_batch / 1e9,
+            "what": "the evaluated h-index updates' algorithmic bytes (id stream, "
+                    "tau gathers, offsets and own tau), each evaluated r-clique at "
+                    "its graph's mean list length, over the path's wall time "
+                    "(build and preparation included); HBM peak 8000 GB/s"},
     }
     if serve:
         # served: Poisson arrivals at 80% of the one-graph-per-launch rate
@@ -631,6 +646,7 @@ def stream_leg(nd, ctx, count, seed=5, n_lo=1000, n_hi=200000, serve=True,
         del got
         srv.close()
         del sctx
+        out["aggregate_algorithmic_GBs"]["served"] = alg_bytes / t_srv / 1e9
         out["served"] = {"arrival_rate_per_s": rate, "graphs_per_s": count / t_srv,
                          "p50_ms": float(np.percentile(lats, 50)),
                          "p99_ms": float(np.percentile(lats, 99)),

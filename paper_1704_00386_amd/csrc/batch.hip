@@ -1006,9 +1006,16 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
   std::unique_ptr<Batch> batches[2];  // 16-bit, 32-bit tau
   bool tuned[2] = {false, false};
   std::map<nd_graph *, Member *> member;
-  hipEvent_t a, b;
-  ND_HIP(hipEventCreate(&a));
-  ND_HIP(hipEventCreate(&b));
+  struct Events {  // the call's timing events, released on every exit
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } evs;
+  ND_HIP(hipEventCreate(&evs.a));
+  ND_HIP(hipEventCreate(&evs.b));
+  hipEvent_t a = evs.a, b = evs.b;
   ND_HIP(hipEventRecord(a, s));
   auto join = [&](nd_graph *g, hipEvent_t ready) {
     const int w = g->ks[kind].tau16 ? 0 : 1;
@@ -1080,8 +1087,6 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
   ND_HIP(hipEventSynchronize(b));
   float ms_total = 0;
   ND_HIP(hipEventElapsedTime(&ms_total, a, b));
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
   nd_status out = ND_OK;
   for (int i = 0; i < count; i++) {
     const Member &m = *member.at(graphs[i]);
