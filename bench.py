@@ -103,14 +103,31 @@ def cpu_baseline(budget_s=10.0, seed=4):
         dt = time.perf_counter() - t
         return int(np.count_nonzero(ds)), dt, og.num_rcliques(3)
 
+    def time_peel(comms):  # the oracle's Alg. Peeling, S-degrees included
+        n, s, d = union_of(comms)
+        og = oracle.Graph(n, s, d)
+        inc = int(og.sdeg(3, 4, threads).sum())
+        t = time.perf_counter()
+        og.peel(3, 4, threads)
+        return time.perf_counter() - t, og.num_rcliques(3), inc
+
     upd0, dt0, _ = time_u(order[:20])
     want = int(min(ncomm, max(20, 20 * budget_s / max(dt0, 1e-6))))
     upd, dt, nt = time_u(order[:want])
+    pt, pnt, pinc = time_peel(order[:3])
+    want_p = int(min(ncomm, max(3, 3 * budget_s / max(pt, 1e-6))))
+    if want_p > 3:
+        pt, pnt, pinc = time_peel(order[:want_p])
     return {"value": upd / dt, "unit": "r-clique h-index updates/s",
             "cores": threads, "kind": "oracle",
             "sample": f"U applied to the {nt} triangles ({upd} with d_s > 0, "
                       f"tau = d_s) of {want} of the {ncomm} communities "
-                      f"(random, seed {seed + 1}) in {dt:.1f} s"}
+                      f"(random, seed {seed + 1}) in {dt:.1f} s",
+            "peeling": {"s": pt, "triangles": pnt, "incidence_P": pinc,
+                        "incidence_per_s": pinc / pt, "cores": threads,
+                        "sample": f"Alg. Peeling (S-degrees, then bucket peeling) "
+                                  f"of the {pnt} triangles of {want_p} communities "
+                                  f"(the same draw)"}}
 
 
 def sweep_source_hash() -> str:
@@ -946,6 +963,12 @@ def main():
         cb["time_to_exact_s_est"] = res["updates"] / cb["value"]
         cb["time_to_exact_s_est_is"] = ("the step's evaluated updates divided "
                                         "by the oracle's rate")
+        pe = cb["peeling"]
+        pe["full_workload_s_est"] = res["n_incidence"] / pe["incidence_per_s"]
+        pe["full_workload_s_est_is"] = ("the workload's incidence pairs divided by "
+                                        "the sample's peeling rate (peeling is "
+                                        "linear in them)")
+        pe["step_speedup_est"] = pe["full_workload_s_est"] / (ms_step * 1e-3)
         line["cpu_baseline"] = cb
     peel = recorded_peeling(HEADLINE)
     if peel is not None:
