@@ -1016,6 +1016,11 @@ __device__ __forceinline__ int nth_and(const uint32_t *x, const uint32_t *y,
   return -1;
 }
 
+// Bit-row words kept per CSR entry between the count and the fill pass: the
+// d rows of vertex p (D / 32 words each) lie packed from
+// rows[row_off[p] * kN34RowWords], inside the region its entries own.
+constexpr int kN34RowWords = 8;
+
 struct N34VArgs {
   const int32_t *items;  // vertices of this degree class
   int64_t nitems;
@@ -1024,6 +1029,9 @@ struct N34VArgs {
   const int32_t *eid;
   const int32_t *nlow;
   const int64_t *eoff;
+  // the bit rows: written by the count pass, read back by the fill pass
+  // (NULL: the fill builds them again)
+  uint32_t *rows;
   TriIsectArgs t;        // triangle tables, outputs and error flag
 };
 
@@ -1043,7 +1051,13 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
     const int nl = a.nlow[p];
     const int64_t e_lo = a.eoff[p];
     wave_lds_sync();  // the previous vertex's reads are done
-    for (int x = lane; x < d * W; x += kWave) L.A[x / W][x % W] = 0;
+    const bool reuse = FILL && a.rows != nullptr;
+    if (reuse) {
+      for (int x = lane; x < d * W; x += kWave)
+        L.A[x / W][x % W] = a.rows[base * kN34RowWords + x];
+    } else {
+      for (int x = lane; x < d * W; x += kWave) L.A[x / W][x % W] = 0;
+    }
     for (int i = lane; i < d; i += kWave) {
       const int32_t v = a.col[base + i];
       L.nb[i] = v;
@@ -1051,28 +1065,33 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
       L.len[i] = (int32_t)(a.row_off[v + 1] - L.ro[i]);
     }
     wave_lds_sync();
-    // bit rows: a short row walks N(nb[i]) and finds each entry in nb; a
-    // long one (a hub's) looks each nb[q] up in N(nb[i]) instead
-    for (int i = lane; i < d; i += kWave)
-      L.pre[i] = L.len[i] <= 4 * d ? L.len[i] : d;
-    wave_lds_sync();
-    wave_scan_lds(L.pre, d);
-    const int32_t work = L.pre[d];
-    for (int32_t t = lane; t < work; t += kWave) {
-      const int i = row_of(L.pre, d, t);
-      const int r = t - L.pre[i];
-      if (L.len[i] <= 4 * d) {
-        const int32_t z = T.col[L.ro[i] + r];
-        const int q = (int)lower_bound<int32_t>(L.nb, 0, d, z);
-        if (q < d && L.nb[q] == z) atomicOr(&L.A[i][q >> 5], 1u << (q & 31));
-      } else {
-        const int32_t z = L.nb[r];
-        const int64_t e1 = L.ro[i] + L.len[i];
-        const int64_t q = lower_bound<int32_t>(T.col, L.ro[i], e1, z);
-        if (q < e1 && T.col[q] == z) atomicOr(&L.A[i][r >> 5], 1u << (r & 31));
+    if (!reuse) {
+      // bit rows: a short row walks N(nb[i]) and finds each entry in nb; a
+      // long one (a hub's) looks each nb[q] up in N(nb[i]) instead
+      for (int i = lane; i < d; i += kWave)
+        L.pre[i] = L.len[i] <= 4 * d ? L.len[i] : d;
+      wave_lds_sync();
+      wave_scan_lds(L.pre, d);
+      const int32_t work = L.pre[d];
+      for (int32_t t = lane; t < work; t += kWave) {
+        const int i = row_of(L.pre, d, t);
+        const int r = t - L.pre[i];
+        if (L.len[i] <= 4 * d) {
+          const int32_t z = T.col[L.ro[i] + r];
+          const int q = (int)lower_bound<int32_t>(L.nb, 0, d, z);
+          if (q < d && L.nb[q] == z) atomicOr(&L.A[i][q >> 5], 1u << (q & 31));
+        } else {
+          const int32_t z = L.nb[r];
+          const int64_t e1 = L.ro[i] + L.len[i];
+          const int64_t q = lower_bound<int32_t>(T.col, L.ro[i], e1, z);
+          if (q < e1 && T.col[q] == z) atomicOr(&L.A[i][r >> 5], 1u << (r & 31));
+        }
       }
+      wave_lds_sync();
+      if (!FILL && a.rows != nullptr)  // keep them for the fill pass
+        for (int x = lane; x < d * W; x += kWave)
+          a.rows[base * kN34RowWords + x] = L.A[x / W][x % W];
     }
-    wave_lds_sync();
     // triangles (p, nb[i], nb[j]), i >= nl, i < j: row i holds those of
     // edge (p, nb[i]), numbered from tb[i]; every row must count exactly
     // the edge's triangles, so that every id below lies in the edge's range
@@ -1494,6 +1513,23 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   va.nlow = g->nlow.p;
   va.eoff = g->eoff.p;
   va.t = a;
+  // the count pass's bit rows, for the fill pass (skipped when they would
+  // take more than a quarter of the budget left: the fill then builds them
+  // again)
+  DArr<uint32_t> rows;
+  const size_t rows_bytes =
+      sizeof(uint32_t) * kN34RowWords * (size_t)std::max<int64_t>(g->nnz, 1);
+  const size_t live = al.live_bytes();
+  if (voff[3] > 0 &&
+      (al.budget() == 0 ||
+       (live < al.budget() && rows_bytes <= (al.budget() - live) / 4))) {
+    try {
+      rows.reset(al, std::max<int64_t>(g->nnz, 1) * kN34RowWords);
+    } catch (const Err &) {  // the device is short of memory
+      rows.p = nullptr;
+    }
+  }
+  va.rows = rows.p;
   {
     Phase phase("nd.incidence.count");
     run_n34_vertex(va, false, vitems.p, voff, s);
@@ -1518,6 +1554,7 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   va.t = a;
   Phase fill_phase("nd.incidence.fill");
   run_n34_vertex(va, true, vitems.p, voff, s);
+  rows.free();
   run_n34_tri(a, true, items.p, bin_off, s);
   if (nt > 0) {
     const unsigned grid = (unsigned)std::min<int64_t>(grid_for(nt, 256), 65536);
