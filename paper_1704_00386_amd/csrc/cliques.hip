@@ -202,10 +202,10 @@ struct TriIsectArgs {
   const int32_t *tri_w;
   const int32_t *tri_e;
   int32_t *count;        // count pass: S-degree of each triangle
-  int32_t *loc;          // count pass: its local 4-cliques (see below)
-  const int32_t *inv;    // fill pass: triangle id -> internal id
-  const int64_t *inc_off;  // fill pass: list of internal triangle i
-  uint32_t *rcur;        // fill pass: next remote slot of internal triangle i
+  // count pass: its local 4-cliques (see below); fill pass: the cursor of
+  // its remote entries, which start there
+  int32_t *loc;
+  const struct TriRec *rec;  // fill pass: each triangle's list (see below)
   int32_t *out;          // fill pass: 3 ids per 4-clique
   int32_t *err;          // set to 1 on an inconsistency (nothing written)
 };
@@ -777,17 +777,24 @@ void run_edge_isect(EdgeIsectArgs a, const int32_t *items,
 // from T's cursor, which starts at T's local count) -- one atomic per
 // 4-clique.
 
-// Write the 3 ids of one entry at place `slot` of internal triangle x's list,
-// if it lies inside the list (else flag an inconsistency).
-__device__ __forceinline__ void n34_put(const TriIsectArgs &a, int32_t x,
+// What the (3,4) fill needs of triangle t, in one 16-byte load: its
+// internal id and the place and length of its list.
+struct alignas(16) TriRec {
+  int64_t base;
+  int32_t inv;
+  int32_t len;
+};
+
+// Write the 3 ids of one entry at place `slot` of the list of r, if it lies
+// inside the list (else flag an inconsistency).
+__device__ __forceinline__ void n34_put(const TriIsectArgs &a, const TriRec &r,
                                         int64_t slot, int32_t i0, int32_t i1,
                                         int32_t i2) {
-  const int64_t p = a.inc_off[x] + slot;
-  if (slot < 0 || p >= a.inc_off[x + 1]) {
+  if (slot < 0 || slot >= r.len) {
     *a.err = 1;
     return;
   }
-  int32_t *o = a.out + 3 * p;
+  int32_t *o = a.out + 3 * (r.base + slot);
   o[0] = i0;
   o[1] = i1;
   o[2] = i2;
@@ -843,7 +850,7 @@ __global__ __launch_bounds__(256) void k_n34_fill_owner(TriIsectArgs a) {
     const int o1 = sh == 0 ? 1 : 0, o2 = sh == 2 ? 1 : 2;
     const int64_t n1 = en[o1] - b[o1], n2 = en[o2] - b[o2];
     const bool staged = n34_stage<G, CAP>(a.col, b[o1], n1, b[o2], n2, l1, l2, sl);
-    const int32_t it = a.inv[t];
+    const TriRec rt = a.rec[t];
     int64_t nloc = 0;  // local entries written so far (uniform)
     for (int64_t j0 = b[sh]; j0 < en[sh]; j0 += G) {  // uniform rounds
       const int64_t j = j0 + sl;
@@ -872,11 +879,11 @@ __global__ __launch_bounds__(256) void k_n34_fill_owner(TriIsectArgs a) {
         if (tuv < 0 || tuw < 0 || tvw < 0) {
           *a.err = 1;
         } else {
-          const int32_t iuv = a.inv[tuv], iuw = a.inv[tuw], ivw = a.inv[tvw];
-          n34_put(a, it, nloc + rank, iuv, iuw, ivw);
+          const TriRec ruv = a.rec[tuv], ruw = a.rec[tuw], rvw = a.rec[tvw];
+          n34_put(a, rt, nloc + rank, ruv.inv, ruw.inv, rvw.inv);
           if (x > w) {  // {u,v,w,x} seen from its lowest triangle: once
-            const uint32_t p = atomicAdd(&a.rcur[ivw], 1u);
-            n34_put(a, ivw, (int64_t)p, it, iuv, iuw);
+            const int32_t p = atomicAdd(&a.loc[tvw], 1);
+            n34_put(a, rvw, p, rt.inv, ruv.inv, ruw.inv);
           }
         }
       }
@@ -933,11 +940,13 @@ struct N34VLds {
   int32_t pre[D + 1];  // exclusive prefix: bit-row work, then triangles
   uint32_t A[D][D / 32];
   int64_t tb[D];       // toff of edge (p, nb[i]), i >= nl
-  // fill pass: one chunk of up to 64 triangles, and for each the range of
-  // triangles of edge (nb[i], nb[j]) in which its 4-cliques' remote
-  // triangles lie (found once per triangle, not once per 4-clique)
+  // fill pass: one chunk of up to 64 triangles with their lists (base,
+  // internal id, length), and for each the range of triangles of edge
+  // (nb[i], nb[j]) in which its 4-cliques' remote triangles lie (found once
+  // per triangle, not once per 4-clique)
   int16_t ci[kWave], cj[kWave];
-  int32_t ct[kWave];
+  int64_t cb[kWave];
+  int32_t cv[kWave], cl[kWave];
   int32_t coff[kWave + 1];
   int64_t cs0[kWave];
   int32_t cn[kWave];
@@ -1128,13 +1137,14 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
     for (int32_t t0 = 0; t0 < nt; t0 += kWave) {
       const int32_t t = t0 + lane;
       int i = 0, j = 0, kc = 0;
-      int64_t id = 0, s0 = 0;
+      int64_t s0 = 0;
       int32_t sn = 0;
+      TriRec rt{0, 0, 0};
       if (t < nt) {
         i = row_of(L.pre, d, t);
         const int r = t - L.pre[i];
         j = nth_and<W>(L.A[i], L.A[i], i + 1, r);
-        id = L.tb[i] + r;
+        rt = T.rec[L.tb[i] + r];
         kc = popc_and<W>(L.A[i], L.A[j], j + 1, d);
         if (kc > 0) {  // the remote triangles' edge: (nb[i], nb[j])
           const int64_t e1 = L.ro[i] + L.len[i];
@@ -1158,7 +1168,9 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
       const int nq = __shfl(x, kWave - 1, kWave);
       L.ci[lane] = (int16_t)i;
       L.cj[lane] = (int16_t)j;
-      L.ct[lane] = (int32_t)id;
+      L.cb[lane] = rt.base;
+      L.cv[lane] = rt.inv;
+      L.cl[lane] = rt.len;
       L.cs0[lane] = s0;
       L.cn[lane] = sn;
       L.coff[lane] = x - kc;
@@ -1168,7 +1180,6 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
         const int c = row_of(L.coff, kWave, q);
         const int ii = L.ci[c], jj = L.cj[c];
         const int k = nth_and<W>(L.A[ii], L.A[jj], jj + 1, q - L.coff[c]);
-        const int32_t tij = L.ct[c];
         const int32_t tik = (int32_t)(L.tb[ii] + popc_and<W>(L.A[ii], L.A[ii], ii + 1, k));
         const int32_t tjk = (int32_t)(L.tb[jj] + popc_and<W>(L.A[jj], L.A[jj], jj + 1, k));
         // the triangle without p: third vertex nb[k] on edge (nb[ii], nb[jj])
@@ -1180,13 +1191,16 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
           *T.err = 1;
           continue;
         }
-        const int32_t iij = T.inv[tij], iik = T.inv[tik], ijk = T.inv[tjk];
-        const int32_t itop = T.inv[top];
-        n34_put(T, iij, popc_and<W>(L.A[ii], L.A[jj], nl, k), iik, ijk, itop);
-        n34_put(T, iik, popc_and<W>(L.A[ii], L.A[k], nl, jj), iij, ijk, itop);
-        n34_put(T, ijk, popc_and<W>(L.A[jj], L.A[k], nl, ii), iij, iik, itop);
-        const uint32_t slot = atomicAdd(&T.rcur[itop], 1u);
-        n34_put(T, itop, (int64_t)slot, iij, iik, ijk);
+        TriRec rij;
+        rij.base = L.cb[c];
+        rij.inv = L.cv[c];
+        rij.len = L.cl[c];
+        const TriRec rik = T.rec[tik], rjk = T.rec[tjk], rtop = T.rec[top];
+        n34_put(T, rij, popc_and<W>(L.A[ii], L.A[jj], nl, k), rik.inv, rjk.inv, rtop.inv);
+        n34_put(T, rik, popc_and<W>(L.A[ii], L.A[k], nl, jj), rij.inv, rjk.inv, rtop.inv);
+        n34_put(T, rjk, popc_and<W>(L.A[jj], L.A[k], nl, ii), rij.inv, rik.inv, rtop.inv);
+        const int32_t slot = atomicAdd(&T.loc[top], 1);
+        n34_put(T, rtop, slot, rij.inv, rik.inv, rjk.inv);
       }
       wave_lds_sync();  // before the next chunk overwrites ci .. coff
     }
@@ -1228,21 +1242,28 @@ __global__ void k_n34_tri_bins(const int32_t *__restrict__ ev,
   bin[t] = isect_bin(m);
 }
 
-__global__ void k_n34_cursor(const int32_t *__restrict__ perm,
-                             const int32_t *__restrict__ loc, int64_t nt,
-                             uint32_t *__restrict__ rcur) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nt) rcur[i] = (uint32_t)loc[perm[i]];
+// The list of every triangle t: internal id inv[t], at inc_off[inv[t]].
+__global__ void k_n34_rec(const int32_t *__restrict__ inv,
+                          const int64_t *__restrict__ off, int64_t nt,
+                          TriRec *__restrict__ rec) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int32_t x = inv[t];
+  TriRec r;
+  r.base = off[x];
+  r.inv = x;
+  r.len = (int32_t)(off[x + 1] - r.base);
+  rec[t] = r;
 }
 
-// Every list full: each cursor ended at its list's length.
-__global__ void k_n34_check_full(const uint32_t *__restrict__ rcur,
-                                 const int64_t *__restrict__ off, int64_t nt,
+// Every list full: each remote cursor ended at its list's length.
+__global__ void k_n34_check_full(const int32_t *__restrict__ cur,
+                                 const TriRec *__restrict__ rec, int64_t nt,
                                  int32_t *__restrict__ err) {
   bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt;
-       i += (int64_t)gridDim.x * blockDim.x)
-    bad |= (int64_t)rcur[i] != off[i + 1] - off[i];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt;
+       t += (int64_t)gridDim.x * blockDim.x)
+    bad |= cur[t] != rec[t].len;
   if (ballot(bad) && lane_id() == 0) atomicOr(err, 1);
 }
 
@@ -1539,17 +1560,13 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   build_layout(g, ks, cnt.p, s);
   cnt.free();
   ks.inc_ids.reset(al, 3 * ks.P);
-  DArr<uint32_t> rcur(al, std::max<int64_t>(nt, 1));
+  DArr<TriRec> rec(al, std::max<int64_t>(nt, 1));
   if (nt > 0) {
-    k_n34_cursor<<<grid_for(nt, 256), 256, 0, s>>>(ks.perm.p, loc.p, nt, rcur.p);
+    k_n34_rec<<<grid_for(nt, 256), 256, 0, s>>>(ks.inv.p, ks.inc_off.p, nt, rec.p);
     ND_LAUNCHED();
   }
-  loc.free();
   a.count = nullptr;
-  a.loc = nullptr;
-  a.inv = ks.inv.p;
-  a.inc_off = ks.inc_off.p;
-  a.rcur = rcur.p;
+  a.rec = rec.p;  // loc: now the remote cursors
   a.out = ks.inc_ids.p;
   va.t = a;
   Phase fill_phase("nd.incidence.fill");
@@ -1558,7 +1575,7 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   run_n34_tri(a, true, items.p, bin_off, s);
   if (nt > 0) {
     const unsigned grid = (unsigned)std::min<int64_t>(grid_for(nt, 256), 65536);
-    k_n34_check_full<<<grid, 256, 0, s>>>(rcur.p, ks.inc_off.p, nt, err.p);
+    k_n34_check_full<<<grid, 256, 0, s>>>(loc.p, rec.p, nt, err.p);
     ND_LAUNCHED();
   }
   const int32_t h = *PinnedChunk().read(err.p, 1, s);
