@@ -256,6 +256,35 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
            "These counters measure L2-to-fabric traffic, which includes Infinity Cache (MALL) hits,",
            "so they bound DRAM bytes from above."]
     open(os.path.join(out_dir, "traffic_sweep_sbm_nucleus34.md"), "w").write("\n".join(md) + "\n")
+
+    # preparation: every kernel that is neither a sweep nor a ceiling or copy
+    # kernel, by total time, with its scaled traffic per dispatch
+    skip = ("k_sweep_", "k_gather", "k_read", "k_copy", "__amd", "at::",
+            "k_incidence_original", "k_to_original")
+
+    def is_prep(r):
+        return not _short_kernel(r["Name"]).replace(
+            "(anonymous namespace)::", "").startswith(skip)
+
+    prep = [r for r in rows if is_prep(r)]
+    prep.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    pm = ["# Preparation kernels: time and HBM-side traffic ((3,4), block model)", "",
+          "Per dispatch, from the same three runs as the sweep's traffic record: the kernel-trace",
+          "average duration, FETCH_SIZE and WRITE_SIZE averaged over the dispatches and scaled",
+          f"by the 1 GiB copy (fetch x{fscale:.3f}, write x{wscale:.3f}), and their sum over the",
+          "duration. Each step (the warm-up and two timed) prepares the graph once.", "",
+          "| kernel | calls | avg ms | FETCH GB | WRITE GB | GB/s |", "|---|---:|---:|---:|---:|---:|"]
+    for r in prep[:16]:
+        name = _short_kernel(r["Name"])
+        avg_ms = float(r["AverageNs"]) / 1e6
+        fb = statistics.mean(fetch.get(name, [0.0])) * 1024 * fscale / 1e9
+        wb = statistics.mean(write.get(name, [0.0])) * 1024 * wscale / 1e9
+        pm.append(f"| `{name}` | {r['Calls']} | {avg_ms:.2f} | {fb:.2f} | {wb:.2f} | "
+                  f"{(fb + wb) / (avg_ms * 1e-3):.0f} |")
+    pm += ["", "Commands: the three of the sweep's traffic record, then "
+           "`python bench.py --summarize-profiles <trace stats csv> <fetch csv> <write csv>`:", "", "```",
+           _profile_command("--kernel-trace --stats", "kt"), *rec["commands"], "```"]
+    open(os.path.join(out_dir, "traffic_prep_sbm_nucleus34.md"), "w").write("\n".join(pm) + "\n")
     print(f"full sweep {full_avg:.0f} us; HBM-side {rec['hbm_bytes_per_sweep'] / 1e9:.2f} GB per sweep")
 
 
@@ -391,12 +420,7 @@ def full_sweep_roofline(g, kind, res, sweeps=None):
             "kappa": kfull, "res": rfull}
 
 
-def ceilings(nd, g, kind, tau_bytes):
-    """Streaming read, streaming copy and the sweep's gather pattern (its id
-    stream and tau gathers without the h-index) on this device, timed with
-    events on the current stream by libndceil.so."""
-    import torch
-
+def _ceiling_lib():
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_1704_00386_amd", "libndceil.so"))
     lib.ndc_read.restype = ctypes.c_float
     lib.ndc_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -408,14 +432,20 @@ def ceilings(nd, g, kind, tau_bytes):
     lib.ndc_gather.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                                ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                ctypes.c_void_p]
+    return lib
+
+
+def gather_ceiling(g, kind, tau_bytes):
+    """The gather pattern alone (the id stream and one tau gather per id, min
+    per s-clique, no h-index) over the incidence as exported: r-cliques in
+    their original order, ids original.  GB/s of (4 + tau bytes) per
+    incidence id, best of 3, timed with events on the current stream by
+    libndceil.so."""
+    import torch
+
+    lib = _ceiling_lib()
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     sink = torch.zeros(1, dtype=torch.int64, device="cuda")
-    nbytes = 8 << 30
-    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
-    b = torch.empty_like(a)
-    reads = [lib.ndc_read(a.data_ptr(), nbytes, sink.data_ptr(), st) for _ in range(3)]
-    copies = [lib.ndc_copy(a.data_ptr(), b.data_ptr(), nbytes, st) for _ in range(3)]
-    del a, b
     off, ids = g.incidence(kind)
     k = ids.shape[1]
     ds = g.sdegree(kind)
@@ -428,15 +458,35 @@ def ceilings(nd, g, kind, tau_bytes):
     del ids, tau
     torch.cuda.synchronize()
     gb = (4 + tau_bytes) * k * nsets
-    return {"read_GBs": nbytes / (min(reads) * 1e-3) / 1e9,
-            "copy_GBs": 2 * nbytes / (min(copies) * 1e-3) / 1e9,
-            "gather_GBs": gb / (min(gathers) * 1e-3) / 1e9,
-            "gather_bytes": gb, "gather_ms": min(gathers),
-            "what": "8 GiB streamed with 16-byte loads (read) and loads+stores "
-                    "(copy); the incidence ids (r-clique-id order, each "
-                    "workgroup streaming contiguous runs of 32768 lists) with one "
-                    f"{tau_bytes}-byte tau gather per id, min per s-clique "
-                    "(gather); best of 3 each"}
+    return {"gather_GBs": gb / (min(gathers) * 1e-3) / 1e9,
+            "gather_bytes": gb, "gather_ms": min(gathers)}
+
+
+def ceilings(nd, g, kind, tau_bytes):
+    """Streaming read, streaming copy and the sweep's gather pattern (its id
+    stream and tau gathers without the h-index) on this device, timed with
+    events on the current stream by libndceil.so."""
+    import torch
+
+    lib = _ceiling_lib()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nbytes = 8 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    reads = [lib.ndc_read(a.data_ptr(), nbytes, sink.data_ptr(), st) for _ in range(3)]
+    copies = [lib.ndc_copy(a.data_ptr(), b.data_ptr(), nbytes, st) for _ in range(3)]
+    del a, b, sink
+    torch.cuda.synchronize()
+    out = {"read_GBs": nbytes / (min(reads) * 1e-3) / 1e9,
+           "copy_GBs": 2 * nbytes / (min(copies) * 1e-3) / 1e9}
+    out.update(gather_ceiling(g, kind, tau_bytes))
+    out["what"] = ("8 GiB streamed with 16-byte loads (read) and loads+stores "
+                   "(copy); the incidence as exported (original r-clique order "
+                   "and ids, each workgroup streaming contiguous runs of 32768 "
+                   f"lists) with one {tau_bytes}-byte tau gather per id, min per "
+                   "s-clique (gather); best of 3 each")
+    return out
 
 
 def headline_leg(nd, ctx, args):
@@ -512,6 +562,16 @@ def workload_leg(nd, ctx, name, kind, quality=False):
                          "achieved_GBs": roof["achieved_GBs"],
                          "frac_of_hbm_peak": roof["achieved_GBs"] / HBM_PEAK_GBS,
                          "kappa_equals_frontier": bool(torch.equal(roof["kappa"], kappa))}
+    gc = gather_ceiling(g, kind, res["tau_bytes"])
+    out["full_sweep"]["gather_original_order_GBs"] = gc["gather_GBs"]
+    out["full_sweep"]["sweep_over_original_order_gather"] = (
+        roof["achieved_GBs"] / gc["gather_GBs"])
+    out["full_sweep"]["gather_what"] = (
+        "the gather pattern alone (ids and tau gathers, no h-index) over the "
+        "incidence in original r-clique order with original ids; the sweep "
+        "runs in the internal (sweep bin, id) numbering, which packs the "
+        "values of high-degree r-cliques together, so on power-law graphs it "
+        "beats this figure: a measure of what the layout gains, not a bound")
     if quality:
         nr = kappa.numel()
         snap = torch.empty(max(nr, 1), dtype=torch.int32, device="cuda")

@@ -39,26 +39,37 @@ __device__ __forceinline__ int bin_of(int64_t d) {
                   : kBinZero;
 }
 
-// Maximum degree and bin sizes: counts per thread in registers, then per
-// block in LDS, then one global atomic per block and bin (a handful of bins
-// would otherwise serialise every thread on the same LDS words).
+// Maximum degree and bin sizes: counts per thread in registers over a
+// grid-stride share, then per block in LDS, then one global atomic per block
+// and bin (atomics from every wave onto the same few words serialise).
+constexpr int kStatsBlocks = 4096;
+
 __global__ __launch_bounds__(256) void k_layout_stats(
     const int32_t *__restrict__ cnt, int64_t nr, int32_t *__restrict__ maxd,
     unsigned long long *__restrict__ bins) {
   __shared__ unsigned int h[kNumBins];
+  __shared__ int32_t hm;
   if (threadIdx.x < kNumBins) h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) hm = 0;
   __syncthreads();
   int32_t m = 0;
   unsigned int c[kNumBins];
 #pragma unroll
   for (int b = 0; b < kNumBins; b++) c[b] = 0;
-  const int64_t base = (int64_t)blockIdx.x * 256 * 8;
-  for (int j = 0; j < 8; j++) {
-    const int64_t i = base + j * 256 + threadIdx.x;
-    if (i < nr) {
-      const int32_t d = cnt[i];
-      m = max(m, d);
-      const int bd = bin_of(d);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x; i0 < nr;
+       i0 += 4 * stride) {
+    int32_t d[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t i = i0 + j * stride;
+      d[j] = i < nr ? cnt[i] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      if (d[j] < 0) continue;
+      m = max(m, d[j]);
+      const int bd = bin_of(d[j]);
 #pragma unroll
       for (int b = 0; b < kNumBins; b++) c[b] += bd == b;
     }
@@ -71,10 +82,11 @@ __global__ __launch_bounds__(256) void k_layout_stats(
     if (lane_id() == 0 && v) atomicAdd(&h[b], v);
   }
   for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
-  if (lane_id() == 0) atomicMax(maxd, m);
+  if (lane_id() == 0) atomicMax(&hm, m);
   __syncthreads();
   if (threadIdx.x < kNumBins && h[threadIdx.x])
     atomicAdd(&bins[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+  if (threadIdx.x == kNumBins) atomicMax(maxd, hm);
 }
 
 // Sort key: sweep bin, then ascending id.
@@ -162,8 +174,9 @@ void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
   fill_i32(maxd.p, 0, 1, s);
   fill_u64((uint64_t *)bins.p, 0, kNumBins, s);
   if (nr > 0) {
-    k_layout_stats<<<grid_for(nr, 256 * 8), 256, 0, s>>>(cnt, nr, maxd.p,
-                                                          bins.p);
+    const unsigned grid =
+        (unsigned)std::min<int64_t>(grid_for(nr, 256 * 4), kStatsBlocks);
+    k_layout_stats<<<grid, 256, 0, s>>>(cnt, nr, maxd.p, bins.p);
     ND_LAUNCHED();
   }
   PinnedChunk pc;
