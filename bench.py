@@ -52,6 +52,7 @@ HEADLINE = "sbm"
 HEADLINE_KIND = "nucleus34"
 STREAM_BUDGET = 96 << 30  # device-memory budget of the served stream
 K_OF = {"core": 1, "truss": 2, "nucleus34": 3}
+TAU_CTYPE = {1: "u8", 2: "u16", 4: "i32"}
 
 
 def progress(msg: str) -> None:
@@ -191,7 +192,8 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
              "SND with the notification frontier until exact), the full-sweep roofline leg (4 SND",
              "sweeps recomputing every r-clique), AND with the frontier, and the ceiling kernels.",
              "`k_sweep_small<k, tau type, AND, frontier>` sweeps the bins of at most 16 values per",
-             "lane (d_s 1..1024) in one launch; `<3, unsigned short, false, false>` is the full sweep.", "",
+             "lane (d_s 1..1024) in one launch; `<3, unsigned char, false, false>` is the full sweep",
+             "(tau in 8 bits: every d_s of this workload is below 256).", "",
              "| % | calls | total ms | avg us | kernel |", "|---:|---:|---:|---:|---|"]
     full_avg = 0.0
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:36]:
@@ -449,11 +451,12 @@ def gather_ceiling(g, kind, tau_bytes):
     off, ids = g.incidence(kind)
     k = ids.shape[1]
     ds = g.sdegree(kind)
-    tau = ds.to(torch.int16) if tau_bytes == 2 else ds
+    tau = {1: torch.uint8, 2: torch.int16, 4: torch.int32}[tau_bytes]
+    tau = ds.to(tau)
     del off
     nsets = ids.shape[0]
     gathers = [lib.ndc_gather(ids.data_ptr(), nsets, k, tau.data_ptr(),
-                              0 if tau_bytes == 2 else 1, sink.data_ptr(), st)
+                              tau_bytes, sink.data_ptr(), st)
                for _ in range(3)]
     del ids, tau
     torch.cuda.synchronize()
@@ -977,7 +980,8 @@ def main():
                      "frac": roof["achieved_GBs"] / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": "full sweep: one application of U to every "
-                               "r-clique with d_s > 0 (k_sweep_small<3, u16>)",
+                               "r-clique with d_s > 0 (k_sweep_small<3, "
+                               f"{TAU_CTYPE[res['tau_bytes']]}>)",
                      "bytes_per_launch": roof["bytes_per_sweep"],
                      "avg_launch_ms": roof["avg_sweep_ms"],
                      "sweeps_timed": roof["sweeps_timed"]},

@@ -165,8 +165,9 @@ typedef struct {
   double ms_prep;      /* device time of prepare work done by this call */
   double ms_iterate;   /* device time of the sweeps */
   int32_t max_sdegree; /* max over R of d_s(R) */
-  int32_t tau_bytes;   /* bytes per stored tau value (2 when every d_s fits
-                          in 15 bits, else 4) */
+  int32_t tau_bytes;   /* bytes per stored tau value: for one graph 1 when
+                          every d_s is below 256, 2 below 32768, else 4;
+                          in batches and the server 2 or 4 */
 } nd_result;
 
 /* ------------------------------------------------------------ context */

@@ -807,9 +807,9 @@ nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
       pout = dout.p;
     }
     check_tau_range(g, ks, pin, s);
-    const size_t tb = ks.tau16 ? 2 : 4;
+    const size_t tb = (size_t)ks.tau_bytes;
     DArr<uint8_t> ta(al, (int64_t)(tb * ks.nr)), tbuf(al, (int64_t)(tb * ks.nr));
-    to_internal(ks, pin, ta.p, ks.tau16, s);
+    to_internal(ks, pin, ta.p, ks.tau_bytes, s);
     DArr<SweepStats> st(al, 1);
     ND_HIP(hipMemsetAsync(st.p, 0, sizeof(SweepStats), s));
     SweepArgs a{};
@@ -821,7 +821,7 @@ nd_status nd_update(nd_graph *g, nd_kind kind, const int32_t *tau_in,
     a.prev = nullptr;
     a.cap_by_tau = 0;
     launch_sweep(ks, a, false, s);
-    to_original(ks, tbuf.p, ks.tau16, pout, s);
+    to_original(ks, tbuf.p, ks.tau_bytes, pout, s);
     if (!on_device)
       ND_HIP(hipMemcpyAsync(tau_out, pout, sizeof(int32_t) * ks.nr, hipMemcpyDeviceToHost, s));
     ND_HIP(hipStreamSynchronize(s));

@@ -394,7 +394,7 @@ void Batch::init_member_tau(Member &m) {
   const KindState &ks = m.g->ks[kind_];
   if (ks.nr == 0) return;
   if (tau16_)
-    init_tau(ks, m.tau0.p, s_);  // ks.tau16 holds (checked in add)
+    init_tau(ks, m.tau0.p, 2, s_);  // ks.tau16 holds (checked in add)
   else
     ND_HIP(hipMemcpyAsync(m.tau0.p, ks.ds.p, sizeof(int32_t) * ks.nr,
                           hipMemcpyDeviceToDevice, s_));
@@ -1097,10 +1097,10 @@ nd_status batch_decompose(nd_ctx *ctx, int32_t count, nd_graph *const *graphs,
     if (ks.nr > 0) {
       ND_REQUIRE(kappas && kappas[i], ND_ERR_INVALID, "kappas[%d] is NULL", i);
       if (on_device) {
-        to_original(ks, bt.result_tau(m), bt.tau16(), kappas[i], bs);
+        to_original(ks, bt.result_tau(m), bt.tau16() ? 2 : 4, kappas[i], bs);
       } else {
         DArr<int32_t> tmp(ctx->alloc, ks.nr);
-        to_original(ks, bt.result_tau(m), bt.tau16(), tmp.p, bs);
+        to_original(ks, bt.result_tau(m), bt.tau16() ? 2 : 4, tmp.p, bs);
         ND_HIP(hipMemcpyAsync(kappas[i], tmp.p, sizeof(int32_t) * ks.nr,
                               hipMemcpyDeviceToHost, bs));
         ND_HIP(hipStreamSynchronize(bs));

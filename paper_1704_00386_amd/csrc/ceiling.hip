@@ -7,7 +7,7 @@
 //                 read bandwidth;
 //   ndc_copy      copies n bytes (16-byte loads and stores);
 //   ndc_gather    for every s-clique j: min over its k listed ids of tau[id]
-//                 (tau 16- or 32-bit), summed -- the id stream and the random
+//                 (tau 8-, 16- or 32-bit), summed -- the id stream and the random
 //                 tau gathers of one sweep without the h-index: the ceiling of
 //                 the gather pattern itself.  Each workgroup takes contiguous
 //                 runs of the id stream (the mapping of the update kernel's
@@ -20,6 +20,8 @@
 // The sums go to *sink so that no load is optimised away.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace {
 
@@ -93,6 +95,11 @@ float timed(hipStream_t s, F &&launch) {
   return ms;
 }
 
+template <typename T>
+struct Tag {
+  using type = T;
+};
+
 unsigned grid_of(int64_t items, int cus) {
   const int64_t g = (items + kThreads - 1) / kThreads;
   const int64_t cap = (int64_t)cus * 32;
@@ -132,24 +139,30 @@ float ndc_copy(const void *src, void *dst, int64_t bytes, void *stream) {
   });
 }
 
-// ids[k * nsets] (every id a valid index of tau), tau 16-bit (tau32 = 0) or
-// 32-bit; k in {1, 2, 3}.
+// ids[k * nsets] (every id a valid index of tau), tau of tau_bytes 1, 2 or
+// 4 bytes per value (8- and 16-bit unsigned, 32-bit signed); k in {1, 2, 3}.
 float ndc_gather(const int32_t *ids, int64_t nsets, int k, const void *tau,
-                 int tau32, unsigned long long *sink, void *stream) {
+                 int tau_bytes, unsigned long long *sink, void *stream) {
   if (!ids || !tau || !sink || nsets < 1 || k < 1 || k > 3) return -1;
+  if (tau_bytes != 1 && tau_bytes != 2 && tau_bytes != 4) return -1;
   hipStream_t s = (hipStream_t)stream;
   const int64_t runs = (nsets + kGatherRun - 1) / kGatherRun;
   const int64_t cap = (int64_t)num_cus() * 8;
   const unsigned grid = (unsigned)(runs < cap ? runs : cap);
+  auto go = [&](auto kc, auto tc) {
+    constexpr int K = decltype(kc)::value;
+    using T = typename decltype(tc)::type;
+    k_gather<K, T><<<grid, kThreads, 0, s>>>(ids, nsets, (const T *)tau, sink);
+  };
+  auto by_type = [&](auto kc) {
+    if (tau_bytes == 1) go(kc, Tag<uint8_t>{});
+    else if (tau_bytes == 2) go(kc, Tag<uint16_t>{});
+    else go(kc, Tag<int32_t>{});
+  };
   return timed(s, [&] {
-    switch (k * 2 + (tau32 ? 1 : 0)) {
-      case 2: k_gather<1, uint16_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const uint16_t *)tau, sink); break;
-      case 3: k_gather<1, int32_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const int32_t *)tau, sink); break;
-      case 4: k_gather<2, uint16_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const uint16_t *)tau, sink); break;
-      case 5: k_gather<2, int32_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const int32_t *)tau, sink); break;
-      case 6: k_gather<3, uint16_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const uint16_t *)tau, sink); break;
-      default: k_gather<3, int32_t><<<grid, kThreads, 0, s>>>(ids, nsets, (const int32_t *)tau, sink); break;
-    }
+    if (k == 1) by_type(std::integral_constant<int, 1>{});
+    else if (k == 2) by_type(std::integral_constant<int, 2>{});
+    else by_type(std::integral_constant<int, 3>{});
   });
 }
 

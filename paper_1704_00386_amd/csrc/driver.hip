@@ -140,7 +140,7 @@ LoopLayout loop_layout(const KindState &ks, const nd_opts &o, bool flags,
                        bool on_device, int ring_len) {
   const int64_t nr = ks.nr;
   LoopLayout L{};
-  L.tau = round256((ks.tau16 ? 2 : 4) * nr);
+  L.tau = round256(ks.tau_bytes * nr);
   L.ntau = o.mode == ND_AND ? 1 : 2;
   L.flags = flags ? round256(nr) : 0;
   L.sums = flags ? round256((nr + (1 << dev::kGroupShift) - 1) >> dev::kGroupShift) : 0;
@@ -164,8 +164,8 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
   const bool frontier = opts.use_frontier != 0;
   const bool indicator = wants_indicator(opts, fixed_set != nullptr);
   const bool flags = frontier || indicator;
-  const int64_t tbytes = (ks.tau16 ? 2 : 4) * nr;
-  init_tau(ks, b.tau[0], s);
+  const int64_t tbytes = ks.tau_bytes * nr;
+  init_tau(ks, b.tau[0], ks.tau_bytes, s);
   if (!and_mode)
     ND_HIP(hipMemcpyAsync(b.tau[1], b.tau[0], tbytes, hipMemcpyDeviceToDevice, s));
   const int64_t ng = (nr + (1 << dev::kGroupShift) - 1) >> dev::kGroupShift;
@@ -268,7 +268,7 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
       if (opts.on_iter &&
           (opts.snapshot_every <= 1 || (j + 1) % opts.snapshot_every == 0 ||
            last)) {
-        to_original(ks, b.tau[(j + 1) & 1], ks.tau16, b.snap, s);
+        to_original(ks, b.tau[(j + 1) & 1], ks.tau_bytes, b.snap, s);
         ND_HIP(hipStreamSynchronize(s));
         nd_iter_info info{};
         info.iter = (int32_t)(j + 1);
@@ -301,9 +301,9 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
   const void *result = b.tau[sweeps & 1];
   Phase out_phase("nd.output");
   if (on_device) {
-    to_original(ks, result, ks.tau16, kappa, s);
+    to_original(ks, result, ks.tau_bytes, kappa, s);
   } else {
-    to_original(ks, result, ks.tau16, b.stage, s);
+    to_original(ks, result, ks.tau_bytes, b.stage, s);
     ND_HIP(hipMemcpyAsync(kappa, b.stage, sizeof(int32_t) * nr,
                           hipMemcpyDeviceToHost, s));
   }
@@ -321,7 +321,7 @@ nd_result result_head(const KindState &ks, bool was_ready) {
   r.n_incidence = ks.P;
   r.ms_prep = was_ready ? 0.0 : ks.ms_prep;
   r.max_sdegree = ks.max_ds;
-  r.tau_bytes = ks.tau16 ? 2 : 4;
+  r.tau_bytes = ks.tau_bytes;
   return r;
 }
 

@@ -164,6 +164,9 @@ struct KindState {
   int64_t bin_lo[kNumBins] = {0}, bin_hi[kNumBins] = {0};
   int32_t max_ds = 0;
   bool tau16 = false;       // tau fits uint16 (max d_s < 32768)
+  // bytes per tau value in the one-graph sweeps: 1 (max d_s < 256), 2 or 4
+  // (batches and the server hold 2 or 4, by tau16)
+  int tau_bytes = 4;
   double ms_prep = 0;
   size_t bytes() const;
 };
@@ -271,17 +274,18 @@ void build_incidence_n24(nd_graph *g, KindState &ks, hipStream_t s);
 // From S-degrees in r-clique-id order: perm, inv, ds, inc_off, bins.
 void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
                   hipStream_t s);
-// Re-index between internal and r-clique-id order.
-void to_internal(const KindState &ks, const int32_t *in, void *out, bool out16,
+// Re-index between internal and r-clique-id order; the internal side holds
+// `bytes` (1, 2 or 4) per value.
+void to_internal(const KindState &ks, const int32_t *in, void *out, int bytes,
                  hipStream_t s);
-void to_original(const KindState &ks, const void *in, bool in16, int32_t *out,
+void to_original(const KindState &ks, const void *in, int bytes, int32_t *out,
                  hipStream_t s);
 // Incidence lists in r-clique-id order with r-clique ids (off[nr+1]).
 void incidence_original(nd_graph *g, const KindState &ks, int64_t *off,
                         int32_t *ids, hipStream_t s);
 void sdegree_original(const KindState &ks, int32_t *ds, hipStream_t s);
-// tau_0 = d_s in the internal numbering and tau type.
-void init_tau(const KindState &ks, void *tau, hipStream_t s);
+// tau_0 = d_s in the internal numbering, `bytes` (1, 2 or 4) per value.
+void init_tau(const KindState &ks, void *tau, int bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- sweeps
 

@@ -151,14 +151,15 @@ __global__ void k_init_tau(const int32_t *__restrict__ ds, int64_t nr,
 
 }  // namespace
 
-void init_tau(const KindState &ks, void *tau, hipStream_t s) {
+void init_tau(const KindState &ks, void *tau, int bytes, hipStream_t s) {
   if (ks.nr == 0) return;
-  if (ks.tau16)
-    k_init_tau<uint16_t><<<grid_for(ks.nr, 256), 256, 0, s>>>(ks.ds.p, ks.nr,
-                                                              (uint16_t *)tau);
+  const unsigned grid = grid_for(ks.nr, 256);
+  if (bytes == 1)
+    k_init_tau<uint8_t><<<grid, 256, 0, s>>>(ks.ds.p, ks.nr, (uint8_t *)tau);
+  else if (bytes == 2)
+    k_init_tau<uint16_t><<<grid, 256, 0, s>>>(ks.ds.p, ks.nr, (uint16_t *)tau);
   else
-    k_init_tau<int32_t><<<grid_for(ks.nr, 256), 256, 0, s>>>(ks.ds.p, ks.nr,
-                                                             (int32_t *)tau);
+    k_init_tau<int32_t><<<grid, 256, 0, s>>>(ks.ds.p, ks.nr, (int32_t *)tau);
   ND_LAUNCHED();
 }
 
@@ -189,6 +190,7 @@ void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
   const int32_t hmax = *hmaxp;
   ks.max_ds = hmax;
   ks.tau16 = hmax < 32768;
+  ks.tau_bytes = hmax < 256 ? 1 : ks.tau16 ? 2 : 4;
   int64_t at = 0;
   for (int b = 0; b < kNumBins; b++) {
     ks.bin_lo[b] = at;
@@ -217,32 +219,34 @@ void build_layout(nd_graph *g, KindState &ks, const int32_t *cnt,
   ks.P = read_i64(ks.inc_off.p + nr, s);
 }
 
-void to_internal(const KindState &ks, const int32_t *in, void *out, bool out16,
+void to_internal(const KindState &ks, const int32_t *in, void *out, int bytes,
                  hipStream_t s) {
   if (ks.nr == 0) return;
-  if (out16)
-    k_to_internal<uint16_t><<<grid_for(ks.nr, 256), 256, 0, s>>>(
-        in, ks.perm.p, ks.nr, (uint16_t *)out);
+  const unsigned grid = grid_for(ks.nr, 256);
+  if (bytes == 1)
+    k_to_internal<uint8_t><<<grid, 256, 0, s>>>(in, ks.perm.p, ks.nr, (uint8_t *)out);
+  else if (bytes == 2)
+    k_to_internal<uint16_t><<<grid, 256, 0, s>>>(in, ks.perm.p, ks.nr, (uint16_t *)out);
   else
-    k_to_internal<int32_t><<<grid_for(ks.nr, 256), 256, 0, s>>>(
-        in, ks.perm.p, ks.nr, (int32_t *)out);
+    k_to_internal<int32_t><<<grid, 256, 0, s>>>(in, ks.perm.p, ks.nr, (int32_t *)out);
   ND_LAUNCHED();
 }
 
-void to_original(const KindState &ks, const void *in, bool in16, int32_t *out,
+void to_original(const KindState &ks, const void *in, int bytes, int32_t *out,
                  hipStream_t s) {
   if (ks.nr == 0) return;
-  if (in16)
-    k_to_original<uint16_t><<<grid_for(ks.nr, 256), 256, 0, s>>>(
-        (const uint16_t *)in, ks.inv.p, ks.nr, out);
+  const unsigned grid = grid_for(ks.nr, 256);
+  if (bytes == 1)
+    k_to_original<uint8_t><<<grid, 256, 0, s>>>((const uint8_t *)in, ks.inv.p, ks.nr, out);
+  else if (bytes == 2)
+    k_to_original<uint16_t><<<grid, 256, 0, s>>>((const uint16_t *)in, ks.inv.p, ks.nr, out);
   else
-    k_to_original<int32_t><<<grid_for(ks.nr, 256), 256, 0, s>>>(
-        (const int32_t *)in, ks.inv.p, ks.nr, out);
+    k_to_original<int32_t><<<grid, 256, 0, s>>>((const int32_t *)in, ks.inv.p, ks.nr, out);
   ND_LAUNCHED();
 }
 
 void sdegree_original(const KindState &ks, int32_t *ds, hipStream_t s) {
-  to_original(ks, ks.ds.p, false, ds, s);
+  to_original(ks, ks.ds.p, 4, ds, s);
 }
 
 void incidence_original(nd_graph *g, const KindState &ks, int64_t *off,

@@ -497,10 +497,10 @@ nd_status levels(nd_graph *g, nd_kind kind, int32_t *level_out,
              hc ? (long long)hc->alive : (long long)nr);
   *num_levels = hc->level;
   if (on_device) {
-    to_original(ks, lvl.p, false, level_out, s);
+    to_original(ks, lvl.p, 4, level_out, s);
   } else {
     DArr<int32_t> o(al, nr);
-    to_original(ks, lvl.p, false, o.p, s);
+    to_original(ks, lvl.p, 4, o.p, s);
     ND_HIP(hipMemcpyAsync(level_out, o.p, sizeof(int32_t) * nr,
                           hipMemcpyDeviceToHost, s));
   }

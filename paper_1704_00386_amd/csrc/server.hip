@@ -180,7 +180,7 @@ void retire(nd_server *srv, Batch &b, std::unique_ptr<Member> m) {
       r->host = take_pinned(srv, bytes, &r->host_cap);
       r->n_result = ks.nr;
       DArr<int32_t> tmp(srv->ctx->alloc, ks.nr);
-      to_original(ks, b.result_tau(*m), b.tau16(), tmp.p, b.stream());
+      to_original(ks, b.result_tau(*m), b.tau16() ? 2 : 4, tmp.p, b.stream());
       ND_HIP(hipMemcpyAsync(r->host, tmp.p, bytes, hipMemcpyDeviceToHost,
                             b.stream()));
       ND_HIP(hipEventCreateWithFlags(&r->copied, hipEventDisableTiming));

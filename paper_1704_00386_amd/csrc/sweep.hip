@@ -480,7 +480,9 @@ void launch_typed(const KindState &ks, const SweepArgs &a, bool and_mode,
 
 void launch_sweep(const KindState &ks, const SweepArgs &a, bool and_mode,
                   hipStream_t s) {
-  if (ks.tau16)
+  if (ks.tau_bytes == 1)
+    launch_typed<uint8_t>(ks, a, and_mode, s);
+  else if (ks.tau_bytes == 2)
     launch_typed<uint16_t>(ks, a, and_mode, s);
   else
     launch_typed<int32_t>(ks, a, and_mode, s);

@@ -1,5 +1,5 @@
 // sweep_dev.h -- device routines of one h-index update, shared by the
-// single-graph sweep kernels (sweep.hip) and the batched persistent kernel
+// single-graph sweep kernels (sweep.hip) and the batched tile kernel
 // (batch.hip).  See sweep.hip for the method and the exactness argument.
 #pragma once
 

@@ -113,9 +113,10 @@ def test_noalloc_errors(nd, ctx):
                                   ctypes.c_void_p(out.data_ptr()), 1, None,
                                   ctypes.byref(res))
     assert st == 1 and b"nd_prepare" in lib.nd_last_error()
-    # 24M isolated vertices: SND needs 2 x 48 MB of tau (fits the 128 MiB
-    # workspace); with the frontier's flags (+48 MB) it does not
-    n = 24 << 20
+    # 48M isolated vertices (every d_s 0: 8-bit tau): SND needs 2 x 48 MiB
+    # of tau (fits the 128 MiB workspace); with the frontier's flags
+    # (+96 MiB) it does not
+    n = 48 << 20
     e = torch.zeros(0, dtype=torch.int32)
     gb = nd.Graph.from_edges(ctx, n, e, e)
     gb.prepare("core")
