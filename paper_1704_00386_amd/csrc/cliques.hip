@@ -938,6 +938,7 @@ struct N34VLds {
   int32_t len[D];      // |N(nb[i])|
   int64_t ro[D];       // row_off[nb[i]]
   int32_t pre[D + 1];  // exclusive prefix: bit-row work, then triangles
+  int32_t st[D];       // count pass: where row i's walk of N(nb[i]) starts
   uint32_t A[D][D / 32];
   int64_t tb[D];       // toff of edge (p, nb[i]), i >= nl
   // fill pass: one chunk of up to 64 triangles with their lists (base,
@@ -1075,25 +1076,43 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
     }
     wave_lds_sync();
     if (!reuse) {
-      // bit rows: a short row walks N(nb[i]) and finds each entry in nb; a
-      // long one (a hub's) looks each nb[q] up in N(nb[i]) instead
-      for (int i = lane; i < d; i += kWave)
-        L.pre[i] = L.len[i] <= 4 * d ? L.len[i] : d;
+      // bit rows, which are symmetric: each pair i < q is looked at once,
+      // from row i, and sets both bits.  A short row walks the part of
+      // N(nb[i]) between nb[i] and the largest neighbour of p, finding each
+      // entry among nb above i; a long one (a hub's) looks each nb[q], q > i,
+      // up in N(nb[i]) instead.
+      const int32_t top = L.nb[d - 1];
+      for (int i = lane; i < d; i += kWave) {
+        int32_t w = d - 1 - i;
+        if (L.len[i] <= 4 * d) {
+          const int64_t e1 = L.ro[i] + L.len[i];
+          const int64_t b = lower_bound<int32_t>(T.col, L.ro[i], e1, L.nb[i] + 1);
+          const int64_t e = lower_bound<int32_t>(T.col, b, e1, top + 1);
+          L.st[i] = (int32_t)(b - L.ro[i]);
+          w = (int32_t)(e - b);
+        }
+        L.pre[i] = w;
+      }
       wave_lds_sync();
       wave_scan_lds(L.pre, d);
       const int32_t work = L.pre[d];
       for (int32_t t = lane; t < work; t += kWave) {
         const int i = row_of(L.pre, d, t);
         const int r = t - L.pre[i];
+        int q = d;
         if (L.len[i] <= 4 * d) {
-          const int32_t z = T.col[L.ro[i] + r];
-          const int q = (int)lower_bound<int32_t>(L.nb, 0, d, z);
-          if (q < d && L.nb[q] == z) atomicOr(&L.A[i][q >> 5], 1u << (q & 31));
+          const int32_t z = T.col[L.ro[i] + L.st[i] + r];
+          q = (int)lower_bound<int32_t>(L.nb, i + 1, d, z);
+          if (q < d && L.nb[q] != z) q = d;
         } else {
-          const int32_t z = L.nb[r];
+          const int32_t z = L.nb[i + 1 + r];
           const int64_t e1 = L.ro[i] + L.len[i];
-          const int64_t q = lower_bound<int32_t>(T.col, L.ro[i], e1, z);
-          if (q < e1 && T.col[q] == z) atomicOr(&L.A[i][r >> 5], 1u << (r & 31));
+          const int64_t pos = lower_bound<int32_t>(T.col, L.ro[i], e1, z);
+          if (pos < e1 && T.col[pos] == z) q = i + 1 + r;
+        }
+        if (q < d) {
+          atomicOr(&L.A[i][q >> 5], 1u << (q & 31));
+          atomicOr(&L.A[q][i >> 5], 1u << (i & 31));
         }
       }
       wave_lds_sync();
