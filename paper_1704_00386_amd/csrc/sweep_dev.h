@@ -390,9 +390,9 @@ __device__ __forceinline__ bool update_regs(const int64_t *__restrict__ inc_off,
 
 // Sparse sweep of the r-cliques [lo, hi) of one bin of G lanes per
 // r-clique, the frontier's flags being valid.  The calling wave (number
-// `wave` of `nwaves`) runs only flagged r-cliques, 64/G at a time, the t-th
-// flagged lane of a ballot found by nth_set_bit; skipped ones need no write
-// (see update_regs).  It finds them either through the group summaries
+// `wave` of `nwaves`) runs only flagged r-cliques, 64/G at a time, found
+// through ballots (nth_set_bit); skipped ones need no write (see
+// update_regs).  It finds them either through the group summaries
 // (act_sum: one stamp per 64 r-cliques, for the big bins, G <= 4: a step
 // tests 64 groups, then loads the flags of flagged groups only), or by
 // loading the flags of kU chunks of kChunk consecutive r-cliques at once
@@ -409,14 +409,18 @@ __device__ __forceinline__ void sweep_sparse(
     const uint8_t *act_sum = nullptr, uint8_t *sum_next = nullptr) {
   constexpr int kPerWave = kWave / G;
   const int sub = lane_id() / G;
-  // runs the flagged r-cliques of mask m (bit i: r-clique cb + i), 64/G at a
-  // time
-  auto run = [&](uint64_t m, int64_t cb) {
-    const int na = __popcll(m);
-    for (int r0 = 0; r0 < na; r0 += kPerWave) {  // uniform over the wave
+  const int lane = lane_id();
+  // The flagged r-cliques found are queued, one per lane (lane l holds the
+  // l-th), and run 64/G at a time when the queue is full or the share ends,
+  // so that a group or chunk with one flagged r-clique does not take a whole
+  // step of the wave.
+  int64_t pend = 0;  // this lane's queued r-clique
+  int np = 0;        // queued r-cliques (uniform)
+  auto flush = [&]() {
+    for (int r0 = 0; r0 < np; r0 += kPerWave) {  // uniform over the wave
       const int t = r0 + sub;
-      const bool has = t < na;
-      const int64_t R = cb + (has ? nth_set_bit(m, t) : 0);
+      const bool has = t < np;
+      const int64_t R = __shfl(pend, has ? t : 0, kWave);
       bool ev;
       const bool changed = update_regs<K, G, M, T, AND, true>(
           inc_off, inc_ids, tin, tout, cap_by_tau, R, has, nullptr, act_next,
@@ -424,6 +428,16 @@ __device__ __forceinline__ void sweep_sparse(
       *n_ch += __popcll(ballot(changed));
       *n_ev += __popcll(ballot(ev));
     }
+    np = 0;
+  };
+  // queues the flagged r-cliques of mask m (bit i: r-clique cb + i), running
+  // the queue first when they would take it past `cap`
+  auto queue = [&](uint64_t m, int64_t cb, int cap) {
+    const int na = __popcll(m);
+    if (np + na > cap) flush();
+    const int slot = lane - np;  // the slot-th flagged r-clique of m
+    if (slot >= 0 && slot < na) pend = cb + nth_set_bit(m, slot);
+    np += na;
   };
   if (G <= 4 && act_sum != nullptr) {
     // Big bins: test 64 group summaries per step (one lane each), then the
@@ -432,18 +446,21 @@ __device__ __forceinline__ void sweep_sparse(
     const int64_t g_lo = lo >> kGroupShift;
     const int64_t g_hi = (hi + (1 << kGroupShift) - 1) >> kGroupShift;
     for (int64_t gb = g_lo + wave * kWave; gb < g_hi; gb += nwaves * kWave) {
-      const int64_t gi = gb + lane_id();
+      const int64_t gi = gb + lane;
       uint64_t gm = ballot(gi < g_hi && act_sum[gi] == stamp);
       while (gm) {  // uniform over the wave
         const int q = __ffsll((unsigned long long)gm) - 1;
         gm &= gm - 1;
         const int64_t cb = (gb + q) << kGroupShift;
-        const int64_t Rl = cb + lane_id();
-        run(ballot(Rl >= lo && Rl < hi && act[Rl] == stamp), cb);
+        const int64_t Rl = cb + lane;
+        queue(ballot(Rl >= lo && Rl < hi && act[Rl] == stamp), cb, kWave);
       }
     }
+    if (np > 0) flush();
     return;
   }
+  // At most 8 rounds of r-cliques per chunk and per queue, so that a run of
+  // flagged hubs is not serialised on one wave for long.
   constexpr int kChunk = kPerWave * 8 < kWave ? kPerWave * 8 : kWave;
   // Several chunks per step only where a chunk is narrow work (G <= 4: the
   // big bins, where the flag scan dominates a sparse sweep); for wide
@@ -455,12 +472,14 @@ __device__ __forceinline__ void sweep_sparse(
     bool on[kU];
 #pragma unroll
     for (int u = 0; u < kU; u++) {
-      const int64_t Rl = base + (int64_t)u * kChunk + lane_id();
-      on[u] = lane_id() < kChunk && Rl < hi && act[Rl] == stamp;
+      const int64_t Rl = base + (int64_t)u * kChunk + lane;
+      on[u] = lane < kChunk && Rl < hi && act[Rl] == stamp;
     }
 #pragma unroll
-    for (int u = 0; u < kU; u++) run(ballot(on[u]), base + (int64_t)u * kChunk);
+    for (int u = 0; u < kU; u++)
+      queue(ballot(on[u]), base + (int64_t)u * kChunk, kChunk);
   }
+  if (np > 0) flush();
 }
 
 // Bins hist[0..nb) count values, bin i standing for the value x0 + i*scale.
