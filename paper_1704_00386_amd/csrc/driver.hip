@@ -36,9 +36,17 @@ static_assert(kMaxChunk < kStaticRing && kStaticRing <= kHostStatsRing &&
               "a chunk and its predecessor must fit every counter ring");
 constexpr int kGridPerCu = 64;    // sweep workgroups per CU (they stride;
                                   // measured best of 8..64 and uncapped)
-constexpr int kGridPerCuFrontier = 40;  // with the frontier: mostly sparse
-                                        // sweeps, where fewer workgroups
-                                        // scan the flags sooner (24..64)
+
+// Sweep workgroups per CU with the frontier (mostly sparse sweeps): about
+// one wave per 4096 swept r-cliques (a wave's step of 64 flag groups), so
+// that many short workgroups balance clustered flagged sets on big graphs,
+// and few on small ones, where idle waves only add scheduling.  Measured
+// per-CU grids of 16..384: the (3,4) block model (4.2e8 swept) best at 96,
+// the Chung-Lu k-truss (8.6e6) and k-core (8.4e6) at 16..24.
+int grid_per_cu_frontier(int64_t swept, int num_cu) {
+  const int64_t waves_per_cu = swept / 4096 / std::max(num_cu, 1);
+  return (int)std::min<int64_t>(96, std::max<int64_t>(16, waves_per_cu / 4));
+}
 
 // Zero the counters of sweeps first .. first+count-1 (a kernel, not a
 // memset, so that the sequence stays capturable).
@@ -187,6 +195,8 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
   }
   SweepStats *hst = (SweepStats *)ctx->host_stats;
   const int ring_len = b.ring_len;
+  const int grid_per_cu =
+      frontier ? grid_per_cu_frontier(ks.bin_lo[kBinZero], ctx->num_cu) : kGridPerCu;
   const bool step_by_step = opts.on_iter != nullptr || opts.stop_active_ratio > 0;
   int chunk = step_by_step ? 1 : 2;
   int64_t t = 0;  // sweeps enqueued
@@ -221,7 +231,7 @@ nd_status sweep_loop(nd_graph *g, const KindState &ks, nd_opts opts,
       a.stats = b.ring + (t % ring_len);
       a.prev = t > 0 ? b.ring + ((t - 1) % ring_len) : nullptr;
       a.cap_by_tau = 1;
-      a.grid_cap = ctx->num_cu * (frontier ? kGridPerCuFrontier : kGridPerCu);
+      a.grid_cap = ctx->num_cu * grid_per_cu;
       if (flags) {
         a.act = b.act[t & 1];
         a.act_next = b.act[(t + 1) & 1];
