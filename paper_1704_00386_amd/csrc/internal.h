@@ -351,6 +351,11 @@ struct SweepArgs {
   // At most this many workgroups per lanes-per-r-clique kernel (they stride
   // over the rest of the bin); 0: one pass, no cap.
   int grid_cap;
+  // Nonzero: a notifying sweep whose previous sweep changed at least this
+  // many r-cliques writes flags but no group summaries (many of its
+  // notifications would store the same summary byte); launch_group_sums
+  // rebuilds them after it from the flags.
+  unsigned long long sums_after;
 };
 
 // The static device workspace of nd_decompose_noalloc: one array per device
@@ -363,9 +368,12 @@ void *noalloc_workspace(int device);
 constexpr int kHostStatsRing = 1024;
 
 // Launch one sweep over every bin of ks (internal numbering, tau of
-// ks.tau16 ? uint16 : int32).  `and_mode` selects in-place reads.
+// ks.tau_bytes per value).  `and_mode` selects in-place reads.
 void launch_sweep(const KindState &ks, const SweepArgs &a, bool and_mode,
                   hipStream_t s);
+// After the sweep of a (same arguments): the group summaries of the flags it
+// wrote, when a.sums_after made it skip them; nothing otherwise.
+void launch_group_sums(const KindState &ks, const SweepArgs &a, hipStream_t s);
 
 // Host threads (each with a stream) that build or prepare several graphs
 // at once: 2, or ND_PREP_THREADS.
