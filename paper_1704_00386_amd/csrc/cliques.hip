@@ -932,25 +932,31 @@ void run_n34_tri(TriIsectArgs a, bool fill, const int32_t *items,
 
 constexpr int kN34VMax = 256;  // largest degree of the per-vertex builder
 
-template <int D>
+// LDS of one wave of the per-vertex builder.  Each pass holds only its own
+// arrays (the other's shrink to one element): the workgroup is one wave, so
+// LDS per wave sets how many waves a CU keeps in flight, and both passes
+// wait on dependent loads.  Triangle ids fit 32 bits (at most 2^31 - 1
+// r-cliques).
+template <int D, bool FILL>
 struct N34VLds {
+  static constexpr int kC = FILL ? kWave : 1;  // fill-pass chunk arrays
   int32_t nb[D];
   int32_t len[D];      // |N(nb[i])|
   int64_t ro[D];       // row_off[nb[i]]
   int32_t pre[D + 1];  // exclusive prefix: bit-row work, then triangles
-  int32_t st[D];       // count pass: where row i's walk of N(nb[i]) starts
+  int32_t st[D];       // where row i's walk of N(nb[i]) starts (row build)
   uint32_t A[D][D / 32];
-  int64_t tb[D];       // toff of edge (p, nb[i]), i >= nl
+  int32_t tb[D];       // toff of edge (p, nb[i]), i >= nl
   // fill pass: one chunk of up to 64 triangles with their lists (base,
   // internal id, length), and for each the range of triangles of edge
   // (nb[i], nb[j]) in which its 4-cliques' remote triangles lie (found once
   // per triangle, not once per 4-clique)
-  int16_t ci[kWave], cj[kWave];
-  int64_t cb[kWave];
-  int32_t cv[kWave], cl[kWave];
-  int32_t coff[kWave + 1];
-  int64_t cs0[kWave];
-  int32_t cn[kWave];
+  int16_t ci[kC], cj[kC];
+  int64_t cb[kC];
+  int32_t cv[kC], cl[kC];
+  int32_t coff[FILL ? kWave + 1 : 1];
+  int32_t cs0[kC];
+  int32_t cn[kC];
 };
 
 // Exclusive prefix sums of v[0..n) in place, v[n] = total (one wave).
@@ -1051,7 +1057,7 @@ struct N34VArgs {
 template <int D, bool FILL>
 __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
   constexpr int W = D / 32;
-  __shared__ N34VLds<D> L;
+  __shared__ N34VLds<D, FILL> L;
   const int lane = lane_id();
   const TriIsectArgs &T = a.t;
   for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
@@ -1129,7 +1135,7 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
       if (i >= nl) {
         const int64_t e = e_lo + (i - nl);
         c = popc_and<W>(L.A[i], L.A[i], i + 1, d);
-        L.tb[i] = T.toff[e];
+        L.tb[i] = (int32_t)T.toff[e];
         bad |= (int64_t)c != T.toff[e + 1] - L.tb[i];
       }
       L.pre[i] = c;
@@ -1152,6 +1158,7 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
       }
       continue;
     }
+    if constexpr (FILL) {
     // fill: 64 triangles (i, j) at a time, then their 4-cliques (k > j)
     for (int32_t t0 = 0; t0 < nt; t0 += kWave) {
       const int32_t t = t0 + lane;
@@ -1190,7 +1197,7 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
       L.cb[lane] = rt.base;
       L.cv[lane] = rt.inv;
       L.cl[lane] = rt.len;
-      L.cs0[lane] = s0;
+      L.cs0[lane] = (int32_t)s0;
       L.cn[lane] = sn;
       L.coff[lane] = x - kc;
       if (lane == 0) L.coff[kWave] = nq;
@@ -1223,6 +1230,7 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
       }
       wave_lds_sync();  // before the next chunk overwrites ci .. coff
     }
+    }  // FILL
   }
 }
 
