@@ -1045,18 +1045,28 @@ struct N34VArgs {
   const int32_t *eid;
   const int32_t *nlow;
   const int64_t *eoff;
-  // the bit rows: written by the count pass, read back by the fill pass
-  // (NULL: the fill builds them again)
+  // the bit rows: written by the first pass that builds them, read back by
+  // the later ones (NULL: every pass builds its own)
   uint32_t *rows;
+  int rows_ready;        // rows already holds every vertex's rows
+  int32_t *tcnt;         // rows pass: triangles per edge (lowest edge)
+  int32_t *tw, *te;      // triangles pass: tri_w / tri_e of those edges
   TriIsectArgs t;        // triangle tables, outputs and error flag
 };
 
-// One wave per vertex p of degree <= D: the S-degrees and local counts of
-// the triangles whose lowest vertex is p (FILL = false), or the entries of
-// the 4-cliques whose lowest vertex is p (FILL = true).
-template <int D, bool FILL>
+// Passes of the per-vertex builder: the bit rows and each edge's triangle
+// count; the triangles themselves; the S-degrees and local counts of the
+// triangles; the 4-cliques' entries.
+constexpr int kVRows = 0, kVTris = 1, kVCount = 2, kVFill = 3;
+
+// One wave per vertex p of degree <= D, one pass (MODE) over the triangles
+// and 4-cliques whose lowest vertex is p: the bit rows (kept in a.rows) and
+// the triangle count of each of p's upper edges; the triangles of those
+// edges; the triangles' S-degrees and local counts; the 4-cliques' entries.
+template <int D, int MODE>
 __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
   constexpr int W = D / 32;
+  constexpr bool FILL = MODE == kVFill;
   __shared__ N34VLds<D, FILL> L;
   const int lane = lane_id();
   const TriIsectArgs &T = a.t;
@@ -1067,7 +1077,8 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
     const int nl = a.nlow[p];
     const int64_t e_lo = a.eoff[p];
     wave_lds_sync();  // the previous vertex's reads are done
-    const bool reuse = FILL && a.rows != nullptr;
+    const bool reuse = MODE == kVTris || (MODE == kVCount && a.rows_ready) ||
+                       (FILL && a.rows != nullptr);
     if (reuse) {
       for (int x = lane; x < d * W; x += kWave)
         L.A[x / W][x % W] = a.rows[base * kN34RowWords + x];
@@ -1122,9 +1133,14 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
         }
       }
       wave_lds_sync();
-      if (!FILL && a.rows != nullptr)  // keep them for the fill pass
+      if (!FILL && a.rows != nullptr)  // keep them for the later passes
         for (int x = lane; x < d * W; x += kWave)
           a.rows[base * kN34RowWords + x] = L.A[x / W][x % W];
+    }
+    if constexpr (MODE == kVRows) {  // triangles (p, nb[i], w), w > nb[i]
+      for (int i = lane; i < d; i += kWave)
+        if (i >= nl) a.tcnt[e_lo + (i - nl)] = popc_and<W>(L.A[i], L.A[i], i + 1, d);
+      continue;
     }
     // triangles (p, nb[i], nb[j]), i >= nl, i < j: row i holds those of
     // edge (p, nb[i]), numbered from tb[i]; every row must count exactly
@@ -1147,7 +1163,18 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
     wave_lds_sync();
     wave_scan_lds(L.pre, d);
     const int32_t nt = L.pre[d];
-    if (!FILL) {
+    if constexpr (MODE == kVTris) {  // third vertices ascending, per edge
+      for (int32_t t = lane; t < nt; t += kWave) {
+        const int i = row_of(L.pre, d, t);
+        const int r = t - L.pre[i];
+        const int j = nth_and<W>(L.A[i], L.A[i], i + 1, r);
+        const int64_t pos = (int64_t)L.tb[i] + r;
+        a.tw[pos] = L.nb[j];
+        a.te[pos] = (int32_t)(e_lo + (i - nl));
+      }
+      continue;
+    }
+    if constexpr (MODE == kVCount) {
       for (int32_t t = lane; t < nt; t += kWave) {
         const int i = row_of(L.pre, d, t);
         const int r = t - L.pre[i];
@@ -1234,6 +1261,30 @@ __global__ __launch_bounds__(kWave) void k_n34_vertex(N34VArgs a) {
   }
 }
 
+// Degree class of vertex p before the triangles exist: 0/1/2 for degree
+// <= 64/128/256 when p has at least two neighbours above it (it may be the
+// lowest vertex of a triangle), 3 for a larger degree, 4 otherwise.
+__global__ void k_n34_degree_bins(const int64_t *__restrict__ row_off,
+                                  const int32_t *__restrict__ nlow, int32_t n,
+                                  uint8_t *__restrict__ bin) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t d = row_off[p + 1] - row_off[p];
+  bin[p] = nlow[p] >= d - 1 ? 4 : d <= 64 ? 0 : d <= 128 ? 1 : d <= kN34VMax ? 2 : 3;
+}
+
+// Intersection bin of the edges whose lower endpoint is too big for the
+// per-vertex builder; kIsectBins (skipped) for the others.
+__global__ void k_edge_bins_big_low(const int32_t *__restrict__ ev,
+                                    const int64_t *__restrict__ row_off,
+                                    int64_t ne, uint8_t *__restrict__ bin) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int32_t u = ev[2 * e], v = ev[2 * e + 1];
+  const int64_t du = row_off[u + 1] - row_off[u], dv = row_off[v + 1] - row_off[v];
+  bin[e] = du <= kN34VMax ? (uint8_t)kIsectBins : isect_bin(min(du, dv));
+}
+
 // Degree class of vertex p for the per-vertex builder: 0/1/2 for degree
 // <= 64/128/256 with at least one triangle whose lowest vertex is p, 3 for
 // a larger degree (its triangles go per triangle), 4 for none.
@@ -1294,21 +1345,28 @@ __global__ void k_n34_check_full(const int32_t *__restrict__ cur,
   if (ballot(bad) && lane_id() == 0) atomicOr(err, 1);
 }
 
-void run_n34_vertex(N34VArgs a, bool fill, const int32_t *items,
+template <int D>
+void launch_n34_vertex(const N34VArgs &a, int mode, unsigned grid, hipStream_t s) {
+  switch (mode) {
+    case kVRows: k_n34_vertex<D, kVRows><<<grid, kWave, 0, s>>>(a); break;
+    case kVTris: k_n34_vertex<D, kVTris><<<grid, kWave, 0, s>>>(a); break;
+    case kVCount: k_n34_vertex<D, kVCount><<<grid, kWave, 0, s>>>(a); break;
+    default: k_n34_vertex<D, kVFill><<<grid, kWave, 0, s>>>(a); break;
+  }
+}
+
+void run_n34_vertex(N34VArgs a, int mode, const int32_t *items,
                     const int64_t *bin_off, hipStream_t s) {
+  ND_REQUIRE((mode != kVRows && mode != kVTris) || a.rows != nullptr,
+             ND_ERR_DEVICE, "internal error: bit-row pass without rows");
   for (int b = 0; b < 3; b++) {
     a.items = items + bin_off[b];
     a.nitems = bin_off[b + 1] - bin_off[b];
     if (a.nitems == 0) continue;
     const unsigned grid = (unsigned)std::min<int64_t>(a.nitems, 1 << 20);
-    switch (b * 2 + (fill ? 1 : 0)) {
-      case 0: k_n34_vertex<64, false><<<grid, kWave, 0, s>>>(a); break;
-      case 1: k_n34_vertex<64, true><<<grid, kWave, 0, s>>>(a); break;
-      case 2: k_n34_vertex<128, false><<<grid, kWave, 0, s>>>(a); break;
-      case 3: k_n34_vertex<128, true><<<grid, kWave, 0, s>>>(a); break;
-      case 4: k_n34_vertex<256, false><<<grid, kWave, 0, s>>>(a); break;
-      default: k_n34_vertex<256, true><<<grid, kWave, 0, s>>>(a); break;
-    }
+    if (b == 0) launch_n34_vertex<64>(a, mode, grid, s);
+    else if (b == 1) launch_n34_vertex<128>(a, mode, grid, s);
+    else launch_n34_vertex<256>(a, mode, grid, s);
     ND_LAUNCHED();
   }
 }
@@ -1509,13 +1567,106 @@ void build_triangles(nd_graph *g, hipStream_t s) {
   g->tris_ready = true;
 }
 
+// The triangle list (the same arrays, in the same order, as build_triangles)
+// from the per-vertex bit rows, which stay in `rows` for the (3,4) passes
+// that follow: a wave per vertex p of degree <= kN34VMax counts, then lists,
+// the triangles of each edge (p, v), v > p, from row v's bits above v; the
+// edges whose lower endpoint has a larger degree are intersected as in
+// build_triangles.
+void build_triangles_rows(nd_graph *g, uint32_t *rows, hipStream_t s) {
+  build_edges(g, s);
+  Phase phase("nd.triangles");
+  Allocator &al = g->ctx->alloc;
+  const int32_t n = g->n;
+  const int64_t ne = g->ne;
+  DArr<uint8_t> vbin(al, std::max<int32_t>(n, 1));
+  DArr<int32_t> vitems(al, std::max<int32_t>(n, 1));
+  if (n > 0) {
+    k_n34_degree_bins<<<grid_for(n, 256), 256, 0, s>>>(g->row_off.p, g->nlow.p, n,
+                                                        vbin.p);
+    ND_LAUNCHED();
+  }
+  int64_t voff[6];
+  partition_by_bin(vbin.p, n, 5, vitems.p, voff, s, al);
+  vbin.free();
+  DArr<int32_t> eitems(al, std::max<int64_t>(ne, 1));
+  int64_t ebin_off[kIsectBins + 2] = {0};
+  if (voff[4] > voff[3]) {  // edges below a vertex too big for the rows
+    DArr<uint8_t> ebin(al, std::max<int64_t>(ne, 1));
+    k_edge_bins_big_low<<<grid_for(ne, 256), 256, 0, s>>>(g->ev.p, g->row_off.p,
+                                                           ne, ebin.p);
+    ND_LAUNCHED();
+    partition_by_bin(ebin.p, ne, kIsectBins + 1, eitems.p, ebin_off, s, al);
+  }
+  DArr<int32_t> cnt(al, std::max<int64_t>(ne, 1)), err(al, 1);
+  fill_i32(cnt.p, 0, ne, s);  // edges below a vertex without two upper ones
+  fill_i32(err.p, 0, 1, s);
+  EdgeIsectArgs ea = edge_args(g);
+  ea.count = cnt.p;
+  run_edge_isect<kCountTri>(ea, eitems.p, ebin_off, s);
+  N34VArgs va{};
+  va.row_off = g->row_off.p;
+  va.col = g->col.p;
+  va.eid = g->eid.p;
+  va.nlow = g->nlow.p;
+  va.eoff = g->eoff.p;
+  va.rows = rows;
+  va.tcnt = cnt.p;
+  va.t.col = g->col.p;
+  va.t.err = err.p;
+  run_n34_vertex(va, kVRows, vitems.p, voff, s);
+  g->toff.reset(al, ne + 1);
+  exclusive_scan_i32(cnt.p, g->toff.p, ne, s, al);
+  cnt.free();
+  g->nt = read_i64(g->toff.p + ne, s);
+  ND_REQUIRE(g->nt < ((int64_t)1 << 31), ND_ERR_INVALID,
+             "%lld triangles: triangle ids must fit int32", (long long)g->nt);
+  g->tri_w.reset(al, g->nt);
+  g->tri_e.reset(al, g->nt);
+  va.rows_ready = 1;
+  va.t.toff = g->toff.p;
+  va.tw = g->tri_w.p;
+  va.te = g->tri_e.p;
+  run_n34_vertex(va, kVTris, vitems.p, voff, s);
+  ea.off = g->toff.p;
+  ea.out_a = g->tri_w.p;
+  ea.out_b = g->tri_e.p;
+  run_edge_isect<kFillTri>(ea, eitems.p, ebin_off, s);
+  const int32_t h = *PinnedChunk().read(err.p, 1, s);
+  ND_REQUIRE(h == 0, ND_ERR_DEVICE,
+             "internal error: the triangle counts of the bit rows disagree");
+  g->tris_ready = true;
+}
+
 // (3,4) incidence: each 4-clique is written once, by the builder of its
 // lowest vertex (per vertex for degrees up to kN34VMax, else per triangle),
 // into the lists of its four triangles: the three that contain that vertex
 // at ranks known from the count pass, the fourth at a cursor.
 void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
-  build_triangles(g, s);
   Allocator &al = g->ctx->alloc;
+  // the bit rows of every vertex of degree <= kN34VMax, built once (with the
+  // triangles when those do not exist yet, else by the count pass) and read
+  // back by the later passes; skipped when they would take more than a
+  // quarter of the budget left (every pass then builds them again)
+  DArr<uint32_t> rows;
+  const size_t rows_bytes =
+      sizeof(uint32_t) * kN34RowWords * (size_t)std::max<int64_t>(g->nnz, 1);
+  const size_t live = al.live_bytes();
+  if (g->nnz > 0 &&
+      (al.budget() == 0 ||
+       (live < al.budget() && rows_bytes <= (al.budget() - live) / 4))) {
+    try {
+      rows.reset(al, std::max<int64_t>(g->nnz, 1) * kN34RowWords);
+    } catch (const Err &) {  // the device is short of memory
+      rows.p = nullptr;
+    }
+  }
+  bool rows_ready = false;
+  if (!g->tris_ready && rows.p) {
+    build_triangles_rows(g, rows.p, s);
+    rows_ready = true;
+  }
+  build_triangles(g, s);
   const int64_t nt = g->nt;
   const int32_t n = g->n;
   // vertices by degree class; triangles of the big ones by intersection bin
@@ -1561,26 +1712,11 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   va.nlow = g->nlow.p;
   va.eoff = g->eoff.p;
   va.t = a;
-  // the count pass's bit rows, for the fill pass (skipped when they would
-  // take more than a quarter of the budget left: the fill then builds them
-  // again)
-  DArr<uint32_t> rows;
-  const size_t rows_bytes =
-      sizeof(uint32_t) * kN34RowWords * (size_t)std::max<int64_t>(g->nnz, 1);
-  const size_t live = al.live_bytes();
-  if (voff[3] > 0 &&
-      (al.budget() == 0 ||
-       (live < al.budget() && rows_bytes <= (al.budget() - live) / 4))) {
-    try {
-      rows.reset(al, std::max<int64_t>(g->nnz, 1) * kN34RowWords);
-    } catch (const Err &) {  // the device is short of memory
-      rows.p = nullptr;
-    }
-  }
   va.rows = rows.p;
+  va.rows_ready = rows_ready ? 1 : 0;
   {
     Phase phase("nd.incidence.count");
-    run_n34_vertex(va, false, vitems.p, voff, s);
+    run_n34_vertex(va, kVCount, vitems.p, voff, s);
     run_n34_tri(a, false, items.p, bin_off, s);
   }
   ks.nr = nt;
@@ -1597,7 +1733,7 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   a.out = ks.inc_ids.p;
   va.t = a;
   Phase fill_phase("nd.incidence.fill");
-  run_n34_vertex(va, true, vitems.p, voff, s);
+  run_n34_vertex(va, kVFill, vitems.p, voff, s);
   rows.free();
   run_n34_tri(a, true, items.p, bin_off, s);
   if (nt > 0) {
