@@ -274,7 +274,9 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str) -> None:
           "Per dispatch, from the same three runs as the sweep's traffic record: the kernel-trace",
           "average duration, FETCH_SIZE and WRITE_SIZE averaged over the dispatches and scaled",
           f"by the 1 GiB copy (fetch x{fscale:.3f}, write x{wscale:.3f}), and their sum over the",
-          "duration. Each step (the warm-up and two timed) prepares the graph once.", "",
+          "duration. Each step (the warm-up and two timed) prepares the graph once.",
+          "`k_n34_vertex<D, pass>`: pass 0 bit rows and triangle counts, 1 triangles, 2 S-degrees",
+          "and local counts, 3 the 4-cliques' entries (D: the degree class).", "",
           "| kernel | calls | avg ms | FETCH GB | WRITE GB | GB/s |", "|---|---:|---:|---:|---:|---:|"]
     for r in prep[:16]:
         name = _short_kernel(r["Name"])

@@ -479,10 +479,13 @@ void launch_typed(const KindState &ks, const SweepArgs &a, bool and_mode,
 }
 
 // The group summaries of the flags a dense notifying sweep wrote without
-// them: one thread per group of 64 flags (four 16-byte loads), which stores
-// the next stamp into the group's summary when any of its flags holds it.
-// Runs only when the sweep it follows took that path (the same test as
-// frontier_mode, on the same counters).
+// them: a thread per group of 64 flags (four 16-byte loads), striding, which
+// stores the next stamp into the group's summary when any of its flags holds
+// it.  Runs only when the sweep it follows took that path (the same test as
+// frontier_mode, on the same counters); a small grid keeps the launches that
+// find nothing to do cheap.
+constexpr int kGroupSumsBlocks = 1024;
+
 __global__ __launch_bounds__(256) void k_group_sums(SweepArgs a, int64_t nr) {
   const unsigned long long pc = prev_changed(a);
   if (pc == 0 || a.sums_after == 0 || pc < a.sums_after) return;
@@ -492,25 +495,26 @@ __global__ __launch_bounds__(256) void k_group_sums(SweepArgs a, int64_t nr) {
   if (!notify) return;
   const uint8_t next = a.stamp == 255 ? 1 : a.stamp + 1;
   const int64_t ng = (nr + (1 << kGroupShift) - 1) >> kGroupShift;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ng) return;
-  const int64_t f0 = g << kGroupShift;
-  bool any = false;
-  if (f0 + (1 << kGroupShift) <= nr) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(a.act_next + f0);
-    const uint32_t pat = 0x01010101u * next;
+  const uint32_t pat = 0x01010101u * next;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f0 = g << kGroupShift;
+    bool any = false;
+    if (f0 + (1 << kGroupShift) <= nr) {
+      const uint4 *p = reinterpret_cast<const uint4 *>(a.act_next + f0);
 #pragma unroll
-    for (int v = 0; v < (1 << kGroupShift) / 16; v++) {
-      const uint4 w = p[v];
-      const uint32_t x[4] = {w.x ^ pat, w.y ^ pat, w.z ^ pat, w.w ^ pat};
+      for (int v = 0; v < (1 << kGroupShift) / 16; v++) {
+        const uint4 w = p[v];
+        const uint32_t x[4] = {w.x ^ pat, w.y ^ pat, w.z ^ pat, w.w ^ pat};
 #pragma unroll
-      for (int c = 0; c < 4; c++)  // a zero byte: a flag equal to next
-        any |= ((x[c] - 0x01010101u) & ~x[c] & 0x80808080u) != 0;
+        for (int c = 0; c < 4; c++)  // a zero byte: a flag equal to next
+          any |= ((x[c] - 0x01010101u) & ~x[c] & 0x80808080u) != 0;
+      }
+    } else {
+      for (int64_t f = f0; f < nr; f++) any |= a.act_next[f] == next;
     }
-  } else {
-    for (int64_t f = f0; f < nr; f++) any |= a.act_next[f] == next;
+    if (any) a.act_sum_next[g] = next;
   }
-  if (any) a.act_sum_next[g] = next;
 }
 
 }  // namespace
@@ -520,7 +524,9 @@ void launch_group_sums(const KindState &ks, const SweepArgs &a, hipStream_t s) {
       ks.nr == 0)
     return;
   const int64_t ng = (ks.nr + (1 << dev::kGroupShift) - 1) >> dev::kGroupShift;
-  k_group_sums<<<grid_for(ng, 256), 256, 0, s>>>(a, ks.nr);
+  const unsigned grid =
+      (unsigned)std::min<int64_t>(grid_for(ng, 256), kGroupSumsBlocks);
+  k_group_sums<<<grid, 256, 0, s>>>(a, ks.nr);
   ND_LAUNCHED();
 }
 
