@@ -64,6 +64,10 @@
  *   ND_TRUSS_NO_TRIBUF=1  the k-truss builder intersects twice instead of
  *                         recording the triangles (the path taken when the
  *                         buffer does not fit the memory budget).
+ *   ND_N34_NO_ROWS=1      the (3,4) builder keeps no bit rows: triangles are
+ *                         listed by intersection and every pass builds its
+ *                         rows again (the path taken when they do not fit a
+ *                         quarter of the memory budget left).
  *   ND_LEVELS_BIG=c       nd_levels runs a level on the whole GPU when it has
  *                         at least c candidate r-cliques (default 1024).
  */

@@ -1652,7 +1652,8 @@ void build_incidence_n34(nd_graph *g, KindState &ks, hipStream_t s) {
   const size_t rows_bytes =
       sizeof(uint32_t) * kN34RowWords * (size_t)std::max<int64_t>(g->nnz, 1);
   const size_t live = al.live_bytes();
-  if (g->nnz > 0 &&
+  const char *no_rows = getenv("ND_N34_NO_ROWS");
+  if (g->nnz > 0 && !(no_rows && no_rows[0] == '1') &&
       (al.budget() == 0 ||
        (live < al.budget() && rows_bytes <= (al.budget() - live) / 4))) {
     try {

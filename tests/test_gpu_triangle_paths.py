@@ -58,3 +58,37 @@ def test_triangle_paths_agree(nd, ctx, name, make):
                           og.sdeg(3, 4))
     rows_first.close()
     isect_first.close()
+
+
+@pytest.mark.parametrize("name,make", GRAPHS, ids=[x[0] for x in GRAPHS])
+def test_n34_without_kept_rows(nd, ctx, name, make, monkeypatch):
+    """The (3,4) builder's path without kept bit rows (tight budgets):
+    triangles by intersection, rows rebuilt by the count and the fill pass.
+    Its incidence lists (as sets), S-degrees and kappa equal the path's with
+    rows and the oracle's."""
+    raw = make()
+    og = oracle.Graph.from_raw(raw)
+    want = og.peel(3, 4)
+    canon = []
+    for env in ({}, {"ND_N34_NO_ROWS": "1"}):
+        with monkeypatch.context() as m:
+            for k, v in env.items():
+                m.setenv(k, v)
+            g = nd.Graph.from_edges(ctx, raw.n, torch.from_numpy(raw.src),
+                                    torch.from_numpy(raw.dst))
+            g.prepare("nucleus34")
+        assert np.array_equal(g.rcliques("nucleus34").cpu().numpy(), og.rcliques(3))
+        assert np.array_equal(g.sdegree("nucleus34").cpu().numpy(), og.sdeg(3, 4))
+        off, ids = g.incidence("nucleus34")
+        nr = off.numel() - 1
+        rid = torch.repeat_interleave(torch.arange(nr, device=off.device),
+                                      off[1:] - off[:-1]).long()
+        srt = torch.sort(ids.long(), dim=1).values
+        key = ((rid * nr + srt[:, 0]) * nr + srt[:, 1]) * nr + srt[:, 2]
+        canon.append(torch.sort(key).values)
+        for mode in ("snd", "and"):
+            kappa, res = g.decompose("nucleus34", mode, use_frontier=True)
+            assert res["converged"] == 1
+            assert np.array_equal(kappa.cpu().numpy(), want), (env, mode)
+        g.close()
+    assert torch.equal(canon[0], canon[1])
